@@ -1,0 +1,161 @@
+"""Element geometry, face matching and flux-point pairing.
+
+Test infrastructure (see ``oracle/__init__``).
+
+Paper, Section 2.1 and Section 3.3: elements of several types on one mixed
+unstructured grid; interfaces couple neighbouring elements only through
+data at their shared faces.  Geometry (reading R4): straight-sided
+elements, the tet affine and the prism mapped by its six-node shape
+functions (linear on the triangle times linear in t); the metric terms
+are evaluated exactly at every point from the mapping's derivatives.
+
+Conventions used here and documented for the library alike:
+* global element id is type-major: tets 0..n_tet-1, then prisms;
+* a face pair's side L is the (global id, local face) that sorts first;
+* flux points pair by physical position (after periodic unwrapping).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import elements
+
+TYPES = ("tet", "pri")
+
+
+def shape_functions(name, x):
+    """Shape functions N [n_pts][n_verts] and their reference derivatives
+    dN [n_pts][n_verts][3] of the straight-sided element map."""
+    r, s, t = x[:, 0], x[:, 1], x[:, 2]
+    one = np.ones_like(r)
+    zero = np.zeros_like(r)
+    if name == "tet":
+        N = np.stack([-(1 + r + s + t) / 2, (1 + r) / 2, (1 + s) / 2, (1 + t) / 2], -1)
+        dN = np.array([[-0.5, -0.5, -0.5], [0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]])
+        dN = np.broadcast_to(dN, (len(x), 4, 3)).copy()
+        return N, dN
+    l = [-(r + s) / 2, (1 + r) / 2, (1 + s) / 2]
+    dl = [(-0.5 * one, -0.5 * one), (0.5 * one, zero), (zero, 0.5 * one)]
+    lo, hi = (1 - t) / 2, (1 + t) / 2
+    N = np.stack([l[0] * lo, l[1] * lo, l[2] * lo, l[0] * hi, l[1] * hi, l[2] * hi], -1)
+    dN = []
+    for half, dh in ((lo, -0.5), (hi, 0.5)):
+        for a in range(3):
+            dN.append(np.stack([dl[a][0] * half, dl[a][1] * half, l[a] * dh], -1))
+    return N, np.stack(dN, axis=1)
+
+
+@dataclass
+class TypeGeom:
+    name: str
+    ref: elements.RefElement
+    nelem: int
+    verts: np.ndarray      # [E][nv] global vertex ids
+    X: np.ndarray          # [E][nv][3] unwrapped vertex coordinates
+    x_upts: np.ndarray     # [E][N_u][3] physical solution point positions
+    x_fpts: np.ndarray     # [E][N_f][3]
+    J_upts: np.ndarray     # [E][N_u]
+    adj_upts: np.ndarray   # [E][N_u][3][3]  adj[k][j] = J dxi_k/dx_j
+    n_fpts: np.ndarray     # [E][N_f][3]  adj^T n_ref (physical normal scaled)
+
+
+def geometry(name, ref, X):
+    """Physical positions, Jacobian determinant and adjugate at the points."""
+    def at(pts):
+        N, dN = shape_functions(name, pts)
+        x = np.einsum("pa,eai->epi", N, X)
+        Jm = np.einsum("pak,eai->epik", dN, X)          # dx_i / dxi_k
+        J = np.linalg.det(Jm)
+        adj = J[..., None, None] * np.linalg.inv(Jm)    # [k][j] = J dxi_k/dx_j
+        return x, J, adj
+    xu, Ju, adju = at(ref.upts)
+    xf, _, adjf = at(ref.fpts)
+    nf = np.einsum("epkj,pk->epj", adjf, ref.norm_ref)
+    return xu, xf, Ju, adju, nf
+
+
+@dataclass
+class Mesh:
+    p: int
+    types: dict            # name -> TypeGeom (only types with elements)
+    fpt_offset: dict       # name -> offset of the type's flux points in the global flux array
+    nfpts_total: int
+    pair_L: np.ndarray     # [n_pairs] global flux index of side L
+    pair_R: np.ndarray     # [n_pairs] global flux index of side R
+    pair_nhat: np.ndarray  # [n_pairs][3] unit normal pointing out of side L
+    pair_sL: np.ndarray    # [n_pairs] |adj^T n_ref| on side L
+    pair_sR: np.ndarray    # [n_pairs]
+
+
+def build_mesh(mesh_arrays, p, tol=1e-9):
+    """Build geometry and the interface pairing from the generator's arrays.
+
+    Raises ValueError on a non-positive Jacobian, an unmatched face, or a
+    face whose flux points do not coincide."""
+    types = {}
+    gid0 = 0
+    gid_base = {}
+    for name in TYPES:
+        v = mesh_arrays[f"{name}_v"]
+        if len(v) == 0:
+            continue
+        ref = elements.get(name, p)
+        X = mesh_arrays["xyz"][v] + mesh_arrays[f"{name}_img"].astype(np.float64) * mesh_arrays["period"]
+        xu, xf, Ju, adju, nf = geometry(name, ref, X)
+        if (Ju <= 0).any():
+            bad = int(np.argwhere((Ju <= 0).any(axis=1))[0, 0])
+            raise ValueError(f"non-positive Jacobian in {name} element {bad}")
+        types[name] = TypeGeom(name, ref, len(v), v, X, xu, xf, Ju, adju, nf)
+        gid_base[name] = gid0
+        gid0 += len(v)
+
+    fpt_offset, off = {}, 0
+    for name, tg in types.items():
+        fpt_offset[name] = off
+        off += tg.nelem * tg.ref.nfpts
+
+    # Face matching by sorted global vertex ids
+    faces = {}
+    for name, tg in types.items():
+        for fi, face in enumerate(tg.ref.faces):
+            keys = np.sort(tg.verts[:, list(face)], axis=1)
+            for e in range(tg.nelem):
+                faces.setdefault(tuple(keys[e]), []).append((gid_base[name] + e, fi, name, e))
+    pL, pR, nh, sL, sR = [], [], [], [], []
+    scale = max(np.ptp(mesh_arrays["xyz"], axis=0).max(), 1.0)
+    for key, lst in faces.items():
+        if len(lst) != 2:
+            raise ValueError(f"face {key} shared by {len(lst)} elements")
+        lst.sort()
+        (_, fa, na, ea), (_, fb, nb, eb) = lst
+        A, B = types[na], types[nb]
+        ja = np.arange(A.ref.face_offsets[fa], A.ref.face_offsets[fa] + _nface(A.ref, fa))
+        jb = np.arange(B.ref.face_offsets[fb], B.ref.face_offsets[fb] + _nface(B.ref, fb))
+        # periodic shift between the two unwrapped copies of the shared face
+        va = A.verts[ea, list(A.ref.faces[fa])[0]]
+        ia = list(A.verts[ea]).index(va)
+        ib = list(B.verts[eb]).index(va)
+        shift = A.X[ea, ia] - B.X[eb, ib]
+        xa = A.x_fpts[ea, ja]
+        xb = B.x_fpts[eb, jb] + shift
+        d = np.linalg.norm(xa[:, None, :] - xb[None, :, :], axis=-1)
+        match = d.argmin(axis=1)
+        if (d[np.arange(len(ja)), match] > tol * scale).any() or len(set(match)) != len(ja):
+            raise ValueError(f"flux points of face {key} do not coincide")
+        for k, j in enumerate(ja):
+            jj = jb[match[k]]
+            pL.append(fpt_offset[na] + ea * A.ref.nfpts + j)
+            pR.append(fpt_offset[nb] + eb * B.ref.nfpts + jj)
+            n = A.n_fpts[ea, j]
+            s = np.linalg.norm(n)
+            nh.append(n / s)
+            sL.append(s)
+            sR.append(np.linalg.norm(B.n_fpts[eb, jj]))
+    return Mesh(p, types, fpt_offset, off, np.array(pL), np.array(pR), np.array(nh),
+                np.array(sL), np.array(sR))
+
+
+def _nface(ref, f):
+    return int((ref.fpt_face == f).sum())

@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs: periodic mixed prism/tet meshes and initial fields.
+
+This module holds input generation only (vertex lattices, jitter, element
+connectivity, closed-form initial conditions evaluated at given physical
+points).  It holds none of the flux reconstruction arithmetic, so both the
+library side and the FP64 oracle may consume what it produces.
+
+Mesh arrays (all numpy, host memory):
+
+* ``xyz``      float64 [n_vertices][3]  unique (periodic) vertex coordinates
+* ``tet_v``    int64   [n_tets][4]      vertex ids, positively oriented
+* ``tet_img``  int8    [n_tets][4][3]   periodic image shift per element vertex;
+                                        the unwrapped vertex is xyz[v] + img*period
+* ``pri_v``    int64   [n_prisms][6]    0-2 bottom triangle (counter-clockwise
+                                        seen from above), 3-5 top, k+3 above k
+* ``pri_img``  int8    [n_prisms][6][3]
+* ``period``   float64 [3]
+
+Element order is chosen for locality of interface gathers: tets are numbered
+shape-major (the six Kuhn shapes of a cube are six blocks, cubes run fastest
+inside a block); prisms are numbered triangle-major (the two triangles of an
+x-y quad are two blocks, then layer, then quad).  With that order the
+neighbour across a given local face of consecutive elements is, away from
+the periodic seams, at a constant index offset.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def _perm_sign(p):
+    s = 1
+    p = list(p)
+    for i in range(len(p)):
+        for j in range(i + 1, len(p)):
+            if p[i] > p[j]:
+                s = -s
+    return s
+
+
+def _kuhn_shapes():
+    """The six tetrahedra of the Kuhn (Freudenthal) split of the unit cube
+    along the (0,0,0)->(1,1,1) diagonal, as corner offsets, each ordered so
+    that det(v1-v0, v2-v0, v3-v0) > 0."""
+    shapes = []
+    for perm in itertools.permutations(range(3)):
+        v0 = np.zeros(3, dtype=int)
+        v1 = v0.copy(); v1[perm[0]] = 1
+        v2 = v1.copy(); v2[perm[1]] = 1
+        v3 = np.ones(3, dtype=int)
+        if _perm_sign(perm) > 0:
+            shapes.append((v0, v1, v2, v3))
+        else:
+            shapes.append((v0, v2, v1, v3))
+    return shapes
+
+
+# Two triangles of the x-y quad, split along (i,j)->(i+1,j+1), both
+# counter-clockwise; the diagonal matches the Kuhn split's z-faces.
+_QUAD_TRIS = (((0, 0), (1, 0), (1, 1)), ((0, 0), (1, 1), (0, 1)))
+
+
+def mixed_box(nx, ny, n_pri_layers, n_tet_layers, lengths, z_split=None,
+              jitter=0.0, seed=0):
+    """Periodic box [0,Lx)x[0,Ly)x[0,Lz): prisms (extruded x-y triangles) on
+    z in [0, z_split), Kuhn-split tets on z in [z_split, Lz).
+
+    ``n_pri_layers`` prism layers, ``n_tet_layers`` cube layers; either may
+    be zero.  Every vertex coordinate is jittered by U(-a, a) times the local
+    spacing on that axis (a = ``jitter``); on z levels between two spacings
+    the smaller is used.  Draw order: vertex id order, x then y then z.
+    """
+    Lx, Ly, Lz = (float(v) for v in lengths)
+    if z_split is None:
+        z_split = 0.0 if n_pri_layers == 0 else (Lz if n_tet_layers == 0 else 0.5 * Lz)
+    zl = []
+    for k in range(n_pri_layers):
+        zl.append(k * z_split / n_pri_layers)
+    for k in range(n_tet_layers):
+        zl.append(z_split + k * (Lz - z_split) / n_tet_layers)
+    zl = np.asarray(zl, dtype=np.float64)
+    nz = len(zl)
+    if nz == 0:
+        raise ValueError("empty mesh")
+    dz = np.diff(np.append(zl, Lz))                # spacing above each level
+    dz_below = np.roll(dz, 1)
+    hz = np.minimum(dz, dz_below)
+
+    hx, hy = Lx / nx, Ly / ny
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    xyz = np.stack([ix * hx, iy * hy, zl[iz]], axis=-1).reshape(-1, 3)
+    if jitter:
+        rng = np.random.default_rng(seed)
+        r = rng.uniform(-1.0, 1.0, size=xyz.shape)
+        scale = np.stack([np.full(nz * ny * nx, hx), np.full(nz * ny * nx, hy),
+                          hz[iz.reshape(-1)]], axis=-1)
+        xyz = xyz + jitter * r * scale
+
+    def vid(kx, ky, kz):
+        return (np.mod(kz, nz) * ny + np.mod(ky, ny)) * nx + np.mod(kx, nx)
+
+    def img(kx, ky, kz):
+        return np.stack([kx >= nx, ky >= ny, kz >= nz], axis=-1).astype(np.int8)
+
+    # tets: shape-major, then cube (layer, y, x)
+    tet_v, tet_img = [], []
+    if n_tet_layers:
+        cz, cy, cx = np.meshgrid(np.arange(n_pri_layers, nz), np.arange(ny),
+                                 np.arange(nx), indexing="ij")
+        cz, cy, cx = cz.reshape(-1), cy.reshape(-1), cx.reshape(-1)
+        for shape in _kuhn_shapes():
+            vs, ims = [], []
+            for off in shape:
+                kx, ky, kz = cx + off[0], cy + off[1], cz + off[2]
+                vs.append(vid(kx, ky, kz))
+                ims.append(img(kx, ky, kz))
+            tet_v.append(np.stack(vs, axis=-1))
+            tet_img.append(np.stack(ims, axis=1))
+    tet_v = np.concatenate(tet_v) if tet_v else np.zeros((0, 4), np.int64)
+    tet_img = np.concatenate(tet_img) if tet_img else np.zeros((0, 4, 3), np.int8)
+
+    # prisms: triangle-major, then layer, then quad (y, x)
+    pri_v, pri_img = [], []
+    if n_pri_layers:
+        cz, cy, cx = np.meshgrid(np.arange(0, n_pri_layers), np.arange(ny),
+                                 np.arange(nx), indexing="ij")
+        cz, cy, cx = cz.reshape(-1), cy.reshape(-1), cx.reshape(-1)
+        for tri in _QUAD_TRIS:
+            vs, ims = [], []
+            for dk in (0, 1):
+                for (di, dj) in tri:
+                    kx, ky, kz = cx + di, cy + dj, cz + dk
+                    vs.append(vid(kx, ky, kz))
+                    ims.append(img(kx, ky, kz))
+            pri_v.append(np.stack(vs, axis=-1))
+            pri_img.append(np.stack(ims, axis=1))
+    pri_v = np.concatenate(pri_v) if pri_v else np.zeros((0, 6), np.int64)
+    pri_img = np.concatenate(pri_img) if pri_img else np.zeros((0, 6, 3), np.int8)
+
+    return {
+        "xyz": np.ascontiguousarray(xyz, dtype=np.float64),
+        "tet_v": np.ascontiguousarray(tet_v, dtype=np.int64),
+        "tet_img": np.ascontiguousarray(tet_img, dtype=np.int8),
+        "pri_v": np.ascontiguousarray(pri_v, dtype=np.int64),
+        "pri_img": np.ascontiguousarray(pri_img, dtype=np.int8),
+        "period": np.array([Lx, Ly, Lz], dtype=np.float64),
+    }
+
+
+def unwrapped(mesh, kind):
+    """Unwrapped vertex coordinates [n_elem][n_vert][3] of 'tet' or 'pri'."""
+    v = mesh[f"{kind}_v"]
+    im = mesh[f"{kind}_img"].astype(np.float64)
+    return mesh["xyz"][v] + im * mesh["period"]
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+def vortex_tet_cube(n=6, jitter=0.05, seed=0):
+    """Periodic unit cube, n^3 cubes x 6 Kuhn tets, jittered (the small FP64
+    Euler workload: n=6 gives 1,296 tets)."""
+    return mixed_box(n, n, 0, n, (1.0, 1.0, 1.0), jitter=jitter, seed=seed)
+
+
+def tgv_mixed_box(nxy=32, n_pri_layers=54, n_tet_layers=32, jitter=0.10, seed=0):
+    """Periodic [0,2pi)^3: prisms on z in [0,pi), Kuhn tets on z in [pi,2pi).
+    Defaults give 110,592 prisms and 196,608 tets with conforming triangular
+    interfaces at z=pi and z=0=2pi."""
+    L = 2.0 * math.pi
+    return mixed_box(nxy, nxy, n_pri_layers, n_tet_layers, (L, L, L),
+                     z_split=math.pi, jitter=jitter, seed=seed)
+
+
+def small_mixed_box(nxy=3, n_pri_layers=2, n_tet_layers=2, jitter=0.10, seed=0,
+                    L=2.0 * math.pi):
+    """A few-dozen-element version of the mixed box for oracle-sized tests."""
+    return mixed_box(nxy, nxy, n_pri_layers, n_tet_layers, (L, L, L),
+                     z_split=0.5 * L, jitter=jitter, seed=seed)
+
+
+# ----------------------------------------------------------------------------
+# Initial conditions: conserved variables (rho, rho u, rho v, rho w, E) at
+# physical points x, y, z (arrays of any common shape).  Output [5, ...].
+# ----------------------------------------------------------------------------
+
+def _conserved(rho, u, v, w, p, gamma=GAMMA):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def isentropic_vortex(x, y, z, eps=5.0, mach=0.5, radius=0.1, centre=(0.5, 0.5),
+                      period=(1.0, 1.0), gamma=GAMMA):
+    """2-D isentropic vortex in x-y (extruded in z) on a freestream with
+    rho = p = 1 moving along +x at the given Mach number.  The vortex is
+    placed at the periodic image of ``centre`` nearest to each point."""
+    u_inf = mach * math.sqrt(gamma)
+    dx = x - centre[0]
+    dy = y - centre[1]
+    dx = dx - period[0] * np.round(dx / period[0])
+    dy = dy - period[1] * np.round(dy / period[1])
+    r2 = (dx * dx + dy * dy) / (radius * radius)
+    f = np.exp(0.5 * (1.0 - r2))
+    du = -eps / (2.0 * math.pi) * f * dy / radius
+    dv = eps / (2.0 * math.pi) * f * dx / radius
+    T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * math.pi ** 2) * f * f
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return _conserved(rho, u_inf + du, dv, np.zeros_like(x) + 0.0 * z, p, gamma)
+
+
+def taylor_green(x, y, z, mach=0.1, gamma=GAMMA, rho0=1.0, v0=1.0):
+    """Taylor-Green vortex on [0,2pi)^3 at constant temperature."""
+    p0 = rho0 * v0 * v0 / (gamma * mach * mach)
+    u = v0 * np.sin(x) * np.cos(y) * np.cos(z)
+    v = -v0 * np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(u)
+    p = p0 + rho0 * v0 * v0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+    rho = rho0 * p / p0
+    return _conserved(rho, u, v, w, p, gamma)
+
+
+def density_wave(x, y, z, amp=0.2, vel=(1.0, 1.0, 1.0), p=1.0, k=2.0 * math.pi,
+                 t=0.0, direction=(1.0, 1.0, 1.0), gamma=GAMMA):
+    """Exact periodic Euler solution: rho = 1 + amp sin(k d.(x - vel t)),
+    constant velocity and pressure (d has integer components so that the
+    wave is periodic on the unit cube)."""
+    ph = k * (direction[0] * (x - vel[0] * t) + direction[1] * (y - vel[1] * t)
+              + direction[2] * (z - vel[2] * t))
+    rho = 1.0 + amp * np.sin(ph)
+    one = np.ones_like(rho)
+    return _conserved(rho, vel[0] * one, vel[1] * one, vel[2] * one, p * one, gamma)
+
+
+def shear_wave(x, y, z, amp=1e-3, Ly=2.0 * math.pi, rho=1.0, p=1.0 / (GAMMA * 0.01),
+               gamma=GAMMA):
+    """u = amp sin(2 pi y / Ly), v = w = 0, constant rho and p."""
+    u = amp * np.sin(2.0 * math.pi * y / Ly)
+    one = np.ones_like(u)
+    return _conserved(rho * one, u, 0 * one, 0 * one, p * one, gamma)
+
+
+def thermal_wave(x, y, z, amp=1e-2, Ly=2.0 * math.pi, p=1.0, gamma=GAMMA):
+    """Fluid at rest, uniform pressure, p/rho = 1 + amp sin(2 pi y / Ly)."""
+    T = 1.0 + amp * np.sin(2.0 * math.pi * y / Ly)
+    rho = p / T
+    zero = np.zeros_like(T)
+    return _conserved(rho, zero, zero, zero, p + zero, gamma)
+
+
+def uniform(x, y, z, rho=1.2, u=0.3, v=-0.2, w=0.1, p=0.9, gamma=GAMMA):
+    one = np.ones_like(np.asarray(x, dtype=np.float64))
+    return _conserved(rho * one, u * one, v * one, w * one, p * one, gamma)
+
+
+def random_perturbation(shape, seed, amp=1e-2):
+    """Seeded multiplicative noise for parity inputs (values in [1-amp, 1+amp])."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + amp * rng.uniform(-1.0, 1.0, size=shape)

@@ -1,0 +1,128 @@
+"""Scheme-level pins of the FP64 oracle on small periodic meshes:
+
+* freestream preservation (uniform state -> zero residual), Euler and NS,
+  tets and prisms, p = 1..4;
+* discrete conservation: sum w J R = 0 on a periodic mesh for any state;
+* interface pairing is a perfect matching with opposite normals;
+* exact-solution convergence for Euler (travelling density wave);
+* the viscous operator against closed forms (shear wave and thermal wave
+  second derivatives, Taylor-Green initial dissipation rate 3/4 mu).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as omesh, reduce, rk
+from paper_1409_0405_amd import inputs
+
+ORDERS = (1, 2, 3, 4)
+
+
+def _mixed(p, **kw):
+    return omesh.build_mesh(inputs.small_mixed_box(**kw), p)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("system", ["euler", "ns"])
+def test_freestream_preservation(p, system):
+    M = _mixed(p, jitter=0.15, seed=4)
+    U = fr.initial_state(M, inputs.uniform)
+    R = fr.rhs(M, U, fr.Params(system=system, mu=0.05))
+    assert max(np.abs(R[n]).max() for n in R) < 1e-12
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("system", ["euler", "ns"])
+def test_discrete_conservation(p, system):
+    M = _mixed(p, jitter=0.1, seed=7)
+    U = fr.initial_state(M, inputs.taylor_green, mach=0.3)
+    for n in U:
+        U[n] = U[n] * inputs.random_perturbation(U[n].shape, 11, 0.05)
+    R = fr.rhs(M, U, fr.Params(system=system, mu=0.02))
+    tot = reduce.integral(M, R)
+    scale = reduce.integral(M, {n: np.abs(R[n]) for n in R})
+    assert np.all(np.abs(tot) <= 1e-12 * scale), tot / scale
+
+
+@pytest.mark.parametrize("p", (1, 3))
+def test_pairing_perfect_matching(p):
+    M = _mixed(p, jitter=0.1)
+    idx = np.concatenate([M.pair_L, M.pair_R])
+    assert np.array_equal(np.sort(idx), np.arange(M.nfpts_total))
+    # the normal seen from side R is the opposite unit vector
+    nR = np.concatenate([M.types[n].n_fpts.reshape(-1, 3) for n in M.types])[M.pair_R]
+    nR = nR / np.linalg.norm(nR, axis=1)[:, None]
+    assert np.abs(nR + M.pair_nhat).max() < 1e-12
+    assert (M.pair_sL > 0).all() and (M.pair_sR > 0).all()
+
+
+def _l2_err(M, U, fn, **kw):
+    Ue = fr.initial_state(M, fn, **kw)
+    e = reduce.l2_norm(M, {n: U[n] - Ue[n] for n in U})
+    return e[0]
+
+
+@pytest.mark.parametrize("p", (1, 2, pytest.param(3, marks=pytest.mark.slow)))
+def test_density_wave_convergence(p):
+    """Euler, exact travelling density wave (wave vector along x, velocity
+    (1, 0.3, 0.2)) on jittered tet cubes; the L2 error of rho after RK4
+    steps to t = 0.1 must fall at >= p + 1/2 from 3 to 6 cubes a side."""
+    kw = dict(direction=(1, 0, 0), vel=(1.0, 0.3, 0.2))
+    errs = []
+    t_end = 0.1
+    for n in (3, 6):
+        M = omesh.build_mesh(inputs.vortex_tet_cube(n=n, jitter=0.05), p)
+        U = fr.initial_state(M, inputs.density_wave, **kw)
+        prm = fr.Params(system="euler")
+        nsteps = int(math.ceil(t_end / (0.3 / (n * (2 * p + 1) * 2.0))))
+        dt = t_end / nsteps
+        U = rk.run(rk.rk4_step, lambda V: fr.rhs(M, V, prm), U, dt, nsteps)
+        errs.append(_l2_err(M, U, inputs.density_wave, t=t_end, **kw))
+    rate = math.log2(errs[0] / errs[1])
+    assert rate >= p + 0.5, (errs, rate)
+
+
+def test_shear_wave_viscous_operator():
+    """u = A sin(y), rho and p uniform: the exact d(rho u)/dt is -mu A sin(y)
+    (the inviscid terms vanish).  The discrete momentum residual must
+    converge to it with p."""
+    mu, A = 0.5, 1e-2
+    errs = []
+    for p in (2, 3, 4):
+        M = _mixed(p, nxy=4, n_pri_layers=2, n_tet_layers=2, jitter=0.05)
+        U = fr.initial_state(M, inputs.shear_wave, amp=A, p=1.0)
+        R = fr.rhs(M, U, fr.Params(system="ns", mu=mu))
+        want = {n: -mu * A * np.sin(M.types[n].x_upts[..., 1]) for n in M.types}
+        err = reduce.l2_norm(M, {n: R[n][..., 1] - want[n] for n in R})
+        errs.append(err / reduce.l2_norm(M, want))
+    assert errs[-1] < 0.05 and errs[0] > errs[1] > errs[2], errs
+
+
+def test_thermal_wave_heat_flux():
+    """Fluid at rest with uniform pressure and p/rho = 1 + a sin(y): the
+    exact dE/dt is div(kappa grad(p/rho)) = -kappa a sin(y), with
+    kappa = mu gamma / (Pr (gamma - 1)); mass and momentum stay at rest."""
+    mu, a, pr = 0.1, 1e-2, 0.71
+    kappa = mu * 1.4 / (pr * 0.4)
+    errs = []
+    for p in (2, 3, 4):
+        M = _mixed(p, nxy=4, n_pri_layers=2, n_tet_layers=2, jitter=0.05)
+        U = fr.initial_state(M, inputs.thermal_wave, amp=a)
+        R = fr.rhs(M, U, fr.Params(system="ns", mu=mu, prandtl=pr))
+        want = {n: -kappa * a * np.sin(M.types[n].x_upts[..., 1]) for n in M.types}
+        err = reduce.l2_norm(M, {n: R[n][..., 4] - want[n] for n in R})
+        errs.append(err / reduce.l2_norm(M, want))
+    assert errs[-1] < 0.05 and errs[0] > errs[1] > errs[2], errs
+
+
+def test_taylor_green_initial_dissipation():
+    """At t = 0 the TGV velocity is divergence-free, so the mean kinetic
+    energy decays at mu <|omega|^2> = 3/4 mu (rho0 = V0 = 1).  The discrete
+    rate from the NS residual must approach it."""
+    mu = 1.0 / 100.0
+    M = _mixed(4, nxy=8, n_pri_layers=4, n_tet_layers=4, jitter=0.05)
+    U = fr.initial_state(M, inputs.taylor_green)
+    R = fr.rhs(M, U, fr.Params(system="ns", mu=mu))
+    rate = reduce.kinetic_energy_rate(M, U, R)
+    assert abs(-rate / (0.75 * mu) - 1.0) < 0.03, -rate / (0.75 * mu)
