@@ -1,0 +1,185 @@
+/*
+ * fr.h - C ABI of the MI355X flux reconstruction (FR) right-hand-side library.
+ *
+ * The library evaluates the FR right-hand side of the compressible Euler and
+ * Navier-Stokes equations (constant viscosity) on mixed tetrahedral / prismatic
+ * periodic grids, and advances it with explicit Runge-Kutta schemes.  The
+ * operations follow the paper "Heterogeneous Computing on Mixed Unstructured
+ * Grids with PyFR" (Witherden, Vermeire, Vincent):
+ *   - Section 2.1: an FR step is mostly products C <- c1 A B + c2 C of a
+ *     constant operator matrix A with row-major state matrices B, C, plus
+ *     point-wise operations at solution and flux points; Table 2 gives the
+ *     dimensions of the volume-to-surface interpolation operator M0;
+ *   - Section 3.4: DG-type spatial scheme, Rusanov interface flux, RK45[2R+];
+ *   - Table 1: element types, arbitrary order, Euler / RK4 / RK45 steppers,
+ *     single and double precision, Euler and Navier-Stokes systems.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Element types: FR_TET = 0, FR_PRI = 1.  Global element ids are type-major
+ * (tets first).  Solution state per type is a device array laid out
+ * [n_upts][5][ld] of the mesh's scalar type (float for FR_FP32, double for
+ * FR_FP64): point-major, then the conserved field (rho, rho u, rho v, rho w,
+ * E), then the element index, fastest; ld >= n_elem is a multiple of 64 and
+ * is reported by fr_mesh_query.  Columns n_elem..ld-1 are padding: they are
+ * read and written but never mix with real elements.
+ *
+ * Ownership: fr_mesh_create allocates every device buffer the mesh needs
+ * (operators, geometry, interface tables, intermediates, Runge-Kutta
+ * registers); fr_rhs and fr_rk_step allocate nothing.  Pointers passed in are
+ * borrowed for the duration of the call (host arrays) or of the enqueued work
+ * (device arrays).
+ *
+ * Streams: every entry point that takes a `stream` (a hipStream_t, NULL for the
+ * default stream) enqueues its work there and returns without waiting, except
+ * fr_reduce and fr_mesh_destroy, which synchronise the stream.
+ *
+ * Errors: every call returns an fr_status; no exception crosses the ABI.
+ * fr_last_error(mesh) returns a message for the last failure on that mesh
+ * (fr_last_error(NULL): the last failure of fr_mesh_create on this thread).
+ * An asynchronous device fault surfaces as FR_ERR_DEVICE on a later call.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FR_OK = 0,
+    FR_ERR_INVALID_ARG = 1,   /* NULL pointer, unknown enum, wrong sizes */
+    FR_ERR_BAD_MESH = 2,      /* J <= 0, unmatched or non-conforming face */
+    FR_ERR_UNSUPPORTED = 3,   /* order outside 1..4, precision not built */
+    FR_ERR_OUT_OF_MEMORY = 4, /* device allocation failed */
+    FR_ERR_DEVICE = 5,        /* HIP runtime error */
+    FR_ERR_NONFINITE = 6      /* FR_CHECK_FINITE found a NaN / Inf */
+} fr_status;
+
+typedef enum { FR_TET = 0, FR_PRI = 1 } fr_etype;
+typedef enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 } fr_system;
+typedef enum { FR_FP32 = 0, FR_FP64 = 1 } fr_precision;
+typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
+
+/* fr_mesh_desc.flags */
+#define FR_VALIDATE_ONLY 0x1u  /* build host-side tables only; no device work */
+#define FR_CHECK_FINITE 0x2u   /* fr_rk_step ends with a finiteness check */
+
+typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
+
+/*
+ * Mesh and physics description (host memory, read during fr_mesh_create).
+ *
+ * order      polynomial order p of the solution, 1..4 on the GPU (Table 2).
+ * system     FR_EULER or FR_NAVIER_STOKES (Section 3.4, Table 1).
+ * precision  scalar type of the state and of the device arithmetic.
+ * gamma      ratio of specific heats; mu dynamic viscosity (ignored for
+ *            Euler); prandtl Prandtl number; ldg_beta, ldg_tau the LDG switch
+ *            and penalty of the viscous interface flux.
+ * xyz        [n_vertices][3] vertex coordinates.
+ * tet_v      [n_tets][4] vertex ids; prism vertex ids pri_v [n_prisms][6] list
+ *            the bottom triangle 0-2 (counter-clockwise seen from above) and
+ *            then the top 3-5, vertex k+3 above vertex k.
+ * tet_img, pri_img  periodic image shift per element vertex [..][n][3] (int8,
+ *            unwrapped vertex = xyz[v] + img * period), or NULL for none.
+ * period     box lengths of the periodic directions (used with the images).
+ */
+typedef struct {
+    int32_t order;
+    int32_t system;
+    int32_t precision;
+    uint32_t flags;
+    double gamma, mu, prandtl, ldg_beta, ldg_tau;
+    int64_t n_vertices;
+    const double *xyz;
+    int64_t n_tets;
+    const int64_t *tet_v;
+    const int8_t *tet_img;
+    int64_t n_prisms;
+    const int64_t *pri_v;
+    const int8_t *pri_img;
+    double period[3];
+} fr_mesh_desc;
+
+/* Build operators (FP64 on the host), geometry and the interface pairing,
+ * allocate and upload every device buffer.  Errors: FR_ERR_INVALID_ARG,
+ * FR_ERR_BAD_MESH (message names the element / face), FR_ERR_UNSUPPORTED,
+ * FR_ERR_OUT_OF_MEMORY, FR_ERR_DEVICE.  With FR_VALIDATE_ONLY no HIP call is
+ * made; only fr_mesh_query, fr_upts_coords, fr_operator and fr_mesh_destroy
+ * may then be used. */
+fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out);
+
+/* Free the mesh and its device buffers (synchronises the stream it was
+ * created on).  NULL is accepted. */
+fr_status fr_mesh_destroy(fr_mesh mesh);
+
+/* Element count, solution points per element and leading dimension ld of
+ * one element type (n_elem = 0 when the mesh has none). */
+fr_status fr_mesh_query(fr_mesh mesh, int32_t etype, int64_t *n_elem,
+                        int32_t *n_upts, int32_t *n_fpts, int64_t *ld);
+
+/* Physical solution-point positions, host array [n_upts][3][n_elem]. */
+fr_status fr_upts_coords(fr_mesh mesh, int32_t etype, double *xyz_host);
+
+/* Copy a host-built FP64 operator of one element type to a host array of
+ * rows*cols doubles, row-major.  which: 0 = M0 (n_fpts x n_upts), 1..3 =
+ * gradient d/dxi_k (n_upts x n_upts), 4 = correction lift L (n_upts x n_fpts),
+ * 5 = quadrature weights (1 x n_upts).  out may be NULL to query the shape. */
+fr_status fr_operator(fr_mesh mesh, int32_t etype, int32_t which, double *out,
+                      int32_t *rows, int32_t *cols);
+
+/* Copy a caller device state of one type into / out of the mesh's solution
+ * register (the state fr_rk_step advances).  u_dev is [n_upts][5][ld]. */
+fr_status fr_set_solution(fr_mesh mesh, int32_t etype, const void *u_dev, void *stream);
+fr_status fr_get_solution(fr_mesh mesh, int32_t etype, void *u_dev, void *stream);
+
+/* One right-hand-side evaluation R = dU/dt (Section 2.1 operator products and
+ * point-wise kernels, Section 3.4 scheme).  u_dev[t] / r_dev[t] are the
+ * caller's device states of type t ([n_upts][5][ld]); entries of types the
+ * mesh does not have are ignored and may be NULL.  r_dev must not alias u_dev. */
+fr_status fr_rhs(fr_mesh mesh, const void *const u_dev[2], void *const r_dev[2],
+                 void *stream);
+
+/* Advance the mesh's solution register n_steps steps of size dt with the
+ * given scheme (Table 1; FR_RK45_2RP is the two-register RK45[2R+] of Section
+ * 3.4, fixed step).  With FR_CHECK_FINITE set at create, ends with a device
+ * reduction and returns FR_ERR_NONFINITE if any value is NaN / Inf (this
+ * synchronises the stream). */
+fr_status fr_rk_step(fr_mesh mesh, int32_t scheme, double dt, int32_t n_steps,
+                     void *stream);
+
+/* Global FP64 reductions over the mesh's solution register U (and, for the
+ * residual items, over R(U), evaluated here).  Integrals use the element
+ * quadrature: int f = sum_e sum_i w_i J_ei f_ei.  `what` selects one item:
+ *   FR_RED_INT_U      5 doubles: integral of each conserved field
+ *   FR_RED_INT_R      5 doubles: integral of each field of R(U) (zero on a
+ *                     periodic mesh up to rounding: discrete conservation)
+ *   FR_RED_NORM2_R    5 doubles: integral of R(U)^2 per field
+ *   FR_RED_KE         2 doubles: mean kinetic energy and its rate d/dt
+ *                     (from R(U)), both divided by the mesh volume
+ * Synchronises the stream. */
+#define FR_RED_INT_U 1
+#define FR_RED_INT_R 2
+#define FR_RED_NORM2_R 3
+#define FR_RED_KE 4
+fr_status fr_reduce(fr_mesh mesh, int32_t what, double *out_host, void *stream);
+
+/* Copy an interface intermediate of the last fr_rhs into a caller device
+ * array of the mesh's scalar type, layout [n_fpts][nvar][ld]:
+ *   which 0: state at flux points U_f (nvar 5)
+ *         1: common normal flux, transformed (nvar 5)
+ *         2: physical gradient at flux points (NS only; nvar 15, direction
+ *            major: index j*5 + field). */
+fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_dev,
+                          void *stream);
+
+/* Message of the last failure on mesh (NULL: of fr_mesh_create on this
+ * thread).  Never NULL; valid until the next call on the same mesh. */
+const char *fr_last_error(fr_mesh mesh);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FR_H */

@@ -1,0 +1,673 @@
+// C ABI of the FR library (declared in include/fr.h): mesh setup, the
+// right-hand-side pipeline, Runge-Kutta stepping and FP64 reductions.
+//
+// Right-hand side per element type (paper Section 2.1: operator products with
+// constant operators plus point-wise kernels; Section 3.4: DG-type scheme):
+//   1  U_f  = M0 U                                   operator product
+//   2  C    = common LDG solution at paired flux points        (NS)
+//   3  Q~   = [G'_k | L_k] [U; C], G'_k = G_k - L_k M0,
+//             L_k = L diag(n_ref,k)                  operator product (NS)
+//   4  Q    = adj^T Q~ / J;  F~ = adj (F_inv - F_vis)  point-wise
+//   5  Q_f  = M0 Q                                   operator product (NS)
+//   6  Fn*  = common transformed normal flux at paired flux points
+//   7  R~   = [G'_0 G'_1 G'_2 | L] [F~; Fn*]         operator product
+//   8  R    = -R~ / J, fused with the Runge-Kutta register update
+// Step 7 folds the correction L (Fn* - n_ref . M0 F~) into the divergence
+// operator, so F~ is read once; step 3 folds L_k (C - M0 U) likewise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_device.hpp"
+#include "fr_host.hpp"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBase {
+    virtual ~DevBase() = default;
+};
+
+template <typename T>
+struct DevType {
+    int nu = 0, nf = 0;
+    int64_t nelem = 0, ld = 0;
+    frd::Op<T> Aint, Agrad, Adiv;
+    T *geom = nullptr, *xi = nullptr;
+    T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
+    T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
+    T *reg[3] = {nullptr, nullptr, nullptr};
+    double *wJ = nullptr;
+};
+
+template <typename T>
+struct Dev : DevBase {
+    DevType<T> t[2];
+    uint32_t *sideL = nullptr, *sideR = nullptr;
+    T *pgeo = nullptr;
+    int64_t npairs = 0;
+    double *partial = nullptr, *red_out = nullptr;
+    std::vector<void *> allocs;
+    ~Dev() override {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct fr_mesh_s {
+    int order = 0, system = 0, precision = 0;
+    uint32_t flags = 0;
+    double gamma = 1.4, mu = 0, prandtl = 0.72, beta = 0.5, tau = 0.1;
+    frh::MeshHost host;
+    hipStream_t create_stream = nullptr;
+    bool device = false;
+    std::unique_ptr<DevBase> dev;
+    std::string err;
+};
+
+namespace {
+
+fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
+    if (m)
+        m->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+#define FR_HIP(m, call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(m, e_ == hipErrorOutOfMemory ? FR_ERR_OUT_OF_MEMORY : FR_ERR_DEVICE, \
+                        std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// Fragment order for the MFMA product kernel.
+template <typename T>
+std::vector<T> fragment(const std::vector<double> &A, int M, int K, int &Mb, int &Kb) {
+    Mb = (M + 15) / 16;
+    Kb = (K + 3) / 4;
+    std::vector<T> f(size_t(Mb) * Kb * 64, T(0));
+    for (int mb = 0; mb < Mb; ++mb)
+        for (int kb = 0; kb < Kb; ++kb)
+            for (int l = 0; l < 64; ++l) {
+                int r = 16 * mb + (l % 16), c = 4 * kb + l / 16;
+                if (r < M && c < K) f[(size_t(mb) * Kb + kb) * 64 + l] = T(A[size_t(r) * K + c]);
+            }
+    return f;
+}
+
+// Folded operators of one reference element:
+//   grad: rows (k, i): [G_k - L_k M0 | L_k]               (3 nu) x (nu + nf)
+//   div:  row i: [G_0 - L_0 M0, G_1 - L_1 M0, G_2 - L_2 M0 | L]  nu x (3 nu + nf)
+void folded_ops(const frh::RefOps &R, std::vector<double> &grad, std::vector<double> &div) {
+    const int nu = R.nu, nf = R.nf;
+    std::vector<double> Gp(3 * size_t(nu) * nu);
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < nu; ++i)
+            for (int j = 0; j < nu; ++j) {
+                double s = R.G[(size_t(k) * nu + i) * nu + j];
+                for (int f = 0; f < nf; ++f)
+                    s -= R.L[size_t(i) * nf + f] * R.nref[3 * f + k] * R.M0[size_t(f) * nu + j];
+                Gp[(size_t(k) * nu + i) * nu + j] = s;
+            }
+    const int Kg = nu + nf;
+    grad.assign(3 * size_t(nu) * Kg, 0);
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < nu; ++i) {
+            double *row = &grad[(size_t(k) * nu + i) * Kg];
+            for (int j = 0; j < nu; ++j) row[j] = Gp[(size_t(k) * nu + i) * nu + j];
+            for (int f = 0; f < nf; ++f) row[nu + f] = R.L[size_t(i) * nf + f] * R.nref[3 * f + k];
+        }
+    const int Kd = 3 * nu + nf;
+    div.assign(size_t(nu) * Kd, 0);
+    for (int i = 0; i < nu; ++i) {
+        double *row = &div[size_t(i) * Kd];
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < nu; ++j) row[k * nu + j] = Gp[(size_t(k) * nu + i) * nu + j];
+        for (int f = 0; f < nf; ++f) row[3 * nu + f] = R.L[size_t(i) * nf + f];
+    }
+}
+
+template <typename T>
+fr_status dev_alloc(fr_mesh m, Dev<T> &d, T *&p, size_t n) {
+    void *q = nullptr;
+    FR_HIP(m, hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+    d.allocs.push_back(q);
+    p = static_cast<T *>(q);
+    return FR_OK;
+}
+
+template <typename T>
+fr_status dev_upload(fr_mesh m, Dev<T> &d, T *&p, const std::vector<T> &h, hipStream_t s) {
+    fr_status st = dev_alloc(m, d, p, h.size());
+    if (st) return st;
+    (void)s;
+    if (!h.empty()) FR_HIP(m, hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FR_OK;
+}
+
+template <typename T>
+std::vector<T> cast(const std::vector<double> &v) {
+    return std::vector<T>(v.begin(), v.end());
+}
+
+template <typename T>
+fr_status setup_device(fr_mesh m, hipStream_t s) {
+    auto dp = std::make_unique<Dev<T>>();
+    Dev<T> &d = *dp;
+    const bool ns = m->system == FR_NAVIER_STOKES;
+    fr_status st;
+#define FR_TRY(x)                 \
+    do {                          \
+        if ((st = (x))) return st; \
+    } while (0)
+    for (int t = 0; t < 2; ++t) {
+        const frh::TypeHost &H = m->host.t[t];
+        DevType<T> &D = d.t[t];
+        D.nelem = H.nelem;
+        D.ld = H.ld;
+        if (!H.nelem) continue;
+        const frh::RefOps &R = H.ops;
+        D.nu = R.nu;
+        D.nf = R.nf;
+        const int nu = R.nu, nf = R.nf;
+        const size_t ld = size_t(H.ld);
+        std::vector<double> grad, div;
+        folded_ops(R, grad, div);
+        int Mb, Kb;
+        T *p;
+        auto f = fragment<T>(R.M0, nf, nu, Mb, Kb);
+        FR_TRY(dev_upload(m, d, p, f, s));
+        D.Aint = {p, nf, Mb, Kb};
+        f = fragment<T>(grad, 3 * nu, nu + nf, Mb, Kb);
+        FR_TRY(dev_upload(m, d, p, f, s));
+        D.Agrad = {p, 3 * nu, Mb, Kb};
+        f = fragment<T>(div, nu, 3 * nu + nf, Mb, Kb);
+        FR_TRY(dev_upload(m, d, p, f, s));
+        D.Adiv = {p, nu, Mb, Kb};
+
+        const int ng = frh::n_geom(t);
+        std::vector<double> g(size_t(ng) * ld, 0.0);
+        for (int k = 0; k < ng; ++k)
+            for (int64_t e = 0; e < H.nelem; ++e) g[k * ld + e] = H.geom[size_t(k) * H.nelem + e];
+        // padding columns: copy element 0 so that padded lanes see a valid metric
+        for (int k = 0; k < ng; ++k)
+            for (size_t e = size_t(H.nelem); e < ld; ++e) g[k * ld + e] = H.geom[size_t(k) * H.nelem];
+        FR_TRY(dev_upload(m, d, D.geom, cast<T>(g), s));
+        FR_TRY(dev_upload(m, d, D.xi, cast<T>(R.upts), s));
+        std::vector<double> wJ(size_t(nu) * ld, 0.0);
+        for (int i = 0; i < nu; ++i)
+            for (int64_t e = 0; e < H.nelem; ++e) wJ[i * ld + e] = R.w[i] * H.jdet[size_t(e) * nu + i];
+        {
+            void *q;
+            FR_HIP(m, hipMalloc(&q, wJ.size() * sizeof(double)));
+            d.allocs.push_back(q);
+            D.wJ = static_cast<double *>(q);
+            FR_HIP(m, hipMemcpy(D.wJ, wJ.data(), wJ.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+        const size_t su = size_t(nu) * 5 * ld, sf = size_t(nf) * 5 * ld;
+        FR_TRY(dev_alloc(m, d, D.Uf, sf));
+        FR_TRY(dev_alloc(m, d, D.Fn, sf));
+        FR_TRY(dev_alloc(m, d, D.Ft, 3 * su));
+        FR_TRY(dev_alloc(m, d, D.Rt, su));
+        FR_TRY(dev_alloc(m, d, D.R, su));
+        if (ns) {
+            FR_TRY(dev_alloc(m, d, D.Cf, sf));
+            FR_TRY(dev_alloc(m, d, D.Qt, 3 * su));
+            FR_TRY(dev_alloc(m, d, D.Q, 3 * su));
+            FR_TRY(dev_alloc(m, d, D.Qf, 3 * sf));
+        }
+        for (int r = 0; r < 3; ++r) {
+            FR_TRY(dev_alloc(m, d, D.reg[r], su));
+            FR_HIP(m, hipMemsetAsync(D.reg[r], 0, su * sizeof(T), s));
+        }
+        FR_HIP(m, hipMemsetAsync(D.Uf, 0, sf * sizeof(T), s));
+        FR_HIP(m, hipMemsetAsync(D.Ft, 0, 3 * su * sizeof(T), s));
+        FR_HIP(m, hipMemsetAsync(D.Fn, 0, sf * sizeof(T), s));
+        if (ns) {
+            FR_HIP(m, hipMemsetAsync(D.Cf, 0, sf * sizeof(T), s));
+            FR_HIP(m, hipMemsetAsync(D.Qf, 0, 3 * sf * sizeof(T), s));
+            FR_HIP(m, hipMemsetAsync(D.Qt, 0, 3 * su * sizeof(T), s));
+            FR_HIP(m, hipMemsetAsync(D.Q, 0, 3 * su * sizeof(T), s));
+        }
+    }
+    const frh::PairTable &P = m->host.pairs;
+    d.npairs = int64_t(P.sideL.size());
+    {
+        void *q;
+        FR_HIP(m, hipMalloc(&q, std::max<size_t>(P.sideL.size(), 1) * 4));
+        d.allocs.push_back(q);
+        d.sideL = static_cast<uint32_t *>(q);
+        FR_HIP(m, hipMalloc(&q, std::max<size_t>(P.sideR.size(), 1) * 4));
+        d.allocs.push_back(q);
+        d.sideR = static_cast<uint32_t *>(q);
+        if (d.npairs) {
+            FR_HIP(m, hipMemcpy(d.sideL, P.sideL.data(), P.sideL.size() * 4, hipMemcpyHostToDevice));
+            FR_HIP(m, hipMemcpy(d.sideR, P.sideR.data(), P.sideR.size() * 4, hipMemcpyHostToDevice));
+        }
+    }
+    std::vector<T> pg(5 * size_t(d.npairs));
+    for (int64_t i = 0; i < d.npairs; ++i) {
+        for (int k = 0; k < 3; ++k) pg[size_t(k) * d.npairs + i] = T(P.nhat[3 * i + k]);
+        pg[3 * size_t(d.npairs) + i] = T(P.sL[i]);
+        pg[4 * size_t(d.npairs) + i] = T(P.sR[i]);
+    }
+    FR_TRY(dev_upload(m, d, d.pgeo, pg, s));
+    {
+        void *q;
+        FR_HIP(m, hipMalloc(&q, frd::RED_BLOCKS * 8 * sizeof(double)));
+        d.allocs.push_back(q);
+        d.partial = static_cast<double *>(q);
+        FR_HIP(m, hipMalloc(&q, 2 * 8 * sizeof(double)));
+        d.allocs.push_back(q);
+        d.red_out = static_cast<double *>(q);
+    }
+    FR_HIP(m, hipStreamSynchronize(s));
+#undef FR_TRY
+    m->dev = std::move(dp);
+    return FR_OK;
+}
+
+template <typename T>
+Dev<T> &dev_of(fr_mesh m) {
+    return *static_cast<Dev<T> *>(m->dev.get());
+}
+
+// Output handling of the last pipeline step (see frd::NegArgs).
+template <typename T>
+struct StageOut {
+    T *out = nullptr, *acc = nullptr;
+    const T *base = nullptr;
+    T a = 0, b = 1;
+};
+
+template <typename T>
+fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    const bool ns = m->system == FR_NAVIER_STOKES;
+    const T gamma = T(m->gamma), mu = T(m->mu), pr = T(m->prandtl);
+    for (int t = 0; t < 2; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        const int64_t w5 = 5 * D.ld;
+        FR_HIP(m, frd::launch_opmul<T>(D.Aint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
+    }
+    frd::PairArgs<T> pa{};
+    pa.sideL = d.sideL;
+    pa.sideR = d.sideR;
+    pa.geo = d.pgeo;
+    pa.npairs = d.npairs;
+    for (int t = 0; t < 2; ++t) {
+        pa.Uf[t] = d.t[t].Uf;
+        pa.Qf[t] = d.t[t].Qf;
+        pa.Cf[t] = d.t[t].Cf;
+        pa.Fn[t] = d.t[t].Fn;
+        pa.ld[t] = d.t[t].ld;
+    }
+    pa.gamma = gamma;
+    pa.mu = mu;
+    pa.prandtl = pr;
+    pa.beta = T(m->beta);
+    pa.tau = T(m->tau);
+    if (ns) {
+        FR_HIP(m, frd::launch_common_solution<T>(pa, s));
+        for (int t = 0; t < 2; ++t) {
+            DevType<T> &D = d.t[t];
+            if (!D.nelem) continue;
+            const int64_t w5 = 5 * D.ld;
+            FR_HIP(m, frd::launch_opmul<T>(D.Agrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
+        }
+    }
+    for (int t = 0; t < 2; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        frd::UptsArgs<T> ua{U[t], D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu, gamma, mu, pr};
+        FR_HIP(m, frd::launch_upts<T>(t, ns, ua, s));
+        if (ns) {
+            const int64_t w15 = 15 * D.ld;
+            FR_HIP(m, frd::launch_opmul<T>(D.Aint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
+        }
+    }
+    FR_HIP(m, frd::launch_common_flux<T>(ns, pa, s));
+    for (int t = 0; t < 2; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        const int64_t w5 = 5 * D.ld;
+        FR_HIP(m, frd::launch_opmul<T>(D.Adiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
+        frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
+                           D.geom, D.xi, D.ld, D.nelem, D.nu};
+        FR_HIP(m, frd::launch_negdivconf<T>(t, na, s));
+    }
+    return FR_OK;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+template <typename T>
+fr_status rhs_entry(fr_mesh m, const void *const u[2], void *const r[2], hipStream_t s) {
+    const T *U[2] = {nullptr, nullptr};
+    StageOut<T> so[2];
+    for (int t = 0; t < 2; ++t) {
+        if (!m->host.t[t].nelem) continue;
+        if (!u || !r || !u[t] || !r[t]) return fail(m, FR_ERR_INVALID_ARG, "null state pointer");
+        if (!aligned(u[t], 4 * sizeof(T)) || !aligned(r[t], 4 * sizeof(T)))
+            return fail(m, FR_ERR_INVALID_ARG, "state pointers must be 4-element aligned");
+        if (u[t] == r[t]) return fail(m, FR_ERR_INVALID_ARG, "r_dev aliases u_dev");
+        U[t] = static_cast<const T *>(u[t]);
+        so[t].out = static_cast<T *>(r[t]);
+    }
+    return rhs_pipeline<T>(m, U, so, s);
+}
+
+template <typename T>
+fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    int nq = (what == 4) ? 2 : (what == 5 ? 1 : 5);
+    std::vector<double> tot(8, 0.0);
+    const bool needR = what == 2 || what == 3 || what == 4;
+    if (needR) {
+        const T *U[2] = {d.t[0].reg[0], d.t[1].reg[0]};
+        StageOut<T> so[2];
+        so[0].out = d.t[0].R;
+        so[1].out = d.t[1].R;
+        fr_status st = rhs_pipeline<T>(m, U, so, s);
+        if (st) return st;
+    }
+    for (int t = 0; t < 2; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, d.partial};
+        FR_HIP(m, frd::launch_reduce<T>(ra, s));
+        FR_HIP(m, frd::launch_reduce_final(d.partial, frd::RED_BLOCKS, d.red_out, s));
+        double h[8];
+        FR_HIP(m, hipMemcpyAsync(h, d.red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        FR_HIP(m, hipStreamSynchronize(s));
+        for (int q = 0; q < 8; ++q) tot[q] += h[q];
+    }
+    if (what == 4) {
+        tot[0] /= m->host.volume;
+        tot[1] /= m->host.volume;
+    }
+    for (int q = 0; q < nq; ++q) out[q] = tot[q];
+    return FR_OK;
+}
+
+template <typename T>
+fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    static const double rk4_a[4] = {0.5, 0.5, 1.0, 0.0};
+    static const double rk4_b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    // RK45[2R+] (Kennedy, Carpenter & Lewis 2000, RK4(3)5[2R+]C): sub-diagonal
+    // a[i+1][i] and weights b; a[i][j] = b[j] for j < i-1.
+    static const double rk45_a[4] = {970286171893.0 / 4311952581923.0,
+                                     6584761158862.0 / 12103376702013.0,
+                                     2251764453980.0 / 15575788980749.0,
+                                     26877169314380.0 / 34165994151039.0};
+    static const double rk45_b[5] = {1153189308089.0 / 22510343858157.0,
+                                     1772645290293.0 / 4653164025191.0,
+                                     -1672844663538.0 / 4480602732383.0,
+                                     2114624349019.0 / 3568978502595.0,
+                                     5198255086312.0 / 14908931495163.0};
+    for (int step = 0; step < nsteps; ++step) {
+        if (scheme == FR_FWD_EULER) {
+            const T *U[2] = {d.t[0].reg[0], d.t[1].reg[0]};
+            StageOut<T> so[2];
+            for (int t = 0; t < 2; ++t) {
+                so[t].acc = d.t[t].reg[0];
+                so[t].a = T(dt);
+            }
+            fr_status st = rhs_pipeline<T>(m, U, so, s);
+            if (st) return st;
+        } else if (scheme == FR_RK4) {
+            for (int t = 0; t < 2; ++t)
+                if (d.t[t].nelem)
+                    FR_HIP(m, frd::launch_copy<T>(d.t[t].reg[2], d.t[t].reg[0],
+                                                  int64_t(d.t[t].nu) * 5 * d.t[t].ld, s));
+            for (int st_i = 0; st_i < 4; ++st_i) {
+                const T *U[2];
+                StageOut<T> so[2];
+                for (int t = 0; t < 2; ++t) {
+                    U[t] = st_i == 0 ? d.t[t].reg[0] : d.t[t].reg[1];
+                    so[t].acc = d.t[t].reg[2];
+                    so[t].a = T(rk4_b[st_i] * dt);
+                    so[t].out = st_i < 3 ? d.t[t].reg[1] : nullptr;
+                    so[t].base = d.t[t].reg[0];
+                    so[t].b = T(rk4_a[st_i] * dt);
+                }
+                fr_status st = rhs_pipeline<T>(m, U, so, s);
+                if (st) return st;
+            }
+            for (int t = 0; t < 2; ++t) std::swap(d.t[t].reg[0], d.t[t].reg[2]);
+        } else if (scheme == FR_RK45_2RP) {
+            for (int st_i = 0; st_i < 5; ++st_i) {
+                const T *U[2];
+                StageOut<T> so[2];
+                for (int t = 0; t < 2; ++t) {
+                    U[t] = st_i == 0 ? d.t[t].reg[0] : d.t[t].reg[1];
+                    so[t].acc = d.t[t].reg[0];
+                    so[t].a = T(rk45_b[st_i] * dt);
+                    so[t].out = st_i < 4 ? d.t[t].reg[1] : nullptr;
+                    so[t].b = st_i < 4 ? T((rk45_a[st_i] - rk45_b[st_i]) * dt) : T(0);
+                }
+                fr_status st = rhs_pipeline<T>(m, U, so, s);
+                if (st) return st;
+            }
+        } else {
+            return fail(m, FR_ERR_INVALID_ARG, "unknown scheme");
+        }
+    }
+    if (m->flags & FR_CHECK_FINITE) {
+        double bad = 0;
+        fr_status st = reduce_impl<T>(m, 5, &bad, s);
+        if (st) return st;
+        if (bad > 0) return fail(m, FR_ERR_NONFINITE, "non-finite value in the solution");
+    }
+    return FR_OK;
+}
+
+fr_status check_mesh(fr_mesh m, int etype, bool need_device) {
+    if (!m) return FR_ERR_INVALID_ARG;
+    if (etype != 0 && etype != 1) return fail(m, FR_ERR_INVALID_ARG, "unknown element type");
+    if (need_device && !m->device) return fail(m, FR_ERR_INVALID_ARG, "mesh was created validate-only");
+    return FR_OK;
+}
+
+template <typename T>
+fr_status copy_state(fr_mesh m, int etype, void *dst, const void *src, bool to_reg,
+                            hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    DevType<T> &D = d.t[etype];
+    if (!D.nelem) return FR_OK;
+    const size_t n = size_t(D.nu) * 5 * D.ld * sizeof(T);
+    if (to_reg)
+        FR_HIP(m, hipMemcpyAsync(D.reg[0], src, n, hipMemcpyDeviceToDevice, s));
+    else
+        FR_HIP(m, hipMemcpyAsync(dst, D.reg[0], n, hipMemcpyDeviceToDevice, s));
+    return FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
+    g_create_error.clear();
+    if (!desc || !out) return fail(nullptr, FR_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (desc->order < 1 || desc->order > 4)
+        return fail(nullptr, FR_ERR_UNSUPPORTED, "order must be 1..4");
+    if (desc->system != FR_EULER && desc->system != FR_NAVIER_STOKES)
+        return fail(nullptr, FR_ERR_INVALID_ARG, "unknown system");
+    if (desc->precision != FR_FP32 && desc->precision != FR_FP64)
+        return fail(nullptr, FR_ERR_UNSUPPORTED, "unsupported precision");
+    if (desc->n_vertices <= 0 || !desc->xyz || desc->n_tets < 0 || desc->n_prisms < 0 ||
+        (desc->n_tets && !desc->tet_v) || (desc->n_prisms && !desc->pri_v) ||
+        desc->n_tets + desc->n_prisms == 0)
+        return fail(nullptr, FR_ERR_INVALID_ARG, "empty or inconsistent mesh arrays");
+    if (!(desc->gamma > 1) || desc->mu < 0 ||
+        (desc->system == FR_NAVIER_STOKES && !(desc->prandtl > 0)))
+        return fail(nullptr, FR_ERR_INVALID_ARG, "invalid physical constants");
+    auto m = std::make_unique<fr_mesh_s>();
+    m->order = desc->order;
+    m->system = desc->system;
+    m->precision = desc->precision;
+    m->flags = desc->flags;
+    m->gamma = desc->gamma;
+    m->mu = desc->mu;
+    m->prandtl = desc->prandtl;
+    m->beta = desc->ldg_beta;
+    m->tau = desc->ldg_tau;
+    std::string err;
+    try {
+        if (!frh::build_mesh_host(desc->order, desc->n_vertices, desc->xyz, desc->n_tets,
+                                  desc->tet_v, desc->tet_img, desc->n_prisms, desc->pri_v,
+                                  desc->pri_img, desc->period, m->host, err))
+            return fail(nullptr, FR_ERR_BAD_MESH, err);
+    } catch (const std::exception &ex) {
+        return fail(nullptr, FR_ERR_BAD_MESH, ex.what());
+    }
+    if (!(desc->flags & FR_VALIDATE_ONLY)) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        m->create_stream = s;
+        fr_status st = m->precision == FR_FP32 ? setup_device<float>(m.get(), s)
+                                               : setup_device<double>(m.get(), s);
+        if (st) {
+            g_create_error = m->err;
+            return st;
+        }
+        m->device = true;
+    }
+    *out = m.release();
+    return FR_OK;
+}
+
+fr_status fr_mesh_destroy(fr_mesh mesh) {
+    if (!mesh) return FR_OK;
+    if (mesh->device) (void)hipStreamSynchronize(mesh->create_stream);
+    delete mesh;
+    return FR_OK;
+}
+
+fr_status fr_mesh_query(fr_mesh m, int32_t etype, int64_t *n_elem, int32_t *n_upts,
+                        int32_t *n_fpts, int64_t *ld) {
+    if (fr_status st = check_mesh(m, etype, false)) return st;
+    const frh::TypeHost &H = m->host.t[etype];
+    if (n_elem) *n_elem = H.nelem;
+    if (n_upts) *n_upts = frh::n_upts(etype, m->order);
+    if (n_fpts) *n_fpts = frh::n_fpts(etype, m->order);
+    if (ld) *ld = H.ld;
+    return FR_OK;
+}
+
+fr_status fr_upts_coords(fr_mesh m, int32_t etype, double *xyz) {
+    if (fr_status st = check_mesh(m, etype, false)) return st;
+    if (!xyz) return fail(m, FR_ERR_INVALID_ARG, "null output");
+    const frh::TypeHost &H = m->host.t[etype];
+    if (!H.nelem) return FR_OK;
+    const int nu = H.ops.nu, nvt = frh::n_verts(etype);
+    for (int i = 0; i < nu; ++i)
+        for (int64_t e = 0; e < H.nelem; ++e) {
+            double x[3];
+            frh::map_point(etype, &H.X[size_t(e) * nvt * 3], &H.ops.upts[3 * i], x);
+            for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * H.nelem + e] = x[d];
+        }
+    return FR_OK;
+}
+
+fr_status fr_operator(fr_mesh m, int32_t etype, int32_t which, double *out, int32_t *rows,
+                      int32_t *cols) {
+    if (fr_status st = check_mesh(m, etype, false)) return st;
+    const frh::TypeHost &H = m->host.t[etype];
+    if (!H.nelem) return fail(m, FR_ERR_INVALID_ARG, "mesh has no elements of that type");
+    const frh::RefOps &R = H.ops;
+    const double *src;
+    int r, c;
+    switch (which) {
+        case 0: src = R.M0.data(); r = R.nf; c = R.nu; break;
+        case 1: case 2: case 3: src = R.G.data() + size_t(which - 1) * R.nu * R.nu; r = R.nu; c = R.nu; break;
+        case 4: src = R.L.data(); r = R.nu; c = R.nf; break;
+        case 5: src = R.w.data(); r = 1; c = R.nu; break;
+        default: return fail(m, FR_ERR_INVALID_ARG, "unknown operator");
+    }
+    if (rows) *rows = r;
+    if (cols) *cols = c;
+    if (out) std::memcpy(out, src, size_t(r) * c * sizeof(double));
+    return FR_OK;
+}
+
+fr_status fr_set_solution(fr_mesh m, int32_t etype, const void *u, void *stream) {
+    if (fr_status st = check_mesh(m, etype, true)) return st;
+    if (!u && m->host.t[etype].nelem) return fail(m, FR_ERR_INVALID_ARG, "null state");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision == FR_FP32 ? copy_state<float>(m, etype, nullptr, u, true, s)
+                                   : copy_state<double>(m, etype, nullptr, u, true, s);
+}
+
+fr_status fr_get_solution(fr_mesh m, int32_t etype, void *u, void *stream) {
+    if (fr_status st = check_mesh(m, etype, true)) return st;
+    if (!u && m->host.t[etype].nelem) return fail(m, FR_ERR_INVALID_ARG, "null state");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision == FR_FP32 ? copy_state<float>(m, etype, u, nullptr, false, s)
+                                   : copy_state<double>(m, etype, u, nullptr, false, s);
+}
+
+fr_status fr_rhs(fr_mesh m, const void *const u[2], void *const r[2], void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision == FR_FP32 ? rhs_entry<float>(m, u, r, s) : rhs_entry<double>(m, u, r, s);
+}
+
+fr_status fr_rk_step(fr_mesh m, int32_t scheme, double dt, int32_t n_steps, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (n_steps < 0 || !std::isfinite(dt)) return fail(m, FR_ERR_INVALID_ARG, "bad step count or dt");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision == FR_FP32 ? rk_impl<float>(m, scheme, dt, n_steps, s)
+                                   : rk_impl<double>(m, scheme, dt, n_steps, s);
+}
+
+fr_status fr_reduce(fr_mesh m, int32_t what, double *out, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!out || what < 1 || what > 4) return fail(m, FR_ERR_INVALID_ARG, "bad reduction request");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision == FR_FP32 ? reduce_impl<float>(m, what, out, s)
+                                   : reduce_impl<double>(m, what, out, s);
+}
+
+fr_status fr_intermediate(fr_mesh m, int32_t etype, int32_t which, void *dst, void *stream) {
+    if (fr_status st = check_mesh(m, etype, true)) return st;
+    if (!dst) return fail(m, FR_ERR_INVALID_ARG, "null destination");
+    if (which == 2 && m->system != FR_NAVIER_STOKES)
+        return fail(m, FR_ERR_INVALID_ARG, "gradients exist for Navier-Stokes only");
+    if (which < 0 || which > 2) return fail(m, FR_ERR_INVALID_ARG, "unknown intermediate");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const frh::TypeHost &H = m->host.t[etype];
+    if (!H.nelem) return FR_OK;
+    const size_t esz = m->precision == FR_FP32 ? 4 : 8;
+    const size_t n = size_t(H.ops.nf) * (which == 2 ? 15 : 5) * H.ld * esz;
+    const void *src;
+    if (m->precision == FR_FP32) {
+        auto &D = dev_of<float>(m).t[etype];
+        src = which == 0 ? (void *)D.Uf : which == 1 ? (void *)D.Fn : (void *)D.Qf;
+    } else {
+        auto &D = dev_of<double>(m).t[etype];
+        src = which == 0 ? (void *)D.Uf : which == 1 ? (void *)D.Fn : (void *)D.Qf;
+    }
+    FR_HIP(m, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s));
+    return FR_OK;
+}
+
+const char *fr_last_error(fr_mesh m) {
+    return m ? m->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Device kernels of the FR library: argument blocks and launchers.
+// Internal header (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace frd {
+
+constexpr int NVAR = 5;
+
+// Fragment-ordered operator for the MFMA product kernel: element
+// [mb][kb][lane] holds A[16 mb + lane % 16][4 kb + lane / 16] (zero padded).
+template <typename T>
+struct Op {
+    const T *frag = nullptr;
+    int M = 0, Mb = 0, Kb = 0;
+};
+
+// C[M][ncols] = A[M][K1 + K2] . [B1 (K1 rows); B2 (K2 rows)], row strides
+// ldb1, ldb2, ldc (elements); ncols a multiple of 64.
+template <typename T>
+hipError_t launch_opmul(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
+                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s);
+
+// Point-wise work at the solution points of one element type (ETYPE 0 tet,
+// 1 prism): physical gradient Q from the reference gradient Qt (NS) and the
+// transformed flux Ft = adj (F_inv - F_vis).
+template <typename T>
+struct UptsArgs {
+    const T *U;        // [nu][5][ld]
+    const T *Qt;       // [3 nu][5][ld] reference gradient (NS)
+    T *Q;              // [nu][15][ld] physical gradient, index j*5+v (NS)
+    T *Ft;             // [3 nu][5][ld] transformed flux, row k*nu+i
+    const T *geom;     // [ng][ld] Jacobian coefficients
+    const T *xi;       // [nu][3] reference coordinates of the solution points
+    int64_t ld, nelem;
+    int nu;
+    T gamma, mu, prandtl;
+};
+template <typename T>
+hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s);
+
+// Interface work on the paired flux points.
+template <typename T>
+struct PairArgs {
+    const uint32_t *sideL, *sideR;   // elem | fpt << 24 | type << 31
+    const T *geo;                    // [5][npairs]: nx, ny, nz, sL, sR
+    int64_t npairs;
+    const T *Uf[2];                  // [nf][5][ld]
+    const T *Qf[2];                  // [nf][15][ld]
+    T *Cf[2];                        // [nf][5][ld]
+    T *Fn[2];                        // [nf][5][ld]
+    int64_t ld[2];
+    T gamma, mu, prandtl, beta, tau;
+};
+template <typename T>
+hipError_t launch_common_solution(const PairArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_common_flux(bool ns, const PairArgs<T> &a, hipStream_t s);
+
+// k = -Rt / J at each solution point, then
+//   acc += a k (if acc), out = (base ? base : (acc ? acc : 0)) + b k (if out).
+template <typename T>
+struct NegArgs {
+    const T *Rt;
+    T *out;
+    T *acc;
+    const T *base;
+    T a, b;
+    const T *geom;
+    const T *xi;
+    int64_t ld, nelem;
+    int nu;
+};
+template <typename T>
+hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s);
+
+// FP64 reductions: per-block partial sums of nq quantities over one type,
+// written to partial[block][nq]; a second pass sums the blocks in order.
+template <typename T>
+struct RedArgs {
+    const T *U;          // [nu][5][ld]
+    const T *R;          // [nu][5][ld] or null
+    const double *wJ;    // [nu][ld]
+    int64_t ld, nelem;
+    int nu, what;
+    double *partial;     // [nblocks][8]
+};
+constexpr int RED_BLOCKS = 512;
+template <typename T>
+hipError_t launch_reduce(const RedArgs<T> &a, hipStream_t s);
+hipError_t launch_reduce_final(const double *partial, int nblocks, double *out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s);
+
+}  // namespace frd

@@ -1,0 +1,92 @@
+// Host-side core of the FR library: reference operators, geometry, pairing.
+// Internal header (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace frh {
+
+constexpr int NVAR = 5;
+
+// Reference element of one type at one order, built in extended precision and
+// stored as double.  Point / face conventions:
+//  * triangle point set (order p): barycentrics with i0+i1+i2 = p,
+//    lambda_a = (1 + 2 v_{i_a} - v_{i_b} - v_{i_c}) / 3 from the Gauss-Legendre
+//    nodes v mapped to (0,1); enumeration i2 outer, i1 inner;
+//  * tet point set: lambda_a = (1 + 3 v_{i_a} - sum_{b!=a} v_{i_b}) / 4,
+//    enumeration i3, i2, i1 (outer to inner);
+//  * prism solution points: Gauss-Legendre layer in zeta (outer) x triangle
+//    set (inner);
+//  * faces: tet (0,1,2) (0,1,3) (0,2,3) (1,2,3); prism (0,1,2) (3,4,5)
+//    (0,1,4,3) (1,2,5,4) (2,0,3,5); triangle-face points l0 a + l1 b + l2 c;
+//    quad-face points a + (1+s_i)/2 (b-a) + (1+t_j)/2 (d-a), index j(p+1)+i.
+struct RefOps {
+    int etype = 0, p = 0, nu = 0, nf = 0;
+    std::vector<double> upts;   // [nu][3]
+    std::vector<double> fpts;   // [nf][3]
+    std::vector<int> fface;     // [nf] local face of each flux point
+    std::vector<int> face_off;  // [nfaces + 1]
+    std::vector<double> nref;   // [nf][3] outward unit reference normals
+    std::vector<double> M0;     // [nf][nu]
+    std::vector<double> G;      // [3][nu][nu]
+    std::vector<double> L;      // [nu][nf]
+    std::vector<double> w;      // [nu]
+    double volume = 0;
+};
+
+RefOps build_ref(int etype, int p);
+
+int n_upts(int etype, int p);
+int n_fpts(int etype, int p);
+
+// Reference vertices and faces
+const std::vector<std::vector<int>> &faces_of(int etype);
+int n_verts(int etype);
+void ref_vertex(int etype, int v, double out[3]);
+
+// Jacobian coefficient vectors of one element from its (unwrapped) vertices:
+// tet  -> 9 values: columns dx/dxi, dx/deta, dx/dzeta (constant);
+// prism-> 15 values: A1, B1, C0, C1, C2 with dx/dxi = A1 + C1 z,
+//         dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.
+int n_geom(int etype);
+void geom_coeffs(int etype, const double *X, double *c);
+// Jacobian matrix columns at a reference point from the coefficients.
+void jac_at(int etype, const double *c, const double *xi, double col[3][3]);
+// Physical position of a reference point.
+void map_point(int etype, const double *X, const double *xi, double out[3]);
+
+struct PairTable {
+    // one entry per paired flux point, sorted by (type L, fpt L, elem L)
+    std::vector<uint32_t> sideL, sideR;   // elem | fpt << 24 | type << 31
+    std::vector<double> nhat;             // [n][3] unit normal out of side L
+    std::vector<double> sL, sR;           // |adj^T n_ref| on each side
+};
+
+struct TypeHost {
+    int64_t nelem = 0, ld = 0;
+    RefOps ops;
+    std::vector<double> X;       // [nelem][nverts][3] unwrapped vertices
+    std::vector<double> geom;    // [n_geom][nelem]
+    std::vector<double> jdet;    // [nelem][nu] Jacobian determinant at upts
+};
+
+struct MeshHost {
+    int p = 0;
+    TypeHost t[2];
+    PairTable pairs;
+    double volume = 0;
+};
+
+// Builds geometry and pairing; returns false with a message on a bad mesh.
+bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet,
+                     const int64_t *tet_v, const int8_t *tet_img, int64_t npri,
+                     const int64_t *pri_v, const int8_t *pri_img, const double period[3],
+                     MeshHost &m, std::string &err);
+
+inline uint32_t pack_side(int64_t e, int f, int t) {
+    return uint32_t(e) | (uint32_t(f) << 24) | (uint32_t(t) << 31);
+}
+
+}  // namespace frh

@@ -1,0 +1,512 @@
+// HIP kernels of the FR right-hand side for gfx950 (CDNA4).
+//
+// Paper, Section 2.1: an FR step is mostly products C <- A B of a small
+// constant operator A with very wide row-major state matrices B (block-by-
+// panel shape), plus point-wise operations at solution and flux points.
+// Section 3.4: DG-type scheme, Rusanov interface flux, compressible
+// Navier-Stokes with constant viscosity.
+//
+// State layout per element type: [point][field][ld], element index fastest,
+// so every point-wise access of a wavefront is one contiguous segment and the
+// operator products see B as K rows of (fields x ld) contiguous columns.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fr_device.hpp"
+
+namespace frd {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = floatx4;
+};
+template <>
+struct Vec4<double> {
+    using type = doublex4;
+};
+
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16 x 16 result held in accumulator element r of lane group g
+// (lanes 16 g .. 16 g + 15 hold columns 0..15).  Both instructions take A as
+// A[lane % 16][lane / 16] and B as B[lane / 16][lane % 16]; the FP32 result
+// holds four consecutive rows per lane group, the FP64 result rows strided
+// by four.
+template <typename T>
+__device__ __forceinline__ int acc_row(int g, int r);
+template <>
+__device__ __forceinline__ int acc_row<float>(int g, int r) { return 4 * g + r; }
+template <>
+__device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r; }
+
+// ---------------------------------------------------------------------------
+// Operator product C = A [B1; B2] on the matrix cores.
+//
+// One wavefront owns a 64-column panel of C and MBW row blocks of 16.  The 64
+// columns are split into four interleaved MFMA column blocks: block n holds
+// columns 4 j + n (j = 0..15), so lane l reads the four consecutive columns
+// 4 (l % 16) .. +3 of one B row with a single vector load and writes four
+// consecutive columns of one C row with a single vector store.  A is read in
+// fragment order (one coalesced load per MFMA) from L2-resident memory.
+// ---------------------------------------------------------------------------
+template <typename T, int MBW>
+__global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict__ B1,
+                                                    int64_t ldb1, int K1,
+                                                    const T *__restrict__ B2, int64_t ldb2,
+                                                    int K2, T *__restrict__ C, int64_t ldc,
+                                                    int64_t npanels, int nmg) {
+    using v4 = typename Vec4<T>::type;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t panel = wid / nmg;
+    const int mg = int(wid - panel * nmg);
+    if (panel >= npanels) return;
+    const int mb0 = mg * MBW;
+    const int64_t col = panel * 64 + 4 * (lane & 15);
+    const int krow = lane >> 4;
+    const int K = K1 + K2;
+
+    v4 acc[MBW][4];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = v4{0, 0, 0, 0};
+
+    const T *Af = A.frag + size_t(mb0) * A.Kb * 64 + lane;
+#pragma unroll 2
+    for (int kb = 0; kb < A.Kb; ++kb) {
+        const int k = 4 * kb + krow;
+        v4 b = v4{0, 0, 0, 0};
+        if (k < K1)
+            b = *reinterpret_cast<const v4 *>(B1 + int64_t(k) * ldb1 + col);
+        else if (k < K)
+            b = *reinterpret_cast<const v4 *>(B2 + int64_t(k - K1) * ldb2 + col);
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) {
+            if (mb0 + m < A.Mb) {
+                const T a = Af[(size_t(m) * A.Kb + kb) * 64];
+                acc[m][0] = mfma16(a, b[0], acc[m][0]);
+                acc[m][1] = mfma16(a, b[1], acc[m][1]);
+                acc[m][2] = mfma16(a, b[2], acc[m][2]);
+                acc[m][3] = mfma16(a, b[3], acc[m][3]);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+        if (mb0 + m >= A.Mb) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (mb0 + m) + acc_row<T>(krow, r);
+            if (row < A.M) {
+                v4 out = v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+                *reinterpret_cast<v4 *>(C + int64_t(row) * ldc + col) = out;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Geometry at a solution point from the Jacobian coefficients.
+// Tet: constant columns c0..c2.  Prism: dx/dxi = A1 + C1 z,
+// dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.
+// adj[k][j] = J dxi_k/dx_j (rows are cross products of the columns).
+// ---------------------------------------------------------------------------
+template <typename T, int ET>
+__device__ __forceinline__ T metric(const T *__restrict__ g, int64_t ld, int64_t e,
+                                    const T *__restrict__ xi, T adj[3][3]) {
+    T c[3][3];
+    if (ET == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c[k][d] = g[(3 * k + d) * ld + e];
+    } else {
+        const T x = xi[0], y = xi[1], z = xi[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T A1 = g[d * ld + e], B1 = g[(3 + d) * ld + e], C0 = g[(6 + d) * ld + e];
+            const T C1 = g[(9 + d) * ld + e], C2 = g[(12 + d) * ld + e];
+            c[0][d] = A1 + C1 * z;
+            c[1][d] = B1 + C2 * z;
+            c[2][d] = C0 + C1 * x + C2 * y;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        adj[k][0] = c[k1][1] * c[k2][2] - c[k1][2] * c[k2][1];
+        adj[k][1] = c[k1][2] * c[k2][0] - c[k1][0] * c[k2][2];
+        adj[k][2] = c[k1][0] * c[k2][1] - c[k1][1] * c[k2][0];
+    }
+    return c[0][0] * adj[0][0] + c[0][1] * adj[0][1] + c[0][2] * adj[0][2];
+}
+
+// Inviscid flux F[j][v] of the conserved state u.
+template <typename T>
+__device__ __forceinline__ void euler_flux(const T u[5], T gamma, T F[3][5], T &p) {
+    const T rinv = T(1) / u[0];
+    const T v[3] = {u[1] * rinv, u[2] * rinv, u[3] * rinv};
+    p = (gamma - T(1)) * (u[4] - T(0.5) * (u[1] * v[0] + u[2] * v[1] + u[3] * v[2]));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[j][0] = u[1 + j];
+        F[j][1] = u[1] * v[j];
+        F[j][2] = u[2] * v[j];
+        F[j][3] = u[3] * v[j];
+        F[j][1 + j] += p;
+        F[j][4] = (u[4] + p) * v[j];
+    }
+}
+
+// Viscous flux Fv[j][v] from the state u and the physical gradient q[j][v]:
+// tau = mu (grad v + grad v^T - 2/3 div v I), heat flux from grad(p/rho) with
+// conductivity mu gamma / (Pr (gamma - 1)).
+template <typename T>
+__device__ __forceinline__ void viscous_flux(const T u[5], const T q[3][5], T gamma, T mu,
+                                             T prandtl, T Fv[3][5]) {
+    const T rinv = T(1) / u[0];
+    const T v[3] = {u[1] * rinv, u[2] * rinv, u[3] * rinv};
+    const T e = u[4] * rinv;
+    T dv[3][3], dT[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dv[i][j] = (q[j][1 + i] - v[i] * q[j][0]) * rinv;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        dT[j] = (gamma - T(1)) * ((q[j][4] - e * q[j][0]) * rinv -
+                                  (v[0] * dv[0][j] + v[1] * dv[1][j] + v[2] * dv[2][j]));
+    const T div = dv[0][0] + dv[1][1] + dv[2][2];
+    const T kappa = mu * gamma / (prandtl * (gamma - T(1)));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Fv[j][0] = 0;
+        T work = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            T tau = mu * (dv[i][j] + dv[j][i]);
+            if (i == j) tau -= mu * T(2.0 / 3.0) * div;
+            Fv[j][1 + i] = tau;
+            work += v[i] * tau;
+        }
+        Fv[j][4] = work + kappa * dT[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Point-wise solution-point kernel: physical gradient and transformed flux.
+// One thread per (element, solution point); blockIdx.y is the point.
+// ---------------------------------------------------------------------------
+template <typename T, int ET, bool NS>
+__global__ __launch_bounds__(256) void upts_kernel(UptsArgs<T> a) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (e >= a.nelem) return;
+    const int64_t ld = a.ld;
+    T adj[3][3];
+    const T J = metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    T u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = a.U[(int64_t(i) * 5 + v) * ld + e];
+    T F[3][5], p;
+    euler_flux(u, a.gamma, F, p);
+    if (NS) {
+        T qt[3][5], q[3][5], Fv[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+                qt[k][v] = a.Qt[((int64_t(k) * a.nu + i) * 5 + v) * ld + e];
+        const T Jinv = T(1) / J;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                q[j][v] = (adj[0][j] * qt[0][v] + adj[1][j] * qt[1][v] + adj[2][j] * qt[2][v]) * Jinv;
+                a.Q[(int64_t(i) * 15 + j * 5 + v) * ld + e] = q[j][v];
+            }
+        viscous_flux(u, q, a.gamma, a.mu, a.prandtl, Fv);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) F[j][v] -= Fv[j][v];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            a.Ft[((int64_t(k) * a.nu + i) * 5 + v) * ld + e] =
+                adj[k][0] * F[0][v] + adj[k][1] * F[1][v] + adj[k][2] * F[2][v];
+}
+
+__device__ __forceinline__ void unpack(uint32_t s, int64_t &e, int &f, int &t) {
+    e = s & 0xffffffu;
+    f = (s >> 24) & 0x7f;
+    t = s >> 31;
+}
+
+// Common solution of the LDG scheme at each paired flux point, written to
+// both sides: C = (1/2 - beta) U_L + (1/2 + beta) U_R.
+template <typename T>
+__global__ __launch_bounds__(256) void common_solution_kernel(PairArgs<T> a) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.npairs) return;
+    int64_t eL, eR;
+    int fL, fR, tL, tR;
+    unpack(a.sideL[p], eL, fL, tL);
+    unpack(a.sideR[p], eR, fR, tR);
+    const int64_t ldL = a.ld[tL], ldR = a.ld[tR];
+    const T wl = T(0.5) - a.beta, wr = T(0.5) + a.beta;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const int64_t oL = (int64_t(fL) * 5 + v) * ldL + eL;
+        const int64_t oR = (int64_t(fR) * 5 + v) * ldR + eR;
+        const T c = wl * a.Uf[tL][oL] + wr * a.Uf[tR][oR];
+        a.Cf[tL][oL] = c;
+        a.Cf[tR][oR] = c;
+    }
+}
+
+// Common transformed normal flux at each paired flux point:
+//   f = Rusanov(U_L, U_R; n) [- ((1/2+beta) Fv_L + (1/2-beta) Fv_R).n
+//       + tau (U_L - U_R)]   (NS terms in brackets)
+// side L stores sL f, side R stores -sR f.
+template <typename T, bool NS>
+__global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.npairs) return;
+    int64_t eL, eR;
+    int fL, fR, tL, tR;
+    unpack(a.sideL[p], eL, fL, tL);
+    unpack(a.sideR[p], eR, fR, tR);
+    const int64_t ldL = a.ld[tL], ldR = a.ld[tR];
+    const int64_t P = a.npairs;
+    const T n[3] = {a.geo[p], a.geo[P + p], a.geo[2 * P + p]};
+    const T sL = a.geo[3 * P + p], sR = a.geo[4 * P + p];
+    T uL[5], uR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        uL[v] = a.Uf[tL][(int64_t(fL) * 5 + v) * ldL + eL];
+        uR[v] = a.Uf[tR][(int64_t(fR) * 5 + v) * ldR + eR];
+    }
+    T FL[3][5], FR[3][5], pL, pR;
+    euler_flux(uL, a.gamma, FL, pL);
+    euler_flux(uR, a.gamma, FR, pR);
+    const T vnL = (uL[1] * n[0] + uL[2] * n[1] + uL[3] * n[2]) / uL[0];
+    const T vnR = (uR[1] * n[0] + uR[2] * n[1] + uR[3] * n[2]) / uR[0];
+    const T cL = sqrt(a.gamma * pL / uL[0]), cR = sqrt(a.gamma * pR / uR[0]);
+    const T lam = fmax(fabs(vnL) + cL, fabs(vnR) + cR);
+    T f[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+        f[v] = T(0.5) * (n[0] * (FL[0][v] + FR[0][v]) + n[1] * (FL[1][v] + FR[1][v]) +
+                         n[2] * (FL[2][v] + FR[2][v])) -
+               T(0.5) * lam * (uR[v] - uL[v]);
+    if (NS) {
+        T qL[3][5], qR[3][5], FvL[3][5], FvR[3][5];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                qL[j][v] = a.Qf[tL][(int64_t(fL) * 15 + j * 5 + v) * ldL + eL];
+                qR[j][v] = a.Qf[tR][(int64_t(fR) * 15 + j * 5 + v) * ldR + eR];
+            }
+        viscous_flux(uL, qL, a.gamma, a.mu, a.prandtl, FvL);
+        viscous_flux(uR, qR, a.gamma, a.mu, a.prandtl, FvR);
+        const T wl = T(0.5) + a.beta, wr = T(0.5) - a.beta;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            T fv = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) fv += n[j] * (wl * FvL[j][v] + wr * FvR[j][v]);
+            f[v] += -fv + a.tau * (uL[v] - uR[v]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        a.Fn[tL][(int64_t(fL) * 5 + v) * ldL + eL] = sL * f[v];
+        a.Fn[tR][(int64_t(fR) * 5 + v) * ldR + eR] = -sR * f[v];
+    }
+}
+
+// R = -Rt / J at each solution point, fused with a Runge-Kutta register update.
+template <typename T, int ET>
+__global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (e >= a.nelem) return;
+    const int64_t ld = a.ld;
+    T adj[3][3];
+    const T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const int64_t o = (int64_t(i) * 5 + v) * ld + e;
+        const T k = -a.Rt[o] * Jinv;
+        T accv = 0;
+        if (a.acc) {
+            accv = a.acc[o] + a.a * k;
+            a.acc[o] = accv;
+        }
+        if (a.out) a.out[o] = (a.base ? a.base[o] : accv) + a.b * k;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_kernel(RedArgs<T> a) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t n = int64_t(a.nu) * a.nelem;
+    for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
+         idx += int64_t(gridDim.x) * blockDim.x) {
+        const int i = int(idx / a.nelem);
+        const int64_t e = idx - int64_t(i) * a.nelem;
+        const double wJ = a.wJ[int64_t(i) * a.ld + e];
+        double u[5], r[5] = {0, 0, 0, 0, 0};
+        for (int v = 0; v < 5; ++v) {
+            u[v] = double(a.U[(int64_t(i) * 5 + v) * a.ld + e]);
+            if (a.R) r[v] = double(a.R[(int64_t(i) * 5 + v) * a.ld + e]);
+        }
+        if (a.what == 1) {
+            for (int v = 0; v < 5; ++v) s[v] += wJ * u[v];
+        } else if (a.what == 2) {
+            for (int v = 0; v < 5; ++v) s[v] += wJ * r[v];
+        } else if (a.what == 3) {
+            for (int v = 0; v < 5; ++v) s[v] += wJ * r[v] * r[v];
+        } else if (a.what == 4) {
+            const double vx = u[1] / u[0], vy = u[2] / u[0], vz = u[3] / u[0];
+            const double v2 = vx * vx + vy * vy + vz * vz;
+            s[0] += wJ * 0.5 * u[0] * v2;
+            s[1] += wJ * (vx * r[1] + vy * r[2] + vz * r[3] - 0.5 * v2 * r[0]);
+        } else if (a.what == 5) {
+            for (int v = 0; v < 5; ++v) s[0] += isfinite(u[v]) ? 0.0 : 1.0;
+        }
+    }
+    __shared__ double sh[8][256];
+    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w)
+            for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) a.partial[int64_t(blockIdx.x) * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void reduce_final_kernel(const double *partial, int nblocks, double *out) {
+    const int q = threadIdx.x;
+    if (q >= 8) return;
+    double s = 0;
+    for (int b = 0; b < nblocks; ++b) s += partial[int64_t(b) * 8 + q];
+    out[q] = s;
+}
+
+template <typename T>
+__global__ void copy_kernel(T *dst, const T *src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_opmul(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
+                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s) {
+    if (ncols % 64) return hipErrorInvalidValue;
+    const int64_t npanels = ncols / 64;
+    const int nmg = (A.Mb + 3) / 4;
+    const int mbw = (A.Mb + nmg - 1) / nmg;
+    const int64_t nwaves = npanels * nmg;
+    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
+    switch (mbw) {
+        case 1: opmul_kernel<T, 1><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        case 2: opmul_kernel<T, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        case 3: opmul_kernel<T, 3><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        default: opmul_kernel<T, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s) {
+    const dim3 grid(unsigned((a.nelem + 255) / 256), unsigned(a.nu)), block(256);
+    if (etype == 0) {
+        if (ns) upts_kernel<T, 0, true><<<grid, block, 0, s>>>(a);
+        else upts_kernel<T, 0, false><<<grid, block, 0, s>>>(a);
+    } else {
+        if (ns) upts_kernel<T, 1, true><<<grid, block, 0, s>>>(a);
+        else upts_kernel<T, 1, false><<<grid, block, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_common_solution(const PairArgs<T> &a, hipStream_t s) {
+    if (!a.npairs) return hipSuccess;
+    common_solution_kernel<T><<<unsigned((a.npairs + 255) / 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_common_flux(bool ns, const PairArgs<T> &a, hipStream_t s) {
+    if (!a.npairs) return hipSuccess;
+    const unsigned g = unsigned((a.npairs + 255) / 256);
+    if (ns) common_flux_kernel<T, true><<<g, 256, 0, s>>>(a);
+    else common_flux_kernel<T, false><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s) {
+    const dim3 grid(unsigned((a.nelem + 255) / 256), unsigned(a.nu)), block(256);
+    if (etype == 0) negdivconf_kernel<T, 0><<<grid, block, 0, s>>>(a);
+    else negdivconf_kernel<T, 1><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reduce(const RedArgs<T> &a, hipStream_t s) {
+    reduce_kernel<T><<<RED_BLOCKS, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double *partial, int nblocks, double *out, hipStream_t s) {
+    reduce_final_kernel<<<1, 64, 0, s>>>(partial, nblocks, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    copy_kernel<T><<<1024, 256, 0, s>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+#define FR_INSTANTIATE(T)                                                                     \
+    template hipError_t launch_opmul<T>(const Op<T> &, const T *, int64_t, int, const T *,    \
+                                        int64_t, int, T *, int64_t, int64_t, hipStream_t);    \
+    template hipError_t launch_upts<T>(int, bool, const UptsArgs<T> &, hipStream_t);          \
+    template hipError_t launch_common_solution<T>(const PairArgs<T> &, hipStream_t);          \
+    template hipError_t launch_common_flux<T>(bool, const PairArgs<T> &, hipStream_t);        \
+    template hipError_t launch_negdivconf<T>(int, const NegArgs<T> &, hipStream_t);           \
+    template hipError_t launch_reduce<T>(const RedArgs<T> &, hipStream_t);                    \
+    template hipError_t launch_copy<T>(T *, const T *, int64_t, hipStream_t);
+
+FR_INSTANTIATE(float)
+FR_INSTANTIATE(double)
+
+}  // namespace frd

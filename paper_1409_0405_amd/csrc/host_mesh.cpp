@@ -1,0 +1,305 @@
+// Element geometry, face matching and flux-point pairing (host).
+//
+// Paper, Sections 2.1 and 3.3: a mixed unstructured grid of tets and prisms;
+// elements interact only through their shared faces.  Straight-sided
+// elements: the tet map is affine, the prism map is linear on the triangle
+// times linear in zeta, and the metric terms are evaluated exactly from the
+// map's derivatives.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "fr_host.hpp"
+
+namespace frh {
+
+int n_geom(int etype) { return etype == 0 ? 9 : 15; }
+
+void geom_coeffs(int etype, const double *X, double *c) {
+    auto V = [&](int v, int d) { return X[3 * v + d]; };
+    if (etype == 0) {
+        for (int d = 0; d < 3; ++d) {
+            c[d] = 0.5 * (V(1, d) - V(0, d));
+            c[3 + d] = 0.5 * (V(2, d) - V(0, d));
+            c[6 + d] = 0.5 * (V(3, d) - V(0, d));
+        }
+        return;
+    }
+    for (int d = 0; d < 3; ++d) {
+        double A1 = 0.25 * (V(1, d) - V(0, d) + V(4, d) - V(3, d));
+        double B1 = 0.25 * (V(2, d) - V(0, d) + V(5, d) - V(3, d));
+        double D0 = 0.5 * (V(3, d) - V(0, d));
+        double D1 = 0.5 * (V(4, d) - V(1, d));
+        double D2 = 0.5 * (V(5, d) - V(2, d));
+        double C1 = 0.5 * (D1 - D0), C2 = 0.5 * (D2 - D0);
+        c[d] = A1;
+        c[3 + d] = B1;
+        c[6 + d] = D0 + C1 + C2;
+        c[9 + d] = C1;
+        c[12 + d] = C2;
+    }
+}
+
+void jac_at(int etype, const double *c, const double *xi, double col[3][3]) {
+    for (int d = 0; d < 3; ++d) {
+        if (etype == 0) {
+            col[0][d] = c[d];
+            col[1][d] = c[3 + d];
+            col[2][d] = c[6 + d];
+        } else {
+            col[0][d] = c[d] + c[9 + d] * xi[2];
+            col[1][d] = c[3 + d] + c[12 + d] * xi[2];
+            col[2][d] = c[6 + d] + c[9 + d] * xi[0] + c[12 + d] * xi[1];
+        }
+    }
+}
+
+void map_point(int etype, const double *X, const double *xi, double out[3]) {
+    double N[6];
+    int nv = n_verts(etype);
+    if (etype == 0) {
+        N[0] = -(1 + xi[0] + xi[1] + xi[2]) / 2;
+        N[1] = (1 + xi[0]) / 2;
+        N[2] = (1 + xi[1]) / 2;
+        N[3] = (1 + xi[2]) / 2;
+    } else {
+        double l[3] = {-(xi[0] + xi[1]) / 2, (1 + xi[0]) / 2, (1 + xi[1]) / 2};
+        for (int a = 0; a < 3; ++a) {
+            N[a] = l[a] * (1 - xi[2]) / 2;
+            N[a + 3] = l[a] * (1 + xi[2]) / 2;
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        out[d] = 0;
+        for (int a = 0; a < nv; ++a) out[d] += N[a] * X[3 * a + d];
+    }
+}
+
+namespace {
+
+void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// adj[k][j] = J dxi_k/dx_j; its rows are cross products of Jacobian columns.
+double adjugate(const double col[3][3], double adj[3][3]) {
+    cross3(col[1], col[2], adj[0]);
+    cross3(col[2], col[0], adj[1]);
+    cross3(col[0], col[1], adj[2]);
+    return col[0][0] * adj[0][0] + col[0][1] * adj[0][1] + col[0][2] * adj[0][2];
+}
+
+struct FaceRec {
+    std::array<int64_t, 4> key;   // sorted vertex ids (4th = -1 for triangles)
+    int64_t gid;
+    int face, type;
+    int64_t elem;
+};
+
+}  // namespace
+
+bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const int64_t *tet_v,
+                     const int8_t *tet_img, int64_t npri, const int64_t *pri_v,
+                     const int8_t *pri_img, const double period[3], MeshHost &m,
+                     std::string &err) {
+    m.p = p;
+    const int64_t nelem[2] = {ntet, npri};
+    const int64_t *conn[2] = {tet_v, pri_v};
+    const int8_t *img[2] = {tet_img, pri_img};
+    m.volume = 0;
+    for (int t = 0; t < 2; ++t) {
+        TypeHost &T = m.t[t];
+        T.nelem = nelem[t];
+        T.ld = (T.nelem + 63) / 64 * 64;
+        if (T.nelem == 0) continue;
+        if (T.nelem >= (int64_t(1) << 24)) {
+            err = "too many elements of one type (limit 2^24)";
+            return false;
+        }
+        T.ops = build_ref(t, p);
+        const int nvt = n_verts(t), ng = n_geom(t), nu = T.ops.nu, nf = T.ops.nf;
+        T.X.resize(size_t(T.nelem) * nvt * 3);
+        T.geom.assign(size_t(ng) * T.nelem, 0);
+        T.jdet.resize(size_t(T.nelem) * nu);
+        for (int64_t e = 0; e < T.nelem; ++e) {
+            double *X = &T.X[size_t(e) * nvt * 3];
+            for (int a = 0; a < nvt; ++a) {
+                int64_t v = conn[t][e * nvt + a];
+                if (v < 0 || v >= nv) {
+                    err = "vertex id out of range in " + std::string(t ? "prism " : "tet ") +
+                          std::to_string(e);
+                    return false;
+                }
+                for (int d = 0; d < 3; ++d) {
+                    double sh = img[t] ? img[t][(e * nvt + a) * 3 + d] * period[d] : 0.0;
+                    X[3 * a + d] = xyz[3 * v + d] + sh;
+                }
+            }
+            double c[15];
+            geom_coeffs(t, X, c);
+            for (int k = 0; k < ng; ++k) T.geom[size_t(k) * T.nelem + e] = c[k];
+            // J > 0 at every solution and flux point
+            for (int i = 0; i < nu + nf; ++i) {
+                const double *xi = i < nu ? &T.ops.upts[3 * i] : &T.ops.fpts[3 * (i - nu)];
+                double col[3][3], adj[3][3];
+                jac_at(t, c, xi, col);
+                double J = adjugate(col, adj);
+                if (!(J > 0)) {
+                    err = std::string("non-positive Jacobian in ") + (t ? "prism " : "tet ") +
+                          std::to_string(e);
+                    return false;
+                }
+                if (i < nu) {
+                    T.jdet[size_t(e) * nu + i] = J;
+                    m.volume += T.ops.w[i] * J;
+                }
+            }
+        }
+    }
+
+    // faces keyed by their sorted vertex ids
+    std::vector<FaceRec> recs;
+    int64_t gbase[2] = {0, ntet};
+    for (int t = 0; t < 2; ++t) {
+        const TypeHost &T = m.t[t];
+        if (!T.nelem) continue;
+        const auto &faces = faces_of(t);
+        const int nvt = n_verts(t);
+        for (int64_t e = 0; e < T.nelem; ++e)
+            for (size_t f = 0; f < faces.size(); ++f) {
+                FaceRec r;
+                r.key = {-1, -1, -1, -1};
+                for (size_t a = 0; a < faces[f].size(); ++a) r.key[a] = conn[t][e * nvt + faces[f][a]];
+                std::sort(r.key.begin(), r.key.begin() + faces[f].size());
+                r.gid = gbase[t] + e;
+                r.face = int(f);
+                r.type = t;
+                r.elem = e;
+                recs.push_back(r);
+            }
+    }
+    std::sort(recs.begin(), recs.end(), [](const FaceRec &a, const FaceRec &b) {
+        if (a.key != b.key) return a.key < b.key;
+        if (a.gid != b.gid) return a.gid < b.gid;
+        return a.face < b.face;
+    });
+
+    struct PP {
+        uint32_t L, R;
+        double n[3], sL, sR;
+    };
+    std::vector<PP> pp;
+    double scale = 1.0;
+    for (int64_t v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) scale = std::max(scale, std::fabs(xyz[3 * v + d]));
+    const double tol = 1e-9 * scale;
+
+    for (size_t i = 0; i < recs.size();) {
+        size_t j = i;
+        while (j < recs.size() && recs[j].key == recs[i].key) ++j;
+        if (j - i != 2) {
+            err = "face shared by " + std::to_string(j - i) + " element(s): " +
+                  (recs[i].type ? "prism " : "tet ") + std::to_string(recs[i].elem) + " face " +
+                  std::to_string(recs[i].face);
+            return false;
+        }
+        const FaceRec &A = recs[i], &B = recs[i + 1];   // A sorts first: side L
+        const TypeHost &TA = m.t[A.type], &TB = m.t[B.type];
+        const int nvA = n_verts(A.type), nvB = n_verts(B.type);
+        const double *XA = &TA.X[size_t(A.elem) * nvA * 3];
+        const double *XB = &TB.X[size_t(B.elem) * nvB * 3];
+        // periodic shift between the two unwrapped copies: via a shared vertex
+        int64_t v0 = A.key[0];
+        int ia = -1, ib = -1;
+        for (int a = 0; a < nvA; ++a)
+            if (conn[A.type][A.elem * nvA + a] == v0) ia = a;
+        for (int a = 0; a < nvB; ++a)
+            if (conn[B.type][B.elem * nvB + a] == v0) ib = a;
+        double shift[3];
+        for (int d = 0; d < 3; ++d) shift[d] = XA[3 * ia + d] - XB[3 * ib + d];
+        const int fa0 = TA.ops.face_off[A.face], fa1 = TA.ops.face_off[A.face + 1];
+        const int fb0 = TB.ops.face_off[B.face], fb1 = TB.ops.face_off[B.face + 1];
+        if (fa1 - fa0 != fb1 - fb0) {
+            err = "non-conforming face between " + std::string(A.type ? "prism " : "tet ") +
+                  std::to_string(A.elem) + " and " + (B.type ? "prism " : "tet ") +
+                  std::to_string(B.elem);
+            return false;
+        }
+        double ca[15], cb[15];
+        for (int k = 0; k < n_geom(A.type); ++k) ca[k] = TA.geom[size_t(k) * TA.nelem + A.elem];
+        for (int k = 0; k < n_geom(B.type); ++k) cb[k] = TB.geom[size_t(k) * TB.nelem + B.elem];
+        std::vector<char> used(fb1 - fb0, 0);
+        double xbs[25][3];
+        for (int jb = fb0; jb < fb1; ++jb) {
+            map_point(B.type, XB, &TB.ops.fpts[3 * jb], xbs[jb - fb0]);
+            for (int d = 0; d < 3; ++d) xbs[jb - fb0][d] += shift[d];
+        }
+        for (int ja = fa0; ja < fa1; ++ja) {
+            double xa[3];
+            map_point(A.type, XA, &TA.ops.fpts[3 * ja], xa);
+            int best = -1;
+            double bd = 1e300;
+            for (int jb = fb0; jb < fb1; ++jb) {
+                const double *xb = xbs[jb - fb0];
+                double d2 = 0;
+                for (int d = 0; d < 3; ++d) d2 += (xa[d] - xb[d]) * (xa[d] - xb[d]);
+                if (d2 < bd) { bd = d2; best = jb; }
+            }
+            if (std::sqrt(bd) > tol || used[best - fb0]) {
+                err = "flux points do not coincide on the face between " +
+                      std::string(A.type ? "prism " : "tet ") + std::to_string(A.elem) + " and " +
+                      (B.type ? "prism " : "tet ") + std::to_string(B.elem);
+                return false;
+            }
+            used[best - fb0] = 1;
+            PP q;
+            q.L = pack_side(A.elem, ja, A.type);
+            q.R = pack_side(B.elem, best, B.type);
+            double col[3][3], adj[3][3], nA[3], nB[3];
+            jac_at(A.type, ca, &TA.ops.fpts[3 * ja], col);
+            adjugate(col, adj);
+            for (int jd = 0; jd < 3; ++jd) {
+                nA[jd] = 0;
+                for (int k = 0; k < 3; ++k) nA[jd] += adj[k][jd] * TA.ops.nref[3 * ja + k];
+            }
+            jac_at(B.type, cb, &TB.ops.fpts[3 * best], col);
+            adjugate(col, adj);
+            for (int jd = 0; jd < 3; ++jd) {
+                nB[jd] = 0;
+                for (int k = 0; k < 3; ++k) nB[jd] += adj[k][jd] * TB.ops.nref[3 * best + k];
+            }
+            q.sL = std::sqrt(nA[0] * nA[0] + nA[1] * nA[1] + nA[2] * nA[2]);
+            q.sR = std::sqrt(nB[0] * nB[0] + nB[1] * nB[1] + nB[2] * nB[2]);
+            for (int d = 0; d < 3; ++d) q.n[d] = nA[d] / q.sL;
+            pp.push_back(q);
+        }
+        i = j;
+    }
+
+    // order by (type L, flux point L, element L) for coalesced side-L access
+    auto keyL = [](uint32_t s) {
+        return (uint64_t(s >> 31) << 40) | (uint64_t((s >> 24) & 0x7f) << 32) | (s & 0xffffff);
+    };
+    std::sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
+    PairTable &P = m.pairs;
+    const size_t n = pp.size();
+    P.sideL.resize(n);
+    P.sideR.resize(n);
+    P.nhat.resize(3 * n);
+    P.sL.resize(n);
+    P.sR.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+        P.sideL[i] = pp[i].L;
+        P.sideR[i] = pp[i].R;
+        for (int d = 0; d < 3; ++d) P.nhat[3 * i + d] = pp[i].n[d];
+        P.sL[i] = pp[i].sL;
+        P.sR[i] = pp[i].sR;
+    }
+    return true;
+}
+
+}  // namespace frh

@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libfr.so (C ABI in include/fr.h).
+
+Argument marshalling only: every step of the right-hand side runs in the HIP
+library.  Device arrays are passed as raw pointers (``torch.Tensor.data_ptr()``)
+together with a HIP stream handle (``torch.cuda.current_stream().cuda_stream``);
+torch is used for device memory and streams only.
+
+Loading fails loudly if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfr.so")
+
+FR_OK, FR_ERR_INVALID_ARG, FR_ERR_BAD_MESH, FR_ERR_UNSUPPORTED = 0, 1, 2, 3
+FR_ERR_OUT_OF_MEMORY, FR_ERR_DEVICE, FR_ERR_NONFINITE = 4, 5, 6
+FR_TET, FR_PRI = 0, 1
+FR_EULER, FR_NAVIER_STOKES = 0, 1
+FR_FP32, FR_FP64 = 0, 1
+FR_RK4, FR_RK45_2RP, FR_FWD_EULER = 0, 1, 2
+FR_VALIDATE_ONLY, FR_CHECK_FINITE = 0x1, 0x2
+FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
+
+EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coords",
+            "fr_operator", "fr_set_solution", "fr_get_solution", "fr_rhs", "fr_rk_step",
+            "fr_reduce", "fr_intermediate", "fr_last_error")
+
+
+class FrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fr status {status}: {msg}")
+        self.status = status
+
+
+class fr_mesh_desc(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32), ("system", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double),
+        ("n_vertices", ctypes.c_int64), ("xyz", ctypes.POINTER(ctypes.c_double)),
+        ("n_tets", ctypes.c_int64), ("tet_v", ctypes.POINTER(ctypes.c_int64)),
+        ("tet_img", ctypes.POINTER(ctypes.c_int8)),
+        ("n_prisms", ctypes.c_int64), ("pri_v", ctypes.POINTER(ctypes.c_int64)),
+        ("pri_img", ctypes.POINTER(ctypes.c_int8)),
+        ("period", ctypes.c_double * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise FrError(-1, f"{_LIB_PATH} is not built; run python -m paper_1409_0405_amd.build")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.fr_mesh_create.argtypes = [ctypes.POINTER(fr_mesh_desc), vp, ctypes.POINTER(vp)]
+        L.fr_mesh_destroy.argtypes = [vp]
+        L.fr_mesh_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.fr_upts_coords.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+        L.fr_operator.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)]
+        L.fr_set_solution.argtypes = [vp, i32, vp, vp]
+        L.fr_get_solution.argtypes = [vp, i32, vp, vp]
+        L.fr_rhs.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.fr_rk_step.argtypes = [vp, i32, dbl, i32, vp]
+        L.fr_reduce.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
+        L.fr_intermediate.argtypes = [vp, i32, i32, vp, vp]
+        L.fr_last_error.argtypes = [vp]
+        L.fr_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "fr_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, mesh_ptr=None):
+    if st != FR_OK:
+        msg = lib().fr_last_error(mesh_ptr).decode()
+        raise FrError(st, msg)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class Mesh:
+    """A mesh handle owning its library-side buffers (fr_mesh)."""
+
+    def __init__(self, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4,
+                 mu=0.0, prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False,
+                 check_finite=False, stream=0):
+        self._keep = []
+        d = fr_mesh_desc()
+        d.order = order
+        d.system = {"euler": FR_EULER, "ns": FR_NAVIER_STOKES}[system]
+        d.precision = {"fp32": FR_FP32, "fp64": FR_FP64}[precision]
+        d.flags = (FR_VALIDATE_ONLY if validate_only else 0) | (FR_CHECK_FINITE if check_finite else 0)
+        d.gamma, d.mu, d.prandtl, d.ldg_beta, d.ldg_tau = gamma, mu, prandtl, ldg_beta, ldg_tau
+        xyz = np.ascontiguousarray(mesh_arrays["xyz"], dtype=np.float64)
+        tv = np.ascontiguousarray(mesh_arrays["tet_v"], dtype=np.int64)
+        ti = np.ascontiguousarray(mesh_arrays["tet_img"], dtype=np.int8)
+        pv = np.ascontiguousarray(mesh_arrays["pri_v"], dtype=np.int64)
+        pi = np.ascontiguousarray(mesh_arrays["pri_img"], dtype=np.int8)
+        self._keep += [xyz, tv, ti, pv, pi]
+        d.n_vertices = len(xyz)
+        d.xyz = _ptr(xyz, ctypes.c_double)
+        d.n_tets = len(tv)
+        d.tet_v = _ptr(tv, ctypes.c_int64) if len(tv) else None
+        d.tet_img = _ptr(ti, ctypes.c_int8) if len(tv) else None
+        d.n_prisms = len(pv)
+        d.pri_v = _ptr(pv, ctypes.c_int64) if len(pv) else None
+        d.pri_img = _ptr(pi, ctypes.c_int8) if len(pv) else None
+        for k in range(3):
+            d.period[k] = float(mesh_arrays["period"][k])
+        h = ctypes.c_void_p()
+        _check(lib().fr_mesh_create(ctypes.byref(d), ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+        self.order, self.system, self.precision = order, system, precision
+        self.dtype = np.float32 if precision == "fp32" else np.float64
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fr_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, etype):
+        ne, ld = ctypes.c_int64(), ctypes.c_int64()
+        nu, nf = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fr_mesh_query(self.h, etype, ctypes.byref(ne), ctypes.byref(nu),
+                                   ctypes.byref(nf), ctypes.byref(ld)), self.h)
+        return {"nelem": ne.value, "nupts": nu.value, "nfpts": nf.value, "ld": ld.value}
+
+    def upts_coords(self, etype):
+        q = self.query(etype)
+        out = np.zeros((q["nupts"], 3, q["nelem"]))
+        if q["nelem"]:
+            _check(lib().fr_upts_coords(self.h, etype, _ptr(out, ctypes.c_double)), self.h)
+        return out
+
+    def operator(self, etype, which):
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fr_operator(self.h, etype, which, None, ctypes.byref(r), ctypes.byref(c)), self.h)
+        out = np.zeros((r.value, c.value))
+        _check(lib().fr_operator(self.h, etype, which, _ptr(out, ctypes.c_double), None, None), self.h)
+        return out
+
+    def set_solution(self, etype, u_ptr, stream=0):
+        _check(lib().fr_set_solution(self.h, etype, ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)), self.h)
+
+    def get_solution(self, etype, u_ptr, stream=0):
+        _check(lib().fr_get_solution(self.h, etype, ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)), self.h)
+
+    def rhs(self, u_ptrs, r_ptrs, stream=0):
+        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        R = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in r_ptrs])
+        _check(lib().fr_rhs(self.h, U, R, ctypes.c_void_p(stream)), self.h)
+
+    def rk_step(self, scheme, dt, n_steps, stream=0):
+        _check(lib().fr_rk_step(self.h, scheme, float(dt), int(n_steps), ctypes.c_void_p(stream)), self.h)
+
+    def reduce(self, what, stream=0):
+        out = np.zeros(8)
+        _check(lib().fr_reduce(self.h, what, _ptr(out, ctypes.c_double), ctypes.c_void_p(stream)), self.h)
+        return out[:2] if what == FR_RED_KE else out[:5]
+
+    def intermediate(self, etype, which, dst_ptr, stream=0):
+        _check(lib().fr_intermediate(self.h, etype, which, ctypes.c_void_p(dst_ptr),
+                                     ctypes.c_void_p(stream)), self.h)
+
+
+# ---------------------------------------------------------------------------
+# torch helpers (device memory and streams only)
+# ---------------------------------------------------------------------------
+
+def state_tensor(mesh: Mesh, etype, device="cuda"):
+    """Zeroed device state [n_upts][5][ld] of the mesh's dtype."""
+    import torch
+    q = mesh.query(etype)
+    dt = torch.float32 if mesh.precision == "fp32" else torch.float64
+    return torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=dt, device=device)
+
+
+def to_device_state(mesh: Mesh, etype, U_host, device="cuda"):
+    """Host array [n_upts][5][n_elem] -> padded device state."""
+    import torch
+    t = state_tensor(mesh, etype, device)
+    ne = U_host.shape[2]
+    t[:, :, :ne] = torch.as_tensor(np.ascontiguousarray(U_host), dtype=t.dtype).to(device)
+    if ne < t.shape[2] and ne > 0:     # padding columns: copy a real element
+        t[:, :, ne:] = t[:, :, :1]
+    return t
+
+
+def current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on
+the same seeded inputs.
+
+Sizes span several MFMA tiles and a ragged element tail (element counts not
+multiples of 64).  Tolerances (relative L2 per conserved field):
+* FP64 build of the kernels:  1e-11 (operators built by two independent
+  routes agree to ~2e-13; the residual amplifies that by ~p^2/h);
+* FP32 build: stated per case, derived from the single-precision unit
+  roundoff times the cancellation factor of the case (see _fp32_tol).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as om, reduce, rk
+from paper_1409_0405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ("tet", "pri")
+
+
+def _lib():
+    from paper_1409_0405_amd import frlib
+    return frlib
+
+
+def _state(O, ic, seed, noise=0.01, **kw):
+    U = fr.initial_state(O, ic, **kw)
+    for n in U:
+        U[n] = U[n] * inputs.random_perturbation(U[n].shape, seed, noise)
+    return U
+
+
+def _round32(U):
+    return {n: U[n].astype(np.float32).astype(np.float64) for n in U}
+
+
+def _gpu_rhs(M, O, U):
+    frlib = _lib()
+    u, r = [], []
+    for t in (0, 1):
+        if NAMES[t] in O.types:
+            u.append(frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))))
+        else:
+            u.append(None)
+        r.append(frlib.state_tensor(M, t) if u[-1] is not None else None)
+    M.rhs([x.data_ptr() if x is not None else 0 for x in u],
+          [x.data_ptr() if x is not None else 0 for x in r])
+    torch.cuda.synchronize()
+    out = {}
+    for t in (0, 1):
+        if r[t] is not None:
+            ne = O.types[NAMES[t]].nelem
+            out[NAMES[t]] = np.transpose(r[t][:, :, :ne].cpu().numpy().astype(np.float64), (2, 0, 1))
+    return out
+
+
+def _field_errors(Rg, Ro):
+    """Per-field relative L2 error over all types."""
+    num = sum(((Rg[n] - Ro[n]) ** 2).sum(axis=(0, 1)) for n in Ro)
+    den = sum((Ro[n] ** 2).sum(axis=(0, 1)) for n in Ro)
+    return np.sqrt(num / den)
+
+
+def _fp32_tol(O, U, prm):
+    """Error scale of a single-precision evaluation: unit roundoff 2^-24 times
+    the ratio of the residual computed from |fluxes| (no cancellation) to the
+    residual itself, per field, times a safety factor of 16."""
+    R = fr.rhs(O, U, prm)
+    # magnitude of the summed terms: the residual of |U| perturbations is not
+    # available in closed form, so use the flux magnitude over the element
+    # size: |F| * (p+1)^2 / h at each point, h from the element Jacobian.
+    num = np.zeros(5)
+    den = np.zeros(5)
+    for n, tg in O.types.items():
+        Ue = np.moveaxis(U[n], 2, 0)
+        from oracle import physics
+        F = np.abs(physics.inviscid_flux(Ue, prm.gamma)).max(axis=0)      # [5][E][N]
+        h = np.cbrt(tg.J_upts)                                               # ~ element size / 2
+        scale = F * (O.p + 1) ** 2 / h[None]
+        num += (scale ** 2).sum(axis=(1, 2))
+        den += (R[n] ** 2).sum(axis=(0, 1))
+    kappa = np.sqrt(num / den)
+    return 16 * 2.0 ** -24 * kappa
+
+
+# ---------------------------------------------------------------------------
+
+CASES = [
+    # (mesh maker, p, system, ic, ic kwargs, mu)
+    ("tetcube", 2, "euler", inputs.isentropic_vortex, {}, 0.0),
+    ("mixed", 1, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("mixed", 3, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("mixed", 1, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("mixed", 2, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("mixed", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("mixed", 4, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("mixed", 4, "euler", inputs.taylor_green, {"mach": 0.1}, 0.0),
+]
+
+
+def _mesh(kind, seed=0):
+    if kind == "tetcube":
+        return inputs.vortex_tet_cube(n=6, jitter=0.05, seed=seed)
+    # 4 x 4 x (3 + 3): 96 prisms and 288 tets -> ragged against 64
+    return inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=seed)
+
+
+def _ids(c):
+    return f"{c[0]}-p{c[1]}-{c[2]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_rhs_fp64_parity(case):
+    kind, p, system, ic, kw, mu = case
+    print(f"case {_ids(case)} fp64", flush=True)
+    arrays = _mesh(kind)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system=system, mu=mu)
+    U = _state(O, ic, 3, **kw)
+    Ro = fr.rhs(O, U, prm)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=mu)
+    Rg = _gpu_rhs(M, O, U)
+    err = _field_errors(Rg, Ro)
+    print("  field errors", err, flush=True)
+    assert (err < 1e-11).all(), err
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_rhs_fp32_parity(case):
+    kind, p, system, ic, kw, mu = case
+    print(f"case {_ids(case)} fp32", flush=True)
+    arrays = _mesh(kind)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system=system, mu=mu)
+    U = _round32(_state(O, ic, 3, **kw))
+    Ro = fr.rhs(O, U, prm)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp32", mu=mu)
+    Rg = _gpu_rhs(M, O, U)
+    err = _field_errors(Rg, Ro)
+    tol = _fp32_tol(O, U, prm)
+    print("  field errors", err, "tol", tol, flush=True)
+    assert (err < tol).all(), (err, tol)
+
+
+@pytest.mark.parametrize("p,system", [(2, "ns"), (4, "ns"), (3, "euler")])
+def test_interface_intermediates_fp64(p, system):
+    """State at flux points, common normal flux and (NS) the gradient at flux
+    points, element by element."""
+    print(f"intermediates p{p} {system}", flush=True)
+    arrays = _mesh("mixed", seed=2)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system=system, mu=0.02)
+    U = _state(O, inputs.taylor_green, 4, mach=0.3)
+    want = {}
+    fr.rhs(O, U, prm, want=want)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=0.02)
+    _gpu_rhs(M, O, U)
+    items = [(0, "Uf", 5), (1, "Fn", 5)] + ([(2, "Qf", 15)] if system == "ns" else [])
+    for which, key, nv in items:
+        for t, n in enumerate(NAMES):
+            q = M.query(t)
+            buf = torch.zeros((q["nfpts"], nv, q["ld"]), dtype=torch.float64, device="cuda")
+            M.intermediate(t, which, buf.data_ptr())
+            torch.cuda.synchronize()
+            g = np.transpose(buf[:, :, :q["nelem"]].cpu().numpy(), (2, 0, 1))
+            o = want[key][n].reshape(g.shape)
+            rel = np.abs(g - o).max() / np.abs(o).max()
+            print(f"  {key} {n} max rel {rel:.2e}", flush=True)
+            assert rel < 1e-11, (key, n, rel)
+
+
+def _vortex_dt(n, p):
+    lam = 0.5 * math.sqrt(1.4) + math.sqrt(1.4)
+    return 0.2 * (1.0 / n) / (lam * (2 * p + 1))
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "rk45"])
+def test_rk_steps_fp64_vortex(scheme):
+    """The small Euler workload: 1,296 jittered tets, p = 2, isentropic vortex,
+    10 steps at CFL 0.2 (RK4 as stated for it, and RK45[2R+])."""
+    frlib = _lib()
+    print(f"rk {scheme}", flush=True)
+    arrays = inputs.vortex_tet_cube(n=6, jitter=0.05, seed=0)
+    p, nsteps = 2, 10
+    dt = _vortex_dt(6, p)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system="euler")
+    U0 = fr.initial_state(O, inputs.isentropic_vortex)
+    stepper = rk.rk4_step if scheme == "rk4" else rk.rk45_step
+    Uo = rk.run(stepper, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
+    M = frlib.Mesh(arrays, p, system="euler", precision="fp64", check_finite=True)
+    u = frlib.to_device_state(M, 0, np.transpose(U0["tet"], (1, 2, 0)))
+    M.set_solution(0, u.data_ptr())
+    M.rk_step(frlib.FR_RK4 if scheme == "rk4" else frlib.FR_RK45_2RP, dt, nsteps)
+    out = frlib.state_tensor(M, 0)
+    M.get_solution(0, out.data_ptr())
+    torch.cuda.synchronize()
+    g = np.transpose(out[:, :, :O.types["tet"].nelem].cpu().numpy(), (2, 0, 1))
+    d = g - Uo["tet"]
+    err = np.sqrt((d ** 2).sum(axis=(0, 1)) / (Uo["tet"] ** 2).sum(axis=(0, 1)))
+    print("  field errors", err, flush=True)
+    assert (err < 1e-12).all(), err
+
+
+def test_reductions_fp64():
+    """FP64 global sums: integral of U and of R(U) (discrete conservation) and
+    the kinetic-energy rate, against the oracle's quadrature."""
+    frlib = _lib()
+    arrays = _mesh("mixed", seed=5)
+    p, mu = 3, 0.02
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system="ns", mu=mu)
+    U = _state(O, inputs.taylor_green, 9, mach=0.3)
+    Ro = fr.rhs(O, U, prm)
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp64", mu=mu)
+    for t, n in enumerate(NAMES):
+        u = frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0)))
+        M.set_solution(t, u.data_ptr())
+    torch.cuda.synchronize()
+    iu = M.reduce(frlib.FR_RED_INT_U)
+    assert np.allclose(iu, reduce.integral(O, U), rtol=1e-12, atol=0)
+    ir = M.reduce(frlib.FR_RED_INT_R)
+    scale = reduce.integral(O, {n: np.abs(Ro[n]) for n in Ro})
+    assert (np.abs(ir) <= 1e-12 * scale).all(), ir / scale
+    n2 = M.reduce(frlib.FR_RED_NORM2_R)
+    assert np.allclose(n2, reduce.integral(O, {n: Ro[n] ** 2 for n in Ro}), rtol=1e-10)
+    ke, dke = M.reduce(frlib.FR_RED_KE)
+    assert abs(ke - reduce.kinetic_energy(O, U)) < 1e-12 * abs(ke)
+    assert abs(dke - reduce.kinetic_energy_rate(O, U, Ro)) < 1e-9 * abs(dke)
+
+
+def test_freestream_and_conservation_fp32_mixed():
+    """Uniform flow gives zero residual (up to FP32 rounding of the flux
+    magnitude); the FP64 conservation sum of R(U) vanishes."""
+    frlib = _lib()
+    arrays = _mesh("mixed", seed=6)
+    p = 4
+    O = om.build_mesh(arrays, p)
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.01)
+    U = _round32(fr.initial_state(O, inputs.uniform))
+    Rg = _gpu_rhs(M, O, U)
+    fscale = 5.0   # |flux| ~ p + rho u^2 ~ 1 for inputs.uniform
+    worst = max(np.abs(Rg[n]).max() for n in Rg)
+    assert worst < 1e-4 * fscale, worst
