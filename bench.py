@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the FR right-hand side on one MI355X.
+
+Workload: compressible Navier-Stokes (Re 1600, Ma 0.1, Pr 0.71), Taylor-Green
+initial state, order p = 4, FP32, on the periodic [0, 2 pi)^3 box with
+110,592 prisms (z < pi) and 196,608 tets (z > pi), vertices jittered by 10 %
+(seed 0); Rusanov + LDG interface fluxes.
+
+One step = one RK45[2R+] step (five right-hand-side evaluations with the
+fused register updates) plus the FP64 conservation integral of the solution.
+The reported value is GDOF/s per right-hand-side evaluation:
+5 * n_dof * steps / wall time, n_dof = solution points x 5 fields.
+
+Also reported: the roofline of the dominant kernel (per-kernel HIP event
+timing on the library's stream, in a separate instrumented pass over the same
+steps) and the FP64 oracle's throughput on a bounded sample of the same
+workload on the host CPU.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDOF/s per RHS eval, mixed prism/tet p=4, plain FP32 vs split-BF16; HBM %"
+PEAK_HBM = 8.0e12          # B/s
+PEAK_FP32_MFMA = 157.3e12  # FLOP/s, dense
+RIDGE = PEAK_FP32_MFMA / PEAK_HBM
+
+
+def kernel_model(mesh, system):
+    """Algorithmic FLOPs and bytes per launch of each kernel class (FP32).
+
+    Operator products C = A B: 2 M K n flops and 4 (K + M) n bytes over the
+    n = fields x elements real columns.  Point-wise kernels: the values they
+    must read and write once (states, gradients, fluxes, geometry)."""
+    ns = system == "ns"
+    out = {}
+    s = 4
+    npairs = 0
+    for t, name in ((0, "tet"), (1, "pri")):
+        q = mesh.query(t)
+        E, nu, nf = q["nelem"], q["nupts"], q["nfpts"]
+        npairs += E * nf
+        cols5 = 5 * E
+        ops = {"interp": (nf, nu, cols5), "div": (nu, 3 * nu + nf, cols5)}
+        if ns:
+            ops["grad"] = (3 * nu, nu + nf, cols5)
+            ops["gradinterp"] = (nf, nu, 3 * cols5)
+        for op, (M, K, n) in ops.items():
+            out[f"{op}_{name}"] = {"flops": 2.0 * M * K * n, "bytes": s * (K + M) * n}
+        ng = 9 if t == 0 else 15
+        pt = (5 + (15 + 15 if ns else 0) + 15) * nu * E * s + ng * E * s
+        out[f"upts_{name}"] = {"flops": 0.0, "bytes": float(pt)}
+        out[f"negdivconf_{name}"] = {"flops": 0.0, "bytes": float((5 + 5 + 5) * nu * E * s + ng * E * s)}
+    npairs //= 2
+    per_pair = (2 * 5 + (2 * 15 if ns else 0) + 2 * 5 + 5) * s + 8
+    out["common_flux"] = {"flops": 0.0, "bytes": float(per_pair * npairs)}
+    if ns:
+        out["common_solution"] = {"flops": 0.0, "bytes": float((2 * 5 + 2 * 5) * s * npairs + 8 * npairs)}
+    return out
+
+
+def cpu_baseline(target_seconds):
+    """The FP64 oracle on a bounded sample of the same workload (same mesh
+    structure, order and physics, fewer elements)."""
+    import numpy as np
+    from oracle import fr, mesh as om
+    from paper_1409_0405_amd import inputs
+    arrays = inputs.tgv_mixed_box(nxy=6, n_pri_layers=10, n_tet_layers=6, jitter=0.10, seed=0)
+    O = om.build_mesh(arrays, 4)
+    U = fr.initial_state(O, inputs.taylor_green, mach=0.1)
+    prm = fr.Params(system="ns", mu=1.0 / 1600.0, prandtl=0.71)
+    dof = sum(tg.nelem * tg.ref.nupts * 5 for tg in O.types.values())
+    fr.rhs(O, U, prm)       # first call outside the timing
+    n, t0 = 0, time.perf_counter()
+    while True:
+        fr.rhs(O, U, prm)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > target_seconds:
+            break
+    nt = O.types["tet"].nelem
+    npri = O.types["pri"].nelem
+    return {"value": dof * n / el / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} NS p=4 RHS evaluations of the FP64 NumPy oracle on a "
+                      f"{npri}-prism / {nt}-tet periodic TGV box of the same structure "
+                      f"({dof} DOF, {el:.1f} s; single-threaded NumPy einsum)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cfl", type=float, default=0.3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the right-hand side runs on a single "
+              "MI355X here (sharding by mesh partition is not built); run with --gpus 1",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import frlib, inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    t_setup = time.perf_counter()
+    arrays = inputs.tgv_mixed_box()
+    mu, mach, pr, p = 1.0 / 1600.0, 0.1, 0.71, 4
+    mesh = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=mu, prandtl=pr,
+                      stream=stream)
+    dof = 0
+    for t in (0, 1):
+        q = mesh.query(t)
+        x = mesh.upts_coords(t)                                        # [nu][3][E]
+        U = inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=mach)  # [5][nu][E]
+        u = frlib.to_device_state(mesh, t, np.transpose(U, (1, 0, 2)))
+        mesh.set_solution(t, u.data_ptr(), stream)
+        dof += q["nupts"] * q["nelem"] * 5
+        del u
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"setup {t_setup:.1f} s, {dof} DOF", file=sys.stderr, flush=True)
+
+    h_ref = math.pi / 54                  # smallest unjittered spacing (prism layers)
+    lam = 1.0 + 1.0 / mach                # V0 + c0
+    dt = args.cfl * h_ref / (lam * (2 * p + 1))
+
+    def step():
+        mesh.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
+        return mesh.reduce(frlib.FR_RED_INT_U, stream)   # FP64, synchronising
+
+    I0 = step()
+    for _ in range(max(args.warmup - 1, 0)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        I1 = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = 5.0 * dof * args.steps / el / 1e9
+    drift = float(np.max(np.abs(I1 - I0)[[0, 4]] / np.abs(I0)[[0, 4]]))
+    finite = bool(np.all(np.isfinite(I1)))
+    print(f"{ms_per_step:.3f} ms/step, {value:.2f} GDOF/s per RHS, mass/energy drift {drift:.2e}",
+          file=sys.stderr, flush=True)
+
+    roof = None
+    if not args.no_profile:
+        nprof = max(3, min(args.steps, 10))
+        mesh.profile(True)
+        for _ in range(nprof):
+            mesh.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
+        prof = mesh.profile_read()
+        mesh.profile(False)
+        model = kernel_model(mesh, "ns")
+        rows = []
+        for k, (ms, cnt) in prof.items():
+            if cnt:
+                rows.append((ms, k, cnt))
+        rows.sort(reverse=True)
+        tot = sum(r[0] for r in rows)
+        for ms, k, cnt in rows:
+            avg = ms / cnt * 1e-3
+            mdl = model.get(k, {"flops": 0, "bytes": 0})
+            print(f"  {k:16s} {ms / nprof:8.3f} ms/step {100 * ms / tot:5.1f}%  avg {avg * 1e6:8.1f} us"
+                  f"  {mdl['flops'] / avg / 1e12:7.1f} TFLOP/s  {mdl['bytes'] / avg / 1e9:7.0f} GB/s",
+                  file=sys.stderr, flush=True)
+        ms, k, cnt = rows[0]
+        avg = ms / cnt * 1e-3
+        mdl = model[k]
+        if mdl["flops"] and mdl["flops"] / mdl["bytes"] > RIDGE:
+            roof = {"bound": "mfma", "achieved": mdl["flops"] / avg / 1e12, "peak": 157.3,
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": mdl["bytes"] / avg / 1e9, "peak": 8000.0,
+                    "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = k
+        roof["avg_launch_us"] = avg * 1e6
+        roof["share_of_step"] = ms / tot
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Navier-Stokes Taylor-Green Re1600 Ma0.1, p=4, FP32, "
+                               "110592 prisms + 196608 tets, RK45[2R+] steps",
+                   "n_dof": dof, "rhs_per_step": 5, "dt": dt, "parallelism": "single GPU",
+                   "finite": finite, "mass_energy_drift": drift},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

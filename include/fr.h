@@ -175,6 +175,20 @@ fr_status fr_reduce(fr_mesh mesh, int32_t what, double *out_host, void *stream);
 fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_dev,
                           void *stream);
 
+/* Per-kernel timing with HIP events (measurement support).  While enabled,
+ * every kernel the library launches is bracketed by two HIP events recorded
+ * on its stream.  fr_profile(mesh, 1) enables and clears, 0 disables.
+ * fr_profile_read waits for the recorded events, writes per kernel class the
+ * summed duration in milliseconds and the launch count (arrays of
+ * FR_PROF_NCLASS), and clears the records.  Classes: 4 * etype + op for the
+ * operator products (op 0 interpolation to flux points, 1 corrected
+ * gradient, 2 gradient interpolation, 3 divergence plus correction), 8 + etype
+ * the solution-point flux kernel, 10 common solution, 11 common interface
+ * flux, 12 + etype negdivconf with the Runge-Kutta update. */
+#define FR_PROF_NCLASS 14
+fr_status fr_profile(fr_mesh mesh, int32_t enable);
+fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
+
 /* Message of the last failure on mesh (NULL: of fr_mesh_create on this
  * thread).  Never NULL; valid until the next call on the same mesh. */
 const char *fr_last_error(fr_mesh mesh);

@@ -62,6 +62,17 @@ struct Dev : DevBase {
 
 }  // namespace
 
+// Per-kernel HIP event timing (fr_profile / fr_profile_read).
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> recs;   // (kernel class, start event index)
+    ~Profiler() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct fr_mesh_s {
     int order = 0, system = 0, precision = 0;
     uint32_t flags = 0;
@@ -70,6 +81,7 @@ struct fr_mesh_s {
     hipStream_t create_stream = nullptr;
     bool device = false;
     std::unique_ptr<DevBase> dev;
+    Profiler prof;
     std::string err;
 };
 
@@ -89,6 +101,40 @@ fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
         if (e_ != hipSuccess)                                                            \
             return fail(m, e_ == hipErrorOutOfMemory ? FR_ERR_OUT_OF_MEMORY : FR_ERR_DEVICE, \
                         std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// Kernel classes of the profiler: 0..7 operator products (4 * type + op),
+// 8/9 solution-point kernel (tet/prism), 10 common solution, 11 common flux,
+// 12/13 negdivconf (tet/prism).
+constexpr int PROF_NCLASS = 14;
+constexpr size_t PROF_NONE = size_t(-1);
+
+size_t prof_begin(fr_mesh m, hipStream_t s) {
+    Profiler &P = m->prof;
+    if (!P.on) return PROF_NONE;
+    while (P.pool.size() < P.used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return PROF_NONE;
+        P.pool.push_back(e);
+    }
+    size_t i = P.used;
+    P.used += 2;
+    (void)hipEventRecord(P.pool[i], s);
+    return i;
+}
+
+void prof_end(fr_mesh m, size_t i, int cls, hipStream_t s) {
+    if (i == PROF_NONE) return;
+    (void)hipEventRecord(m->prof.pool[i + 1], s);
+    m->prof.recs.push_back({cls, i});
+}
+
+// Launch wrapped in profiler events.
+#define FR_LAUNCH(m, cls, s, call)            \
+    do {                                       \
+        size_t pi_ = prof_begin(m, s);         \
+        FR_HIP(m, call);                       \
+        prof_end(m, pi_, cls, s);              \
     } while (0)
 
 // Fragment order for the MFMA product kernel.
@@ -300,7 +346,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
-        FR_HIP(m, frd::launch_opmul<T>(D.Aint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
+        FR_LAUNCH(m, 4 * t + frd::OP_INTERP, s,
+                  frd::launch_opmul<T>(4 * t + frd::OP_INTERP, D.Aint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
     }
     frd::PairArgs<T> pa{};
     pa.sideL = d.sideL;
@@ -320,33 +367,36 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
     pa.beta = T(m->beta);
     pa.tau = T(m->tau);
     if (ns) {
-        FR_HIP(m, frd::launch_common_solution<T>(pa, s));
+        FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
         for (int t = 0; t < 2; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
             const int64_t w5 = 5 * D.ld;
-            FR_HIP(m, frd::launch_opmul<T>(D.Agrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
+            FR_LAUNCH(m, 4 * t + frd::OP_GRAD, s,
+                      frd::launch_opmul<T>(4 * t + frd::OP_GRAD, D.Agrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
         }
     }
     for (int t = 0; t < 2; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         frd::UptsArgs<T> ua{U[t], D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu, gamma, mu, pr};
-        FR_HIP(m, frd::launch_upts<T>(t, ns, ua, s));
+        FR_LAUNCH(m, 8 + t, s, frd::launch_upts<T>(t, ns, ua, s));
         if (ns) {
             const int64_t w15 = 15 * D.ld;
-            FR_HIP(m, frd::launch_opmul<T>(D.Aint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
+            FR_LAUNCH(m, 4 * t + frd::OP_GRADINTERP, s,
+                      frd::launch_opmul<T>(4 * t + frd::OP_GRADINTERP, D.Aint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
         }
     }
-    FR_HIP(m, frd::launch_common_flux<T>(ns, pa, s));
+    FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
     for (int t = 0; t < 2; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
-        FR_HIP(m, frd::launch_opmul<T>(D.Adiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
+        FR_LAUNCH(m, 4 * t + frd::OP_DIV, s,
+                  frd::launch_opmul<T>(4 * t + frd::OP_DIV, D.Adiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.geom, D.xi, D.ld, D.nelem, D.nu};
-        FR_HIP(m, frd::launch_negdivconf<T>(t, na, s));
+        FR_LAUNCH(m, 12 + t, s, frd::launch_negdivconf<T>(t, na, s));
     }
     return FR_OK;
 }
@@ -663,6 +713,34 @@ fr_status fr_intermediate(fr_mesh m, int32_t etype, int32_t which, void *dst, vo
         src = which == 0 ? (void *)D.Uf : which == 1 ? (void *)D.Fn : (void *)D.Qf;
     }
     FR_HIP(m, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s));
+    return FR_OK;
+}
+
+fr_status fr_profile(fr_mesh m, int32_t enable) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    m->prof.on = enable != 0;
+    m->prof.recs.clear();
+    m->prof.used = 0;
+    return FR_OK;
+}
+
+fr_status fr_profile_read(fr_mesh m, double *total_ms, int64_t *count) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!total_ms || !count) return fail(m, FR_ERR_INVALID_ARG, "null output");
+    for (int c = 0; c < PROF_NCLASS; ++c) {
+        total_ms[c] = 0;
+        count[c] = 0;
+    }
+    Profiler &P = m->prof;
+    for (auto &r : P.recs) {
+        FR_HIP(m, hipEventSynchronize(P.pool[r.second + 1]));
+        float ms = 0;
+        FR_HIP(m, hipEventElapsedTime(&ms, P.pool[r.second], P.pool[r.second + 1]));
+        total_ms[r.first] += ms;
+        count[r.first] += 1;
+    }
+    P.recs.clear();
+    P.used = 0;
     return FR_OK;
 }
 

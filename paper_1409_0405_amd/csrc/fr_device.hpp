@@ -19,9 +19,12 @@ struct Op {
 };
 
 // C[M][ncols] = A[M][K1 + K2] . [B1 (K1 rows); B2 (K2 rows)], row strides
-// ldb1, ldb2, ldc (elements); ncols a multiple of 64.
+// ldb1, ldb2, ldc (elements); ncols a multiple of 64.  tag = 4 * element type +
+// operator (0 interpolation, 1 gradient, 2 gradient interpolation, 3
+// divergence) names the kernel instantiation.
+enum { OP_INTERP = 0, OP_GRAD = 1, OP_GRADINTERP = 2, OP_DIV = 3 };
 template <typename T>
-hipError_t launch_opmul(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
+hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
                         int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s);
 
 // Point-wise work at the solution points of one element type (ETYPE 0 tet,

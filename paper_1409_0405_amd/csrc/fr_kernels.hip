@@ -53,7 +53,9 @@ template <>
 __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r; }
 
 // ---------------------------------------------------------------------------
-// Operator product C = A [B1; B2] on the matrix cores.
+// Operator product C = A [B1; B2] on the matrix cores.  TAG (4 * element type
+// + operator id) only names the instantiation, so that a profiler reports each
+// operator separately.
 //
 // One wavefront owns a 64-column panel of C and MBW row blocks of 16.  The 64
 // columns are split into four interleaved MFMA column blocks: block n holds
@@ -62,7 +64,7 @@ __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r;
 // consecutive columns of one C row with a single vector store.  A is read in
 // fragment order (one coalesced load per MFMA) from L2-resident memory.
 // ---------------------------------------------------------------------------
-template <typename T, int MBW>
+template <typename T, int MBW, int TAG>
 __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict__ B1,
                                                     int64_t ldb1, int K1,
                                                     const T *__restrict__ B2, int64_t ldb2,
@@ -423,22 +425,35 @@ __global__ void copy_kernel(T *dst, const T *src, int64_t n) {
 
 }  // namespace
 
+template <typename T, int TAG>
+hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
+                            int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels, int nmg,
+                            int mbw, hipStream_t s) {
+    const int64_t nwaves = npanels * nmg;
+    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
+    switch (mbw) {
+        case 1: opmul_kernel<T, 1, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        case 2: opmul_kernel<T, 2, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        case 3: opmul_kernel<T, 3, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+        default: opmul_kernel<T, 4, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_opmul(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
+hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
                         int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s) {
     if (ncols % 64) return hipErrorInvalidValue;
     const int64_t npanels = ncols / 64;
     const int nmg = (A.Mb + 3) / 4;
     const int mbw = (A.Mb + nmg - 1) / nmg;
-    const int64_t nwaves = npanels * nmg;
-    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
-    switch (mbw) {
-        case 1: opmul_kernel<T, 1><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        case 2: opmul_kernel<T, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        case 3: opmul_kernel<T, 3><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        default: opmul_kernel<T, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+#define FR_TAG(t) \
+    case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg, mbw, s);
+    switch (tag) {
+        FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+#undef FR_TAG
 }
 
 template <typename T>
@@ -497,8 +512,9 @@ hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s) {
 }
 
 #define FR_INSTANTIATE(T)                                                                     \
-    template hipError_t launch_opmul<T>(const Op<T> &, const T *, int64_t, int, const T *,    \
-                                        int64_t, int, T *, int64_t, int64_t, hipStream_t);    \
+    template hipError_t launch_opmul<T>(int, const Op<T> &, const T *, int64_t, int,          \
+                                        const T *, int64_t, int, T *, int64_t, int64_t,       \
+                                        hipStream_t);                                         \
     template hipError_t launch_upts<T>(int, bool, const UptsArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_solution<T>(const PairArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_flux<T>(bool, const PairArgs<T> &, hipStream_t);        \

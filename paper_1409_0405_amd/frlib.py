@@ -27,7 +27,12 @@ FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
 
 EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coords",
             "fr_operator", "fr_set_solution", "fr_get_solution", "fr_rhs", "fr_rk_step",
-            "fr_reduce", "fr_intermediate", "fr_last_error")
+            "fr_reduce", "fr_intermediate", "fr_profile", "fr_profile_read", "fr_last_error")
+
+PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
+                "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
+                "upts_tet", "upts_pri", "common_solution", "common_flux",
+                "negdivconf_tet", "negdivconf_pri")
 
 
 class FrError(RuntimeError):
@@ -75,6 +80,8 @@ def lib():
         L.fr_rk_step.argtypes = [vp, i32, dbl, i32, vp]
         L.fr_reduce.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
         L.fr_intermediate.argtypes = [vp, i32, i32, vp, vp]
+        L.fr_profile.argtypes = [vp, i32]
+        L.fr_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.fr_last_error.argtypes = [vp]
         L.fr_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -179,6 +186,17 @@ class Mesh:
         out = np.zeros(8)
         _check(lib().fr_reduce(self.h, what, _ptr(out, ctypes.c_double), ctypes.c_void_p(stream)), self.h)
         return out[:2] if what == FR_RED_KE else out[:5]
+
+    def profile(self, enable):
+        _check(lib().fr_profile(self.h, 1 if enable else 0), self.h)
+
+    def profile_read(self):
+        """{class name: (total ms, launches)} of the kernels recorded since
+        profiling was enabled or last read."""
+        ms = np.zeros(len(PROF_CLASSES))
+        cnt = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+        _check(lib().fr_profile_read(self.h, _ptr(ms, ctypes.c_double), _ptr(cnt, ctypes.c_int64)), self.h)
+        return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_CLASSES)}
 
     def intermediate(self, etype, which, dst_ptr, stream=0):
         _check(lib().fr_intermediate(self.h, etype, which, ctypes.c_void_p(dst_ptr),
