@@ -137,19 +137,22 @@ void prof_end(fr_mesh m, size_t i, int cls, hipStream_t s) {
         prof_end(m, pi_, cls, s);              \
     } while (0)
 
-// Fragment order for the MFMA product kernel.
+// Fragment order for the MFMA product kernel (see frd::Op).
 template <typename T>
-std::vector<T> fragment(const std::vector<double> &A, int M, int K, int &Mb, int &Kb) {
-    Mb = (M + 15) / 16;
-    Kb = (K + 3) / 4;
-    std::vector<T> f(size_t(Mb) * Kb * 64, T(0));
+frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f) {
+    frd::Op<T> op;
+    op.M = M;
+    op.Kb = ((K + 3) / 4 + 1) / 2 * 2;   // even number of K steps
+    frd::row_groups(M, sizeof(T) == 4 ? 8 : 4, op.nmg, op.mbw);
+    const int Mb = op.nmg * op.mbw;
+    f.assign(size_t(Mb) * op.Kb * 64, T(0));
     for (int mb = 0; mb < Mb; ++mb)
-        for (int kb = 0; kb < Kb; ++kb)
+        for (int kb = 0; kb < op.Kb; ++kb)
             for (int l = 0; l < 64; ++l) {
                 int r = 16 * mb + (l % 16), c = 4 * kb + l / 16;
-                if (r < M && c < K) f[(size_t(mb) * Kb + kb) * 64 + l] = T(A[size_t(r) * K + c]);
+                if (r < M && c < K) f[(size_t(mb) * op.Kb + kb) * 64 + l] = T(A[size_t(r) * K + c]);
             }
-    return f;
+    return op;
 }
 
 // Folded operators of one reference element:
@@ -230,17 +233,17 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         const size_t ld = size_t(H.ld);
         std::vector<double> grad, div;
         folded_ops(R, grad, div);
-        int Mb, Kb;
         T *p;
-        auto f = fragment<T>(R.M0, nf, nu, Mb, Kb);
+        std::vector<T> f;
+        D.Aint = fragment<T>(R.M0, nf, nu, f);
         FR_TRY(dev_upload(m, d, p, f, s));
-        D.Aint = {p, nf, Mb, Kb};
-        f = fragment<T>(grad, 3 * nu, nu + nf, Mb, Kb);
+        D.Aint.frag = p;
+        D.Agrad = fragment<T>(grad, 3 * nu, nu + nf, f);
         FR_TRY(dev_upload(m, d, p, f, s));
-        D.Agrad = {p, 3 * nu, Mb, Kb};
-        f = fragment<T>(div, nu, 3 * nu + nf, Mb, Kb);
+        D.Agrad.frag = p;
+        D.Adiv = fragment<T>(div, nu, 3 * nu + nf, f);
         FR_TRY(dev_upload(m, d, p, f, s));
-        D.Adiv = {p, nu, Mb, Kb};
+        D.Adiv.frag = p;
 
         const int ng = frh::n_geom(t);
         std::vector<double> g(size_t(ng) * ld, 0.0);

@@ -11,12 +11,22 @@ namespace frd {
 constexpr int NVAR = 5;
 
 // Fragment-ordered operator for the MFMA product kernel: element
-// [mb][kb][lane] holds A[16 mb + lane % 16][4 kb + lane / 16] (zero padded).
+// [mb][kb][lane] holds A[16 mb + lane % 16][4 kb + lane / 16], zero padded to
+// nmg * mbw row blocks of 16 (nmg row groups of mbw blocks, one wavefront per
+// row group and column panel) and to Kb * 4 columns, Kb even.
 template <typename T>
 struct Op {
     const T *frag = nullptr;
-    int M = 0, Mb = 0, Kb = 0;
+    int M = 0, Kb = 0, nmg = 0, mbw = 0;
 };
+
+// Row grouping of an M-row operator: at most `cap` blocks of 16 rows per
+// wavefront, as few groups as possible, blocks spread evenly.
+inline void row_groups(int M, int cap, int &nmg, int &mbw) {
+    const int Mb = (M + 15) / 16;
+    nmg = (Mb + cap - 1) / cap;
+    mbw = (Mb + nmg - 1) / nmg;
+}
 
 // C[M][ncols] = A[M][K1 + K2] . [B1 (K1 rows); B2 (K2 rows)], row strides
 // ldb1, ldb2, ldc (elements); ncols a multiple of 64.  tag = 4 * element type +

@@ -62,7 +62,10 @@ __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r;
 // columns 4 j + n (j = 0..15), so lane l reads the four consecutive columns
 // 4 (l % 16) .. +3 of one B row with a single vector load and writes four
 // consecutive columns of one C row with a single vector store.  A is read in
-// fragment order (one coalesced load per MFMA) from L2-resident memory.
+// fragment order (one coalesced load per MFMA) from L2-resident memory and is
+// zero padded to whole row groups and to an even number of K steps, so the K
+// loop is branch free: rows of B past K are clamped to a real row (finite
+// values times zero columns of A).
 // ---------------------------------------------------------------------------
 template <typename T, int MBW, int TAG>
 __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict__ B1,
@@ -80,6 +83,13 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
     const int64_t col = panel * 64 + 4 * (lane & 15);
     const int krow = lane >> 4;
     const int K = K1 + K2;
+    const int Kb = A.Kb;
+
+    auto bptr = [&](int kb) -> const v4 * {
+        const int k = min(4 * kb + krow, K - 1);
+        const T *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+        return reinterpret_cast<const v4 *>(p + col);
+    };
 
     v4 acc[MBW][4];
 #pragma unroll
@@ -87,29 +97,42 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = v4{0, 0, 0, 0};
 
-    const T *Af = A.frag + size_t(mb0) * A.Kb * 64 + lane;
-#pragma unroll 2
-    for (int kb = 0; kb < A.Kb; ++kb) {
-        const int k = 4 * kb + krow;
-        v4 b = v4{0, 0, 0, 0};
-        if (k < K1)
-            b = *reinterpret_cast<const v4 *>(B1 + int64_t(k) * ldb1 + col);
-        else if (k < K)
-            b = *reinterpret_cast<const v4 *>(B2 + int64_t(k - K1) * ldb2 + col);
+    // Two register sets (even and odd K steps; Kb is even): a set is
+    // reloaded right after its matrix instructions issue, so its loads are
+    // in flight while the other set is multiplied.
+    const T *Af = A.frag + size_t(mb0) * Kb * 64 + lane;
+    T a0[MBW], a1[MBW];
+    v4 b0 = *bptr(0), b1 = *bptr(1);
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+        a0[m] = Af[size_t(m) * Kb * 64];
+        a1[m] = Af[(size_t(m) * Kb + 1) * 64];
+    }
+    for (int kb = 0; kb < Kb; kb += 2) {
 #pragma unroll
         for (int m = 0; m < MBW; ++m) {
-            if (mb0 + m < A.Mb) {
-                const T a = Af[(size_t(m) * A.Kb + kb) * 64];
-                acc[m][0] = mfma16(a, b[0], acc[m][0]);
-                acc[m][1] = mfma16(a, b[1], acc[m][1]);
-                acc[m][2] = mfma16(a, b[2], acc[m][2]);
-                acc[m][3] = mfma16(a, b[3], acc[m][3]);
-            }
+            acc[m][0] = mfma16(a0[m], b0[0], acc[m][0]);
+            acc[m][1] = mfma16(a0[m], b0[1], acc[m][1]);
+            acc[m][2] = mfma16(a0[m], b0[2], acc[m][2]);
+            acc[m][3] = mfma16(a0[m], b0[3], acc[m][3]);
         }
+        const int k2 = min(kb + 2, Kb - 2), k3 = min(kb + 3, Kb - 1);
+        b0 = *bptr(k2);
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) a0[m] = Af[(size_t(m) * Kb + k2) * 64];
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) {
+            acc[m][0] = mfma16(a1[m], b1[0], acc[m][0]);
+            acc[m][1] = mfma16(a1[m], b1[1], acc[m][1]);
+            acc[m][2] = mfma16(a1[m], b1[2], acc[m][2]);
+            acc[m][3] = mfma16(a1[m], b1[3], acc[m][3]);
+        }
+        b1 = *bptr(k3);
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) a1[m] = Af[(size_t(m) * Kb + k3) * 64];
     }
 #pragma unroll
     for (int m = 0; m < MBW; ++m) {
-        if (mb0 + m >= A.Mb) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * (mb0 + m) + acc_row<T>(krow, r);
@@ -427,28 +450,38 @@ __global__ void copy_kernel(T *dst, const T *src, int64_t n) {
 
 template <typename T, int TAG>
 hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
-                            int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels, int nmg,
-                            int mbw, hipStream_t s) {
+                            int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels,
+                            hipStream_t s) {
+    const int nmg = A.nmg, mbw = A.mbw;
     const int64_t nwaves = npanels * nmg;
     const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
-    switch (mbw) {
-        case 1: opmul_kernel<T, 1, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        case 2: opmul_kernel<T, 2, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        case 3: opmul_kernel<T, 3, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
-        default: opmul_kernel<T, 4, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); break;
+#define FR_MBW(w)                                                                             \
+    case w:                                                                                   \
+        opmul_kernel<T, w, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
+                                                       npanels, nmg);                         \
+        break;
+    if (sizeof(T) == 4) {
+        switch (mbw) {
+            FR_MBW(1) FR_MBW(2) FR_MBW(3) FR_MBW(4) FR_MBW(5) FR_MBW(6) FR_MBW(7) FR_MBW(8)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (mbw) {
+            FR_MBW(1) FR_MBW(2) FR_MBW(3) FR_MBW(4)
+            default: return hipErrorInvalidValue;
+        }
     }
+#undef FR_MBW
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
                         int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s) {
-    if (ncols % 64) return hipErrorInvalidValue;
+    if (ncols % 64 || K1 + K2 <= 0 || A.nmg * A.mbw * 16 < A.M) return hipErrorInvalidValue;
     const int64_t npanels = ncols / 64;
-    const int nmg = (A.Mb + 3) / 4;
-    const int mbw = (A.Mb + nmg - 1) / nmg;
 #define FR_TAG(t) \
-    case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg, mbw, s);
+    case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, s);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
         default: return hipErrorInvalidValue;
