@@ -13,8 +13,10 @@ The reported value is GDOF/s per right-hand-side evaluation:
 
 Also reported: the roofline of the dominant kernel (per-kernel HIP event
 timing on the library's stream, in a separate instrumented pass over the same
-steps) and the FP64 oracle's throughput on a bounded sample of the same
-workload on the host CPU.
+steps), the FP64 oracle's throughput on a bounded sample of the same
+workload on the host CPU, and the split-precision forms (16-bit matrix-core
+operator products) with their speedup over FP32 and the relative L2 error of
+their right-hand side against the FP64 build of the same kernels.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -103,6 +105,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,20 +121,22 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    t_setup = time.perf_counter()
-    arrays = inputs.tgv_mixed_box()
     mu, mach, pr, p = 1.0 / 1600.0, 0.1, 0.71, 4
-    mesh = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=mu, prandtl=pr,
-                      stream=stream)
-    dof = 0
+    arrays = inputs.tgv_mixed_box()
+
+    def make_mesh(precision):
+        return frlib.Mesh(arrays, p, system="ns", precision=precision, mu=mu, prandtl=pr,
+                          stream=stream)
+
+    t_setup = time.perf_counter()
+    mesh = make_mesh("fp32")
+    host_state, dof = [], 0
     for t in (0, 1):
         q = mesh.query(t)
         x = mesh.upts_coords(t)                                        # [nu][3][E]
         U = inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=mach)  # [5][nu][E]
-        u = frlib.to_device_state(mesh, t, np.transpose(U, (1, 0, 2)))
-        mesh.set_solution(t, u.data_ptr(), stream)
+        host_state.append(np.transpose(U, (1, 0, 2)).astype(np.float32))
         dof += q["nupts"] * q["nelem"] * 5
-        del u
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     print(f"setup {t_setup:.1f} s, {dof} DOF", file=sys.stderr, flush=True)
@@ -140,40 +145,55 @@ def main():
     lam = 1.0 + 1.0 / mach                # V0 + c0
     dt = args.cfl * h_ref / (lam * (2 * p + 1))
 
-    def step():
-        mesh.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
-        return mesh.reduce(frlib.FR_RED_INT_U, stream)   # FP64, synchronising
+    def load(m):
+        for t in (0, 1):
+            u = frlib.to_device_state(m, t, host_state[t])
+            m.set_solution(t, u.data_ptr(), stream)
+            torch.cuda.synchronize()
+            del u
 
-    I0 = step()
-    for _ in range(max(args.warmup - 1, 0)):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        I1 = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_per_step = 1e3 * el / args.steps
-    value = 5.0 * dof * args.steps / el / 1e9
-    drift = float(np.max(np.abs(I1 - I0)[[0, 4]] / np.abs(I0)[[0, 4]]))
-    finite = bool(np.all(np.isfinite(I1)))
-    print(f"{ms_per_step:.3f} ms/step, {value:.2f} GDOF/s per RHS, mass/energy drift {drift:.2e}",
+    def timed(m, steps, warmup):
+        """RK45[2R+] steps plus the FP64 conservation integral, timed."""
+        load(m)
+
+        def step():
+            m.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
+            return m.reduce(frlib.FR_RED_INT_U, stream)   # FP64, synchronising
+        i0 = step()
+        for _ in range(max(warmup - 1, 0)):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            i1 = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        drift = float(np.max(np.abs(i1 - i0)[[0, 4]] / np.abs(i0)[[0, 4]]))
+        return 1e3 * el / steps, 5.0 * dof * steps / el / 1e9, drift, bool(np.all(np.isfinite(i1)))
+
+    def rhs_of(m):
+        u = [frlib.to_device_state(m, t, host_state[t]) for t in (0, 1)]
+        r = [frlib.state_tensor(m, t) for t in (0, 1)]
+        m.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r], stream)
+        torch.cuda.synchronize()
+        out = [x.double() for x in r]
+        del u, r
+        return out
+
+    ms_per_step, value, drift, finite = timed(mesh, args.steps, args.warmup)
+    print(f"fp32: {ms_per_step:.3f} ms/step, {value:.2f} GDOF/s per RHS, mass/energy drift {drift:.2e}",
           file=sys.stderr, flush=True)
-
     roof = None
     if not args.no_profile:
         nprof = max(3, min(args.steps, 10))
+        load(mesh)
         mesh.profile(True)
         for _ in range(nprof):
             mesh.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
         prof = mesh.profile_read()
         mesh.profile(False)
         model = kernel_model(mesh, "ns")
-        rows = []
-        for k, (ms, cnt) in prof.items():
-            if cnt:
-                rows.append((ms, k, cnt))
-        rows.sort(reverse=True)
+        rows = sorted(((ms, k, cnt) for k, (ms, cnt) in prof.items() if cnt), reverse=True)
         tot = sum(r[0] for r in rows)
         for ms, k, cnt in rows:
             avg = ms / cnt * 1e-3
@@ -196,6 +216,42 @@ def main():
         roof["avg_launch_us"] = avg * 1e6
         roof["share_of_step"] = ms / tot
 
+    forms = None
+    if not args.no_forms:
+        # accuracy of each precision on this workload: RHS of the same FP32
+        # input against the FP64 build of the same kernels
+        ref64 = make_mesh("fp64")
+        R64 = rhs_of(ref64)
+        ref64.close()
+        del ref64
+        torch.cuda.empty_cache()
+
+        def rel_err(R):
+            num = np.zeros(5)
+            den = np.zeros(5)
+            for t in (0, 1):
+                ne = mesh.query(t)["nelem"]
+                d = (R[t][:, :, :ne] - R64[t][:, :, :ne])
+                num += (d ** 2).sum(dim=(0, 2)).cpu().numpy()
+                den += (R64[t][:, :, :ne] ** 2).sum(dim=(0, 2)).cpu().numpy()
+            den[1:4] = den[1:4].sum()
+            return [float(x) for x in np.sqrt(num / den)]
+        forms = {"fp32": {"value": value, "ms_per_step": ms_per_step,
+                          "rhs_rel_l2_vs_fp64": rel_err(rhs_of(mesh))}}
+        for prec in ("split_bf16", "split_fp16"):
+            m2 = make_mesh(prec)
+            ms2, v2, d2, f2 = timed(m2, args.steps, args.warmup)
+            forms[prec] = {"value": v2, "ms_per_step": ms2, "speedup_vs_fp32": v2 / value,
+                           "rhs_rel_l2_vs_fp64": rel_err(rhs_of(m2)), "finite": f2,
+                           "mass_energy_drift": d2}
+            print(f"{prec}: {ms2:.3f} ms/step, {v2:.2f} GDOF/s per RHS "
+                  f"(x{v2 / value:.2f}), rhs error {forms[prec]['rhs_rel_l2_vs_fp64']}",
+                  file=sys.stderr, flush=True)
+            m2.close()
+            del m2
+            torch.cuda.empty_cache()
+        print(f"fp32 rhs error {forms['fp32']['rhs_rel_l2_vs_fp64']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -209,7 +265,7 @@ def main():
                                "110592 prisms + 196608 tets, RK45[2R+] steps",
                    "n_dof": dof, "rhs_per_step": 5, "dt": dt, "parallelism": "single GPU",
                    "finite": finite, "mass_energy_drift": drift},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "forms": forms,
     }
     print(json.dumps(out), flush=True)
 

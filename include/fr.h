@@ -18,8 +18,8 @@
  * ---------------------------------------
  * Element types: FR_TET = 0, FR_PRI = 1.  Global element ids are type-major
  * (tets first).  Solution state per type is a device array laid out
- * [n_upts][5][ld] of the mesh's scalar type (float for FR_FP32, double for
- * FR_FP64): point-major, then the conserved field (rho, rho u, rho v, rho w,
+ * [n_upts][5][ld] of the mesh's scalar type (double for FR_FP64, float for
+ * every other precision): point-major, then the conserved field (rho, rho u, rho v, rho w,
  * E), then the element index, fastest; ld >= n_elem is a multiple of 64 and
  * is reported by fr_mesh_query.  Columns n_elem..ld-1 are padding: they are
  * read and written but never mix with real elements.
@@ -60,7 +60,12 @@ typedef enum {
 
 typedef enum { FR_TET = 0, FR_PRI = 1 } fr_etype;
 typedef enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 } fr_system;
-typedef enum { FR_FP32 = 0, FR_FP64 = 1 } fr_precision;
+/* FR_SPLIT_BF16 / FR_SPLIT_FP16: FP32 state and point-wise arithmetic; the
+ * operator products run on the 16-bit matrix cores with both operands split
+ * into 16-bit parts and FP32 accumulation: BF16 three parts (six products,
+ * ~24-bit operands), FP16 two parts (three products, ~22-bit operands; the
+ * state must stay below 65504 in magnitude). */
+typedef enum { FR_FP32 = 0, FR_FP64 = 1, FR_SPLIT_BF16 = 2, FR_SPLIT_FP16 = 3 } fr_precision;
 typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
 
 /* fr_mesh_desc.flags */
@@ -74,7 +79,8 @@ typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
  *
  * order      polynomial order p of the solution, 1..4 on the GPU (Table 2).
  * system     FR_EULER or FR_NAVIER_STOKES (Section 3.4, Table 1).
- * precision  scalar type of the state and of the device arithmetic.
+ * precision  scalar type of the state and of the device arithmetic (the split
+ *            forms keep an FP32 state).
  * gamma      ratio of specific heats; mu dynamic viscosity (ignored for
  *            Euler); prandtl Prandtl number; ldg_beta, ldg_tau the LDG switch
  *            and penalty of the viscous interface flux.

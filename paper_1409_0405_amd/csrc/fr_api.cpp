@@ -21,6 +21,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fr.h"
@@ -40,6 +41,7 @@ struct DevType {
     int nu = 0, nf = 0;
     int64_t nelem = 0, ld = 0;
     frd::Op<T> Aint, Agrad, Adiv;
+    frd::OpSplit Sint, Sgrad, Sdiv;   // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
     T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
     T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
@@ -155,6 +157,68 @@ frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &
     return op;
 }
 
+// 16-bit parts of an operator for the split-precision product kernel (see
+// frd::OpSplit), each rounded to nearest even: BF16 (format 1) h, m, l with
+// A = h + m + l to ~24 bits; FP16 (format 2) h = round(A),
+// l = round((A - h) 2^11).
+uint16_t to_bf16(double x) {
+    float f = float(x);
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return uint16_t(b >> 16);
+}
+double from_bf16(uint16_t h) {
+    uint32_t b = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+uint16_t to_f16(double x) {
+    _Float16 h = _Float16(float(x));
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+double from_f16(uint16_t u) {
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return double(float(h));
+}
+
+frd::OpSplit fragment_split(const std::vector<double> &A, int M, int K, int format,
+                            std::vector<uint16_t> parts[3]) {
+    frd::OpSplit op;
+    op.M = M;
+    op.format = format;
+    op.Kb = ((K + 31) / 32 + 1) / 2 * 2;
+    frd::row_groups(M, format == 2 ? 2 : 4, op.nmg, op.mbw);
+    const int np = format == 2 ? 2 : 3;
+    const double scale = format == 2 ? 2048.0 : 1.0;
+    op.inv_scale = float(1.0 / scale);
+    const int Mb = op.nmg * op.mbw;
+    for (int q = 0; q < 3; ++q) parts[q].assign(q < np ? size_t(Mb) * op.Kb * 64 * 8 : 0, 0);
+    for (int mb = 0; mb < Mb; ++mb)
+        for (int kb = 0; kb < op.Kb; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 8; ++j) {
+                    const int r = 16 * mb + l % 16, c = 32 * kb + 8 * (l / 16) + j;
+                    if (r >= M || c >= K) continue;
+                    double rem = A[size_t(r) * K + c];
+                    const size_t o = ((size_t(mb) * op.Kb + kb) * 64 + l) * 8 + j;
+                    if (format == 2) {
+                        parts[0][o] = to_f16(rem);
+                        parts[1][o] = to_f16((rem - from_f16(parts[0][o])) * scale);
+                    } else {
+                        for (int q = 0; q < 3; ++q) {
+                            parts[q][o] = to_bf16(rem);
+                            rem -= from_bf16(parts[q][o]);
+                        }
+                    }
+                }
+    return op;
+}
+
 // Folded operators of one reference element:
 //   grad: rows (k, i): [G_k - L_k M0 | L_k]               (3 nu) x (nu + nf)
 //   div:  row i: [G_0 - L_0 M0, G_1 - L_1 M0, G_2 - L_2 M0 | L]  nu x (3 nu + nf)
@@ -244,6 +308,25 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         D.Adiv = fragment<T>(div, nu, 3 * nu + nf, f);
         FR_TRY(dev_upload(m, d, p, f, s));
         D.Adiv.frag = p;
+        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
+            const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
+            std::vector<uint16_t> parts[3];
+            auto up = [&](frd::OpSplit op, frd::OpSplit &dst) -> fr_status {
+                for (int q = 0; q < 3; ++q) {
+                    if (parts[q].empty()) continue;
+                    void *ptr;
+                    FR_HIP(m, hipMalloc(&ptr, parts[q].size() * 2));
+                    d.allocs.push_back(ptr);
+                    FR_HIP(m, hipMemcpy(ptr, parts[q].data(), parts[q].size() * 2, hipMemcpyHostToDevice));
+                    op.part[q] = static_cast<uint16_t *>(ptr);
+                }
+                dst = op;
+                return FR_OK;
+            };
+            FR_TRY(up(fragment_split(R.M0, nf, nu, fmt, parts), D.Sint));
+            FR_TRY(up(fragment_split(grad, 3 * nu, nu + nf, fmt, parts), D.Sgrad));
+            FR_TRY(up(fragment_split(div, nu, 3 * nu + nf, fmt, parts), D.Sdiv));
+        }
 
         const int ng = frh::n_geom(t);
         std::vector<double> g(size_t(ng) * ld, 0.0);
@@ -340,6 +423,18 @@ struct StageOut {
     T a = 0, b = 1;
 };
 
+// Operator product through the kernel of the mesh's precision.
+template <typename T>
+hipError_t opmul(fr_mesh m, int tag, const frd::Op<T> &A, const frd::OpSplit &S, const T *B1,
+                 int64_t ldb1, int K1, const T *B2, int64_t ldb2, int K2, T *C, int64_t ldc,
+                 int64_t ncols, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16)
+            return frd::launch_opmul_split(tag, S, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s);
+    }
+    return frd::launch_opmul<T>(tag, A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s);
+}
+
 template <typename T>
 fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
@@ -350,7 +445,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
         FR_LAUNCH(m, 4 * t + frd::OP_INTERP, s,
-                  frd::launch_opmul<T>(4 * t + frd::OP_INTERP, D.Aint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
+                  opmul<T>(m, 4 * t + frd::OP_INTERP, D.Aint, D.Sint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
     }
     frd::PairArgs<T> pa{};
     pa.sideL = d.sideL;
@@ -376,7 +471,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
             if (!D.nelem) continue;
             const int64_t w5 = 5 * D.ld;
             FR_LAUNCH(m, 4 * t + frd::OP_GRAD, s,
-                      frd::launch_opmul<T>(4 * t + frd::OP_GRAD, D.Agrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
+                      opmul<T>(m, 4 * t + frd::OP_GRAD, D.Agrad, D.Sgrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
         }
     }
     for (int t = 0; t < 2; ++t) {
@@ -387,7 +482,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         if (ns) {
             const int64_t w15 = 15 * D.ld;
             FR_LAUNCH(m, 4 * t + frd::OP_GRADINTERP, s,
-                      frd::launch_opmul<T>(4 * t + frd::OP_GRADINTERP, D.Aint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
+                      opmul<T>(m, 4 * t + frd::OP_GRADINTERP, D.Aint, D.Sint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
         }
     }
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
@@ -396,7 +491,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
         FR_LAUNCH(m, 4 * t + frd::OP_DIV, s,
-                  frd::launch_opmul<T>(4 * t + frd::OP_DIV, D.Adiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
+                  opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.geom, D.xi, D.ld, D.nelem, D.nu};
         FR_LAUNCH(m, 12 + t, s, frd::launch_negdivconf<T>(t, na, s));
@@ -561,7 +656,7 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
         return fail(nullptr, FR_ERR_UNSUPPORTED, "order must be 1..4");
     if (desc->system != FR_EULER && desc->system != FR_NAVIER_STOKES)
         return fail(nullptr, FR_ERR_INVALID_ARG, "unknown system");
-    if (desc->precision != FR_FP32 && desc->precision != FR_FP64)
+    if (desc->precision < FR_FP32 || desc->precision > FR_SPLIT_FP16)
         return fail(nullptr, FR_ERR_UNSUPPORTED, "unsupported precision");
     if (desc->n_vertices <= 0 || !desc->xyz || desc->n_tets < 0 || desc->n_prisms < 0 ||
         (desc->n_tets && !desc->tet_v) || (desc->n_prisms && !desc->pri_v) ||
@@ -592,7 +687,7 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
     if (!(desc->flags & FR_VALIDATE_ONLY)) {
         hipStream_t s = static_cast<hipStream_t>(stream);
         m->create_stream = s;
-        fr_status st = m->precision == FR_FP32 ? setup_device<float>(m.get(), s)
+        fr_status st = m->precision != FR_FP64 ? setup_device<float>(m.get(), s)
                                                : setup_device<double>(m.get(), s);
         if (st) {
             g_create_error = m->err;
@@ -662,7 +757,7 @@ fr_status fr_set_solution(fr_mesh m, int32_t etype, const void *u, void *stream)
     if (fr_status st = check_mesh(m, etype, true)) return st;
     if (!u && m->host.t[etype].nelem) return fail(m, FR_ERR_INVALID_ARG, "null state");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision == FR_FP32 ? copy_state<float>(m, etype, nullptr, u, true, s)
+    return m->precision != FR_FP64 ? copy_state<float>(m, etype, nullptr, u, true, s)
                                    : copy_state<double>(m, etype, nullptr, u, true, s);
 }
 
@@ -670,21 +765,21 @@ fr_status fr_get_solution(fr_mesh m, int32_t etype, void *u, void *stream) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
     if (!u && m->host.t[etype].nelem) return fail(m, FR_ERR_INVALID_ARG, "null state");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision == FR_FP32 ? copy_state<float>(m, etype, u, nullptr, false, s)
+    return m->precision != FR_FP64 ? copy_state<float>(m, etype, u, nullptr, false, s)
                                    : copy_state<double>(m, etype, u, nullptr, false, s);
 }
 
 fr_status fr_rhs(fr_mesh m, const void *const u[2], void *const r[2], void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision == FR_FP32 ? rhs_entry<float>(m, u, r, s) : rhs_entry<double>(m, u, r, s);
+    return m->precision != FR_FP64 ? rhs_entry<float>(m, u, r, s) : rhs_entry<double>(m, u, r, s);
 }
 
 fr_status fr_rk_step(fr_mesh m, int32_t scheme, double dt, int32_t n_steps, void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     if (n_steps < 0 || !std::isfinite(dt)) return fail(m, FR_ERR_INVALID_ARG, "bad step count or dt");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision == FR_FP32 ? rk_impl<float>(m, scheme, dt, n_steps, s)
+    return m->precision != FR_FP64 ? rk_impl<float>(m, scheme, dt, n_steps, s)
                                    : rk_impl<double>(m, scheme, dt, n_steps, s);
 }
 
@@ -692,7 +787,7 @@ fr_status fr_reduce(fr_mesh m, int32_t what, double *out, void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     if (!out || what < 1 || what > 4) return fail(m, FR_ERR_INVALID_ARG, "bad reduction request");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision == FR_FP32 ? reduce_impl<float>(m, what, out, s)
+    return m->precision != FR_FP64 ? reduce_impl<float>(m, what, out, s)
                                    : reduce_impl<double>(m, what, out, s);
 }
 
@@ -705,10 +800,10 @@ fr_status fr_intermediate(fr_mesh m, int32_t etype, int32_t which, void *dst, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     const frh::TypeHost &H = m->host.t[etype];
     if (!H.nelem) return FR_OK;
-    const size_t esz = m->precision == FR_FP32 ? 4 : 8;
+    const size_t esz = m->precision != FR_FP64 ? 4 : 8;
     const size_t n = size_t(H.ops.nf) * (which == 2 ? 15 : 5) * H.ld * esz;
     const void *src;
-    if (m->precision == FR_FP32) {
+    if (m->precision != FR_FP64) {
         auto &D = dev_of<float>(m).t[etype];
         src = which == 0 ? (void *)D.Uf : which == 1 ? (void *)D.Fn : (void *)D.Qf;
     } else {

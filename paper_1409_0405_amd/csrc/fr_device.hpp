@@ -37,6 +37,23 @@ template <typename T>
 hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
                         int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s);
 
+// Split-precision operator for the 16-bit MFMA product kernel.  BF16
+// (format 1): A = h + m + l, three parts; FP16 (format 2): A = h + l / 2^11,
+// two parts.  Fragment element [mb][kb][lane][j] of each part =
+// part[16 mb + lane % 16][32 kb + 8 (lane / 16) + j], zero padded to
+// nmg * mbw row blocks and Kb (even) steps of 32 columns.
+struct OpSplit {
+    const uint16_t *part[3] = {nullptr, nullptr, nullptr};
+    int M = 0, Kb = 0, nmg = 0, mbw = 0, format = 1;
+    float inv_scale = 1.0f;
+};
+// C = A [B1; B2] with the FP32 state B split on the fly into 16-bit parts
+// like A, products of the leading part pairs on the matrix cores, FP32
+// accumulation (six products for BF16, three for FP16).
+hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_t ldb1, int K1,
+                              const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
+                              int64_t ncols, hipStream_t s);
+
 // Point-wise work at the solution points of one element type (ETYPE 0 tet,
 // 1 prism): physical gradient Q from the reference gradient Qt (NS) and the
 // transformed flux Ft = adj (F_inv - F_vis).

@@ -145,6 +145,160 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Split-precision operator product (16-bit matrix cores, FP32 accumulate).
+//
+// Same panel / row-group decomposition as opmul_kernel, with the 16x16x32
+// BF16 or FP16 instruction: lane l holds row l % 16 of A and column l % 16 of
+// a B block with the eight K values 8 (l / 16) .. +7.  Each lane loads eight
+// consecutive B rows of its four interleaved columns (eight 16-byte loads)
+// and splits every value on the fly:
+//  * BF16, three parts (x = h + m + l, each a truncation of the remainder,
+//    exact up to the last bits of FP32): six products h.h + h.m + m.h +
+//    h.l + m.m + l.h, one accumulator (BF16 has the FP32 exponent range);
+//  * FP16, two parts (h = x rounded toward zero, l = (x - h) 2^11): three
+//    products h.h + (h.l + l.h) / 2^11, the scaled terms in a second
+//    accumulator against FP16 underflow.
+// A is split on the host the same way (rounded to nearest).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+
+template <bool F16>
+__device__ __forceinline__ floatx4 mfma16x32(uintx4 a, uintx4 b, floatx4 c) {
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned hi16x2(float x0, float x1) {
+    return (__builtin_bit_cast(unsigned, x0) >> 16) |
+           (__builtin_bit_cast(unsigned, x1) & 0xffff0000u);
+}
+__device__ __forceinline__ float trunc16(float x) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) & 0xffff0000u);
+}
+
+// Parts of two values, packed two per 32-bit word: p[0] = h, p[1] = m or l, p[2] = l.
+template <bool F16>
+__device__ __forceinline__ void split2(float x0, float x1, unsigned p[F16 ? 2 : 3]) {
+    if constexpr (F16) {
+        typedef __fp16 half2v __attribute__((ext_vector_type(2)));
+        const half2v h = __builtin_amdgcn_cvt_pkrtz(x0, x1);
+        const float l0 = (x0 - float(h[0])) * 2048.0f, l1 = (x1 - float(h[1])) * 2048.0f;
+        p[0] = __builtin_bit_cast(unsigned, h);
+        p[1] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(l0, l1));
+    } else {
+        const float r0 = x0 - trunc16(x0), r1 = x1 - trunc16(x1);
+        const float q0 = r0 - trunc16(r0), q1 = r1 - trunc16(r1);
+        p[0] = hi16x2(x0, x1);
+        p[1] = hi16x2(r0, r1);
+        p[2] = hi16x2(q0, q1);
+    }
+}
+
+template <int MBW, bool F16, int TAG>
+__global__ __launch_bounds__(256) void opmul_split_kernel(OpSplit A, const float *__restrict__ B1,
+                                                          int64_t ldb1, int K1,
+                                                          const float *__restrict__ B2,
+                                                          int64_t ldb2, int K2,
+                                                          float *__restrict__ C, int64_t ldc,
+                                                          int64_t npanels, int nmg) {
+    constexpr int NP = F16 ? 2 : 3;       // parts per operand
+    constexpr int NACC = F16 ? 2 : 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t panel = wid / nmg;
+    const int mg = int(wid - panel * nmg);
+    if (panel >= npanels) return;
+    const int mb0 = mg * MBW;
+    const int64_t col = panel * 64 + 4 * (lane & 15);
+    const int g = lane >> 4;
+    const int K = K1 + K2;
+    const int Kb = A.Kb;
+
+    auto row = [&](int k) -> floatx4 {
+        k = min(k, K - 1);
+        const float *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+        return *reinterpret_cast<const floatx4 *>(p + col);
+    };
+
+    floatx4 acc[NACC][MBW][4];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c)
+#pragma unroll
+        for (int m = 0; m < MBW; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[c][m][n] = floatx4{0, 0, 0, 0};
+
+    const uintx4 *Ap[3];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+        Ap[q] = reinterpret_cast<const uintx4 *>(A.part[q]) + size_t(mb0) * Kb * 64 + lane;
+
+    // One register set of B rows: it is split into 16-bit parts, then
+    // refilled with the next K step while the matrix instructions run.
+    floatx4 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = row(8 * g + j);
+    for (int kb = 0; kb < Kb; ++kb) {
+        uintx4 b[NP][4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                unsigned pp[NP];
+                split2<F16>(x[2 * q][n], x[2 * q + 1][n], pp);
+#pragma unroll
+                for (int t = 0; t < NP; ++t) b[t][n][q] = pp[t];
+            }
+        const int kn = 32 * min(kb + 1, Kb - 1) + 8 * g;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = row(kn + j);
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) {
+            uintx4 a[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) a[q] = Ap[q][(size_t(m) * Kb + kb) * 64];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                if constexpr (F16) {
+                    acc[0][m][n] = mfma16x32<F16>(a[0], b[0][n], acc[0][m][n]);
+                    acc[1][m][n] = mfma16x32<F16>(a[0], b[1][n], acc[1][m][n]);
+                    acc[1][m][n] = mfma16x32<F16>(a[1], b[0][n], acc[1][m][n]);
+                } else {
+                    // smallest terms first
+                    floatx4 t = mfma16x32<F16>(a[0], b[2][n], acc[0][m][n]);
+                    t = mfma16x32<F16>(a[1], b[1][n], t);
+                    t = mfma16x32<F16>(a[2], b[0][n], t);
+                    t = mfma16x32<F16>(a[0], b[1][n], t);
+                    t = mfma16x32<F16>(a[1], b[0][n], t);
+                    acc[0][m][n] = mfma16x32<F16>(a[0], b[0][n], t);
+                }
+            }
+        }
+    }
+    const float is = A.inv_scale;
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rw = 16 * (mb0 + m) + 4 * g + r;
+            if (rw < A.M) {
+                floatx4 out;
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    out[n] = NACC == 2 ? acc[0][m][n][r] + acc[NACC - 1][m][n][r] * is : acc[0][m][n][r];
+                *reinterpret_cast<floatx4 *>(C + int64_t(rw) * ldc + col) = out;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Geometry at a solution point from the Jacobian coefficients.
 // Tet: constant columns c0..c2.  Prism: dx/dxi = A1 + C1 z,
 // dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.
@@ -482,6 +636,42 @@ hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int 
     const int64_t npanels = ncols / 64;
 #define FR_TAG(t) \
     case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, s);
+    switch (tag) {
+        FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
+        default: return hipErrorInvalidValue;
+    }
+#undef FR_TAG
+}
+
+template <bool F16, int TAG>
+hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int K1,
+                            const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
+                            int64_t npanels, hipStream_t s) {
+    const int64_t nwaves = npanels * A.nmg;
+    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
+#define FR_MBW(w)                                                                           \
+    case w:                                                                                 \
+        opmul_split_kernel<w, F16, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, \
+                                                               C, ldc, npanels, A.nmg);      \
+        break;
+    switch (A.mbw) {
+        FR_MBW(1) FR_MBW(2) FR_MBW(3) FR_MBW(4)
+        default: return hipErrorInvalidValue;
+    }
+#undef FR_MBW
+    return hipGetLastError();
+}
+
+hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_t ldb1, int K1,
+                              const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
+                              int64_t ncols, hipStream_t s) {
+    if (ncols % 64 || K1 + K2 <= 0 || A.nmg * A.mbw * 16 < A.M || (A.Kb & 1))
+        return hipErrorInvalidValue;
+    const int64_t np = ncols / 64;
+#define FR_TAG(t)                                                                            \
+    case t:                                                                                  \
+        return A.format == 2 ? launch_split_tag<true, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s) \
+                             : launch_split_tag<false, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
         default: return hipErrorInvalidValue;

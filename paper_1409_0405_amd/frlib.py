@@ -20,7 +20,9 @@ FR_OK, FR_ERR_INVALID_ARG, FR_ERR_BAD_MESH, FR_ERR_UNSUPPORTED = 0, 1, 2, 3
 FR_ERR_OUT_OF_MEMORY, FR_ERR_DEVICE, FR_ERR_NONFINITE = 4, 5, 6
 FR_TET, FR_PRI = 0, 1
 FR_EULER, FR_NAVIER_STOKES = 0, 1
-FR_FP32, FR_FP64 = 0, 1
+FR_FP32, FR_FP64, FR_SPLIT_BF16, FR_SPLIT_FP16 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FR_FP32, "fp64": FR_FP64, "split_bf16": FR_SPLIT_BF16,
+              "split_fp16": FR_SPLIT_FP16}
 FR_RK4, FR_RK45_2RP, FR_FWD_EULER = 0, 1, 2
 FR_VALIDATE_ONLY, FR_CHECK_FINITE = 0x1, 0x2
 FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
@@ -111,7 +113,7 @@ class Mesh:
         d = fr_mesh_desc()
         d.order = order
         d.system = {"euler": FR_EULER, "ns": FR_NAVIER_STOKES}[system]
-        d.precision = {"fp32": FR_FP32, "fp64": FR_FP64}[precision]
+        d.precision = PRECISIONS[precision]
         d.flags = (FR_VALIDATE_ONLY if validate_only else 0) | (FR_CHECK_FINITE if check_finite else 0)
         d.gamma, d.mu, d.prandtl, d.ldg_beta, d.ldg_tau = gamma, mu, prandtl, ldg_beta, ldg_tau
         xyz = np.ascontiguousarray(mesh_arrays["xyz"], dtype=np.float64)
@@ -134,7 +136,7 @@ class Mesh:
         _check(lib().fr_mesh_create(ctypes.byref(d), ctypes.c_void_p(stream), ctypes.byref(h)))
         self.h = h
         self.order, self.system, self.precision = order, system, precision
-        self.dtype = np.float32 if precision == "fp32" else np.float64
+        self.dtype = np.float64 if precision == "fp64" else np.float32
 
     def close(self):
         if getattr(self, "h", None):
@@ -211,7 +213,7 @@ def state_tensor(mesh: Mesh, etype, device="cuda"):
     """Zeroed device state [n_upts][5][ld] of the mesh's dtype."""
     import torch
     q = mesh.query(etype)
-    dt = torch.float32 if mesh.precision == "fp32" else torch.float64
+    dt = torch.float64 if mesh.precision == "fp64" else torch.float32
     return torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=dt, device=device)
 
 

@@ -1,0 +1,87 @@
+"""GPU parity of the split-precision forms: operator products on the 16-bit
+matrix cores with hi + lo split operands and FP32 accumulation.
+
+Bounds (relative L2 per conserved field against the FP64 oracle):
+* split-BF16 right-hand side: 1e-4 (the stated target of the form);
+* split-FP16 right-hand side: 1e-4 as well;
+  (BF16 splits into three parts, FP16 into two: both carry >= 22 bits, and
+  the residual's cancellation factor of ~1e2 leaves errors ~1e-5);
+* after 20 RK45[2R+] steps of the NS Taylor-Green state, the split solution
+  stays within 1e-5 of the oracle's solution (state errors are far smaller
+  than residual errors: dt R is a small update of O(1) fields)."""
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as om, rk
+from paper_1409_0405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ("tet", "pri")
+
+
+def _setup(p, mach=0.3, seed=3):
+    arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=0)
+    O = om.build_mesh(arrays, p)
+    U = fr.initial_state(O, inputs.taylor_green, mach=mach)
+    for n in U:
+        U[n] = (U[n] * inputs.random_perturbation(U[n].shape, seed, 0.01)).astype(np.float32).astype(np.float64)
+    return arrays, O, U
+
+
+def _rhs(M, O, U):
+    from paper_1409_0405_amd import frlib
+    u = [frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))) for t in (0, 1)]
+    r = [frlib.state_tensor(M, t) for t in (0, 1)]
+    M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r])
+    torch.cuda.synchronize()
+    return {NAMES[t]: np.transpose(r[t][:, :, :O.types[NAMES[t]].nelem].cpu().numpy().astype(np.float64),
+                                   (2, 0, 1)) for t in (0, 1)}
+
+
+def _err(G, R):
+    """Per-field relative L2; the three momentum components are normalised by
+    the momentum magnitude (a component can be near zero everywhere)."""
+    num = sum(((G[n] - R[n]) ** 2).sum(axis=(0, 1)) for n in R)
+    den = sum((R[n] ** 2).sum(axis=(0, 1)) for n in R)
+    den[1:4] = den[1:4].sum()
+    return np.sqrt(num / den)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("p,system", [(1, "ns"), (2, "euler"), (3, "ns"), (4, "ns")])
+def test_split_rhs_parity(prec, p, system):
+    from paper_1409_0405_amd import frlib
+    print(f"{prec} p{p} {system}", flush=True)
+    arrays, O, U = _setup(p)
+    prm = fr.Params(system=system, mu=0.02)
+    Ro = fr.rhs(O, U, prm)
+    M = frlib.Mesh(arrays, p, system=system, precision=prec, mu=0.02)
+    err = _err(_rhs(M, O, U), Ro)
+    print("  field errors", err, flush=True)
+    assert (err < 1e-4).all(), err
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_rk45_steps(prec):
+    """20 RK45[2R+] steps, NS Taylor-Green (Ma 0.3), p = 3."""
+    from paper_1409_0405_amd import frlib
+    p, nsteps, mu = 3, 20, 0.02
+    arrays, O, U0 = _setup(p, seed=8)
+    prm = fr.Params(system="ns", mu=mu)
+    dt = 0.3 * (2 * np.pi / 4 / 3) / ((1 + 1 / 0.3) * (2 * p + 1))
+    Uo = rk.run(rk.rk45_step, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
+    M = frlib.Mesh(arrays, p, system="ns", precision=prec, mu=mu, check_finite=True)
+    for t, n in enumerate(NAMES):
+        M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U0[n], (1, 2, 0))).data_ptr())
+    M.rk_step(frlib.FR_RK45_2RP, dt, nsteps)
+    G = {}
+    for t, n in enumerate(NAMES):
+        out = frlib.state_tensor(M, t)
+        M.get_solution(t, out.data_ptr())
+        torch.cuda.synchronize()
+        G[n] = np.transpose(out[:, :, :O.types[n].nelem].cpu().numpy().astype(np.float64), (2, 0, 1))
+    err = _err(G, Uo)
+    print(f"  {prec} after {nsteps} steps: field errors {err}", flush=True)
+    assert (err < 1e-5).all(), err
