@@ -96,6 +96,56 @@ def cpu_baseline(target_seconds):
                       f"({dof} DOF, {el:.1f} s; single-threaded NumPy einsum)"}
 
 
+def batch_form(steps, warmup, cfl=0.2):
+    """512 independent periodic Euler problems (vortex at a random centre,
+    element counts log-uniform in [100, 20000], orders uniform in 1..4, half
+    prisms and half tets by volume), FP32, advanced together: one HIP-graph
+    launch per RK45[2R+] step, operator products autotuned per order."""
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import frlib, inputs
+    probs = inputs.batch_problems(n=512, seed=0)
+    t0 = time.perf_counter()
+    B = frlib.Batch([(b["mesh"], b["p"]) for b in probs], system="euler", precision="fp32")
+    t_create = time.perf_counter() - t0
+    lam = 0.5 * math.sqrt(1.4) + math.sqrt(1.4)
+    dts, dof, nelem = [], 0, 0
+    for i, b in enumerate(probs):
+        for t in (0, 1):
+            q = B.query(i, t)
+            if not q["nelem"]:
+                continue
+            x = B.upts_coords(i, t)
+            U = inputs.isentropic_vortex(x[:, 0], x[:, 1], x[:, 2], centre=b["centre"], radius=0.15)
+            dev = torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=torch.float32, device="cuda")
+            dev[:, :, :q["nelem"]] = torch.as_tensor(np.transpose(U, (1, 0, 2)), dtype=torch.float32)
+            B.set_solution(i, t, dev.data_ptr())
+            torch.cuda.synchronize()
+            dof += q["nupts"] * q["nelem"] * 5
+            nelem += q["nelem"]
+        dts.append(cfl * (0.5 / b["m"]) / (lam * (2 * b["p"] + 1)))
+    B.set_dt(dts)
+    out = {"problems": len(probs), "elements": nelem, "n_dof": dof, "create_s": t_create}
+    for graph in (True, False):
+        B.set_graph(graph)
+        B.rk_step(frlib.FR_RK45_2RP, max(warmup, 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.rk_step(frlib.FR_RK45_2RP, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        key = "graph" if graph else "eager"
+        out[key] = {"ms_per_step": 1e3 * el / steps, "value": 5.0 * dof * steps / el / 1e9}
+    # the state must stay finite
+    x = B.state_tensor(0, 0 if B.query(0, 0)["nelem"] else 1)
+    B.get_solution(0, 0 if B.query(0, 0)["nelem"] else 1, x.data_ptr())
+    torch.cuda.synchronize()
+    out["finite"] = bool(torch.isfinite(x).all().item())
+    out["unit"] = "GDOF/s per RHS"
+    B.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +156,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -130,6 +181,7 @@ def main():
 
     t_setup = time.perf_counter()
     mesh = make_mesh("fp32")
+    qs = [mesh.query(t) for t in (0, 1)]
     host_state, dof = [], 0
     for t in (0, 1):
         q = mesh.query(t)
@@ -170,6 +222,28 @@ def main():
         el = time.perf_counter() - t0
         drift = float(np.max(np.abs(i1 - i0)[[0, 4]] / np.abs(i0)[[0, 4]]))
         return 1e3 * el / steps, 5.0 * dof * steps / el / 1e9, drift, bool(np.all(np.isfinite(i1)))
+
+    def state_of(m):
+        out = []
+        for t in (0, 1):
+            x = frlib.state_tensor(m, t)
+            m.get_solution(t, x.data_ptr(), stream)
+            torch.cuda.synchronize()
+            out.append(x.double())
+        return out
+
+    def rel_err_pair(A, B):
+        """Per-field relative L2 of A against B over both types (momentum
+        components normalised by the momentum magnitude)."""
+        num = np.zeros(5)
+        den = np.zeros(5)
+        for t in (0, 1):
+            ne = mesh.query(t)["nelem"]
+            d = A[t][:, :, :ne] - B[t][:, :, :ne]
+            num += (d ** 2).sum(dim=(0, 2)).cpu().numpy()
+            den += (B[t][:, :, :ne] ** 2).sum(dim=(0, 2)).cpu().numpy()
+        den[1:4] = den[1:4].sum()
+        return [float(x) for x in np.sqrt(num / den)]
 
     def rhs_of(m):
         u = [frlib.to_device_state(m, t, host_state[t]) for t in (0, 1)]
@@ -220,41 +294,61 @@ def main():
     if not args.no_forms:
         # accuracy of each precision on this workload: RHS of the same FP32
         # input against the FP64 build of the same kernels
+        # reference: the FP64 build of the same kernels (pinned to the oracle),
+        # RHS of the same FP32 input and the state after the same steps
+        nsteps_total = args.steps + max(args.warmup, 1)
         ref64 = make_mesh("fp64")
         R64 = rhs_of(ref64)
+        load(ref64)
+        ref64.rk_step(frlib.FR_RK45_2RP, dt, nsteps_total, stream)
+        U64 = state_of(ref64)
         ref64.close()
         del ref64
         torch.cuda.empty_cache()
-
-        def rel_err(R):
-            num = np.zeros(5)
-            den = np.zeros(5)
-            for t in (0, 1):
-                ne = mesh.query(t)["nelem"]
-                d = (R[t][:, :, :ne] - R64[t][:, :, :ne])
-                num += (d ** 2).sum(dim=(0, 2)).cpu().numpy()
-                den += (R64[t][:, :, :ne] ** 2).sum(dim=(0, 2)).cpu().numpy()
-            den[1:4] = den[1:4].sum()
-            return [float(x) for x in np.sqrt(num / den)]
+        fp32_state = state_of(mesh)    # after the timed run of the FP32 mesh above
         forms = {"fp32": {"value": value, "ms_per_step": ms_per_step,
-                          "rhs_rel_l2_vs_fp64": rel_err(rhs_of(mesh))}}
+                          "rhs_rel_l2_vs_fp64": rel_err_pair(rhs_of(mesh), R64),
+                          "state_rel_l2_vs_fp64": rel_err_pair(fp32_state, U64)}}
+        del fp32_state
         for prec in ("split_bf16", "split_fp16"):
             m2 = make_mesh(prec)
             ms2, v2, d2, f2 = timed(m2, args.steps, args.warmup)
+            st = rel_err_pair(state_of(m2), U64)
             forms[prec] = {"value": v2, "ms_per_step": ms2, "speedup_vs_fp32": v2 / value,
-                           "rhs_rel_l2_vs_fp64": rel_err(rhs_of(m2)), "finite": f2,
+                           "rhs_rel_l2_vs_fp64": rel_err_pair(rhs_of(m2), R64),
+                           "state_rel_l2_vs_fp64": st, "finite": f2,
                            "mass_energy_drift": d2}
             print(f"{prec}: {ms2:.3f} ms/step, {v2:.2f} GDOF/s per RHS "
-                  f"(x{v2 / value:.2f}), rhs error {forms[prec]['rhs_rel_l2_vs_fp64']}",
+                  f"(x{v2 / value:.2f}), rhs error {forms[prec]['rhs_rel_l2_vs_fp64']}, state error {st}",
                   file=sys.stderr, flush=True)
             m2.close()
             del m2
             torch.cuda.empty_cache()
-        print(f"fp32 rhs error {forms['fp32']['rhs_rel_l2_vs_fp64']}", file=sys.stderr, flush=True)
+        print(f"fp32 rhs error {forms['fp32']['rhs_rel_l2_vs_fp64']}, state error "
+              f"{forms['fp32']['state_rel_l2_vs_fp64']}", file=sys.stderr, flush=True)
+
+    if not args.no_batch:
+        mesh.close()
+        torch.cuda.empty_cache()
+        bf = batch_form(args.steps, args.warmup)
+        forms = forms or {}
+        forms["batch_512_euler"] = bf
+        print(f"batch: {bf}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
+
+    # whole right-hand side against the HBM roof of its algorithmic bytes:
+    # 4 B x 5 fields x (2 N_u + 8 N_f) per element (state in and out, traces
+    # and gradient traces written and read once) plus geometry
+    b_alg = 0
+    for t in (0, 1):
+        q = qs[t]
+        b_alg += 4 * 5 * (2 * q["nupts"] + 8 * q["nfpts"]) * q["nelem"] + 4 * (9 if t == 0 else 15) * q["nelem"]
+    t_rhs = ms_per_step / 5 * 1e-3
+    hbm = {"algorithmic_bytes_per_rhs": b_alg, "achieved_GBps": b_alg / t_rhs / 1e9,
+           "frac_of_8TBps": b_alg / t_rhs / PEAK_HBM}
 
     out = {
         "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1,
@@ -265,7 +359,7 @@ def main():
                                "110592 prisms + 196608 tets, RK45[2R+] steps",
                    "n_dof": dof, "rhs_per_step": 5, "dt": dt, "parallelism": "single GPU",
                    "finite": finite, "mass_energy_drift": drift},
-        "roofline": roof, "cpu_baseline": cpu, "forms": forms,
+        "roofline": roof, "cpu_baseline": cpu, "forms": forms, "rhs_hbm": hbm,
     }
     print(json.dumps(out), flush=True)
 

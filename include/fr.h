@@ -195,6 +195,46 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 
+/* Operator-product autotuner: for every operator of every element type,
+ * time the row-blocking candidates (16-row blocks per wavefront) on this
+ * mesh's buffers and keep the fastest.  Results are bitwise unchanged (the
+ * blocking does not change any output's accumulation order).  Synchronises
+ * the stream; the choice is reported by fr_last_error(mesh) on success. */
+fr_status fr_autotune(fr_mesh mesh, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent problems (many small meshes, mixed orders).
+ *
+ * fr_batch_create builds each problem's operators, geometry and pairing,
+ * then merges the problems of one order into one element array per type
+ * (elements are independent and interfaces pair only within a problem, so
+ * the merged right-hand side equals the per-problem ones).  All problems
+ * must share system, precision and physical constants; orders 1..4 may mix.
+ * Every merged group is autotuned at creation.  The batch owns all buffers.
+ *
+ * Per-problem states use the same layout as a single mesh of that problem:
+ * [n_upts][5][ld] with ld from fr_batch_query.  fr_batch_set_dt sets one step
+ * size per problem (host array of n doubles).  fr_batch_rk_step advances every
+ * problem n_steps steps on `stream`; with graphs enabled (the default) an
+ * RK45[2R+] step of all groups is captured once as a HIP graph and replayed
+ * (one graph launch per step).  Errors as for meshes; messages from
+ * fr_batch_last_error. */
+typedef struct fr_batch_s *fr_batch;
+fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr_batch *out);
+fr_status fr_batch_destroy(fr_batch batch);
+fr_status fr_batch_query(fr_batch batch, int32_t problem, int32_t etype, int64_t *n_elem,
+                         int32_t *n_upts, int64_t *ld);
+/* Physical solution-point positions of one problem, host [n_upts][3][n_elem]. */
+fr_status fr_batch_upts_coords(fr_batch batch, int32_t problem, int32_t etype, double *xyz_host);
+fr_status fr_batch_set_solution(fr_batch batch, int32_t problem, int32_t etype,
+                                const void *u_dev, void *stream);
+fr_status fr_batch_get_solution(fr_batch batch, int32_t problem, int32_t etype, void *u_dev,
+                                void *stream);
+fr_status fr_batch_set_dt(fr_batch batch, const double *dt_host, void *stream);
+fr_status fr_batch_set_graph(fr_batch batch, int32_t enable);
+fr_status fr_batch_rk_step(fr_batch batch, int32_t scheme, int32_t n_steps, void *stream);
+const char *fr_batch_last_error(fr_batch batch);
+
 /* Message of the last failure on mesh (NULL: of fr_mesh_create on this
  * thread).  Never NULL; valid until the next call on the same mesh. */
 const char *fr_last_error(fr_mesh mesh);

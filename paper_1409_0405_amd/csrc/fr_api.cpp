@@ -40,12 +40,13 @@ template <typename T>
 struct DevType {
     int nu = 0, nf = 0;
     int64_t nelem = 0, ld = 0;
-    frd::Op<T> Aint, Agrad, Adiv;
-    frd::OpSplit Sint, Sgrad, Sdiv;   // split-precision forms only
+    frd::Op<T> Aint, Agint, Agrad, Adiv;          // Agint: M0 for the gradients
+    frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
     T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
     T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
     T *reg[3] = {nullptr, nullptr, nullptr};
+    T *dte = nullptr;         // per-element step size (batched problems)
     double *wJ = nullptr;
 };
 
@@ -141,11 +142,11 @@ void prof_end(fr_mesh m, size_t i, int cls, hipStream_t s) {
 
 // Fragment order for the MFMA product kernel (see frd::Op).
 template <typename T>
-frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f) {
+frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f, int cap = 0) {
     frd::Op<T> op;
     op.M = M;
     op.Kb = ((K + 3) / 4 + 1) / 2 * 2;   // even number of K steps
-    frd::row_groups(M, sizeof(T) == 4 ? 8 : 4, op.nmg, op.mbw);
+    frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
     f.assign(size_t(Mb) * op.Kb * 64, T(0));
     for (int mb = 0; mb < Mb; ++mb)
@@ -187,12 +188,12 @@ double from_f16(uint16_t u) {
 }
 
 frd::OpSplit fragment_split(const std::vector<double> &A, int M, int K, int format,
-                            std::vector<uint16_t> parts[3]) {
+                            std::vector<uint16_t> parts[3], int cap = 0) {
     frd::OpSplit op;
     op.M = M;
     op.format = format;
     op.Kb = ((K + 31) / 32 + 1) / 2 * 2;
-    frd::row_groups(M, format == 2 ? 2 : 4, op.nmg, op.mbw);
+    frd::row_groups(M, cap ? cap : (format == 2 ? 2 : 4), op.nmg, op.mbw);
     const int np = format == 2 ? 2 : 3;
     const double scale = format == 2 ? 2048.0 : 1.0;
     op.inv_scale = float(1.0 / scale);
@@ -308,6 +309,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         D.Adiv = fragment<T>(div, nu, 3 * nu + nf, f);
         FR_TRY(dev_upload(m, d, p, f, s));
         D.Adiv.frag = p;
+        D.Agint = D.Aint;
         if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
             const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
             std::vector<uint16_t> parts[3];
@@ -326,6 +328,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             FR_TRY(up(fragment_split(R.M0, nf, nu, fmt, parts), D.Sint));
             FR_TRY(up(fragment_split(grad, 3 * nu, nu + nf, fmt, parts), D.Sgrad));
             FR_TRY(up(fragment_split(div, nu, 3 * nu + nf, fmt, parts), D.Sdiv));
+            D.Sgint = D.Sint;
         }
 
         const int ng = frh::n_geom(t);
@@ -421,6 +424,7 @@ struct StageOut {
     T *out = nullptr, *acc = nullptr;
     const T *base = nullptr;
     T a = 0, b = 1;
+    bool per_elem_dt = false;   // scale the stage by the per-element step size
 };
 
 // Operator product through the kernel of the mesh's precision.
@@ -482,7 +486,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         if (ns) {
             const int64_t w15 = 15 * D.ld;
             FR_LAUNCH(m, 4 * t + frd::OP_GRADINTERP, s,
-                      opmul<T>(m, 4 * t + frd::OP_GRADINTERP, D.Aint, D.Sint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
+                      opmul<T>(m, 4 * t + frd::OP_GRADINTERP, D.Agint, D.Sgint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
         }
     }
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
@@ -493,7 +497,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         FR_LAUNCH(m, 4 * t + frd::OP_DIV, s,
                   opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
-                           D.geom, D.xi, D.ld, D.nelem, D.nu};
+                           D.geom, D.xi, D.ld, D.nelem, D.nu,
+                           so[t].per_elem_dt ? D.dte : nullptr};
         FR_LAUNCH(m, 12 + t, s, frd::launch_negdivconf<T>(t, na, s));
     }
     return FR_OK;
@@ -551,7 +556,8 @@ fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
 }
 
 template <typename T>
-fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
+fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
+                  bool per_elem_dt = false, bool allow_check = true) {
     Dev<T> &d = dev_of<T>(m);
     static const double rk4_a[4] = {0.5, 0.5, 1.0, 0.0};
     static const double rk4_b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
@@ -573,6 +579,7 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
             for (int t = 0; t < 2; ++t) {
                 so[t].acc = d.t[t].reg[0];
                 so[t].a = T(dt);
+                so[t].per_elem_dt = per_elem_dt;
             }
             fr_status st = rhs_pipeline<T>(m, U, so, s);
             if (st) return st;
@@ -591,6 +598,7 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
                     so[t].out = st_i < 3 ? d.t[t].reg[1] : nullptr;
                     so[t].base = d.t[t].reg[0];
                     so[t].b = T(rk4_a[st_i] * dt);
+                    so[t].per_elem_dt = per_elem_dt;
                 }
                 fr_status st = rhs_pipeline<T>(m, U, so, s);
                 if (st) return st;
@@ -606,6 +614,7 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
                     so[t].a = T(rk45_b[st_i] * dt);
                     so[t].out = st_i < 4 ? d.t[t].reg[1] : nullptr;
                     so[t].b = st_i < 4 ? T((rk45_a[st_i] - rk45_b[st_i]) * dt) : T(0);
+                    so[t].per_elem_dt = per_elem_dt;
                 }
                 fr_status st = rhs_pipeline<T>(m, U, so, s);
                 if (st) return st;
@@ -614,7 +623,7 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s) {
             return fail(m, FR_ERR_INVALID_ARG, "unknown scheme");
         }
     }
-    if (m->flags & FR_CHECK_FINITE) {
+    if (allow_check && (m->flags & FR_CHECK_FINITE)) {
         double bad = 0;
         fr_status st = reduce_impl<T>(m, 5, &bad, s);
         if (st) return st;
@@ -642,6 +651,197 @@ fr_status copy_state(fr_mesh m, int etype, void *dst, const void *src, bool to_r
     else
         FR_HIP(m, hipMemcpyAsync(dst, D.reg[0], n, hipMemcpyDeviceToDevice, s));
     return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: for every operator product of every element type, time each
+// row-blocking candidate (row blocks of 16 per wavefront) on the mesh's own
+// buffers and keep the fastest.  The blocking does not change any output's
+// accumulation order, so results are bitwise unchanged.
+// ---------------------------------------------------------------------------
+template <typename T>
+fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
+    Dev<T> &d = dev_of<T>(m);
+    const bool split = m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16;
+    const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
+    const bool ns = m->system == FR_NAVIER_STOKES;
+    hipEvent_t e0, e1;
+    FR_HIP(m, hipEventCreate(&e0));
+    FR_HIP(m, hipEventCreate(&e1));
+    std::vector<int> caps;
+    if (split) caps = fmt == 2 ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    else caps = sizeof(T) == 4 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 4};
+    fr_status st = FR_OK;
+    for (int t = 0; t < 2 && !st; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        const frh::RefOps &R = m->host.t[t].ops;
+        std::vector<double> grad, div;
+        folded_ops(R, grad, div);
+        const int nu = D.nu, nf = D.nf;
+        const int64_t w5 = 5 * D.ld, w15 = 15 * D.ld;
+        struct Case {
+            int op;
+            const std::vector<double> *A;
+            int M, K;
+            const T *B1;
+            int64_t l1;
+            int K1;
+            const T *B2;
+            int64_t l2;
+            int K2;
+            T *C;
+            int64_t lc, ncols;
+            frd::Op<T> *dst;
+            frd::OpSplit *sdst;
+        };
+        std::vector<Case> cases = {
+            {frd::OP_INTERP, &R.M0, nf, nu, D.reg[0], w5, nu, nullptr, 0, 0, D.Uf, w5, w5, &D.Aint, &D.Sint},
+            {frd::OP_DIV, &div, nu, 3 * nu + nf, D.Ft, w5, 3 * nu, D.Fn, w5, nf, D.Rt, w5, w5, &D.Adiv, &D.Sdiv}};
+        if (ns) {
+            cases.push_back({frd::OP_GRAD, &grad, 3 * nu, nu + nf, D.reg[0], w5, nu, D.Cf, w5, nf, D.Qt, w5, w5,
+                             &D.Agrad, &D.Sgrad});
+            cases.push_back({frd::OP_GRADINTERP, &R.M0, nf, nu, D.Q, w15, nu, nullptr, 0, 0, D.Qf, w15, w15,
+                             &D.Agint, &D.Sgint});
+        }
+        for (const Case &c : cases) {
+            float best = 1e30f;
+            int best_cap = -1;
+            std::vector<void *> bufs;
+            frd::Op<T> best_op;
+            frd::OpSplit best_sop;
+            for (int cap : caps) {
+                frd::Op<T> op;
+                frd::OpSplit sop;
+                std::vector<void *> mine;
+                if (split) {
+                    std::vector<uint16_t> parts[3];
+                    sop = fragment_split(*c.A, c.M, c.K, fmt, parts, cap);
+                    for (int q = 0; q < 3; ++q) {
+                        if (parts[q].empty()) continue;
+                        void *p;
+                        FR_HIP(m, hipMalloc(&p, parts[q].size() * 2));
+                        FR_HIP(m, hipMemcpy(p, parts[q].data(), parts[q].size() * 2, hipMemcpyHostToDevice));
+                        sop.part[q] = static_cast<uint16_t *>(p);
+                        mine.push_back(p);
+                    }
+                } else {
+                    std::vector<T> f;
+                    op = fragment<T>(*c.A, c.M, c.K, f, cap);
+                    void *p;
+                    FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
+                    FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
+                    op.frag = static_cast<T *>(p);
+                    mine.push_back(p);
+                }
+                auto run = [&]() -> hipError_t {
+                    if constexpr (std::is_same<T, float>::value) {
+                        if (split)
+                            return frd::launch_opmul_split(4 * t + c.op, sop, c.B1, c.l1, c.K1, c.B2, c.l2,
+                                                           c.K2, c.C, c.lc, c.ncols, s);
+                    }
+                    return frd::launch_opmul<T>(4 * t + c.op, op, c.B1, c.l1, c.K1, c.B2, c.l2, c.K2,
+                                                c.C, c.lc, c.ncols, s);
+                };
+                FR_HIP(m, run());
+                FR_HIP(m, hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) FR_HIP(m, run());
+                FR_HIP(m, hipEventRecord(e1, s));
+                FR_HIP(m, hipEventSynchronize(e1));
+                float ms = 0;
+                FR_HIP(m, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    for (void *p : bufs) (void)hipFree(p);
+                    bufs = mine;
+                    best = ms;
+                    best_cap = cap;
+                    best_op = op;
+                    best_sop = sop;
+                } else {
+                    for (void *p : mine) (void)hipFree(p);
+                }
+            }
+            for (void *p : bufs) d.allocs.push_back(p);
+            if (split)
+                *c.sdst = best_sop;
+            else
+                *c.dst = best_op;
+            report += (t ? "pri" : "tet") + std::string(" op") + std::to_string(c.op) + " cap " +
+                      std::to_string(best_cap) + " " + std::to_string(best / 3 * 1e3) + " us; ";
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems
+// ---------------------------------------------------------------------------
+struct fr_batch_s {
+    int n = 0, system = 0, precision = 0;
+    std::unique_ptr<fr_mesh_s> group[4];     // one merged mesh per order p = 1..4
+    struct Prob {
+        int g = 0;
+        int64_t off[2] = {0, 0}, ne[2] = {0, 0}, ld[2] = {0, 0};
+        int nu[2] = {0, 0};
+    };
+    std::vector<Prob> prob;
+    hipStream_t stream = nullptr;             // stream the step graph replays on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    std::string err;
+    ~fr_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+fr_status bfail(fr_batch b, fr_status st, const std::string &msg) {
+    if (b)
+        b->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+#define FR_BHIP(b, call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return bfail(b, e_ == hipErrorOutOfMemory ? FR_ERR_OUT_OF_MEMORY : FR_ERR_DEVICE, \
+                         std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+template <typename T>
+fr_status batch_alloc_dt(fr_mesh m) {
+    Dev<T> &d = dev_of<T>(m);
+    for (int t = 0; t < 2; ++t) {
+        if (!d.t[t].nelem) continue;
+        FR_HIP(m, hipMalloc(reinterpret_cast<void **>(&d.t[t].dte), size_t(d.t[t].ld) * sizeof(T)));
+        d.allocs.push_back(d.t[t].dte);
+        FR_HIP(m, hipMemset(d.t[t].dte, 0, size_t(d.t[t].ld) * sizeof(T)));
+    }
+    return FR_OK;
+}
+
+template <typename T>
+void *group_reg(fr_mesh m, int t) {
+    return dev_of<T>(m).t[t].reg[0];
+}
+
+template <typename T>
+T *group_dte(fr_mesh m, int t) {
+    return dev_of<T>(m).t[t].dte;
 }
 
 }  // namespace
@@ -841,6 +1041,241 @@ fr_status fr_profile_read(fr_mesh m, double *total_ms, int64_t *count) {
     P.used = 0;
     return FR_OK;
 }
+
+fr_status fr_autotune(fr_mesh m, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string rep;
+    fr_status st = m->precision != FR_FP64 ? autotune_impl<float>(m, s, rep) : autotune_impl<double>(m, s, rep);
+    if (!st) m->err = rep;
+    return st;
+}
+
+fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr_batch *out) {
+    g_create_error.clear();
+    if (n <= 0 || !descs || !out) return bfail(nullptr, FR_ERR_INVALID_ARG, "null argument or empty batch");
+    *out = nullptr;
+    const fr_mesh_desc &d0 = descs[0];
+    for (int i = 0; i < n; ++i) {
+        const fr_mesh_desc &d = descs[i];
+        if (d.system != d0.system || d.precision != d0.precision || d.gamma != d0.gamma ||
+            d.mu != d0.mu || d.prandtl != d0.prandtl || d.ldg_beta != d0.ldg_beta ||
+            d.ldg_tau != d0.ldg_tau)
+            return bfail(nullptr, FR_ERR_INVALID_ARG,
+                         "problem " + std::to_string(i) + ": system, precision and constants must match");
+        if (d.order < 1 || d.order > 4)
+            return bfail(nullptr, FR_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": order must be 1..4");
+        if (d.flags & FR_VALIDATE_ONLY)
+            return bfail(nullptr, FR_ERR_INVALID_ARG, "batches are built on the device");
+    }
+    if (d0.precision < FR_FP32 || d0.precision > FR_SPLIT_FP16)
+        return bfail(nullptr, FR_ERR_UNSUPPORTED, "unsupported precision");
+    auto b = std::make_unique<fr_batch_s>();
+    b->n = n;
+    b->system = d0.system;
+    b->precision = d0.precision;
+    b->prob.resize(n);
+    std::vector<frh::MeshHost> parts[4];
+    std::vector<int> members[4];
+    for (int i = 0; i < n; ++i) {
+        const fr_mesh_desc &d = descs[i];
+        frh::MeshHost h;
+        std::string err;
+        try {
+            if (!frh::build_mesh_host(d.order, d.n_vertices, d.xyz, d.n_tets, d.tet_v, d.tet_img,
+                                      d.n_prisms, d.pri_v, d.pri_img, d.period, h, err))
+                return bfail(nullptr, FR_ERR_BAD_MESH, "problem " + std::to_string(i) + ": " + err);
+        } catch (const std::exception &ex) {
+            return bfail(nullptr, FR_ERR_BAD_MESH, ex.what());
+        }
+        b->prob[i].g = d.order - 1;
+        for (int t = 0; t < 2; ++t) {
+            b->prob[i].ne[t] = h.t[t].nelem;
+            b->prob[i].ld[t] = h.t[t].ld;
+            b->prob[i].nu[t] = frh::n_upts(t, d.order);
+        }
+        parts[d.order - 1].push_back(std::move(h));
+        members[d.order - 1].push_back(i);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int g = 0; g < 4; ++g) {
+        if (parts[g].empty()) continue;
+        auto m = std::make_unique<fr_mesh_s>();
+        m->order = g + 1;
+        m->system = d0.system;
+        m->precision = d0.precision;
+        m->flags = d0.flags & ~uint32_t(FR_CHECK_FINITE);
+        m->gamma = d0.gamma;
+        m->mu = d0.mu;
+        m->prandtl = d0.prandtl;
+        m->beta = d0.ldg_beta;
+        m->tau = d0.ldg_tau;
+        std::vector<std::array<int64_t, 2>> off;
+        std::string err;
+        if (!frh::merge_meshes(parts[g], m->host, off, err)) return bfail(nullptr, FR_ERR_BAD_MESH, err);
+        parts[g].clear();
+        for (size_t j = 0; j < members[g].size(); ++j)
+            for (int t = 0; t < 2; ++t) b->prob[members[g][j]].off[t] = off[j][t];
+        m->create_stream = s;
+        fr_status st = m->precision != FR_FP64 ? setup_device<float>(m.get(), s) : setup_device<double>(m.get(), s);
+        if (!st) st = m->precision != FR_FP64 ? batch_alloc_dt<float>(m.get()) : batch_alloc_dt<double>(m.get());
+        if (st) return bfail(nullptr, st, m->err);
+        m->device = true;
+        std::string rep;
+        st = m->precision != FR_FP64 ? autotune_impl<float>(m.get(), s, rep) : autotune_impl<double>(m.get(), s, rep);
+        if (st) return bfail(nullptr, st, m->err);
+        b->group[g] = std::move(m);
+    }
+    FR_BHIP(nullptr, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    FR_BHIP(nullptr, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    FR_BHIP(nullptr, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    *out = b.release();
+    return FR_OK;
+}
+
+fr_status fr_batch_destroy(fr_batch b) {
+    if (!b) return FR_OK;
+    for (auto &g : b->group)
+        if (g) (void)hipStreamSynchronize(g->create_stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+    return FR_OK;
+}
+
+fr_status fr_batch_query(fr_batch b, int32_t problem, int32_t etype, int64_t *n_elem, int32_t *n_upts,
+                         int64_t *ld) {
+    if (!b) return FR_ERR_INVALID_ARG;
+    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+        return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
+    const auto &P = b->prob[problem];
+    if (n_elem) *n_elem = P.ne[etype];
+    if (n_upts) *n_upts = P.nu[etype];
+    if (ld) *ld = P.ld[etype];
+    return FR_OK;
+}
+
+static fr_status batch_copy(fr_batch b, int problem, int etype, void *dst, const void *src, bool to_reg,
+                            hipStream_t s) {
+    if (!b) return FR_ERR_INVALID_ARG;
+    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+        return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
+    const auto &P = b->prob[problem];
+    if (!P.ne[etype]) return FR_OK;
+    if (!(to_reg ? src : dst)) return bfail(b, FR_ERR_INVALID_ARG, "null state");
+    fr_mesh m = b->group[P.g].get();
+    const size_t esz = m->precision != FR_FP64 ? 4 : 8;
+    char *reg = static_cast<char *>(m->precision != FR_FP64 ? group_reg<float>(m, etype) : group_reg<double>(m, etype));
+    const size_t gpitch = size_t(m->host.t[etype].ld) * esz, ppitch = size_t(P.ld[etype]) * esz;
+    char *greg = reg + size_t(P.off[etype]) * esz;
+    const size_t rows = size_t(P.nu[etype]) * 5, width = size_t(P.ne[etype]) * esz;
+    if (to_reg)
+        FR_BHIP(b, hipMemcpy2DAsync(greg, gpitch, src, ppitch, width, rows, hipMemcpyDeviceToDevice, s));
+    else
+        FR_BHIP(b, hipMemcpy2DAsync(dst, ppitch, greg, gpitch, width, rows, hipMemcpyDeviceToDevice, s));
+    return FR_OK;
+}
+
+fr_status fr_batch_upts_coords(fr_batch b, int32_t problem, int32_t etype, double *xyz) {
+    if (!b || !xyz) return FR_ERR_INVALID_ARG;
+    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+        return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
+    const auto &P = b->prob[problem];
+    if (!P.ne[etype]) return FR_OK;
+    const frh::TypeHost &H = b->group[P.g]->host.t[etype];
+    const int nu = H.ops.nu, nvt = frh::n_verts(etype);
+    for (int i = 0; i < nu; ++i)
+        for (int64_t e = 0; e < P.ne[etype]; ++e) {
+            double x[3];
+            frh::map_point(etype, &H.X[size_t(P.off[etype] + e) * nvt * 3], &H.ops.upts[3 * i], x);
+            for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * P.ne[etype] + e] = x[d];
+        }
+    return FR_OK;
+}
+
+fr_status fr_batch_set_solution(fr_batch b, int32_t problem, int32_t etype, const void *u_dev, void *stream) {
+    return batch_copy(b, problem, etype, nullptr, u_dev, true, static_cast<hipStream_t>(stream));
+}
+
+fr_status fr_batch_get_solution(fr_batch b, int32_t problem, int32_t etype, void *u_dev, void *stream) {
+    return batch_copy(b, problem, etype, u_dev, nullptr, false, static_cast<hipStream_t>(stream));
+}
+
+fr_status fr_batch_set_dt(fr_batch b, const double *dt_host, void *stream) {
+    if (!b || !dt_host) return FR_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int g = 0; g < 4; ++g) {
+        fr_mesh m = b->group[g].get();
+        if (!m) continue;
+        for (int t = 0; t < 2; ++t) {
+            const int64_t ld = m->host.t[t].ld;
+            if (!ld) continue;
+            std::vector<double> h(size_t(ld), 0.0);
+            for (int i = 0; i < b->n; ++i) {
+                const auto &P = b->prob[i];
+                if (P.g != g) continue;
+                if (!(dt_host[i] >= 0) || !std::isfinite(dt_host[i]))
+                    return bfail(b, FR_ERR_INVALID_ARG, "dt of problem " + std::to_string(i));
+                for (int64_t e = 0; e < P.ne[t]; ++e) h[size_t(P.off[t] + e)] = dt_host[i];
+            }
+            if (m->precision != FR_FP64) {
+                std::vector<float> f(h.begin(), h.end());
+                FR_BHIP(b, hipMemcpyAsync(group_dte<float>(m, t), f.data(), f.size() * 4, hipMemcpyHostToDevice, s));
+                FR_BHIP(b, hipStreamSynchronize(s));
+            } else {
+                FR_BHIP(b, hipMemcpyAsync(group_dte<double>(m, t), h.data(), h.size() * 8, hipMemcpyHostToDevice, s));
+                FR_BHIP(b, hipStreamSynchronize(s));
+            }
+        }
+    }
+    return FR_OK;
+}
+
+fr_status fr_batch_set_graph(fr_batch b, int32_t enable) {
+    if (!b) return FR_ERR_INVALID_ARG;
+    b->use_graph = enable != 0;
+    return FR_OK;
+}
+
+fr_status fr_batch_rk_step(fr_batch b, int32_t scheme, int32_t n_steps, void *stream) {
+    if (!b) return FR_ERR_INVALID_ARG;
+    if (n_steps < 0) return bfail(b, FR_ERR_INVALID_ARG, "negative step count");
+    if (scheme != FR_RK4 && scheme != FR_RK45_2RP && scheme != FR_FWD_EULER)
+        return bfail(b, FR_ERR_INVALID_ARG, "unknown scheme");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto step_all = [&](hipStream_t st, int steps) -> fr_status {
+        for (int g = 0; g < 4; ++g) {
+            fr_mesh m = b->group[g].get();
+            if (!m) continue;
+            fr_status r = m->precision != FR_FP64 ? rk_impl<float>(m, scheme, 1.0, steps, st, true, false)
+                                                  : rk_impl<double>(m, scheme, 1.0, steps, st, true, false);
+            if (r) return bfail(b, r, m->err);
+        }
+        return FR_OK;
+    };
+    // RK4 swaps its registers every step and cannot be replayed as one graph
+    if (!b->use_graph || scheme != FR_RK45_2RP) return step_all(s, n_steps);
+    if (!b->exec) {
+        FR_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        fr_status r = step_all(b->stream, 1);
+        hipGraph_t gph = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &gph);
+        if (r) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return r;
+        }
+        if (e != hipSuccess) return bfail(b, FR_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        b->graph = gph;
+        FR_BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    FR_BHIP(b, hipEventRecord(b->ev_in, s));
+    FR_BHIP(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    for (int i = 0; i < n_steps; ++i) FR_BHIP(b, hipGraphLaunch(b->exec, b->stream));
+    FR_BHIP(b, hipEventRecord(b->ev_out, b->stream));
+    FR_BHIP(b, hipStreamWaitEvent(s, b->ev_out, 0));
+    return FR_OK;
+}
+
+const char *fr_batch_last_error(fr_batch b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 const char *fr_last_error(fr_mesh m) {
     return m ? m->err.c_str() : g_create_error.c_str();

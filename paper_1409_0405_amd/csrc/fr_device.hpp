@@ -90,7 +90,7 @@ hipError_t launch_common_solution(const PairArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_common_flux(bool ns, const PairArgs<T> &a, hipStream_t s);
 
-// k = -Rt / J at each solution point, then
+// k = -Rt / J at each solution point (times dte[e] if given), then
 //   acc += a k (if acc), out = (base ? base : (acc ? acc : 0)) + b k (if out).
 template <typename T>
 struct NegArgs {
@@ -103,6 +103,7 @@ struct NegArgs {
     const T *xi;
     int64_t ld, nelem;
     int nu;
+    const T *dte;      // per-element step size, or null
 };
 template <typename T>
 hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s);

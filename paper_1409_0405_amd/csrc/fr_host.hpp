@@ -2,6 +2,7 @@
 // Internal header (not part of the C ABI).
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -37,6 +38,8 @@ struct RefOps {
 };
 
 RefOps build_ref(int etype, int p);
+// build_ref memoised per (type, order); thread safe.
+const RefOps &ref_cached(int etype, int p);
 
 int n_upts(int etype, int p);
 int n_fpts(int etype, int p);
@@ -84,6 +87,12 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet,
                      const int64_t *tet_v, const int8_t *tet_img, int64_t npri,
                      const int64_t *pri_v, const int8_t *pri_img, const double period[3],
                      MeshHost &m, std::string &err);
+
+// Merge independent meshes of one order into one element array per type.
+// Element indices of each part are offset by the elements of the parts
+// before it (elem_off[part][type]); the pairing stays within each part.
+bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
+                  std::vector<std::array<int64_t, 2>> &elem_off, std::string &err);
 
 inline uint32_t pack_side(int64_t e, int f, int t) {
     return uint32_t(e) | (uint32_t(f) << 24) | (uint32_t(t) << 31);

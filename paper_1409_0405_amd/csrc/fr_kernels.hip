@@ -531,7 +531,8 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
     if (e >= a.nelem) return;
     const int64_t ld = a.ld;
     T adj[3][3];
-    const T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    if (a.dte) Jinv *= a.dte[e];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         const int64_t o = (int64_t(i) * 5 + v) * ld + e;

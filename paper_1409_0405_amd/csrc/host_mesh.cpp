@@ -120,7 +120,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
             err = "too many elements of one type (limit 2^24)";
             return false;
         }
-        T.ops = build_ref(t, p);
+        T.ops = ref_cached(t, p);
         const int nvt = n_verts(t), ng = n_geom(t), nu = T.ops.nu, nf = T.ops.nf;
         T.X.resize(size_t(T.nelem) * nvt * 3);
         T.geom.assign(size_t(ng) * T.nelem, 0);
@@ -298,6 +298,83 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
         for (int d = 0; d < 3; ++d) P.nhat[3 * i + d] = pp[i].n[d];
         P.sL[i] = pp[i].sL;
         P.sR[i] = pp[i].sR;
+    }
+    return true;
+}
+
+bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
+                  std::vector<std::array<int64_t, 2>> &elem_off, std::string &err) {
+    if (parts.empty()) {
+        err = "no meshes to merge";
+        return false;
+    }
+    out = MeshHost();
+    out.p = parts[0].p;
+    elem_off.assign(parts.size(), {0, 0});
+    for (int t = 0; t < 2; ++t) {
+        int64_t n = 0;
+        for (size_t i = 0; i < parts.size(); ++i) {
+            if (parts[i].p != out.p) {
+                err = "merged meshes must share one order";
+                return false;
+            }
+            elem_off[i][t] = n;
+            n += parts[i].t[t].nelem;
+            if (parts[i].t[t].nelem && !out.t[t].ops.nu) out.t[t].ops = parts[i].t[t].ops;
+        }
+        if (n >= (int64_t(1) << 24)) {
+            err = "too many elements of one type in a merged batch (limit 2^24)";
+            return false;
+        }
+        TypeHost &T = out.t[t];
+        T.nelem = n;
+        T.ld = (n + 63) / 64 * 64;
+        if (!n) continue;
+        const int ng = n_geom(t);
+        T.geom.assign(size_t(ng) * n, 0.0);
+        for (size_t i = 0; i < parts.size(); ++i) {
+            const TypeHost &P = parts[i].t[t];
+            if (!P.nelem) continue;
+            T.X.insert(T.X.end(), P.X.begin(), P.X.end());
+            T.jdet.insert(T.jdet.end(), P.jdet.begin(), P.jdet.end());
+            for (int k = 0; k < ng; ++k)
+                std::copy(P.geom.begin() + size_t(k) * P.nelem, P.geom.begin() + size_t(k + 1) * P.nelem,
+                          T.geom.begin() + size_t(k) * n + elem_off[i][t]);
+        }
+    }
+    struct PP {
+        uint32_t L, R;
+        double n[3], sL, sR;
+    };
+    std::vector<PP> pp;
+    auto shift = [&](uint32_t side, size_t i) {
+        const int t = int(side >> 31);
+        const int64_t e = int64_t(side & 0xffffffu) + elem_off[i][t];
+        return pack_side(e, int((side >> 24) & 0x7f), t);
+    };
+    for (size_t i = 0; i < parts.size(); ++i) {
+        const PairTable &P = parts[i].pairs;
+        for (size_t j = 0; j < P.sideL.size(); ++j)
+            pp.push_back({shift(P.sideL[j], i), shift(P.sideR[j], i),
+                          {P.nhat[3 * j], P.nhat[3 * j + 1], P.nhat[3 * j + 2]}, P.sL[j], P.sR[j]});
+        out.volume += parts[i].volume;
+    }
+    auto keyL = [](uint32_t s) {
+        return (uint64_t(s >> 31) << 40) | (uint64_t((s >> 24) & 0x7f) << 32) | (s & 0xffffff);
+    };
+    std::stable_sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
+    PairTable &T = out.pairs;
+    T.sideL.resize(pp.size());
+    T.sideR.resize(pp.size());
+    T.nhat.resize(3 * pp.size());
+    T.sL.resize(pp.size());
+    T.sR.resize(pp.size());
+    for (size_t j = 0; j < pp.size(); ++j) {
+        T.sideL[j] = pp[j].L;
+        T.sideR[j] = pp[j].R;
+        for (int d = 0; d < 3; ++d) T.nhat[3 * j + d] = pp[j].n[d];
+        T.sL[j] = pp[j].sL;
+        T.sR[j] = pp[j].sR;
     }
     return true;
 }

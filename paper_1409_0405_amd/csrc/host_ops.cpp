@@ -16,6 +16,8 @@
 // quadrature points.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 
 #include "fr_host.hpp"
@@ -493,6 +495,16 @@ RefOps build_ref(int etype, int p) {
     R.G = todbl(G);
     R.L = todbl(L);
     return R;
+}
+
+const RefOps &ref_cached(int etype, int p) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, RefOps> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(etype, p);
+    auto it = cache.find(key);
+    if (it == cache.end()) it = cache.emplace(key, build_ref(etype, p)).first;
+    return it->second;
 }
 
 }  // namespace frh

@@ -29,7 +29,11 @@ FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
 
 EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coords",
             "fr_operator", "fr_set_solution", "fr_get_solution", "fr_rhs", "fr_rk_step",
-            "fr_reduce", "fr_intermediate", "fr_profile", "fr_profile_read", "fr_last_error")
+            "fr_reduce", "fr_intermediate", "fr_profile", "fr_profile_read", "fr_autotune",
+            "fr_batch_create", "fr_batch_destroy", "fr_batch_query", "fr_batch_upts_coords",
+            "fr_batch_set_solution",
+            "fr_batch_get_solution", "fr_batch_set_dt", "fr_batch_set_graph", "fr_batch_rk_step",
+            "fr_batch_last_error", "fr_last_error")
 
 PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
@@ -84,10 +88,23 @@ def lib():
         L.fr_intermediate.argtypes = [vp, i32, i32, vp, vp]
         L.fr_profile.argtypes = [vp, i32]
         L.fr_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+        L.fr_autotune.argtypes = [vp, vp]
+        L.fr_batch_create.argtypes = [i32, ctypes.POINTER(fr_mesh_desc), vp, ctypes.POINTER(vp)]
+        L.fr_batch_destroy.argtypes = [vp]
+        L.fr_batch_query.argtypes = [vp, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i64)]
+        L.fr_batch_upts_coords.argtypes = [vp, i32, i32, ctypes.POINTER(dbl)]
+        L.fr_batch_set_solution.argtypes = [vp, i32, i32, vp, vp]
+        L.fr_batch_get_solution.argtypes = [vp, i32, i32, vp, vp]
+        L.fr_batch_set_dt.argtypes = [vp, ctypes.POINTER(dbl), vp]
+        L.fr_batch_set_graph.argtypes = [vp, i32]
+        L.fr_batch_rk_step.argtypes = [vp, i32, i32, vp]
+        L.fr_batch_last_error.argtypes = [vp]
+        L.fr_batch_last_error.restype = ctypes.c_char_p
         L.fr_last_error.argtypes = [vp]
         L.fr_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name != "fr_last_error":
+            if name not in ("fr_last_error", "fr_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -103,6 +120,35 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4, mu=0.0,
+              prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False, check_finite=False):
+    """fr_mesh_desc for the generator's mesh arrays; the numpy arrays it points
+    into are appended to ``keep`` (they must outlive the create call)."""
+    d = fr_mesh_desc()
+    d.order = order
+    d.system = {"euler": FR_EULER, "ns": FR_NAVIER_STOKES}[system]
+    d.precision = PRECISIONS[precision]
+    d.flags = (FR_VALIDATE_ONLY if validate_only else 0) | (FR_CHECK_FINITE if check_finite else 0)
+    d.gamma, d.mu, d.prandtl, d.ldg_beta, d.ldg_tau = gamma, mu, prandtl, ldg_beta, ldg_tau
+    xyz = np.ascontiguousarray(mesh_arrays["xyz"], dtype=np.float64)
+    tv = np.ascontiguousarray(mesh_arrays["tet_v"], dtype=np.int64)
+    ti = np.ascontiguousarray(mesh_arrays["tet_img"], dtype=np.int8)
+    pv = np.ascontiguousarray(mesh_arrays["pri_v"], dtype=np.int64)
+    pi = np.ascontiguousarray(mesh_arrays["pri_img"], dtype=np.int8)
+    keep += [xyz, tv, ti, pv, pi]
+    d.n_vertices = len(xyz)
+    d.xyz = _ptr(xyz, ctypes.c_double)
+    d.n_tets = len(tv)
+    d.tet_v = _ptr(tv, ctypes.c_int64) if len(tv) else None
+    d.tet_img = _ptr(ti, ctypes.c_int8) if len(tv) else None
+    d.n_prisms = len(pv)
+    d.pri_v = _ptr(pv, ctypes.c_int64) if len(pv) else None
+    d.pri_img = _ptr(pi, ctypes.c_int8) if len(pv) else None
+    for k in range(3):
+        d.period[k] = float(mesh_arrays["period"][k])
+    return d
+
+
 class Mesh:
     """A mesh handle owning its library-side buffers (fr_mesh)."""
 
@@ -110,33 +156,19 @@ class Mesh:
                  mu=0.0, prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False,
                  check_finite=False, stream=0):
         self._keep = []
-        d = fr_mesh_desc()
-        d.order = order
-        d.system = {"euler": FR_EULER, "ns": FR_NAVIER_STOKES}[system]
-        d.precision = PRECISIONS[precision]
-        d.flags = (FR_VALIDATE_ONLY if validate_only else 0) | (FR_CHECK_FINITE if check_finite else 0)
-        d.gamma, d.mu, d.prandtl, d.ldg_beta, d.ldg_tau = gamma, mu, prandtl, ldg_beta, ldg_tau
-        xyz = np.ascontiguousarray(mesh_arrays["xyz"], dtype=np.float64)
-        tv = np.ascontiguousarray(mesh_arrays["tet_v"], dtype=np.int64)
-        ti = np.ascontiguousarray(mesh_arrays["tet_img"], dtype=np.int8)
-        pv = np.ascontiguousarray(mesh_arrays["pri_v"], dtype=np.int64)
-        pi = np.ascontiguousarray(mesh_arrays["pri_img"], dtype=np.int8)
-        self._keep += [xyz, tv, ti, pv, pi]
-        d.n_vertices = len(xyz)
-        d.xyz = _ptr(xyz, ctypes.c_double)
-        d.n_tets = len(tv)
-        d.tet_v = _ptr(tv, ctypes.c_int64) if len(tv) else None
-        d.tet_img = _ptr(ti, ctypes.c_int8) if len(tv) else None
-        d.n_prisms = len(pv)
-        d.pri_v = _ptr(pv, ctypes.c_int64) if len(pv) else None
-        d.pri_img = _ptr(pi, ctypes.c_int8) if len(pv) else None
-        for k in range(3):
-            d.period[k] = float(mesh_arrays["period"][k])
+        d = make_desc(self._keep, mesh_arrays, order, system, precision, gamma, mu, prandtl,
+                      ldg_beta, ldg_tau, validate_only, check_finite)
         h = ctypes.c_void_p()
         _check(lib().fr_mesh_create(ctypes.byref(d), ctypes.c_void_p(stream), ctypes.byref(h)))
         self.h = h
         self.order, self.system, self.precision = order, system, precision
         self.dtype = np.float64 if precision == "fp64" else np.float32
+
+    def autotune(self, stream=0):
+        """Pick the fastest row blocking of every operator product; returns the
+        library's report."""
+        _check(lib().fr_autotune(self.h, ctypes.c_void_p(stream)), self.h)
+        return lib().fr_last_error(self.h).decode()
 
     def close(self):
         if getattr(self, "h", None):
@@ -203,6 +235,78 @@ class Mesh:
     def intermediate(self, etype, which, dst_ptr, stream=0):
         _check(lib().fr_intermediate(self.h, etype, which, ctypes.c_void_p(dst_ptr),
                                      ctypes.c_void_p(stream)), self.h)
+
+
+class Batch:
+    """Many independent problems advanced together (fr_batch)."""
+
+    def __init__(self, problems, system="euler", precision="fp32", stream=0, **kw):
+        """problems: list of (mesh arrays, order)."""
+        self._keep = []
+        descs = (fr_mesh_desc * len(problems))()
+        for i, (arrays, p) in enumerate(problems):
+            descs[i] = make_desc(self._keep, arrays, p, system, precision, **kw)
+        h = ctypes.c_void_p()
+        st = lib().fr_batch_create(len(problems), descs, ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != FR_OK:
+            raise FrError(st, lib().fr_batch_last_error(None).decode())
+        self.h = h
+        self.n = len(problems)
+        self.precision = precision
+        self.orders = [p for _, p in problems]
+
+    def _check(self, st):
+        if st != FR_OK:
+            raise FrError(st, lib().fr_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, problem, etype):
+        ne, ld = ctypes.c_int64(), ctypes.c_int64()
+        nu = ctypes.c_int32()
+        self._check(lib().fr_batch_query(self.h, problem, etype, ctypes.byref(ne), ctypes.byref(nu),
+                                         ctypes.byref(ld)))
+        return {"nelem": ne.value, "nupts": nu.value, "ld": ld.value}
+
+    def upts_coords(self, problem, etype):
+        q = self.query(problem, etype)
+        out = np.zeros((q["nupts"], 3, q["nelem"]))
+        if q["nelem"]:
+            self._check(lib().fr_batch_upts_coords(self.h, problem, etype, _ptr(out, ctypes.c_double)))
+        return out
+
+    def set_solution(self, problem, etype, u_ptr, stream=0):
+        self._check(lib().fr_batch_set_solution(self.h, problem, etype, ctypes.c_void_p(u_ptr),
+                                                ctypes.c_void_p(stream)))
+
+    def get_solution(self, problem, etype, u_ptr, stream=0):
+        self._check(lib().fr_batch_get_solution(self.h, problem, etype, ctypes.c_void_p(u_ptr),
+                                                ctypes.c_void_p(stream)))
+
+    def set_dt(self, dts, stream=0):
+        a = np.ascontiguousarray(dts, dtype=np.float64)
+        self._check(lib().fr_batch_set_dt(self.h, _ptr(a, ctypes.c_double), ctypes.c_void_p(stream)))
+
+    def set_graph(self, enable):
+        self._check(lib().fr_batch_set_graph(self.h, 1 if enable else 0))
+
+    def rk_step(self, scheme, n_steps, stream=0):
+        self._check(lib().fr_batch_rk_step(self.h, scheme, int(n_steps), ctypes.c_void_p(stream)))
+
+    def state_tensor(self, problem, etype, device="cuda"):
+        import torch
+        q = self.query(problem, etype)
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        return torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=dt, device=device)
 
 
 # ---------------------------------------------------------------------------

@@ -263,3 +263,27 @@ def random_perturbation(shape, seed, amp=1e-2):
     """Seeded multiplicative noise for parity inputs (values in [1-amp, 1+amp])."""
     rng = np.random.default_rng(seed)
     return 1.0 + amp * rng.uniform(-1.0, 1.0, size=shape)
+
+
+# ----------------------------------------------------------------------------
+# Batched workload: many independent periodic Euler problems
+# ----------------------------------------------------------------------------
+
+def batch_problems(n=512, seed=0, e_min=100, e_max=20000):
+    """n independent problems on the unit box, each half prisms (z < 1/2) and
+    half tets (z > 1/2) by volume on an m x m x 2m grid (8 m^3 elements):
+    target element counts log-uniform in [e_min, e_max], m = max(2,
+    round((E/8)^(1/3))), orders uniform in {1, 2, 3, 4}, vertex jitter 5 %.
+    Returns a list of dicts: mesh arrays, order p, vortex centre (random
+    phase) and the problem's seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n):
+        e = float(np.exp(rng.uniform(np.log(e_min), np.log(e_max))))
+        p = int(rng.integers(1, 5))
+        centre = (float(rng.uniform()), float(rng.uniform()))
+        m = max(2, int(round((e / 8.0) ** (1.0 / 3.0))))
+        arrays = mixed_box(m, m, m, m, (1.0, 1.0, 1.0), z_split=0.5, jitter=0.05,
+                           seed=seed * 100003 + b)
+        out.append({"mesh": arrays, "p": p, "centre": centre, "m": m, "seed": seed * 100003 + b})
+    return out

@@ -1,0 +1,165 @@
+"""GPU tests of the batched form: many independent problems with mixed orders
+merged per order, per-problem step sizes, HIP-graph replay of whole RK45[2R+]
+steps, and the operator-product autotuner.
+
+* A batch of problems equals the same problems run as separate meshes
+  (FP64: to 1e-13, the only difference being where dt multiplies).
+* Graph replays equal the eager steps, replay by replay, with eager work
+  and synchronisations between replays.
+* The autotuner leaves right-hand sides bitwise unchanged.
+* Batched problems match the FP64 oracle after RK45 steps (FP32 bound).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as om, rk
+from paper_1409_0405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ("tet", "pri")
+
+
+def _problems(n=6, seed=3):
+    return inputs.batch_problems(n=n, seed=seed, e_min=64, e_max=700)
+
+
+def _dt(prob):
+    lam = 0.5 * math.sqrt(1.4) + math.sqrt(1.4)
+    h = 0.5 / prob["m"]
+    return 0.2 * h / (lam * (2 * prob["p"] + 1))
+
+
+def _host_state(arrays, p, centre):
+    O = om.build_mesh(arrays, p)
+    return O, fr.initial_state(O, inputs.isentropic_vortex, centre=centre, radius=0.15)
+
+
+def _to_dev(U_host, q, dtype):
+    """[E][N][5] oracle layout -> padded device state [N][5][ld]."""
+    t = torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=dtype, device="cuda")
+    ne = q["nelem"]
+    t[:, :, :ne] = torch.as_tensor(np.transpose(U_host, (1, 2, 0)), dtype=dtype)
+    t[:, :, ne:] = t[:, :, :1]
+    return t
+
+
+def _batch(probs, precision):
+    from paper_1409_0405_amd import frlib
+    B = frlib.Batch([(b["mesh"], b["p"]) for b in probs], system="euler", precision=precision)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    states = []
+    for i, b in enumerate(probs):
+        O, U = _host_state(b["mesh"], b["p"], b["centre"])
+        states.append((O, U))
+        for t, n in enumerate(NAMES):
+            q = B.query(i, t)
+            if q["nelem"]:
+                B.set_solution(i, t, _to_dev(U[n], q, dtype).data_ptr())
+    torch.cuda.synchronize()
+    B.set_dt([_dt(b) for b in probs])
+    return B, states
+
+
+def _get(B, i, t, ne):
+    x = B.state_tensor(i, t)
+    B.get_solution(i, t, x.data_ptr())
+    torch.cuda.synchronize()
+    return x[:, :, :ne].double().cpu().numpy()
+
+
+def test_batch_equals_separate_meshes_fp64():
+    from paper_1409_0405_amd import frlib
+    probs = _problems()
+    assert len({b["p"] for b in probs}) >= 3
+    B, states = _batch(probs, "fp64")
+    nsteps = 3
+    B.rk_step(frlib.FR_RK45_2RP, nsteps)
+    torch.cuda.synchronize()
+    for i, b in enumerate(probs):
+        O, U = states[i]
+        M = frlib.Mesh(b["mesh"], b["p"], system="euler", precision="fp64")
+        for t, n in enumerate(NAMES):
+            M.set_solution(t, _to_dev(U[n], M.query(t), torch.float64).data_ptr())
+        M.rk_step(frlib.FR_RK45_2RP, _dt(b), nsteps)
+        for t, n in enumerate(NAMES):
+            q = M.query(t)
+            x = frlib.state_tensor(M, t)
+            M.get_solution(t, x.data_ptr())
+            torch.cuda.synchronize()
+            ref = x[:, :, :q["nelem"]].cpu().numpy()
+            got = _get(B, i, t, q["nelem"])
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"problem {i} p{b['p']} {n}: {err:.2e}", flush=True)
+            assert err < 1e-13, (i, n, err)
+        M.close()
+
+
+def test_graph_replays_match_eager():
+    from paper_1409_0405_amd import frlib
+    probs = _problems(n=5, seed=11)
+    nsteps = 4
+    # eager reference, step by step
+    B, _ = _batch(probs, "fp32")
+    B.set_graph(False)
+    ref = []
+    for s in range(nsteps):
+        B.rk_step(frlib.FR_RK45_2RP, 1)
+        ref.append([[_get(B, i, t, B.query(i, t)["nelem"]) for t in (0, 1)] for i in range(len(probs))])
+    B.close()
+    # graph replays with eager work in between
+    G, _ = _batch(probs, "fp32")
+    G.set_graph(True)
+    for s in range(nsteps):
+        G.rk_step(frlib.FR_RK45_2RP, 1)
+        scratch = torch.randn(1 << 20, device="cuda")
+        (scratch * 2).sum().item()
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            for t in (0, 1):
+                got = _get(G, i, t, G.query(i, t)["nelem"])
+                assert np.array_equal(got, ref[s][i][t]), (s, i, t)
+
+
+def test_autotune_keeps_results_bitwise():
+    from paper_1409_0405_amd import frlib
+    arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=2)
+    p = 3
+    O = om.build_mesh(arrays, p)
+    U = fr.initial_state(O, inputs.taylor_green, mach=0.3)
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.02)
+    u = [frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0))) for t, n in enumerate(NAMES)]
+    r0 = [frlib.state_tensor(M, t) for t in (0, 1)]
+    r1 = [frlib.state_tensor(M, t) for t in (0, 1)]
+    M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r0])
+    rep = M.autotune()
+    print(rep, flush=True)
+    M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r1])
+    torch.cuda.synchronize()
+    for t in (0, 1):
+        assert torch.equal(r0[t], r1[t])
+
+
+def test_batched_problems_match_oracle_fp32():
+    from paper_1409_0405_amd import frlib
+    probs = _problems(n=4, seed=5)
+    B, states = _batch(probs, "fp32")
+    nsteps = 3
+    B.rk_step(frlib.FR_RK45_2RP, nsteps)
+    torch.cuda.synchronize()
+    prm = fr.Params(system="euler")
+    for i, b in enumerate(probs):
+        O, U = states[i]
+        U32 = {n: U[n].astype(np.float32).astype(np.float64) for n in U}
+        Uo = rk.run(rk.rk45_step, lambda V: fr.rhs(O, V, prm), U32, _dt(b), nsteps)
+        num = den = 0.0
+        for t, n in enumerate(NAMES):
+            g = np.transpose(_get(B, i, t, O.types[n].nelem), (2, 0, 1))
+            num += ((g - Uo[n]) ** 2).sum()
+            den += (Uo[n] ** 2).sum()
+        err = math.sqrt(num / den)
+        print(f"problem {i} p{b['p']}: state rel L2 {err:.2e}", flush=True)
+        assert err < 1e-6, (i, err)
