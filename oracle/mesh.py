@@ -125,11 +125,33 @@ def build_mesh(mesh_arrays, p, tol=1e-9):
                 faces.setdefault(tuple(keys[e]), []).append((gid_base[name] + e, fi, name, e))
     pL, pR, nh, sL, sR = [], [], [], [], []
     scale = max(np.ptp(mesh_arrays["xyz"], axis=0).max(), 1.0)
+    period = np.asarray(mesh_arrays["period"], dtype=np.float64)
+
+    def centroid(rec):
+        _, fi, name, e = rec
+        return types[name].X[e, list(types[name].ref.faces[fi])].mean(axis=0)
+
+    def same_face(r1, r2):
+        """Same vertex ids and centroids equal modulo the period: the two
+        sides of one face.  (On periodic meshes two cells wide, distinct faces
+        can share all vertex ids.)"""
+        d = centroid(r1) - centroid(r2)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            d = np.where(period > 0, d - period * np.round(d / np.where(period > 0, period, 1.0)), d)
+        return np.abs(d).max() <= tol * scale
+
+    pairs = []
     for key, lst in faces.items():
-        if len(lst) != 2:
-            raise ValueError(f"face {key} shared by {len(lst)} elements")
         lst.sort()
-        (_, fa, na, ea), (_, fb, nb, eb) = lst
+        left = list(lst)
+        while left:
+            r1 = left.pop(0)
+            match = [r2 for r2 in left if same_face(r1, r2)]
+            if len(match) != 1:
+                raise ValueError(f"face {key} of element {r1[0]} matches {len(match)} faces")
+            left.remove(match[0])
+            pairs.append((r1, match[0]))
+    for (_, fa, na, ea), (_, fb, nb, eb) in pairs:
         A, B = types[na], types[nb]
         ja = np.arange(A.ref.face_offsets[fa], A.ref.face_offsets[fa] + _nface(A.ref, fa))
         jb = np.arange(B.ref.face_offsets[fb], B.ref.face_offsets[fb] + _nface(B.ref, fb))

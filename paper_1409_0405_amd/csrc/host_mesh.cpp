@@ -198,16 +198,30 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
         for (int d = 0; d < 3; ++d) scale = std::max(scale, std::fabs(xyz[3 * v + d]));
     const double tol = 1e-9 * scale;
 
-    for (size_t i = 0; i < recs.size();) {
-        size_t j = i;
-        while (j < recs.size() && recs[j].key == recs[i].key) ++j;
-        if (j - i != 2) {
-            err = "face shared by " + std::to_string(j - i) + " element(s): " +
-                  (recs[i].type ? "prism " : "tet ") + std::to_string(recs[i].elem) + " face " +
-                  std::to_string(recs[i].face);
-            return false;
+    // Faces with the same vertex set are the same physical face seen from two
+    // elements, except on periodic meshes only two cells wide, where distinct
+    // faces can share all vertex ids: those are told apart by their centroids,
+    // which coincide modulo the period for the two sides of one face.
+    auto centroid = [&](const FaceRec &r, double c[3]) {
+        const int nvt = n_verts(r.type);
+        const double *X = &m.t[r.type].X[size_t(r.elem) * nvt * 3];
+        const auto &F = faces_of(r.type)[r.face];
+        c[0] = c[1] = c[2] = 0;
+        for (int a : F)
+            for (int d = 0; d < 3; ++d) c[d] += X[3 * a + d] / double(F.size());
+    };
+    auto same_face = [&](const FaceRec &x, const FaceRec &y) {
+        double cx[3], cy[3];
+        centroid(x, cx);
+        centroid(y, cy);
+        for (int d = 0; d < 3; ++d) {
+            double dd = cx[d] - cy[d];
+            if (period[d] > 0) dd -= period[d] * std::round(dd / period[d]);
+            if (std::fabs(dd) > tol) return false;
         }
-        const FaceRec &A = recs[i], &B = recs[i + 1];   // A sorts first: side L
+        return true;
+    };
+    auto pair_faces = [&](const FaceRec &A, const FaceRec &B) -> bool {   // A sorts first: side L
         const TypeHost &TA = m.t[A.type], &TB = m.t[B.type];
         const int nvA = n_verts(A.type), nvB = n_verts(B.type);
         const double *XA = &TA.X[size_t(A.elem) * nvA * 3];
@@ -276,6 +290,24 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
             q.sR = std::sqrt(nB[0] * nB[0] + nB[1] * nB[1] + nB[2] * nB[2]);
             for (int d = 0; d < 3; ++d) q.n[d] = nA[d] / q.sL;
             pp.push_back(q);
+        }
+        return true;
+    };
+    for (size_t i = 0; i < recs.size();) {
+        size_t j = i;
+        while (j < recs.size() && recs[j].key == recs[i].key) ++j;
+        std::vector<char> done(j - i, 0);
+        for (size_t x = i; x < j; ++x) {
+            if (done[x - i]) continue;
+            size_t y = x + 1;
+            while (y < j && (done[y - i] || !same_face(recs[x], recs[y]))) ++y;
+            if (y == j) {
+                err = "unmatched face: " + std::string(recs[x].type ? "prism " : "tet ") +
+                      std::to_string(recs[x].elem) + " face " + std::to_string(recs[x].face);
+                return false;
+            }
+            done[x - i] = done[y - i] = 1;
+            if (!pair_faces(recs[x], recs[y])) return false;
         }
         i = j;
     }

@@ -96,3 +96,13 @@ def test_error_codes():
     # validate-only meshes refuse device work
     M = frlib.Mesh(good, 2, validate_only=True)
     _expect(frlib.FR_ERR_INVALID_ARG, lambda: M.rk_step(frlib.FR_RK4, 1e-3, 1))
+
+
+def test_two_cell_periodic_mesh_validates():
+    """Distinct faces sharing all vertex ids (periodic, two cells wide) are
+    told apart; solution points match the oracle's."""
+    arrays = inputs.mixed_box(2, 2, 2, 2, (1.0, 1.0, 1.0), z_split=0.5, jitter=0.05, seed=9)
+    M = frlib.Mesh(arrays, 2, validate_only=True)
+    O = om.build_mesh(arrays, 2)
+    for t, name in enumerate(("tet", "pri")):
+        assert np.abs(M.upts_coords(t) - np.transpose(O.types[name].x_upts, (1, 2, 0))).max() < 1e-13

@@ -126,3 +126,22 @@ def test_taylor_green_initial_dissipation():
     R = fr.rhs(M, U, fr.Params(system="ns", mu=mu))
     rate = reduce.kinetic_energy_rate(M, U, R)
     assert abs(-rate / (0.75 * mu) - 1.0) < 0.03, -rate / (0.75 * mu)
+
+
+@pytest.mark.parametrize("p", (1, 3))
+def test_two_cell_periodic_mesh(p):
+    """On a periodic mesh two cells wide distinct faces share all vertex ids;
+    the pairing must still be a perfect matching, and freestream and
+    conservation must hold."""
+    arrays = inputs.mixed_box(2, 2, 2, 2, (1.0, 1.0, 1.0), z_split=0.5, jitter=0.05, seed=9)
+    M = omesh.build_mesh(arrays, p)
+    idx = np.concatenate([M.pair_L, M.pair_R])
+    assert np.array_equal(np.sort(idx), np.arange(M.nfpts_total))
+    prm = fr.Params(system="ns", mu=0.01)
+    R = fr.rhs(M, fr.initial_state(M, inputs.uniform), prm)
+    assert max(np.abs(R[n]).max() for n in R) < 1e-12
+    U = fr.initial_state(M, inputs.isentropic_vortex, radius=0.2)
+    R = fr.rhs(M, U, prm)
+    tot = reduce.integral(M, R)
+    scale = reduce.integral(M, {n: np.abs(R[n]) for n in R})
+    assert np.all(np.abs(tot) <= 1e-12 * scale)
