@@ -235,6 +235,61 @@ fr_status fr_batch_set_graph(fr_batch batch, int32_t enable);
 fr_status fr_batch_rk_step(fr_batch batch, int32_t scheme, int32_t n_steps, void *stream);
 const char *fr_batch_last_error(fr_batch batch);
 
+/* ------------------------------------------------------------------------
+ * Learned closure (low-order meshes) and its network.
+ *
+ * The closure adds to the residual of a mesh the P1 part of a correction
+ * predicted per element by a fully connected network, 120 -> 64 -> 64 -> 20
+ * with tanh, from the P1 moments of the element and of its face neighbours.
+ * P1 moments of a field: m_a = integral over the reference element of
+ * phi_a u, phi_a the Gram-Schmidt orthonormalisation of (1, xi, eta, zeta) in
+ * that order.  Network inputs, element g (type-major), 120 floats: the 5 x 4
+ * moments of g (field-major), then those of the neighbours across local
+ * faces 0..4 (zeros where a tet has no fifth face).  Outputs: 5 x 4 moments
+ * of the residual correction, lifted to the solution points as
+ * sum_a phi_a(x_i) y_a.  Parameters (FP32, FR_MLP_NPARAM floats): W1 [64][120],
+ * b1 [64], W2 [64][64], b2 [64], W3 [20][64], b3 [20].  Statistics
+ * (FR_MLP_NSTATS floats): mu_x [120], s_x [120], mu_y [20], s_y [20]; inputs
+ * are normalised as (x - mu_x) / s_x and outputs scaled back as y s_y + mu_y.
+ */
+#define FR_MLP_NPARAM 13204
+#define FR_MLP_NSTATS 280
+typedef struct fr_mlp_s *fr_mlp;
+/* Network with seeded initial weights, Adam state and gradient workspace. */
+fr_status fr_mlp_create(uint64_t seed, fr_mlp *out);
+fr_status fr_mlp_destroy(fr_mlp net);
+fr_status fr_mlp_set_params(fr_mlp net, const float *params_host);
+fr_status fr_mlp_get_params(fr_mlp net, float *params_host);
+/* y[n][20] = network(x[n][120]) on the device; stats may be NULL (raw in and
+ * out); bf16_weights: use the weights rounded to BF16 (FP32 accumulation). */
+fr_status fr_mlp_forward(fr_mlp net, const float *x_dev, int64_t n, const float *stats_dev,
+                         float *y_dev, int32_t bf16_weights, void *stream);
+/* Gradient of L = sum_s |y_s - t_s|^2 / n (FP32 weights) over the rows
+ * idx_dev[0..n) of x_dev / t_dev (idx_dev NULL: rows 0..n).  The loss is
+ * written to *loss_host if not NULL (this synchronises the stream). */
+fr_status fr_mlp_grad(fr_mlp net, const float *x_dev, const float *t_dev, const int32_t *idx_dev,
+                      int64_t n, double *loss_host, void *stream);
+fr_status fr_mlp_get_grad(fr_mlp net, float *grad_host, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the last gradient. */
+fr_status fr_mlp_adam(fr_mlp net, float lr, void *stream);
+const char *fr_mlp_last_error(fr_mlp net);
+
+/* L2 projection (reference element) of a state of mesh src, order p, to the
+ * order q of mesh dst; both meshes have the same elements and scalar type.
+ * States [n_upts][5][ld] of each mesh.  Allocates its operators on first use. */
+fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void *const u_dst[2],
+                     void *stream);
+/* P1 moments [n_tet + n_pri][20] of a state, and the network inputs
+ * [n_tet + n_pri][120] (normalised with stats_dev unless NULL). */
+fr_status fr_closure_moments(fr_mesh mesh, const void *const u_dev[2], float *mom_dev, void *stream);
+fr_status fr_closure_features(fr_mesh mesh, const void *const u_dev[2], const float *stats_dev,
+                              float *feat_dev, void *stream);
+/* Attach (net != NULL) or detach (net == NULL) the closure: every later
+ * fr_rhs / fr_rk_step of this mesh adds the lifted network correction to the
+ * residual.  net and stats_dev stay owned by the caller and must outlive the
+ * attachment. */
+fr_status fr_closure_attach(fr_mesh mesh, fr_mlp net, const float *stats_dev, int32_t bf16_weights);
+
 /* Message of the last failure on mesh (NULL: of fr_mesh_create on this
  * thread).  Never NULL; valid until the next call on the same mesh. */
 const char *fr_last_error(fr_mesh mesh);

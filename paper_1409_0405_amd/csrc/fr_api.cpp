@@ -76,6 +76,22 @@ struct Profiler {
     }
 };
 
+// Learned closure attached to a mesh (fr_closure_attach).
+struct Closure {
+    const float *params = nullptr;
+    const uint16_t *params_bf16 = nullptr;
+    const float *stats = nullptr;
+    bool bf16 = true;
+    int32_t *nb = nullptr;                    // [ntot][5]
+    float *mom = nullptr, *feat = nullptr, *y = nullptr;
+    float *Mom[2] = {nullptr, nullptr};       // [4][nu] per type
+    float *lift[2] = {nullptr, nullptr};      // [nu][4] per type
+    std::vector<void *> allocs;
+    ~Closure() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
 struct fr_mesh_s {
     int order = 0, system = 0, precision = 0;
     uint32_t flags = 0;
@@ -85,6 +101,7 @@ struct fr_mesh_s {
     bool device = false;
     std::unique_ptr<DevBase> dev;
     Profiler prof;
+    std::unique_ptr<Closure> closure;
     std::string err;
 };
 
@@ -490,6 +507,19 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         }
     }
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
+    const Closure *cl = (m->closure && m->closure->params) ? m->closure.get() : nullptr;
+    if (cl) {
+        for (int t = 0; t < 2; ++t) {
+            DevType<T> &D = d.t[t];
+            if (!D.nelem) continue;
+            FR_HIP(m, frd::launch_moments<T>(U[t], D.ld, D.nelem, D.nu, cl->Mom[t], cl->mom,
+                                             t ? d.t[0].nelem : 0, s));
+        }
+        const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
+        FR_HIP(m, frd::launch_features(cl->mom, cl->nb, ntot, cl->stats, cl->feat, s));
+        FR_HIP(m, frd::launch_mlp_forward(cl->params, cl->params_bf16, cl->bf16, cl->feat, ntot,
+                                          cl->stats, cl->y, s));
+    }
     for (int t = 0; t < 2; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
@@ -499,6 +529,11 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.geom, D.xi, D.ld, D.nelem, D.nu,
                            so[t].per_elem_dt ? D.dte : nullptr};
+        if (cl) {
+            na.cy = cl->y;
+            na.clift = cl->lift[t];
+            na.goff = t ? d.t[0].nelem : 0;
+        }
         FR_LAUNCH(m, 12 + t, s, frd::launch_negdivconf<T>(t, na, s));
     }
     return FR_OK;
@@ -1276,6 +1311,263 @@ fr_status fr_batch_rk_step(fr_batch b, int32_t scheme, int32_t n_steps, void *st
 }
 
 const char *fr_batch_last_error(fr_batch b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"
+
+struct fr_mlp_s {
+    float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *partial = nullptr;
+    uint16_t *params_bf16 = nullptr;
+    int step = 0;
+    std::string err;
+    std::vector<void *> allocs;
+    ~fr_mlp_s() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+fr_status mfail(fr_mlp n, fr_status st, const std::string &msg) {
+    if (n)
+        n->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+#define FR_MHIP(n, call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return mfail(n, e_ == hipErrorOutOfMemory ? FR_ERR_OUT_OF_MEMORY : FR_ERR_DEVICE, \
+                         std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// Host-side FP32 upload into a fresh device allocation owned by `allocs`.
+template <typename V>
+hipError_t upload_vec(std::vector<void *> &allocs, const std::vector<V> &h, V *&dst) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(h.size(), 1) * sizeof(V));
+    if (e != hipSuccess) return e;
+    allocs.push_back(p);
+    dst = static_cast<V *>(p);
+    return h.empty() ? hipSuccess : hipMemcpy(p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice);
+}
+}  // namespace
+
+extern "C" {
+
+fr_status fr_mlp_create(uint64_t seed, fr_mlp *out) {
+    if (!out) return FR_ERR_INVALID_ARG;
+    *out = nullptr;
+    auto n = std::make_unique<fr_mlp_s>();
+    const int np = frd::MLP_NPARAM;
+    // Glorot-style init from a 64-bit LCG + Box-Muller (seeded, portable)
+    std::vector<float> p(np, 0.0f);
+    uint64_t st = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto unif = [&]() {
+        st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+        return (double((st >> 11) & ((1ULL << 53) - 1)) + 0.5) / double(1ULL << 53);
+    };
+    auto normal = [&]() { return std::sqrt(-2.0 * std::log(unif())) * std::cos(6.283185307179586 * unif()); };
+    const int H = frd::MLP_H, I = frd::MLP_IN, O = frd::MLP_OUT;
+    int o = 0;
+    for (int i = 0; i < H * I; ++i) p[o++] = float(normal() * std::sqrt(1.0 / I));
+    o += H;
+    for (int i = 0; i < H * H; ++i) p[o++] = float(normal() * std::sqrt(1.0 / H));
+    o += H;
+    for (int i = 0; i < O * H; ++i) p[o++] = float(0.1 * normal() * std::sqrt(1.0 / H));
+    std::vector<float> z(np + 1, 0.0f);
+    FR_MHIP(nullptr, upload_vec(n->allocs, p, n->params));
+    FR_MHIP(nullptr, upload_vec(n->allocs, z, n->grad));
+    FR_MHIP(nullptr, upload_vec(n->allocs, z, n->m));
+    FR_MHIP(nullptr, upload_vec(n->allocs, z, n->v));
+    std::vector<uint16_t> zb(np, 0);
+    FR_MHIP(nullptr, upload_vec(n->allocs, zb, n->params_bf16));
+    std::vector<float> part(size_t(frd::MLP_GRAD_BLOCKS) * (np + 1), 0.0f);
+    FR_MHIP(nullptr, upload_vec(n->allocs, part, n->partial));
+    FR_MHIP(nullptr, frd::launch_to_bf16(n->params, n->params_bf16, nullptr));
+    FR_MHIP(nullptr, hipDeviceSynchronize());
+    *out = n.release();
+    return FR_OK;
+}
+
+fr_status fr_mlp_destroy(fr_mlp n) {
+    if (n) (void)hipDeviceSynchronize();
+    delete n;
+    return FR_OK;
+}
+
+fr_status fr_mlp_set_params(fr_mlp n, const float *host) {
+    if (!n || !host) return FR_ERR_INVALID_ARG;
+    FR_MHIP(n, hipMemcpy(n->params, host, frd::MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    FR_MHIP(n, frd::launch_to_bf16(n->params, n->params_bf16, nullptr));
+    FR_MHIP(n, hipDeviceSynchronize());
+    n->step = 0;
+    return FR_OK;
+}
+
+fr_status fr_mlp_get_params(fr_mlp n, float *host) {
+    if (!n || !host) return FR_ERR_INVALID_ARG;
+    FR_MHIP(n, hipMemcpy(host, n->params, frd::MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    return FR_OK;
+}
+
+fr_status fr_mlp_forward(fr_mlp n, const float *x, int64_t count, const float *stats, float *y,
+                         int32_t bf16_weights, void *stream) {
+    if (!n || !x || !y || count < 0) return FR_ERR_INVALID_ARG;
+    FR_MHIP(n, frd::launch_mlp_forward(n->params, n->params_bf16, bf16_weights != 0, x, count, stats, y,
+                                       static_cast<hipStream_t>(stream)));
+    return FR_OK;
+}
+
+fr_status fr_mlp_grad(fr_mlp n, const float *x, const float *target, const int32_t *idx, int64_t count,
+                      double *loss_host, void *stream) {
+    if (!n || !x || !target || count <= 0) return FR_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FR_MHIP(n, frd::launch_mlp_grad(n->params, x, target, idx, count, n->partial, frd::MLP_GRAD_BLOCKS,
+                                    n->grad, s));
+    if (loss_host) {
+        float l = 0;
+        FR_MHIP(n, hipMemcpyAsync(&l, n->grad + frd::MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, s));
+        FR_MHIP(n, hipStreamSynchronize(s));
+        *loss_host = l;
+    }
+    return FR_OK;
+}
+
+fr_status fr_mlp_get_grad(fr_mlp n, float *host, void *stream) {
+    if (!n || !host) return FR_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FR_MHIP(n, hipMemcpyAsync(host, n->grad, frd::MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    FR_MHIP(n, hipStreamSynchronize(s));
+    return FR_OK;
+}
+
+fr_status fr_mlp_adam(fr_mlp n, float lr, void *stream) {
+    if (!n || !(lr >= 0)) return FR_ERR_INVALID_ARG;
+    n->step += 1;
+    FR_MHIP(n, frd::launch_adam(n->params, n->grad, n->m, n->v, lr, 0.9f, 0.999f, 1e-8f, n->step,
+                                n->params_bf16, static_cast<hipStream_t>(stream)));
+    return FR_OK;
+}
+
+const char *fr_mlp_last_error(fr_mlp n) { return n ? n->err.c_str() : g_create_error.c_str(); }
+
+fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void *const u_dst[2],
+                     void *stream) {
+    if (fr_status st = check_mesh(src, 0, true)) return st;
+    if (fr_status st = check_mesh(dst, 0, true)) return st;
+    if ((src->precision == FR_FP64) != (dst->precision == FR_FP64))
+        return fail(src, FR_ERR_INVALID_ARG, "projection between meshes of different scalar types");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int t = 0; t < 2; ++t) {
+        const int64_t ne = src->host.t[t].nelem;
+        if (ne != dst->host.t[t].nelem) return fail(src, FR_ERR_INVALID_ARG, "meshes differ in element counts");
+        if (!ne) continue;
+        if (!u_src || !u_dst || !u_src[t] || !u_dst[t]) return fail(src, FR_ERR_INVALID_ARG, "null state");
+        const std::vector<double> P = frh::build_projection(t, src->order, dst->order);
+        const int M = frh::n_upts(t, dst->order), K = frh::n_upts(t, src->order);
+        const int64_t w5 = 5 * src->host.t[t].ld;
+        if (src->precision != FR_FP64) {
+            std::vector<float> f;
+            frd::Op<float> op = fragment<float>(P, M, K, f);
+            {
+                float *p;
+                FR_HIP(src, upload_vec(dev_of<float>(src).allocs, f, p));
+                op.frag = p;
+                FR_HIP(src, frd::launch_opmul<float>(4 * t, op, static_cast<const float *>(u_src[t]), w5, K,
+                                                     nullptr, 0, 0, static_cast<float *>(u_dst[t]), w5, w5, s));
+            }
+        } else {
+            std::vector<double> f;
+            frd::Op<double> op = fragment<double>(P, M, K, f);
+            double *p;
+            FR_HIP(src, upload_vec(dev_of<double>(src).allocs, f, p));
+            op.frag = p;
+            FR_HIP(src, frd::launch_opmul<double>(4 * t, op, static_cast<const double *>(u_src[t]), w5, K,
+                                                  nullptr, 0, 0, static_cast<double *>(u_dst[t]), w5, w5, s));
+        }
+    }
+    return FR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+fr_status closure_tables(fr_mesh m) {
+    if (m->closure) return FR_OK;
+    auto c = std::make_unique<Closure>();
+    const int64_t ntot = m->host.t[0].nelem + m->host.t[1].nelem;
+    std::vector<int32_t> nb = frh::face_neighbours(m->host);
+    FR_HIP(m, upload_vec(c->allocs, nb, c->nb));
+    std::vector<float> z(size_t(ntot) * 20, 0.0f), zf(size_t(ntot) * frd::MLP_IN, 0.0f);
+    FR_HIP(m, upload_vec(c->allocs, z, c->mom));
+    FR_HIP(m, upload_vec(c->allocs, z, c->y));
+    FR_HIP(m, upload_vec(c->allocs, zf, c->feat));
+    for (int t = 0; t < 2; ++t) {
+        if (!m->host.t[t].nelem) continue;
+        const std::vector<double> Mo = frh::build_moments(t, m->order), Li = frh::build_lift(t, m->order);
+        FR_HIP(m, upload_vec(c->allocs, std::vector<float>(Mo.begin(), Mo.end()), c->Mom[t]));
+        FR_HIP(m, upload_vec(c->allocs, std::vector<float>(Li.begin(), Li.end()), c->lift[t]));
+    }
+    c->params = nullptr;
+    m->closure = std::move(c);
+    return FR_OK;
+}
+
+template <typename T>
+fr_status closure_moments_impl(fr_mesh m, const void *const u[2], float *mom, hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    for (int t = 0; t < 2; ++t) {
+        if (!d.t[t].nelem) continue;
+        if (!u || !u[t]) return fail(m, FR_ERR_INVALID_ARG, "null state");
+        FR_HIP(m, frd::launch_moments<T>(static_cast<const T *>(u[t]), d.t[t].ld, d.t[t].nelem, d.t[t].nu,
+                                         m->closure->Mom[t], mom, t ? d.t[0].nelem : 0, s));
+    }
+    return FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_closure_moments(fr_mesh m, const void *const u[2], float *mom, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!mom) return fail(m, FR_ERR_INVALID_ARG, "null output");
+    if (fr_status st = closure_tables(m)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, mom, s)
+                                   : closure_moments_impl<double>(m, u, mom, s);
+}
+
+fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *stats, float *feat,
+                              void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!feat) return fail(m, FR_ERR_INVALID_ARG, "null output");
+    if (fr_status st = closure_tables(m)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    fr_status st = m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, m->closure->mom, s)
+                                           : closure_moments_impl<double>(m, u, m->closure->mom, s);
+    if (st) return st;
+    FR_HIP(m, frd::launch_features(m->closure->mom, m->closure->nb, m->host.t[0].nelem + m->host.t[1].nelem,
+                                   stats, feat, s));
+    return FR_OK;
+}
+
+fr_status fr_closure_attach(fr_mesh m, fr_mlp net, const float *stats, int32_t bf16_weights) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!net) {
+        if (m->closure) m->closure->params = nullptr;
+        m->closure.reset();
+        return FR_OK;
+    }
+    if (!stats) return fail(m, FR_ERR_INVALID_ARG, "normalisation statistics are required");
+    if (fr_status st = closure_tables(m)) return st;
+    m->closure->params = net->params;
+    m->closure->params_bf16 = net->params_bf16;
+    m->closure->stats = stats;
+    m->closure->bf16 = bf16_weights != 0;
+    return FR_OK;
+}
 
 const char *fr_last_error(fr_mesh m) {
     return m ? m->err.c_str() : g_create_error.c_str();

@@ -1,0 +1,292 @@
+// Learned closure kernels: per-element P1 moments, network inputs, and a
+// small fully connected network (120 -> 64 -> 64 -> 20, tanh) with its
+// forward pass, hand-derived backward pass and Adam update.
+//
+// The closure adds to an order-1 residual the P1 part of the difference
+// between the filtered high-order residual and the order-1 residual of the
+// filtered state, as predicted from the element's and its face neighbours'
+// P1 moments.  Parameter layout: W1 [64][120], b1 [64], W2 [64][64], b2 [64],
+// W3 [20][64], b3 [20] (row-major, in this order).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fr_device.hpp"
+
+namespace frd {
+
+namespace {
+
+constexpr int OW1 = 0, OB1 = OW1 + MLP_H * MLP_IN, OW2 = OB1 + MLP_H, OB2 = OW2 + MLP_H * MLP_H;
+constexpr int OW3 = OB2 + MLP_H, OB3 = OW3 + MLP_OUT * MLP_H;
+static_assert(OB3 + MLP_OUT == MLP_NPARAM, "parameter layout");
+
+// Weight read: FP32 master copy, or its BF16 rounding (stored as the high
+// half of the FP32 bit pattern).
+template <bool BF16W>
+__device__ __forceinline__ float wt(const float *p, const uint16_t *pb, int i) {
+    if constexpr (BF16W)
+        return __builtin_bit_cast(float, uint32_t(pb[i]) << 16);
+    else
+        return p[i];
+}
+
+// moments mom[g][v * 4 + a] = sum_i Mom[a][i] U[i][v][e], g = goff + e
+template <typename T>
+__global__ __launch_bounds__(256) void moments_kernel(const T *__restrict__ U, int64_t ld,
+                                                      int64_t nelem, int nu,
+                                                      const float *__restrict__ Mom,
+                                                      float *__restrict__ mom, int64_t goff) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nelem) return;
+    float m[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) m[q] = 0;
+    for (int i = 0; i < nu; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const float u = float(U[(int64_t(i) * 5 + v) * ld + e]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) m[v * 4 + a] += Mom[a * nu + i] * u;
+        }
+    float *out = mom + (goff + e) * 20;
+#pragma unroll
+    for (int q = 0; q < 20; ++q) out[q] = m[q];
+}
+
+// inputs x[g][0..119]: own moments, then the neighbours' across faces 0..4
+// (zeros where there is no such face), normalised (x - mu) / s if stats
+__global__ __launch_bounds__(256) void features_kernel(const float *__restrict__ mom,
+                                                       const int32_t *__restrict__ nb,
+                                                       int64_t ntot,
+                                                       const float *__restrict__ stats,
+                                                       float *__restrict__ feat) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    float *out = feat + g * MLP_IN;
+    for (int b = 0; b < 6; ++b) {
+        const int64_t src = b == 0 ? g : nb[g * 5 + b - 1];
+        for (int q = 0; q < 20; ++q) {
+            float v = src >= 0 ? mom[src * 20 + q] : 0.0f;
+            if (stats) v = (v - stats[b * 20 + q]) / stats[MLP_IN + b * 20 + q];
+            out[b * 20 + q] = v;
+        }
+    }
+}
+
+// y = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3, scaled back y s_y + mu_y if stats.
+template <bool BF16W>
+__global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict__ P,
+                                                         const uint16_t *__restrict__ Pb,
+                                                         const float *__restrict__ X, int64_t n,
+                                                         const float *__restrict__ stats,
+                                                         float *__restrict__ Y) {
+    __shared__ float h1s[64][MLP_H + 1];
+    const int tid = threadIdx.x;
+    const int64_t s = int64_t(blockIdx.x) * 64 + tid;
+    const bool live = s < n;
+    float x[MLP_IN];
+#pragma unroll
+    for (int k = 0; k < MLP_IN; ++k) x[k] = live ? X[s * MLP_IN + k] : 0.0f;
+    for (int j = 0; j < MLP_H; ++j) {
+        float z = wt<BF16W>(P, Pb, OB1 + j);
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) z += wt<BF16W>(P, Pb, OW1 + j * MLP_IN + k) * x[k];
+        h1s[tid][j] = tanhf(z);
+    }
+    float h2[MLP_H];
+    for (int j = 0; j < MLP_H; ++j) {
+        float z = wt<BF16W>(P, Pb, OB2 + j);
+        for (int k = 0; k < MLP_H; ++k) z += wt<BF16W>(P, Pb, OW2 + j * MLP_H + k) * h1s[tid][k];
+        h2[j] = tanhf(z);
+    }
+    if (!live) return;
+    for (int o = 0; o < MLP_OUT; ++o) {
+        float z = wt<BF16W>(P, Pb, OB3 + o);
+#pragma unroll
+        for (int k = 0; k < MLP_H; ++k) z += wt<BF16W>(P, Pb, OW3 + o * MLP_H + k) * h2[k];
+        if (stats) z = z * stats[2 * MLP_IN + MLP_OUT + o] + stats[2 * MLP_IN + o];
+        Y[s * MLP_OUT + o] = z;
+    }
+}
+
+// Gradient of L = sum_s |y_s - t_s|^2 / n over the samples idx[0..n) (or
+// 0..n), FP32 master weights.  Each block (one wavefront) takes chunks of 64
+// samples: every lane runs one sample forward and backward, stages the
+// per-sample vectors in shared memory, then every lane sums the outer
+// products of the parameters it owns over the chunk into the block's
+// partial-gradient row (entry MLP_NPARAM holds the partial loss).
+__global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ P,
+                                                      const float *__restrict__ X,
+                                                      const float *__restrict__ Tg,
+                                                      const int32_t *__restrict__ idx,
+                                                      int64_t n, float *__restrict__ partial) {
+    __shared__ float Xs[64][MLP_IN];
+    __shared__ float H1[64][MLP_H], H2[64][MLP_H], D1[64][MLP_H], D2[64][MLP_H], DY[64][MLP_OUT];
+    const int tid = threadIdx.x;
+    float *part = partial + int64_t(blockIdx.x) * (MLP_NPARAM + 1);
+    for (int p = tid; p <= MLP_NPARAM; p += 64) part[p] = 0.0f;
+    __syncthreads();
+    const float inv_n = 1.0f / float(n);
+    for (int64_t c0 = int64_t(blockIdx.x) * 64; c0 < n; c0 += int64_t(gridDim.x) * 64) {
+        const int64_t s = c0 + tid;
+        const bool live = s < n;
+        const int64_t row = live ? (idx ? int64_t(idx[s]) : s) : 0;
+        for (int k = 0; k < MLP_IN; ++k) Xs[tid][k] = live ? X[row * MLP_IN + k] : 0.0f;
+        for (int j = 0; j < MLP_H; ++j) {
+            float z = P[OB1 + j];
+            for (int k = 0; k < MLP_IN; ++k) z += P[OW1 + j * MLP_IN + k] * Xs[tid][k];
+            H1[tid][j] = tanhf(z);
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            float z = P[OB2 + j];
+            for (int k = 0; k < MLP_H; ++k) z += P[OW2 + j * MLP_H + k] * H1[tid][k];
+            H2[tid][j] = tanhf(z);
+        }
+        float loss = 0.0f;
+        for (int o = 0; o < MLP_OUT; ++o) {
+            float z = P[OB3 + o];
+            for (int k = 0; k < MLP_H; ++k) z += P[OW3 + o * MLP_H + k] * H2[tid][k];
+            const float d = live ? z - Tg[row * MLP_OUT + o] : 0.0f;
+            loss += d * d;
+            DY[tid][o] = 2.0f * d * inv_n;
+        }
+        for (int j = 0; j < MLP_H; ++j) {          // dz2 = (W3^T dy) (1 - h2^2)
+            float a = 0.0f;
+            for (int o = 0; o < MLP_OUT; ++o) a += P[OW3 + o * MLP_H + j] * DY[tid][o];
+            D2[tid][j] = a * (1.0f - H2[tid][j] * H2[tid][j]);
+        }
+        for (int j = 0; j < MLP_H; ++j) {          // dz1 = (W2^T dz2) (1 - h1^2)
+            float a = 0.0f;
+            for (int k = 0; k < MLP_H; ++k) a += P[OW2 + k * MLP_H + j] * D2[tid][k];
+            D1[tid][j] = a * (1.0f - H1[tid][j] * H1[tid][j]);
+        }
+        __syncthreads();
+        // outer products summed over the chunk; lane tid owns every 64th parameter
+        for (int p = tid; p < MLP_NPARAM; p += 64) {
+            float a = 0.0f;
+            if (p < OB1) {
+                const int j = p / MLP_IN, k = p % MLP_IN;
+                for (int q = 0; q < 64; ++q) a += D1[q][j] * Xs[q][k];
+            } else if (p < OW2) {
+                for (int q = 0; q < 64; ++q) a += D1[q][p - OB1];
+            } else if (p < OB2) {
+                const int j = (p - OW2) / MLP_H, k = (p - OW2) % MLP_H;
+                for (int q = 0; q < 64; ++q) a += D2[q][j] * H1[q][k];
+            } else if (p < OW3) {
+                for (int q = 0; q < 64; ++q) a += D2[q][p - OB2];
+            } else if (p < OB3) {
+                const int o = (p - OW3) / MLP_H, k = (p - OW3) % MLP_H;
+                for (int q = 0; q < 64; ++q) a += DY[q][o] * H2[q][k];
+            } else {
+                for (int q = 0; q < 64; ++q) a += DY[q][p - OB3];
+            }
+            part[p] += a;
+        }
+        // partial loss: lane 0 sums the chunk's per-lane losses through shared memory
+        __syncthreads();
+        H1[tid][0] = loss;
+        __syncthreads();
+        if (tid == 0) {
+            float l = 0.0f;
+            for (int q = 0; q < 64; ++q) l += H1[q][0];
+            part[MLP_NPARAM] += l * inv_n;
+        }
+        __syncthreads();
+    }
+}
+
+// grad[p] = sum over blocks of partial[b][p], blocks in order
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *__restrict__ partial,
+                                                         int nblk, float *__restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > MLP_NPARAM) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += partial[int64_t(b) * (MLP_NPARAM + 1) + p];
+    grad[p] = s;
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr (m / c1) / (sqrt(v / c2) + eps); also refresh the BF16 copy.
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ P, const float *__restrict__ G,
+                                                   float *__restrict__ M, float *__restrict__ V,
+                                                   float lr, float b1, float b2, float eps, float c1,
+                                                   float c2, uint16_t *__restrict__ Pb) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    const float g = G[p];
+    const float m = b1 * M[p] + (1.0f - b1) * g;
+    const float v = b2 * V[p] + (1.0f - b2) * g * g;
+    M[p] = m;
+    V[p] = v;
+    const float w = P[p] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    P[p] = w;
+    uint32_t b = __builtin_bit_cast(uint32_t, w);
+    b += 0x7fffu + ((b >> 16) & 1u);   // round to nearest even
+    Pb[p] = uint16_t(b >> 16);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float *__restrict__ P, uint16_t *__restrict__ Pb) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    uint32_t b = __builtin_bit_cast(uint32_t, P[p]);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    Pb[p] = uint16_t(b >> 16);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_moments(const T *U, int64_t ld, int64_t nelem, int nu, const float *Mom, float *mom,
+                          int64_t goff, hipStream_t s) {
+    if (!nelem) return hipSuccess;
+    moments_kernel<T><<<unsigned((nelem + 255) / 256), 256, 0, s>>>(U, ld, nelem, nu, Mom, mom, goff);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, const float *stats,
+                           float *feat, hipStream_t s) {
+    if (!ntot) return hipSuccess;
+    features_kernel<<<unsigned((ntot + 255) / 256), 256, 0, s>>>(mom, nb, ntot, stats, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
+                              const float *stats, float *Y, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const unsigned g = unsigned((n + 63) / 64);
+    if (bf16)
+        mlp_forward_kernel<true><<<g, 64, 0, s>>>(P, Pb, X, n, stats, Y);
+    else
+        mlp_forward_kernel<false><<<g, 64, 0, s>>>(P, Pb, X, n, stats, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
+                           float *partial, int nblk, float *grad, hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    const int64_t chunks = (n + 63) / 64;
+    const int g = int(chunks < nblk ? chunks : nblk);
+    mlp_grad_kernel<<<g, 64, 0, s>>>(P, X, Tg, idx, n, partial);
+    mlp_reduce_kernel<<<(MLP_NPARAM + 256) / 256, 256, 0, s>>>(partial, g, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps,
+                       int t, uint16_t *Pb, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, float(t)), c2 = 1.0f - powf(b2, float(t));
+    adam_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(P, G, M, V, lr, b1, b2, eps, c1, c2, Pb);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *P, uint16_t *Pb, hipStream_t s) {
+    to_bf16_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(P, Pb);
+    return hipGetLastError();
+}
+
+template hipError_t launch_moments<float>(const float *, int64_t, int64_t, int, const float *, float *,
+                                          int64_t, hipStream_t);
+template hipError_t launch_moments<double>(const double *, int64_t, int64_t, int, const float *, float *,
+                                           int64_t, hipStream_t);
+
+}  // namespace frd

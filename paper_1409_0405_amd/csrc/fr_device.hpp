@@ -104,6 +104,10 @@ struct NegArgs {
     int64_t ld, nelem;
     int nu;
     const T *dte;      // per-element step size, or null
+    // learned closure: k += sum_a lift[i][a] y[goff + e][v * 4 + a]
+    const float *cy = nullptr;
+    const float *clift = nullptr;   // [nu][4]
+    int64_t goff = 0;
 };
 template <typename T>
 hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s);
@@ -123,6 +127,24 @@ constexpr int RED_BLOCKS = 512;
 template <typename T>
 hipError_t launch_reduce(const RedArgs<T> &a, hipStream_t s);
 hipError_t launch_reduce_final(const double *partial, int nblocks, double *out, hipStream_t s);
+
+// Learned closure (fr_closure.hip).
+constexpr int MLP_IN = 120, MLP_H = 64, MLP_OUT = 20;
+constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_OUT * MLP_H + MLP_OUT;
+constexpr int MLP_NSTATS = 2 * MLP_IN + 2 * MLP_OUT;   // mu_x, s_x, mu_y, s_y
+constexpr int MLP_GRAD_BLOCKS = 256;
+template <typename T>
+hipError_t launch_moments(const T *U, int64_t ld, int64_t nelem, int nu, const float *Mom, float *mom,
+                          int64_t goff, hipStream_t s);
+hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, const float *stats,
+                           float *feat, hipStream_t s);
+hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
+                              const float *stats, float *Y, hipStream_t s);
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
+                           float *partial, int nblk, float *grad, hipStream_t s);
+hipError_t launch_adam(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps,
+                       int t, uint16_t *Pb, hipStream_t s);
+hipError_t launch_to_bf16(const float *P, uint16_t *Pb, hipStream_t s);
 
 template <typename T>
 hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s);

@@ -44,6 +44,16 @@ const RefOps &ref_cached(int etype, int p);
 int n_upts(int etype, int p);
 int n_fpts(int etype, int p);
 
+// Learned-closure operators (reference element).  phi_a (a = 0..3) is the
+// Gram-Schmidt orthonormalisation of (1, xi, eta, zeta), in that order,
+// under the reference L2 inner product.
+//   moments    [4][nu(p)]   m_a = int phi_a u from nodal values of order p
+//   lift       [nu(p)][4]   nodal values of sum_a phi_a y_a
+//   projection [nu(q)][nu(p)]  L2 projection from order p to order q
+std::vector<double> build_moments(int etype, int p);
+std::vector<double> build_lift(int etype, int p);
+std::vector<double> build_projection(int etype, int p, int q);
+
 // Reference vertices and faces
 const std::vector<std::vector<int>> &faces_of(int etype);
 int n_verts(int etype);
@@ -81,6 +91,10 @@ struct MeshHost {
     PairTable pairs;
     double volume = 0;
 };
+
+// Neighbour across each local face, global type-major element id
+// [n_tet + n_pri][5], -1 where the element has no such face.
+std::vector<int32_t> face_neighbours(const MeshHost &m);
 
 // Builds geometry and pairing; returns false with a message on a bad mesh.
 bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet,

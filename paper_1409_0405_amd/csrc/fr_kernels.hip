@@ -531,12 +531,18 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
     if (e >= a.nelem) return;
     const int64_t ld = a.ld;
     T adj[3][3];
-    T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
-    if (a.dte) Jinv *= a.dte[e];
+    const T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    const T sc = a.dte ? a.dte[e] : T(1);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         const int64_t o = (int64_t(i) * 5 + v) * ld + e;
-        const T k = -a.Rt[o] * Jinv;
+        T k = -a.Rt[o] * Jinv;
+        if (a.cy) {
+            const float *y = a.cy + (a.goff + e) * 20 + v * 4;
+            const float *l = a.clift + i * 4;
+            k += T(l[0] * y[0] + l[1] * y[1] + l[2] * y[2] + l[3] * y[3]);
+        }
+        k *= sc;
         T accv = 0;
         if (a.acc) {
             accv = a.acc[o] + a.a * k;

@@ -334,6 +334,26 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
     return true;
 }
 
+std::vector<int32_t> face_neighbours(const MeshHost &m) {
+    const int64_t nt = m.t[0].nelem, ntot = nt + m.t[1].nelem;
+    std::vector<int32_t> nb(size_t(ntot) * 5, -1);
+    auto info = [&](uint32_t s, int64_t &g, int &f) {
+        const int t = int(s >> 31);
+        const int64_t e = s & 0xffffffu;
+        g = (t ? nt : 0) + e;
+        f = m.t[t].ops.fface[(s >> 24) & 0x7f];
+    };
+    for (size_t j = 0; j < m.pairs.sideL.size(); ++j) {
+        int64_t gl, gr;
+        int fl, fr;
+        info(m.pairs.sideL[j], gl, fl);
+        info(m.pairs.sideR[j], gr, fr);
+        nb[size_t(gl) * 5 + fl] = int32_t(gr);
+        nb[size_t(gr) * 5 + fr] = int32_t(gl);
+    }
+    return nb;
+}
+
 bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
                   std::vector<std::array<int64_t, 2>> &elem_off, std::string &err) {
     if (parts.empty()) {

@@ -497,6 +497,120 @@ RefOps build_ref(int etype, int p) {
     return R;
 }
 
+namespace {
+
+// Nodal Lagrange values of order p at reference point x (monomial route).
+struct Lagrange {
+    Monos B;
+    std::vector<ld> Vinv;
+    int n;
+    Lagrange(int etype, int p) : B(etype, p) {
+        const RefOps &R = ref_cached(etype, p);
+        n = R.nu;
+        Vinv.assign(size_t(n) * n, 0);
+        std::vector<ld> val(n);
+        for (int i = 0; i < n; ++i) {
+            ld x[3] = {R.upts[3 * i], R.upts[3 * i + 1], R.upts[3 * i + 2]};
+            B.eval(x, val.data(), nullptr);
+            for (int a = 0; a < n; ++a) Vinv[size_t(i) * n + a] = val[a];
+        }
+        invert(Vinv, n);
+    }
+    void eval(const ld *x, ld *out) const {
+        std::vector<ld> val(n);
+        B.eval(x, val.data(), nullptr);
+        for (int i = 0; i < n; ++i) {
+            ld s = 0;
+            for (int a = 0; a < n; ++a) s += val[a] * Vinv[size_t(a) * n + i];
+            out[i] = s;
+        }
+    }
+};
+
+// phi = Linv (1, xi, eta, zeta) with G = L L^T over the reference element.
+void p1_basis(int etype, ld Linv[4][4]) {
+    std::vector<ld> qp, qw;
+    volume_rule(etype, 3, qp, qw);
+    ld G[4][4] = {};
+    for (size_t q = 0; q < qw.size(); ++q) {
+        ld m[4] = {1, qp[3 * q], qp[3 * q + 1], qp[3 * q + 2]};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) G[a][b] += qw[q] * m[a] * m[b];
+    }
+    ld L[4][4] = {};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j <= i; ++j) {
+            ld s = G[i][j];
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = (i == j) ? std::sqrt(s) : s / L[j][j];
+        }
+    for (int c = 0; c < 4; ++c)           // Linv columns by forward substitution
+        for (int i = 0; i < 4; ++i) {
+            ld s = (i == c) ? 1 : 0;
+            for (int k = 0; k < i; ++k) s -= L[i][k] * Linv[k][c];
+            Linv[i][c] = s / L[i][i];
+        }
+}
+
+void p1_eval(const ld Linv[4][4], const ld *x, ld phi[4]) {
+    const ld m[4] = {1, x[0], x[1], x[2]};
+    for (int a = 0; a < 4; ++a) {
+        phi[a] = 0;
+        for (int b = 0; b <= a; ++b) phi[a] += Linv[a][b] * m[b];
+    }
+}
+
+}  // namespace
+
+std::vector<double> build_moments(int etype, int p) {
+    Lagrange Lg(etype, p);
+    ld Linv[4][4];
+    p1_basis(etype, Linv);
+    std::vector<ld> qp, qw;
+    volume_rule(etype, p + 3, qp, qw);
+    std::vector<ld> acc(size_t(4) * Lg.n, 0), l(Lg.n);
+    for (size_t q = 0; q < qw.size(); ++q) {
+        ld phi[4];
+        p1_eval(Linv, &qp[3 * q], phi);
+        Lg.eval(&qp[3 * q], l.data());
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < Lg.n; ++i) acc[size_t(a) * Lg.n + i] += qw[q] * phi[a] * l[i];
+    }
+    return std::vector<double>(acc.begin(), acc.end());
+}
+
+std::vector<double> build_lift(int etype, int p) {
+    const RefOps &R = ref_cached(etype, p);
+    ld Linv[4][4];
+    p1_basis(etype, Linv);
+    std::vector<double> out(size_t(R.nu) * 4);
+    for (int i = 0; i < R.nu; ++i) {
+        ld x[3] = {R.upts[3 * i], R.upts[3 * i + 1], R.upts[3 * i + 2]}, phi[4];
+        p1_eval(Linv, x, phi);
+        for (int a = 0; a < 4; ++a) out[size_t(i) * 4 + a] = double(phi[a]);
+    }
+    return out;
+}
+
+std::vector<double> build_projection(int etype, int p, int q) {
+    Lagrange Ls(etype, p), Ld(etype, q);
+    std::vector<ld> qp, qw;
+    volume_rule(etype, (p + q) / 2 + 3, qp, qw);
+    const int ns = Ls.n, nd = Ld.n;
+    std::vector<ld> M(size_t(nd) * nd, 0), C(size_t(nd) * ns, 0), ls(ns), lq(nd);
+    for (size_t k = 0; k < qw.size(); ++k) {
+        Ls.eval(&qp[3 * k], ls.data());
+        Ld.eval(&qp[3 * k], lq.data());
+        for (int i = 0; i < nd; ++i) {
+            for (int j = 0; j < nd; ++j) M[size_t(i) * nd + j] += qw[k] * lq[i] * lq[j];
+            for (int j = 0; j < ns; ++j) C[size_t(i) * ns + j] += qw[k] * lq[i] * ls[j];
+        }
+    }
+    invert(M, nd);
+    auto P = matmul(M, C, nd, nd, ns);
+    return std::vector<double>(P.begin(), P.end());
+}
+
 const RefOps &ref_cached(int etype, int p) {
     static std::mutex mu;
     static std::map<std::pair<int, int>, RefOps> cache;

@@ -33,7 +33,11 @@ EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coord
             "fr_batch_create", "fr_batch_destroy", "fr_batch_query", "fr_batch_upts_coords",
             "fr_batch_set_solution",
             "fr_batch_get_solution", "fr_batch_set_dt", "fr_batch_set_graph", "fr_batch_rk_step",
-            "fr_batch_last_error", "fr_last_error")
+            "fr_batch_last_error", "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_params",
+            "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_get_grad", "fr_mlp_adam",
+            "fr_mlp_last_error", "fr_project", "fr_closure_moments", "fr_closure_features",
+            "fr_closure_attach", "fr_last_error")
+MLP_NPARAM, MLP_NSTATS = 13204, 280
 
 PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
@@ -101,10 +105,25 @@ def lib():
         L.fr_batch_rk_step.argtypes = [vp, i32, i32, vp]
         L.fr_batch_last_error.argtypes = [vp]
         L.fr_batch_last_error.restype = ctypes.c_char_p
+        fp, ip = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)
+        L.fr_mlp_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.fr_mlp_destroy.argtypes = [vp]
+        L.fr_mlp_set_params.argtypes = [vp, fp]
+        L.fr_mlp_get_params.argtypes = [vp, fp]
+        L.fr_mlp_forward.argtypes = [vp, vp, i64, vp, vp, i32, vp]
+        L.fr_mlp_grad.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(dbl), vp]
+        L.fr_mlp_get_grad.argtypes = [vp, fp, vp]
+        L.fr_mlp_adam.argtypes = [vp, ctypes.c_float, vp]
+        L.fr_mlp_last_error.argtypes = [vp]
+        L.fr_mlp_last_error.restype = ctypes.c_char_p
+        L.fr_project.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp]
+        L.fr_closure_moments.argtypes = [vp, ctypes.POINTER(vp), vp, vp]
+        L.fr_closure_features.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp]
+        L.fr_closure_attach.argtypes = [vp, vp, vp, i32]
         L.fr_last_error.argtypes = [vp]
         L.fr_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("fr_last_error", "fr_batch_last_error"):
+            if name not in ("fr_last_error", "fr_batch_last_error", "fr_mlp_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -232,6 +251,25 @@ class Mesh:
         _check(lib().fr_profile_read(self.h, _ptr(ms, ctypes.c_double), _ptr(cnt, ctypes.c_int64)), self.h)
         return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_CLASSES)}
 
+    def project_to(self, dst, u_ptrs, v_ptrs, stream=0):
+        """L2-project a state of this mesh onto mesh dst (same elements)."""
+        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        V = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in v_ptrs])
+        _check(lib().fr_project(self.h, U, dst.h, V, ctypes.c_void_p(stream)), self.h)
+
+    def closure_moments(self, u_ptrs, mom_ptr, stream=0):
+        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        _check(lib().fr_closure_moments(self.h, U, ctypes.c_void_p(mom_ptr), ctypes.c_void_p(stream)), self.h)
+
+    def closure_features(self, u_ptrs, stats_ptr, feat_ptr, stream=0):
+        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        _check(lib().fr_closure_features(self.h, U, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(feat_ptr),
+                                         ctypes.c_void_p(stream)), self.h)
+
+    def closure_attach(self, net, stats_ptr=0, bf16_weights=True):
+        _check(lib().fr_closure_attach(self.h, net.h if net is not None else None,
+                                       ctypes.c_void_p(stats_ptr or 0), 1 if bf16_weights else 0), self.h)
+
     def intermediate(self, etype, which, dst_ptr, stream=0):
         _check(lib().fr_intermediate(self.h, etype, which, ctypes.c_void_p(dst_ptr),
                                      ctypes.c_void_p(stream)), self.h)
@@ -307,6 +345,62 @@ class Batch:
         q = self.query(problem, etype)
         dt = torch.float64 if self.precision == "fp64" else torch.float32
         return torch.zeros((q["nupts"], 5, max(q["ld"], 64)), dtype=dt, device=device)
+
+
+class MLP:
+    """The closure network (fr_mlp): weights, Adam state, gradient workspace."""
+
+    def __init__(self, seed=0):
+        h = ctypes.c_void_p()
+        st = lib().fr_mlp_create(int(seed), ctypes.byref(h))
+        if st != FR_OK:
+            raise FrError(st, lib().fr_mlp_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != FR_OK:
+            raise FrError(st, lib().fr_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == MLP_NPARAM
+        self._check(lib().fr_mlp_set_params(self.h, _ptr(a, ctypes.c_float)))
+
+    def get_params(self):
+        a = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(lib().fr_mlp_get_params(self.h, _ptr(a, ctypes.c_float)))
+        return a
+
+    def forward(self, x_ptr, n, y_ptr, stats_ptr=0, bf16_weights=False, stream=0):
+        self._check(lib().fr_mlp_forward(self.h, ctypes.c_void_p(x_ptr), int(n), ctypes.c_void_p(stats_ptr or 0),
+                                         ctypes.c_void_p(y_ptr), 1 if bf16_weights else 0,
+                                         ctypes.c_void_p(stream)))
+
+    def grad(self, x_ptr, t_ptr, n, idx_ptr=0, want_loss=True, stream=0):
+        loss = ctypes.c_double()
+        self._check(lib().fr_mlp_grad(self.h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr),
+                                      ctypes.c_void_p(idx_ptr or 0), int(n),
+                                      ctypes.byref(loss) if want_loss else None, ctypes.c_void_p(stream)))
+        return loss.value if want_loss else None
+
+    def get_grad(self, stream=0):
+        a = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(lib().fr_mlp_get_grad(self.h, _ptr(a, ctypes.c_float), ctypes.c_void_p(stream)))
+        return a
+
+    def adam(self, lr, stream=0):
+        self._check(lib().fr_mlp_adam(self.h, float(lr), ctypes.c_void_p(stream)))
 
 
 # ---------------------------------------------------------------------------
