@@ -265,10 +265,13 @@ fr_status fr_mlp_get_params(fr_mlp net, float *params_host);
 fr_status fr_mlp_forward(fr_mlp net, const float *x_dev, int64_t n, const float *stats_dev,
                          float *y_dev, int32_t bf16_weights, void *stream);
 /* Gradient of L = sum_s |y_s - t_s|^2 / n (FP32 weights) over the rows
- * idx_dev[0..n) of x_dev / t_dev (idx_dev NULL: rows 0..n).  The loss is
- * written to *loss_host if not NULL (this synchronises the stream). */
+ * idx_dev[0..n) of x_dev / t_dev (idx_dev NULL: rows 0..n).  With stats_dev,
+ * rows are standardised as they are read: x by (mu_x, s_x), t by (mu_y, s_y)
+ * (the loss is then that of the normalised targets).  The loss is written to
+ * *loss_host if not NULL (this synchronises the stream).  The gradient stays
+ * in the network's workspace for fr_mlp_get_grad / fr_mlp_adam. */
 fr_status fr_mlp_grad(fr_mlp net, const float *x_dev, const float *t_dev, const int32_t *idx_dev,
-                      int64_t n, double *loss_host, void *stream);
+                      int64_t n, const float *stats_dev, double *loss_host, void *stream);
 fr_status fr_mlp_get_grad(fr_mlp net, float *grad_host, void *stream);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the last gradient. */
 fr_status fr_mlp_adam(fr_mlp net, float lr, void *stream);
@@ -284,6 +287,10 @@ fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void 
 fr_status fr_closure_moments(fr_mesh mesh, const void *const u_dev[2], float *mom_dev, void *stream);
 fr_status fr_closure_features(fr_mesh mesh, const void *const u_dev[2], const float *stats_dev,
                               float *feat_dev, void *stream);
+/* Network targets [n_tet + n_pri][20]: P1 moments of a_dev - b_dev,
+ * normalised as (m - mu_y) / s_y with stats_dev unless NULL. */
+fr_status fr_closure_targets(fr_mesh mesh, const void *const a_dev[2], const void *const b_dev[2],
+                             const float *stats_dev, float *out_dev, void *stream);
 /* Attach (net != NULL) or detach (net == NULL) the closure: every later
  * fr_rhs / fr_rk_step of this mesh adds the lifted network correction to the
  * residual.  net and stats_dev stay owned by the caller and must outlive the

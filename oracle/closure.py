@@ -196,3 +196,13 @@ def correction(mesh, U, p, theta, stats, nb=None):
         out[n] = np.einsum("ia,eva->eiv", Phi, y[g:g + E].reshape(E, 5, 4))
         g += E
     return out
+
+
+def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) at step t >= 1; returns the
+    new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -102,6 +103,10 @@ struct fr_mesh_s {
     std::unique_ptr<DevBase> dev;
     Profiler prof;
     std::unique_ptr<Closure> closure;
+    // projection operators to other orders, key 16 * type + target order
+    // (fragments live in the device allocations of this mesh)
+    std::map<int, frd::Op<float>> proj_f;
+    std::map<int, frd::Op<double>> proj_d;
     std::string err;
 };
 
@@ -512,8 +517,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         for (int t = 0; t < 2; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
-            FR_HIP(m, frd::launch_moments<T>(U[t], D.ld, D.nelem, D.nu, cl->Mom[t], cl->mom,
-                                             t ? d.t[0].nelem : 0, s));
+            FR_HIP(m, frd::launch_moments<T>(U[t], nullptr, D.ld, D.nelem, D.nu, cl->Mom[t], cl->mom,
+                                             t ? d.t[0].nelem : 0, nullptr, s));
         }
         const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
         FR_HIP(m, frd::launch_features(cl->mom, cl->nb, ntot, cl->stats, cl->feat, s));
@@ -1420,10 +1425,10 @@ fr_status fr_mlp_forward(fr_mlp n, const float *x, int64_t count, const float *s
 }
 
 fr_status fr_mlp_grad(fr_mlp n, const float *x, const float *target, const int32_t *idx, int64_t count,
-                      double *loss_host, void *stream) {
+                      const float *stats, double *loss_host, void *stream) {
     if (!n || !x || !target || count <= 0) return FR_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    FR_MHIP(n, frd::launch_mlp_grad(n->params, x, target, idx, count, n->partial, frd::MLP_GRAD_BLOCKS,
+    FR_MHIP(n, frd::launch_mlp_grad(n->params, x, target, idx, count, stats, n->partial, frd::MLP_GRAD_BLOCKS,
                                     n->grad, s));
     if (loss_host) {
         float l = 0;
@@ -1464,26 +1469,32 @@ fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void 
         if (ne != dst->host.t[t].nelem) return fail(src, FR_ERR_INVALID_ARG, "meshes differ in element counts");
         if (!ne) continue;
         if (!u_src || !u_dst || !u_src[t] || !u_dst[t]) return fail(src, FR_ERR_INVALID_ARG, "null state");
-        const std::vector<double> P = frh::build_projection(t, src->order, dst->order);
         const int M = frh::n_upts(t, dst->order), K = frh::n_upts(t, src->order);
         const int64_t w5 = 5 * src->host.t[t].ld;
+        const int key = 16 * t + dst->order;
         if (src->precision != FR_FP64) {
-            std::vector<float> f;
-            frd::Op<float> op = fragment<float>(P, M, K, f);
-            {
+            auto it = src->proj_f.find(key);
+            if (it == src->proj_f.end()) {
+                std::vector<float> f;
+                frd::Op<float> op = fragment<float>(frh::build_projection(t, src->order, dst->order), M, K, f);
                 float *p;
                 FR_HIP(src, upload_vec(dev_of<float>(src).allocs, f, p));
                 op.frag = p;
-                FR_HIP(src, frd::launch_opmul<float>(4 * t, op, static_cast<const float *>(u_src[t]), w5, K,
-                                                     nullptr, 0, 0, static_cast<float *>(u_dst[t]), w5, w5, s));
+                it = src->proj_f.emplace(key, op).first;
             }
+            FR_HIP(src, frd::launch_opmul<float>(4 * t, it->second, static_cast<const float *>(u_src[t]), w5, K,
+                                                 nullptr, 0, 0, static_cast<float *>(u_dst[t]), w5, w5, s));
         } else {
-            std::vector<double> f;
-            frd::Op<double> op = fragment<double>(P, M, K, f);
-            double *p;
-            FR_HIP(src, upload_vec(dev_of<double>(src).allocs, f, p));
-            op.frag = p;
-            FR_HIP(src, frd::launch_opmul<double>(4 * t, op, static_cast<const double *>(u_src[t]), w5, K,
+            auto it = src->proj_d.find(key);
+            if (it == src->proj_d.end()) {
+                std::vector<double> f;
+                frd::Op<double> op = fragment<double>(frh::build_projection(t, src->order, dst->order), M, K, f);
+                double *p;
+                FR_HIP(src, upload_vec(dev_of<double>(src).allocs, f, p));
+                op.frag = p;
+                it = src->proj_d.emplace(key, op).first;
+            }
+            FR_HIP(src, frd::launch_opmul<double>(4 * t, it->second, static_cast<const double *>(u_src[t]), w5, K,
                                                   nullptr, 0, 0, static_cast<double *>(u_dst[t]), w5, w5, s));
         }
     }
@@ -1515,13 +1526,15 @@ fr_status closure_tables(fr_mesh m) {
 }
 
 template <typename T>
-fr_status closure_moments_impl(fr_mesh m, const void *const u[2], float *mom, hipStream_t s) {
+fr_status closure_moments_impl(fr_mesh m, const void *const u[2], const void *const b[2], float *mom,
+                               const float *ystats, hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
     for (int t = 0; t < 2; ++t) {
         if (!d.t[t].nelem) continue;
-        if (!u || !u[t]) return fail(m, FR_ERR_INVALID_ARG, "null state");
-        FR_HIP(m, frd::launch_moments<T>(static_cast<const T *>(u[t]), d.t[t].ld, d.t[t].nelem, d.t[t].nu,
-                                         m->closure->Mom[t], mom, t ? d.t[0].nelem : 0, s));
+        if (!u || !u[t] || (b && !b[t])) return fail(m, FR_ERR_INVALID_ARG, "null state");
+        FR_HIP(m, frd::launch_moments<T>(static_cast<const T *>(u[t]), b ? static_cast<const T *>(b[t]) : nullptr,
+                                         d.t[t].ld, d.t[t].nelem, d.t[t].nu, m->closure->Mom[t], mom,
+                                         t ? d.t[0].nelem : 0, ystats, s));
     }
     return FR_OK;
 }
@@ -1535,8 +1548,19 @@ fr_status fr_closure_moments(fr_mesh m, const void *const u[2], float *mom, void
     if (!mom) return fail(m, FR_ERR_INVALID_ARG, "null output");
     if (fr_status st = closure_tables(m)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, mom, s)
-                                   : closure_moments_impl<double>(m, u, mom, s);
+    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, nullptr, mom, nullptr, s)
+                                   : closure_moments_impl<double>(m, u, nullptr, mom, nullptr, s);
+}
+
+fr_status fr_closure_targets(fr_mesh m, const void *const a[2], const void *const b[2], const float *stats,
+                             float *out, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!out || !b) return fail(m, FR_ERR_INVALID_ARG, "null argument");
+    if (fr_status st = closure_tables(m)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const float *ys = stats ? stats + 2 * frd::MLP_IN : nullptr;
+    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, a, b, out, ys, s)
+                                   : closure_moments_impl<double>(m, a, b, out, ys, s);
 }
 
 fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *stats, float *feat,
@@ -1545,8 +1569,8 @@ fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *st
     if (!feat) return fail(m, FR_ERR_INVALID_ARG, "null output");
     if (fr_status st = closure_tables(m)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    fr_status st = m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, m->closure->mom, s)
-                                           : closure_moments_impl<double>(m, u, m->closure->mom, s);
+    fr_status st = m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, nullptr, m->closure->mom, nullptr, s)
+                                           : closure_moments_impl<double>(m, u, nullptr, m->closure->mom, nullptr, s);
     if (st) return st;
     FR_HIP(m, frd::launch_features(m->closure->mom, m->closure->nb, m->host.t[0].nelem + m->host.t[1].nelem,
                                    stats, feat, s));

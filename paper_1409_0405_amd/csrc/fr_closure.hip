@@ -32,11 +32,13 @@ __device__ __forceinline__ float wt(const float *p, const uint16_t *pb, int i) {
 }
 
 // moments mom[g][v * 4 + a] = sum_i Mom[a][i] U[i][v][e], g = goff + e
+// (of U - B when B is given; targets then normalised (m - mu_y) / s_y if ystats)
 template <typename T>
-__global__ __launch_bounds__(256) void moments_kernel(const T *__restrict__ U, int64_t ld,
-                                                      int64_t nelem, int nu,
+__global__ __launch_bounds__(256) void moments_kernel(const T *__restrict__ U, const T *__restrict__ B,
+                                                      int64_t ld, int64_t nelem, int nu,
                                                       const float *__restrict__ Mom,
-                                                      float *__restrict__ mom, int64_t goff) {
+                                                      float *__restrict__ mom, int64_t goff,
+                                                      const float *__restrict__ ystats) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= nelem) return;
     float m[20];
@@ -45,13 +47,14 @@ __global__ __launch_bounds__(256) void moments_kernel(const T *__restrict__ U, i
     for (int i = 0; i < nu; ++i)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const float u = float(U[(int64_t(i) * 5 + v) * ld + e]);
+            const int64_t o = (int64_t(i) * 5 + v) * ld + e;
+            const float u = B ? float(U[o] - B[o]) : float(U[o]);
 #pragma unroll
             for (int a = 0; a < 4; ++a) m[v * 4 + a] += Mom[a * nu + i] * u;
         }
     float *out = mom + (goff + e) * 20;
 #pragma unroll
-    for (int q = 0; q < 20; ++q) out[q] = m[q];
+    for (int q = 0; q < 20; ++q) out[q] = ystats ? (m[q] - ystats[q]) / ystats[MLP_OUT + q] : m[q];
 }
 
 // inputs x[g][0..119]: own moments, then the neighbours' across faces 0..4
@@ -111,7 +114,8 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict
 }
 
 // Gradient of L = sum_s |y_s - t_s|^2 / n over the samples idx[0..n) (or
-// 0..n), FP32 master weights.  Each block (one wavefront) takes chunks of 64
+// 0..n), FP32 master weights; with stats, rows are standardised on load
+// (x - mu_x) / s_x and (t - mu_y) / s_y.  Each block (one wavefront) takes chunks of 64
 // samples: every lane runs one sample forward and backward, stages the
 // per-sample vectors in shared memory, then every lane sums the outer
 // products of the parameters it owns over the chunk into the block's
@@ -120,7 +124,8 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
                                                       const float *__restrict__ X,
                                                       const float *__restrict__ Tg,
                                                       const int32_t *__restrict__ idx,
-                                                      int64_t n, float *__restrict__ partial) {
+                                                      int64_t n, const float *__restrict__ stats,
+                                                      float *__restrict__ partial) {
     __shared__ float Xs[64][MLP_IN];
     __shared__ float H1[64][MLP_H], H2[64][MLP_H], D1[64][MLP_H], D2[64][MLP_H], DY[64][MLP_OUT];
     const int tid = threadIdx.x;
@@ -132,7 +137,11 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
         const int64_t s = c0 + tid;
         const bool live = s < n;
         const int64_t row = live ? (idx ? int64_t(idx[s]) : s) : 0;
-        for (int k = 0; k < MLP_IN; ++k) Xs[tid][k] = live ? X[row * MLP_IN + k] : 0.0f;
+        for (int k = 0; k < MLP_IN; ++k) {
+            float x = live ? X[row * MLP_IN + k] : 0.0f;
+            if (stats && live) x = (x - stats[k]) / stats[MLP_IN + k];
+            Xs[tid][k] = x;
+        }
         for (int j = 0; j < MLP_H; ++j) {
             float z = P[OB1 + j];
             for (int k = 0; k < MLP_IN; ++k) z += P[OW1 + j * MLP_IN + k] * Xs[tid][k];
@@ -147,7 +156,9 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
         for (int o = 0; o < MLP_OUT; ++o) {
             float z = P[OB3 + o];
             for (int k = 0; k < MLP_H; ++k) z += P[OW3 + o * MLP_H + k] * H2[tid][k];
-            const float d = live ? z - Tg[row * MLP_OUT + o] : 0.0f;
+            float t = live ? Tg[row * MLP_OUT + o] : 0.0f;
+            if (stats) t = (t - stats[2 * MLP_IN + o]) / stats[2 * MLP_IN + MLP_OUT + o];
+            const float d = live ? z - t : 0.0f;
             loss += d * d;
             DY[tid][o] = 2.0f * d * inv_n;
         }
@@ -237,10 +248,11 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const float *__restrict__ 
 }  // namespace
 
 template <typename T>
-hipError_t launch_moments(const T *U, int64_t ld, int64_t nelem, int nu, const float *Mom, float *mom,
-                          int64_t goff, hipStream_t s) {
+hipError_t launch_moments(const T *U, const T *B, int64_t ld, int64_t nelem, int nu, const float *Mom,
+                          float *mom, int64_t goff, const float *ystats, hipStream_t s) {
     if (!nelem) return hipSuccess;
-    moments_kernel<T><<<unsigned((nelem + 255) / 256), 256, 0, s>>>(U, ld, nelem, nu, Mom, mom, goff);
+    moments_kernel<T><<<unsigned((nelem + 255) / 256), 256, 0, s>>>(U, B, ld, nelem, nu, Mom, mom, goff,
+                                                                    ystats);
     return hipGetLastError();
 }
 
@@ -263,11 +275,11 @@ hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, con
 }
 
 hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
-                           float *partial, int nblk, float *grad, hipStream_t s) {
+                           const float *stats, float *partial, int nblk, float *grad, hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
     const int64_t chunks = (n + 63) / 64;
     const int g = int(chunks < nblk ? chunks : nblk);
-    mlp_grad_kernel<<<g, 64, 0, s>>>(P, X, Tg, idx, n, partial);
+    mlp_grad_kernel<<<g, 64, 0, s>>>(P, X, Tg, idx, n, stats, partial);
     mlp_reduce_kernel<<<(MLP_NPARAM + 256) / 256, 256, 0, s>>>(partial, g, grad);
     return hipGetLastError();
 }
@@ -284,9 +296,9 @@ hipError_t launch_to_bf16(const float *P, uint16_t *Pb, hipStream_t s) {
     return hipGetLastError();
 }
 
-template hipError_t launch_moments<float>(const float *, int64_t, int64_t, int, const float *, float *,
-                                          int64_t, hipStream_t);
-template hipError_t launch_moments<double>(const double *, int64_t, int64_t, int, const float *, float *,
-                                           int64_t, hipStream_t);
+template hipError_t launch_moments<float>(const float *, const float *, int64_t, int64_t, int, const float *,
+                                          float *, int64_t, const float *, hipStream_t);
+template hipError_t launch_moments<double>(const double *, const double *, int64_t, int64_t, int,
+                                           const float *, float *, int64_t, const float *, hipStream_t);
 
 }  // namespace frd

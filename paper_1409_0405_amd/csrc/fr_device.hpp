@@ -134,14 +134,14 @@ constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_
 constexpr int MLP_NSTATS = 2 * MLP_IN + 2 * MLP_OUT;   // mu_x, s_x, mu_y, s_y
 constexpr int MLP_GRAD_BLOCKS = 256;
 template <typename T>
-hipError_t launch_moments(const T *U, int64_t ld, int64_t nelem, int nu, const float *Mom, float *mom,
-                          int64_t goff, hipStream_t s);
+hipError_t launch_moments(const T *U, const T *B, int64_t ld, int64_t nelem, int nu, const float *Mom,
+                          float *mom, int64_t goff, const float *ystats, hipStream_t s);
 hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, const float *stats,
                            float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
                               const float *stats, float *Y, hipStream_t s);
 hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
-                           float *partial, int nblk, float *grad, hipStream_t s);
+                           const float *stats, float *partial, int nblk, float *grad, hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps,
                        int t, uint16_t *Pb, hipStream_t s);
 hipError_t launch_to_bf16(const float *P, uint16_t *Pb, hipStream_t s);

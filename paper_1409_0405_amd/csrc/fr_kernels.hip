@@ -592,12 +592,19 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs<T> a) {
     if (threadIdx.x < 8) a.partial[int64_t(blockIdx.x) * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void reduce_final_kernel(const double *partial, int nblocks, double *out) {
-    const int q = threadIdx.x;
-    if (q >= 8) return;
+// out[q] = sum_b partial[b][q]: block q, fixed summation tree (deterministic)
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double *partial, int nblocks, double *out) {
+    const int q = blockIdx.x;
     double s = 0;
-    for (int b = 0; b < nblocks; ++b) s += partial[int64_t(b) * 8 + q];
-    out[q] = s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[int64_t(b) * 8 + q];
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = sh[0];
 }
 
 template <typename T>
@@ -730,7 +737,7 @@ hipError_t launch_reduce(const RedArgs<T> &a, hipStream_t s) {
 }
 
 hipError_t launch_reduce_final(const double *partial, int nblocks, double *out, hipStream_t s) {
-    reduce_final_kernel<<<1, 64, 0, s>>>(partial, nblocks, out);
+    reduce_final_kernel<<<8, 256, 0, s>>>(partial, nblocks, out);
     return hipGetLastError();
 }
 

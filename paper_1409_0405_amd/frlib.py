@@ -36,6 +36,7 @@ EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coord
             "fr_batch_last_error", "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_params",
             "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_get_grad", "fr_mlp_adam",
             "fr_mlp_last_error", "fr_project", "fr_closure_moments", "fr_closure_features",
+            "fr_closure_targets",
             "fr_closure_attach", "fr_last_error")
 MLP_NPARAM, MLP_NSTATS = 13204, 280
 
@@ -111,7 +112,7 @@ def lib():
         L.fr_mlp_set_params.argtypes = [vp, fp]
         L.fr_mlp_get_params.argtypes = [vp, fp]
         L.fr_mlp_forward.argtypes = [vp, vp, i64, vp, vp, i32, vp]
-        L.fr_mlp_grad.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(dbl), vp]
+        L.fr_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.POINTER(dbl), vp]
         L.fr_mlp_get_grad.argtypes = [vp, fp, vp]
         L.fr_mlp_adam.argtypes = [vp, ctypes.c_float, vp]
         L.fr_mlp_last_error.argtypes = [vp]
@@ -119,6 +120,7 @@ def lib():
         L.fr_project.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp]
         L.fr_closure_moments.argtypes = [vp, ctypes.POINTER(vp), vp, vp]
         L.fr_closure_features.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp]
+        L.fr_closure_targets.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.fr_closure_attach.argtypes = [vp, vp, vp, i32]
         L.fr_last_error.argtypes = [vp]
         L.fr_last_error.restype = ctypes.c_char_p
@@ -266,6 +268,12 @@ class Mesh:
         _check(lib().fr_closure_features(self.h, U, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(feat_ptr),
                                          ctypes.c_void_p(stream)), self.h)
 
+    def closure_targets(self, a_ptrs, b_ptrs, stats_ptr, out_ptr, stream=0):
+        A = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in a_ptrs])
+        B = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in b_ptrs])
+        _check(lib().fr_closure_targets(self.h, A, B, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(out_ptr),
+                                        ctypes.c_void_p(stream)), self.h)
+
     def closure_attach(self, net, stats_ptr=0, bf16_weights=True):
         _check(lib().fr_closure_attach(self.h, net.h if net is not None else None,
                                        ctypes.c_void_p(stats_ptr or 0), 1 if bf16_weights else 0), self.h)
@@ -387,10 +395,10 @@ class MLP:
                                          ctypes.c_void_p(y_ptr), 1 if bf16_weights else 0,
                                          ctypes.c_void_p(stream)))
 
-    def grad(self, x_ptr, t_ptr, n, idx_ptr=0, want_loss=True, stream=0):
+    def grad(self, x_ptr, t_ptr, n, idx_ptr=0, stats_ptr=0, want_loss=True, stream=0):
         loss = ctypes.c_double()
         self._check(lib().fr_mlp_grad(self.h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr),
-                                      ctypes.c_void_p(idx_ptr or 0), int(n),
+                                      ctypes.c_void_p(idx_ptr or 0), int(n), ctypes.c_void_p(stats_ptr or 0),
                                       ctypes.byref(loss) if want_loss else None, ctypes.c_void_p(stream)))
         return loss.value if want_loss else None
 

@@ -90,3 +90,18 @@ def test_face_neighbours_symmetric():
         for f in range(5):
             if nb[e, f] >= 0:
                 assert e in nb[nb[e, f]]
+
+
+def test_adam_first_step_is_signed_lr():
+    """With bias correction the first Adam step moves every parameter by
+    lr * g / (|g| + eps): a signed step of size lr where |g| >> eps."""
+    rng = np.random.default_rng(4)
+    th = rng.normal(size=50)
+    g = rng.normal(size=50)
+    new, m, v = closure.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-3)
+    bound = 1e-3 * 1e-8 / np.abs(g) + 1e-15           # lr eps / |g|
+    assert (np.abs(new - (th - 1e-3 * np.sign(g))) <= bound).all()
+    # a constant gradient keeps the step at lr (bias corrections cancel)
+    for t in range(2, 6):
+        new, m, v = closure.adam_step(new, g, m, v, t, 1e-3)
+    assert (np.abs(new - (th - 5e-3 * np.sign(g))) <= 5 * bound + 1e-14).all()
