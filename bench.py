@@ -157,6 +157,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -175,9 +176,15 @@ def main():
     mu, mach, pr, p = 1.0 / 1600.0, 0.1, 0.71, 4
     arrays = inputs.tgv_mixed_box()
 
+    tuned = {}
+
     def make_mesh(precision):
-        return frlib.Mesh(arrays, p, system="ns", precision=precision, mu=mu, prandtl=pr,
-                          stream=stream)
+        m = frlib.Mesh(arrays, p, system="ns", precision=precision, mu=mu, prandtl=pr,
+                       stream=stream)
+        if not args.no_autotune and precision != "fp64":
+            tuned[precision] = m.autotune(stream)
+            print(f"autotune {precision}: {tuned[precision]}", file=sys.stderr, flush=True)
+        return m
 
     t_setup = time.perf_counter()
     mesh = make_mesh("fp32")
@@ -358,7 +365,8 @@ def main():
         "config": {"workload": "Navier-Stokes Taylor-Green Re1600 Ma0.1, p=4, FP32, "
                                "110592 prisms + 196608 tets, RK45[2R+] steps",
                    "n_dof": dof, "rhs_per_step": 5, "dt": dt, "parallelism": "single GPU",
-                   "finite": finite, "mass_energy_drift": drift},
+                   "finite": finite, "mass_energy_drift": drift,
+                   "autotuned": not args.no_autotune},
         "roofline": roof, "cpu_baseline": cpu, "forms": forms, "rhs_hbm": hbm,
     }
     print(json.dumps(out), flush=True)

@@ -202,6 +202,16 @@ fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
  * the stream; the choice is reported by fr_last_error(mesh) on success. */
 fr_status fr_autotune(fr_mesh mesh, void *stream);
 
+/* Force the operator-product variant of one operator of one element type:
+ * op 0 interpolation, 1 corrected gradient, 2 gradient interpolation,
+ * 3 divergence; cap = most 16-row blocks per wavefront (1..8 FP32, 1..4
+ * FP64 and split BF16, 1..2 split FP16); stage 0 = direct B loads, 1 / 2 =
+ * B staged through LDS in chunks of 4 / 8 K steps (FP32 only, at most 8 row
+ * groups).  Results are bitwise the same for every variant.  Synchronous
+ * (uploads the operator); FR_ERR_UNSUPPORTED for a combination the form
+ * does not have. */
+fr_status fr_set_blocking(fr_mesh mesh, int32_t etype, int32_t op, int32_t cap, int32_t stage);
+
 /* ------------------------------------------------------------------------
  * Batches of independent problems (many small meshes, mixed orders).
  *
@@ -260,8 +270,10 @@ fr_status fr_mlp_create(uint64_t seed, fr_mlp *out);
 fr_status fr_mlp_destroy(fr_mlp net);
 fr_status fr_mlp_set_params(fr_mlp net, const float *params_host);
 fr_status fr_mlp_get_params(fr_mlp net, float *params_host);
-/* y[n][20] = network(x[n][120]) on the device; stats may be NULL (raw in and
- * out); bf16_weights: use the weights rounded to BF16 (FP32 accumulation). */
+/* y[n][20] = network(x[n][120]) on the device.  With stats_dev, x is
+ * standardised (x - mu_x) / s_x as it is read and y scaled back y s_y + mu_y
+ * (the same convention as fr_mlp_grad); NULL: raw in and out.
+ * bf16_weights: use the weights rounded to BF16 (FP32 accumulation). */
 fr_status fr_mlp_forward(fr_mlp net, const float *x_dev, int64_t n, const float *stats_dev,
                          float *y_dev, int32_t bf16_weights, void *stream);
 /* Gradient of L = sum_s |y_s - t_s|^2 / n (FP32 weights) over the rows

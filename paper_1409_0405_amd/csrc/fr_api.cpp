@@ -523,7 +523,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
         FR_HIP(m, frd::launch_features(cl->mom, cl->nb, ntot, cl->stats, cl->feat, s));
         FR_HIP(m, frd::launch_mlp_forward(cl->params, cl->params_bf16, cl->bf16, cl->feat, ntot,
-                                          cl->stats, cl->y, s));
+                                          cl->stats, false, cl->y, s));
     }
     for (int t = 0; t < 2; ++t) {
         DevType<T> &D = d.t[t];
@@ -746,11 +746,19 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
         }
         for (const Case &c : cases) {
             float best = 1e30f;
-            int best_cap = -1;
+            int best_cap = -1, best_stage = 0;
             std::vector<void *> bufs;
             frd::Op<T> best_op;
             frd::OpSplit best_sop;
-            for (int cap : caps) {
+            std::vector<std::pair<int, int>> cands;
+            for (int cap : caps)
+                for (int stage = 0; stage < (!split && sizeof(T) == 4 ? 3 : 1); ++stage) {
+                    int nmg, mbw;
+                    frd::row_groups(c.M, cap, nmg, mbw);
+                    if (stage && nmg > 8) continue;
+                    cands.push_back({cap, stage});
+                }
+            for (auto [cap, stage] : cands) {
                 frd::Op<T> op;
                 frd::OpSplit sop;
                 std::vector<void *> mine;
@@ -768,6 +776,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                 } else {
                     std::vector<T> f;
                     op = fragment<T>(*c.A, c.M, c.K, f, cap);
+                    op.stage = stage;
                     void *p;
                     FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
                     FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -795,6 +804,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                     bufs = mine;
                     best = ms;
                     best_cap = cap;
+                    best_stage = stage;
                     best_op = op;
                     best_sop = sop;
                 } else {
@@ -807,7 +817,8 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             else
                 *c.dst = best_op;
             report += (t ? "pri" : "tet") + std::string(" op") + std::to_string(c.op) + " cap " +
-                      std::to_string(best_cap) + " " + std::to_string(best / 3 * 1e3) + " us; ";
+                      std::to_string(best_cap) + " stage " + std::to_string(best_stage) + " " +
+                      std::to_string(best / 3 * 1e3) + " us; ";
         }
     }
     (void)hipEventDestroy(e0);
@@ -1080,6 +1091,67 @@ fr_status fr_profile_read(fr_mesh m, double *total_ms, int64_t *count) {
     P.recs.clear();
     P.used = 0;
     return FR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
+    Dev<T> &d = dev_of<T>(m);
+    DevType<T> &D = d.t[t];
+    const frh::RefOps &R = m->host.t[t].ops;
+    std::vector<double> grad, div;
+    folded_ops(R, grad, div);
+    const int nu = D.nu, nf = D.nf;
+    const std::vector<double> *A = op == frd::OP_GRAD ? &grad : op == frd::OP_DIV ? &div : &R.M0;
+    const int M = op == frd::OP_GRAD ? 3 * nu : op == frd::OP_DIV ? nu : nf;
+    const int K = op == frd::OP_GRAD ? nu + nf : op == frd::OP_DIV ? 3 * nu + nf : nu;
+    const bool split = m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16;
+    if (split) {
+        if (stage) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
+        const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
+        if (cap > (fmt == 2 ? 2 : 4)) return fail(m, FR_ERR_UNSUPPORTED, "row-block cap too large for this form");
+        std::vector<uint16_t> parts[3];
+        frd::OpSplit so = fragment_split(*A, M, K, fmt, parts, cap);
+        for (int q = 0; q < 3; ++q) {
+            if (parts[q].empty()) continue;
+            void *p;
+            FR_HIP(m, hipMalloc(&p, parts[q].size() * 2));
+            d.allocs.push_back(p);
+            FR_HIP(m, hipMemcpy(p, parts[q].data(), parts[q].size() * 2, hipMemcpyHostToDevice));
+            so.part[q] = static_cast<uint16_t *>(p);
+        }
+        frd::OpSplit *dst[4] = {&D.Sint, &D.Sgrad, &D.Sgint, &D.Sdiv};
+        *dst[op] = so;
+        return FR_OK;
+    }
+    if (cap > (sizeof(T) == 4 ? 8 : 4)) return fail(m, FR_ERR_UNSUPPORTED, "row-block cap too large for this precision");
+    if (stage && sizeof(T) != 4) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
+    std::vector<T> f;
+    frd::Op<T> o = fragment<T>(*A, M, K, f, cap);
+    if (stage && o.nmg > 8) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
+    o.stage = stage;
+    void *p;
+    FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
+    d.allocs.push_back(p);
+    FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
+    o.frag = static_cast<T *>(p);
+    frd::Op<T> *dst[4] = {&D.Aint, &D.Agrad, &D.Agint, &D.Adiv};
+    *dst[op] = o;
+    return FR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
+    if (fr_status st = check_mesh(m, etype, true)) return st;
+    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 2)
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..2");
+    if (!m->host.t[etype].nelem) return FR_OK;
+    return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
+                                   : set_blocking_impl<double>(m, etype, op, cap, stage);
 }
 
 fr_status fr_autotune(fr_mesh m, void *stream) {
@@ -1419,7 +1491,7 @@ fr_status fr_mlp_get_params(fr_mlp n, float *host) {
 fr_status fr_mlp_forward(fr_mlp n, const float *x, int64_t count, const float *stats, float *y,
                          int32_t bf16_weights, void *stream) {
     if (!n || !x || !y || count < 0) return FR_ERR_INVALID_ARG;
-    FR_MHIP(n, frd::launch_mlp_forward(n->params, n->params_bf16, bf16_weights != 0, x, count, stats, y,
+    FR_MHIP(n, frd::launch_mlp_forward(n->params, n->params_bf16, bf16_weights != 0, x, count, stats, true, y,
                                        static_cast<hipStream_t>(stream)));
     return FR_OK;
 }

@@ -77,20 +77,24 @@ __global__ __launch_bounds__(256) void features_kernel(const float *__restrict__
     }
 }
 
-// y = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3, scaled back y s_y + mu_y if stats.
+// y = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3, scaled back y s_y + mu_y if
+// stats; with norm_in also x standardised (x - mu_x) / s_x as it is read.
 template <bool BF16W>
 __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict__ P,
                                                          const uint16_t *__restrict__ Pb,
                                                          const float *__restrict__ X, int64_t n,
                                                          const float *__restrict__ stats,
-                                                         float *__restrict__ Y) {
+                                                         bool norm_in, float *__restrict__ Y) {
     __shared__ float h1s[64][MLP_H + 1];
     const int tid = threadIdx.x;
     const int64_t s = int64_t(blockIdx.x) * 64 + tid;
     const bool live = s < n;
     float x[MLP_IN];
 #pragma unroll
-    for (int k = 0; k < MLP_IN; ++k) x[k] = live ? X[s * MLP_IN + k] : 0.0f;
+    for (int k = 0; k < MLP_IN; ++k) {
+        x[k] = live ? X[s * MLP_IN + k] : 0.0f;
+        if (norm_in && live) x[k] = (x[k] - stats[k]) / stats[MLP_IN + k];
+    }
     for (int j = 0; j < MLP_H; ++j) {
         float z = wt<BF16W>(P, Pb, OB1 + j);
 #pragma unroll
@@ -264,13 +268,14 @@ hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, co
 }
 
 hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
-                              const float *stats, float *Y, hipStream_t s) {
+                              const float *stats, bool norm_in, float *Y, hipStream_t s) {
     if (!n) return hipSuccess;
     const unsigned g = unsigned((n + 63) / 64);
+    norm_in = norm_in && stats;
     if (bf16)
-        mlp_forward_kernel<true><<<g, 64, 0, s>>>(P, Pb, X, n, stats, Y);
+        mlp_forward_kernel<true><<<g, 64, 0, s>>>(P, Pb, X, n, stats, norm_in, Y);
     else
-        mlp_forward_kernel<false><<<g, 64, 0, s>>>(P, Pb, X, n, stats, Y);
+        mlp_forward_kernel<false><<<g, 64, 0, s>>>(P, Pb, X, n, stats, norm_in, Y);
     return hipGetLastError();
 }
 

@@ -18,6 +18,10 @@ template <typename T>
 struct Op {
     const T *frag = nullptr;
     int M = 0, Kb = 0, nmg = 0, mbw = 0;
+    // FP32 only: 0 = every wavefront streams its B panel itself; 1 / 2 = the
+    // row groups of a panel share B staged through LDS in chunks of 4 / 8
+    // K steps (nmg <= 8).  All variants give identical bits.
+    int stage = 0;
 };
 
 // Row grouping of an M-row operator: at most `cap` blocks of 16 rows per
@@ -139,7 +143,7 @@ hipError_t launch_moments(const T *U, const T *B, int64_t ld, int64_t nelem, int
 hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, const float *stats,
                            float *feat, hipStream_t s);
 hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
-                              const float *stats, float *Y, hipStream_t s);
+                              const float *stats, bool norm_in, float *Y, hipStream_t s);
 hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
                            const float *stats, float *partial, int nblk, float *grad, hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps,

@@ -145,6 +145,112 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// FP32 operator product with the B panel staged through LDS.  One workgroup
+// per 64-column panel and one wavefront per row group (nmg waves): the group
+// loads B cooperatively in chunks of KS K steps (4 KS rows x 64 columns,
+// one 16-byte load per thread and row quarter), double buffered, so each B
+// element is read from memory once per panel instead of once per row group,
+// and the next chunk's loads (and A fragments) are in flight while the
+// current chunk is multiplied.  Every output sums the same products in the
+// same order as opmul_kernel, so both kernels give identical bits.
+// ---------------------------------------------------------------------------
+template <int MBW, int TAG, int KS>
+__global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float *__restrict__ B1,
+                                                        int64_t ldb1, int K1,
+                                                        const float *__restrict__ B2,
+                                                        int64_t ldb2, int K2,
+                                                        float *__restrict__ C, int64_t ldc) {
+    constexpr int NV = 64 * KS;                 // 16-byte vectors per chunk
+    __shared__ floatx4 Bs[2][NV];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, mg = tid >> 6;
+    const int krow = lane >> 4;
+    const int64_t col0 = int64_t(blockIdx.x) * 64;
+    const int K = K1 + K2, Kb = A.Kb;
+    const int nchunk = (Kb + KS - 1) / KS;
+
+    floatx4 rv[KS];                             // nthr >= 64: at most KS vectors per thread
+    auto gload = [&](int c) {
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int i = tid + j * nthr;
+            if (i < NV) {
+                const int k = min(4 * KS * c + (i >> 4), K - 1);
+                const float *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+                rv[j] = *reinterpret_cast<const floatx4 *>(p + col0 + 4 * (i & 15));
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int i = tid + j * nthr;
+            if (i < NV) Bs[buf][i] = rv[j];
+        }
+    };
+    const float *Af = A.frag + size_t(mg) * MBW * Kb * 64 + lane;
+    float ac[MBW][KS], an[MBW][KS];
+    auto aload = [&](int c, float (&a)[MBW][KS]) {
+#pragma unroll
+        for (int m = 0; m < MBW; ++m)
+#pragma unroll
+            for (int q = 0; q < KS; ++q) a[m][q] = Af[(size_t(m) * Kb + min(KS * c + q, Kb - 1)) * 64];
+    };
+
+    floatx4 acc[MBW][4];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = floatx4{0, 0, 0, 0};
+
+    gload(0);
+    aload(0, ac);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const bool more = c + 1 < nchunk;
+        if (more) {
+            gload(c + 1);
+            aload(c + 1, an);
+        }
+        const floatx4 *Bc = Bs[c & 1];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            if (KS * c + q < Kb) {
+                const floatx4 b = Bc[(4 * q + krow) * 16 + (lane & 15)];
+#pragma unroll
+                for (int m = 0; m < MBW; ++m) {
+                    acc[m][0] = mfma16(ac[m][q], b[0], acc[m][0]);
+                    acc[m][1] = mfma16(ac[m][q], b[1], acc[m][1]);
+                    acc[m][2] = mfma16(ac[m][q], b[2], acc[m][2]);
+                    acc[m][3] = mfma16(ac[m][q], b[3], acc[m][3]);
+                }
+            }
+        }
+        if (more) {
+            sstore((c + 1) & 1);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int q = 0; q < KS; ++q) ac[m][q] = an[m][q];
+        }
+        __syncthreads();
+    }
+    const int64_t col = col0 + 4 * (lane & 15);
+    const int mb0 = mg * MBW;
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (mb0 + m) + acc_row<float>(krow, r);
+            if (row < A.M)
+                *reinterpret_cast<floatx4 *>(C + int64_t(row) * ldc + col) =
+                    floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Split-precision operator product (16-bit matrix cores, FP32 accumulate).
 //
 // Same panel / row-group decomposition as opmul_kernel, with the 16x16x32
@@ -621,6 +727,25 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
                             int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels,
                             hipStream_t s) {
     const int nmg = A.nmg, mbw = A.mbw;
+    if constexpr (sizeof(T) == 4) {
+        if (A.stage) {
+            if (nmg > 8) return hipErrorInvalidValue;
+            const dim3 g{unsigned(npanels)}, b{unsigned(64 * nmg)};
+#define FR_LDS(w)                                                                                  \
+    case w:                                                                                        \
+        if (A.stage == 2)                                                                          \
+            opmul_lds_kernel<w, TAG, 8><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+        else                                                                                       \
+            opmul_lds_kernel<w, TAG, 4><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+        break;
+            switch (mbw) {
+                FR_LDS(1) FR_LDS(2) FR_LDS(3) FR_LDS(4) FR_LDS(5) FR_LDS(6) FR_LDS(7) FR_LDS(8)
+                default: return hipErrorInvalidValue;
+            }
+#undef FR_LDS
+            return hipGetLastError();
+        }
+    }
     const int64_t nwaves = npanels * nmg;
     const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
 #define FR_MBW(w)                                                                             \

@@ -36,7 +36,7 @@ EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coord
             "fr_batch_last_error", "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_params",
             "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_get_grad", "fr_mlp_adam",
             "fr_mlp_last_error", "fr_project", "fr_closure_moments", "fr_closure_features",
-            "fr_closure_targets",
+            "fr_closure_targets", "fr_set_blocking",
             "fr_closure_attach", "fr_last_error")
 MLP_NPARAM, MLP_NSTATS = 13204, 280
 
@@ -120,6 +120,7 @@ def lib():
         L.fr_project.argtypes = [vp, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp]
         L.fr_closure_moments.argtypes = [vp, ctypes.POINTER(vp), vp, vp]
         L.fr_closure_features.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp]
+        L.fr_set_blocking.argtypes = [vp, i32, i32, i32, i32]
         L.fr_closure_targets.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.fr_closure_attach.argtypes = [vp, vp, vp, i32]
         L.fr_last_error.argtypes = [vp]
@@ -267,6 +268,9 @@ class Mesh:
         U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
         _check(lib().fr_closure_features(self.h, U, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(feat_ptr),
                                          ctypes.c_void_p(stream)), self.h)
+
+    def set_blocking(self, etype, op, cap, stage=0):
+        _check(lib().fr_set_blocking(self.h, int(etype), int(op), int(cap), int(stage)), self.h)
 
     def closure_targets(self, a_ptrs, b_ptrs, stats_ptr, out_ptr, stream=0):
         A = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in a_ptrs])
