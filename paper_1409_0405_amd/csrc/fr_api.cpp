@@ -164,10 +164,15 @@ void prof_end(fr_mesh m, size_t i, int cls, hipStream_t s) {
 
 // Fragment order for the MFMA product kernel (see frd::Op).
 template <typename T>
-frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f, int cap = 0) {
+frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f, int cap = 0,
+                    int stage = 0) {
     frd::Op<T> op;
     op.M = M;
-    op.Kb = ((K + 3) / 4 + 1) / 2 * 2;   // even number of K steps
+    op.stage = stage;
+    // an even number of K steps; a multiple of the chunk (4 or 8 steps) when
+    // the B panel is staged through LDS
+    const int kmul = stage == 2 ? 8 : (stage == 1 || stage == 3) ? 4 : 2;
+    op.Kb = ((K + 3) / 4 + kmul - 1) / kmul * kmul;
     frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
     f.assign(size_t(Mb) * op.Kb * 64, T(0));
@@ -752,10 +757,11 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             frd::OpSplit best_sop;
             std::vector<std::pair<int, int>> cands;
             for (int cap : caps)
-                for (int stage = 0; stage < (!split && sizeof(T) == 4 ? 3 : 1); ++stage) {
+                for (int stage = 0; stage < (split ? 1 : 4); ++stage) {
+                    if (sizeof(T) != 4 && (stage == 1 || stage == 2)) continue;
                     int nmg, mbw;
                     frd::row_groups(c.M, cap, nmg, mbw);
-                    if (stage && nmg > 8) continue;
+                    if ((stage == 1 || stage == 2) && nmg > 8) continue;
                     cands.push_back({cap, stage});
                 }
             for (auto [cap, stage] : cands) {
@@ -775,8 +781,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                     }
                 } else {
                     std::vector<T> f;
-                    op = fragment<T>(*c.A, c.M, c.K, f, cap);
-                    op.stage = stage;
+                    op = fragment<T>(*c.A, c.M, c.K, f, cap, stage);
                     void *p;
                     FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
                     FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -1127,11 +1132,11 @@ fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
         return FR_OK;
     }
     if (cap > (sizeof(T) == 4 ? 8 : 4)) return fail(m, FR_ERR_UNSUPPORTED, "row-block cap too large for this precision");
-    if (stage && sizeof(T) != 4) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
+    const bool lds = stage == 1 || stage == 2;
+    if (lds && sizeof(T) != 4) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
     std::vector<T> f;
-    frd::Op<T> o = fragment<T>(*A, M, K, f, cap);
-    if (stage && o.nmg > 8) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
-    o.stage = stage;
+    frd::Op<T> o = fragment<T>(*A, M, K, f, cap, stage);
+    if (lds && o.nmg > 8) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
     void *p;
     FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
     d.allocs.push_back(p);
@@ -1147,8 +1152,8 @@ extern "C" {
 
 fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
-    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 2)
-        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..2");
+    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 3)
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..3");
     if (!m->host.t[etype].nelem) return FR_OK;
     return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
                                    : set_blocking_impl<double>(m, etype, op, cap, stage);

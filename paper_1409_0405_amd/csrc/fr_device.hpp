@@ -18,9 +18,10 @@ template <typename T>
 struct Op {
     const T *frag = nullptr;
     int M = 0, Kb = 0, nmg = 0, mbw = 0;
-    // FP32 only: 0 = every wavefront streams its B panel itself; 1 / 2 = the
-    // row groups of a panel share B staged through LDS in chunks of 4 / 8
-    // K steps (nmg <= 8).  All variants give identical bits.
+    // 0 / 3 = every wavefront streams its B panel itself with 2 / 4 K steps
+    // of loads in flight; 1 / 2 (FP32 only) = the row groups of a panel share
+    // B staged through LDS in chunks of 4 / 8 K steps (nmg <= 8).  Kb is a
+    // multiple of 2, 4, 8, 4 respectively.  All variants give identical bits.
     int stage = 0;
 };
 

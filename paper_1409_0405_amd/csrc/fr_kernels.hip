@@ -52,6 +52,17 @@ __device__ __forceinline__ int acc_row<float>(int g, int r) { return 4 * g + r; 
 template <>
 __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r; }
 
+// Returns x unchanged, but opaque to the optimiser: used on the values that
+// enter a software-pipelined loop, so that the loop-carried registers are not
+// all plain loads (otherwise the loads of the next K step get merged into
+// one load at the loop head, right before their use, and every step waits
+// for memory).
+template <typename V>
+__device__ __forceinline__ V opaque(V x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // Operator product C = A [B1; B2] on the matrix cores.  TAG (4 * element type
 // + operator id) only names the instantiation, so that a profiler reports each
@@ -67,7 +78,7 @@ __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r;
 // loop is branch free: rows of B past K are clamped to a real row (finite
 // values times zero columns of A).
 // ---------------------------------------------------------------------------
-template <typename T, int MBW, int TAG>
+template <typename T, int MBW, int TAG, int D>
 __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict__ B1,
                                                     int64_t ldb1, int K1,
                                                     const T *__restrict__ B2, int64_t ldb2,
@@ -97,39 +108,33 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = v4{0, 0, 0, 0};
 
-    // Two register sets (even and odd K steps; Kb is even): a set is
-    // reloaded right after its matrix instructions issue, so its loads are
-    // in flight while the other set is multiplied.
+    // D register sets, one per K step in flight (Kb is a multiple of D): set
+    // d is refilled with step kb + d + D right after its matrix instructions
+    // issue, so D steps of loads are outstanding while the others multiply.
     const T *Af = A.frag + size_t(mb0) * Kb * 64 + lane;
-    T a0[MBW], a1[MBW];
-    v4 b0 = *bptr(0), b1 = *bptr(1);
+    T a[D][MBW];
+    v4 b[D];
 #pragma unroll
-    for (int m = 0; m < MBW; ++m) {
-        a0[m] = Af[size_t(m) * Kb * 64];
-        a1[m] = Af[(size_t(m) * Kb + 1) * 64];
+    for (int d = 0; d < D; ++d) {
+        b[d] = opaque(*bptr(d));
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) a[d][m] = opaque(Af[(size_t(m) * Kb + d) * 64]);
     }
-    for (int kb = 0; kb < Kb; kb += 2) {
+    for (int kb = 0; kb < Kb; kb += D) {
 #pragma unroll
-        for (int m = 0; m < MBW; ++m) {
-            acc[m][0] = mfma16(a0[m], b0[0], acc[m][0]);
-            acc[m][1] = mfma16(a0[m], b0[1], acc[m][1]);
-            acc[m][2] = mfma16(a0[m], b0[2], acc[m][2]);
-            acc[m][3] = mfma16(a0[m], b0[3], acc[m][3]);
+        for (int d = 0; d < D; ++d) {
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) {
+                acc[m][0] = mfma16(a[d][m], b[d][0], acc[m][0]);
+                acc[m][1] = mfma16(a[d][m], b[d][1], acc[m][1]);
+                acc[m][2] = mfma16(a[d][m], b[d][2], acc[m][2]);
+                acc[m][3] = mfma16(a[d][m], b[d][3], acc[m][3]);
+            }
+            const int kn = min(kb + d + D, Kb - 1);
+            b[d] = *bptr(kn);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) a[d][m] = Af[(size_t(m) * Kb + kn) * 64];
         }
-        const int k2 = min(kb + 2, Kb - 2), k3 = min(kb + 3, Kb - 1);
-        b0 = *bptr(k2);
-#pragma unroll
-        for (int m = 0; m < MBW; ++m) a0[m] = Af[(size_t(m) * Kb + k2) * 64];
-#pragma unroll
-        for (int m = 0; m < MBW; ++m) {
-            acc[m][0] = mfma16(a1[m], b1[0], acc[m][0]);
-            acc[m][1] = mfma16(a1[m], b1[1], acc[m][1]);
-            acc[m][2] = mfma16(a1[m], b1[2], acc[m][2]);
-            acc[m][3] = mfma16(a1[m], b1[3], acc[m][3]);
-        }
-        b1 = *bptr(k3);
-#pragma unroll
-        for (int m = 0; m < MBW; ++m) a1[m] = Af[(size_t(m) * Kb + k3) * 64];
     }
 #pragma unroll
     for (int m = 0; m < MBW; ++m) {
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
     const int krow = lane >> 4;
     const int64_t col0 = int64_t(blockIdx.x) * 64;
     const int K = K1 + K2, Kb = A.Kb;
-    const int nchunk = (Kb + KS - 1) / KS;
+    const int nchunk = Kb / KS;
 
     floatx4 rv[KS];                             // nthr >= 64: at most KS vectors per thread
     auto gload = [&](int c) {
@@ -205,6 +210,10 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
 
     gload(0);
     aload(0, ac);
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int q = 0; q < KS; ++q) ac[m][q] = opaque(ac[m][q]);
     sstore(0);
     __syncthreads();
     for (int c = 0; c < nchunk; ++c) {
@@ -214,17 +223,16 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
             aload(c + 1, an);
         }
         const floatx4 *Bc = Bs[c & 1];
+        // Kb is a multiple of KS (the fragment is zero padded): no tail test
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-            if (KS * c + q < Kb) {
-                const floatx4 b = Bc[(4 * q + krow) * 16 + (lane & 15)];
+            const floatx4 b = Bc[(4 * q + krow) * 16 + (lane & 15)];
 #pragma unroll
-                for (int m = 0; m < MBW; ++m) {
-                    acc[m][0] = mfma16(ac[m][q], b[0], acc[m][0]);
-                    acc[m][1] = mfma16(ac[m][q], b[1], acc[m][1]);
-                    acc[m][2] = mfma16(ac[m][q], b[2], acc[m][2]);
-                    acc[m][3] = mfma16(ac[m][q], b[3], acc[m][3]);
-                }
+            for (int m = 0; m < MBW; ++m) {
+                acc[m][0] = mfma16(ac[m][q], b[0], acc[m][0]);
+                acc[m][1] = mfma16(ac[m][q], b[1], acc[m][1]);
+                acc[m][2] = mfma16(ac[m][q], b[2], acc[m][2]);
+                acc[m][3] = mfma16(ac[m][q], b[3], acc[m][3]);
             }
         }
         if (more) {
@@ -603,17 +611,30 @@ __global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
                          n[2] * (FL[2][v] + FR[2][v])) -
                T(0.5) * lam * (uR[v] - uL[v]);
     if (NS) {
-        T qL[3][5], qR[3][5], FvL[3][5], FvR[3][5];
+        // a side whose weight is zero (beta = +-1/2, the usual LDG choice) is
+        // neither read nor evaluated: its term would be an exact zero
+        const T wl = T(0.5) + a.beta, wr = T(0.5) - a.beta;
+        T FvL[3][5], FvR[3][5];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                qL[j][v] = a.Qf[tL][(int64_t(fL) * 15 + j * 5 + v) * ldL + eL];
-                qR[j][v] = a.Qf[tR][(int64_t(fR) * 15 + j * 5 + v) * ldR + eR];
-            }
-        viscous_flux(uL, qL, a.gamma, a.mu, a.prandtl, FvL);
-        viscous_flux(uR, qR, a.gamma, a.mu, a.prandtl, FvR);
-        const T wl = T(0.5) + a.beta, wr = T(0.5) - a.beta;
+            for (int v = 0; v < 5; ++v) FvL[j][v] = FvR[j][v] = T(0);
+        if (wl != T(0)) {
+            T q[3][5];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) q[j][v] = a.Qf[tL][(int64_t(fL) * 15 + j * 5 + v) * ldL + eL];
+            viscous_flux(uL, q, a.gamma, a.mu, a.prandtl, FvL);
+        }
+        if (wr != T(0)) {
+            T q[3][5];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) q[j][v] = a.Qf[tR][(int64_t(fR) * 15 + j * 5 + v) * ldR + eR];
+            viscous_flux(uR, q, a.gamma, a.mu, a.prandtl, FvR);
+        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             T fv = 0;
@@ -727,8 +748,9 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
                             int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels,
                             hipStream_t s) {
     const int nmg = A.nmg, mbw = A.mbw;
+    if (A.Kb % (A.stage == 2 ? 8 : (A.stage == 1 || A.stage == 3) ? 4 : 2)) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        if (A.stage) {
+        if (A.stage == 1 || A.stage == 2) {
             if (nmg > 8) return hipErrorInvalidValue;
             const dim3 g{unsigned(npanels)}, b{unsigned(64 * nmg)};
 #define FR_LDS(w)                                                                                  \
@@ -748,10 +770,14 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
     }
     const int64_t nwaves = npanels * nmg;
     const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
-#define FR_MBW(w)                                                                             \
-    case w:                                                                                   \
-        opmul_kernel<T, w, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
-                                                       npanels, nmg);                         \
+#define FR_MBW(w)                                                                                \
+    case w:                                                                                      \
+        if (A.stage == 3)                                                                        \
+            opmul_kernel<T, w, TAG, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
+                                                              npanels, nmg);                     \
+        else                                                                                     \
+            opmul_kernel<T, w, TAG, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
+                                                              npanels, nmg);                     \
         break;
     if (sizeof(T) == 4) {
         switch (mbw) {
