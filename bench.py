@@ -22,6 +22,7 @@ their right-hand side against the FP64 build of the same kernels.
 """
 import argparse
 import json
+import re
 import math
 import os
 import sys
@@ -34,6 +35,16 @@ METRIC = "GDOF/s per RHS eval, mixed prism/tet p=4, plain FP32 vs split-BF16; HB
 PEAK_HBM = 8.0e12          # B/s
 PEAK_FP32_MFMA = 157.3e12  # FLOP/s, dense
 RIDGE = PEAK_FP32_MFMA / PEAK_HBM
+
+# HBM bytes per launch measured with rocprofv3 --pmc on this workload
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors read off the state
+# copies of known size), per kernel class and operator-product variant
+# (16-row blocks per wavefront, staging); profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md.
+# A variant not listed here reports traffic null.
+MEASURED_TRAFFIC = {
+    ("grad_pri", 4, 0): 898.3e6,
+    ("grad_pri", 2, 1): 900.8e6,
+}
 
 
 def kernel_model(mesh, system):
@@ -295,6 +306,12 @@ def main():
                     "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
         roof["traffic"] = None
+        m_ = re.search(r"pri op1 cap (\d+) stage (\d+)", tuned.get("fp32", "")) if k == "grad_pri" else None
+        if m_:
+            cap_, stage_ = int(m_.group(1)), int(m_.group(2))
+            nmg_ = -(-15 // cap_)                  # 225 rows = 15 blocks of 16
+            roof["variant"] = {"rows_blocks_per_wave": -(-15 // nmg_), "stage": stage_}
+            roof["traffic"] = MEASURED_TRAFFIC.get((k, -(-15 // nmg_), stage_))
         roof["kernel"] = k
         roof["avg_launch_us"] = avg * 1e6
         roof["share_of_step"] = ms / tot
