@@ -59,14 +59,15 @@ def dt_for(order, h_min, mach=0.1, cfl=0.3):
 def generate(hi, lo, dt, n_snap, steps_between, stream=0):
     """Inputs [N][120] and targets [N][20] (device float32) from snapshots of
     the order-q run of mesh hi (whose solution register holds the state),
-    plus the times and the order-q dissipation rates at the snapshots."""
+    plus the times, the order-q dissipation rates at the snapshots and the
+    projected order-1 states (device tensors per element type)."""
     import torch
     ntot = sum(hi.query(t)["nelem"] for t in (0, 1))
     X = torch.zeros((n_snap, ntot, 120), dtype=torch.float32, device="cuda")
     Y = torch.zeros((n_snap, ntot, 20), dtype=torch.float32, device="cuda")
     uq, rq = _states(hi), _states(hi)
     u1, r1, pr = _states(lo), _states(lo), _states(lo)
-    times, rates = [], []
+    times, rates, states = [], [], []
     t_now = 0.0
     for k in range(n_snap):
         if k:
@@ -83,7 +84,8 @@ def generate(hi, lo, dt, n_snap, steps_between, stream=0):
         torch.cuda.synchronize()
         times.append(t_now)
         rates.append(-hi.reduce(frlib.FR_RED_KE, stream)[1])
-    return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates)
+        states.append([x.clone() for x in u1])
+    return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates), states
 
 
 def stats_of(X, Y):
@@ -136,4 +138,23 @@ def dissipation_history(mesh, dt, n_snap, steps_between, stream=0):
         if k:
             mesh.rk_step(frlib.FR_RK45_2RP, dt, steps_between, stream)
         out.append(-mesh.reduce(frlib.FR_RED_KE, stream)[1])
+    return np.array(out)
+
+
+def apriori_rates(lo, states, net=None, stats=None, bf16_weights=False, stream=0):
+    """-dE_k/dt of the order-1 residual at each projected state, with the
+    closure attached when net is given (a-priori: no time integration)."""
+    import torch
+    if net is not None:
+        lo.closure_attach(net, stats.data_ptr(), bf16_weights=bf16_weights)
+    out = []
+    try:
+        for st in states:
+            for t in (0, 1):
+                lo.set_solution(t, st[t].data_ptr(), stream)
+            torch.cuda.synchronize()
+            out.append(-lo.reduce(frlib.FR_RED_KE, stream)[1])
+    finally:
+        if net is not None:
+            lo.closure_attach(None)
     return np.array(out)
