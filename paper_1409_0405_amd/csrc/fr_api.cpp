@@ -171,16 +171,19 @@ frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &
     op.stage = stage;
     // an even number of K steps; a multiple of the chunk (4 or 8 steps) when
     // the B panel is staged through LDS
-    const int kmul = stage == 2 ? 8 : (stage == 1 || stage == 3) ? 4 : 2;
+    const int kmul = (stage == 2 || stage == 4) ? 8 : (stage == 1 || stage == 3) ? 4 : 2;
     op.Kb = ((K + 3) / 4 + kmul - 1) / kmul * kmul;
     frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
     f.assign(size_t(Mb) * op.Kb * 64, T(0));
+    // stage 4 groups four K steps per lane: [mb][Kb / 4][lane][4]
     for (int mb = 0; mb < Mb; ++mb)
         for (int kb = 0; kb < op.Kb; ++kb)
             for (int l = 0; l < 64; ++l) {
                 int r = 16 * mb + (l % 16), c = 4 * kb + l / 16;
-                if (r < M && c < K) f[(size_t(mb) * op.Kb + kb) * 64 + l] = T(A[size_t(r) * K + c]);
+                const size_t at = stage == 4 ? ((size_t(mb) * (op.Kb / 4) + kb / 4) * 64 + l) * 4 + kb % 4
+                                             : (size_t(mb) * op.Kb + kb) * 64 + l;
+                if (r < M && c < K) f[at] = T(A[size_t(r) * K + c]);
             }
     return op;
 }
@@ -757,11 +760,12 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             frd::OpSplit best_sop;
             std::vector<std::pair<int, int>> cands;
             for (int cap : caps)
-                for (int stage = 0; stage < (split ? 1 : 4); ++stage) {
-                    if (sizeof(T) != 4 && (stage == 1 || stage == 2)) continue;
+                for (int stage = 0; stage < (split ? 1 : 5); ++stage) {
+                    if (sizeof(T) != 4 && (stage == 1 || stage == 2 || stage == 4)) continue;
                     int nmg, mbw;
                     frd::row_groups(c.M, cap, nmg, mbw);
                     if ((stage == 1 || stage == 2) && nmg > 8) continue;
+                    if (stage == 4 && size_t(mbw) * ((((c.K + 3) / 4) + 7) / 8 * 8) * 256 > 65536) continue;
                     cands.push_back({cap, stage});
                 }
             for (auto [cap, stage] : cands) {
@@ -1132,11 +1136,14 @@ fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
         return FR_OK;
     }
     if (cap > (sizeof(T) == 4 ? 8 : 4)) return fail(m, FR_ERR_UNSUPPORTED, "row-block cap too large for this precision");
-    const bool lds = stage == 1 || stage == 2;
+    const bool lds = stage == 1 || stage == 2 || stage == 4;
     if (lds && sizeof(T) != 4) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
     std::vector<T> f;
     frd::Op<T> o = fragment<T>(*A, M, K, f, cap, stage);
-    if (lds && o.nmg > 8) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
+    if ((stage == 1 || stage == 2) && o.nmg > 8)
+        return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
+    if (stage == 4 && size_t(o.mbw) * o.Kb * 256 > 65536)
+        return fail(m, FR_ERR_UNSUPPORTED, "operator slice too large for LDS");
     void *p;
     FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
     d.allocs.push_back(p);
@@ -1152,8 +1159,8 @@ extern "C" {
 
 fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
-    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 3)
-        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..3");
+    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 4)
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..4");
     if (!m->host.t[etype].nelem) return FR_OK;
     return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
                                    : set_blocking_impl<double>(m, etype, op, cap, stage);

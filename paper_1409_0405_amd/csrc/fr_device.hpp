@@ -20,8 +20,11 @@ struct Op {
     int M = 0, Kb = 0, nmg = 0, mbw = 0;
     // 0 / 3 = every wavefront streams its B panel itself with 2 / 4 K steps
     // of loads in flight; 1 / 2 (FP32 only) = the row groups of a panel share
-    // B staged through LDS in chunks of 4 / 8 K steps (nmg <= 8).  Kb is a
-    // multiple of 2, 4, 8, 4 respectively.  All variants give identical bits.
+    // B staged through LDS in chunks of 4 / 8 K steps (nmg <= 8); 4 (FP32
+    // only) = the row group's A slice sits in LDS, shared by four panels
+    // (fragments grouped by four K steps, mbw * Kb * 256 bytes <= 64 KiB).
+    // Kb is a multiple of 2, 4, 8, 4, 8 respectively.  All variants give
+    // identical bits.
     int stage = 0;
 };
 

@@ -259,6 +259,83 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
 }
 
 // ---------------------------------------------------------------------------
+// FP32 operator product with the operator slice in LDS.  A workgroup of four
+// wavefronts takes four consecutive 64-column panels and one row group; the
+// group's A fragments (MBW row blocks x Kb steps) are copied to LDS once and
+// read from there by all four (16 bytes per lane and row block for four K
+// steps), so the matrix instructions no longer wait on L2 latency for A.  B
+// streams from memory as in opmul_kernel, two groups of four K steps in
+// flight (Kb is a multiple of 8).  Fragment layout for this variant:
+// [mb][Kb / 4][lane][4], element j of lane l = A[16 mb + l % 16][4 (4 q + j) + l / 16].
+// Every output sums the same products in the same order as opmul_kernel.
+// ---------------------------------------------------------------------------
+template <int MBW, int TAG>
+__global__ __launch_bounds__(256) void opmul_ldsa_kernel(Op<float> A, const float *__restrict__ B1,
+                                                         int64_t ldb1, int K1,
+                                                         const float *__restrict__ B2, int64_t ldb2,
+                                                         int K2, float *__restrict__ C, int64_t ldc,
+                                                         int64_t npanels, int nmg) {
+    extern __shared__ floatx4 As[];             // [MBW][Kb / 4][64]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Kb = A.Kb, Kq = Kb / 4;
+    const int mg = int(blockIdx.x % unsigned(nmg));
+    const int64_t panel = int64_t(blockIdx.x / unsigned(nmg)) * 4 + w;
+    const int mb0 = mg * MBW;
+    const floatx4 *Ag = reinterpret_cast<const floatx4 *>(A.frag) + size_t(mb0) * Kq * 64;
+    for (int i = threadIdx.x; i < MBW * Kq * 64; i += 256) As[i] = Ag[i];
+    __syncthreads();
+    if (panel >= npanels) return;
+    const int64_t col = panel * 64 + 4 * (lane & 15);
+    const int krow = lane >> 4;
+    const int K = K1 + K2;
+    auto bptr = [&](int kb) -> const floatx4 * {
+        const int k = min(4 * kb + krow, K - 1);
+        const float *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+        return reinterpret_cast<const floatx4 *>(p + col);
+    };
+    floatx4 acc[MBW][4];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = floatx4{0, 0, 0, 0};
+    floatx4 b[2][4];
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[d][q] = opaque(*bptr(4 * d + q));
+    for (int g = 0; g < Kq; g += 2) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            floatx4 a[MBW];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) a[m] = As[(m * Kq + g + d) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int m = 0; m < MBW; ++m) {
+                    acc[m][0] = mfma16(a[m][q], b[d][q][0], acc[m][0]);
+                    acc[m][1] = mfma16(a[m][q], b[d][q][1], acc[m][1]);
+                    acc[m][2] = mfma16(a[m][q], b[d][q][2], acc[m][2]);
+                    acc[m][3] = mfma16(a[m][q], b[d][q][3], acc[m][3]);
+                }
+            const int gn = min(g + d + 2, Kq - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[d][q] = *bptr(4 * gn + q);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (mb0 + m) + acc_row<float>(krow, r);
+            if (row < A.M)
+                *reinterpret_cast<floatx4 *>(C + int64_t(row) * ldc + col) =
+                    floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Split-precision operator product (16-bit matrix cores, FP32 accumulate).
 //
 // Same panel / row-group decomposition as opmul_kernel, with the 16x16x32
@@ -748,8 +825,25 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
                             int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels,
                             hipStream_t s) {
     const int nmg = A.nmg, mbw = A.mbw;
-    if (A.Kb % (A.stage == 2 ? 8 : (A.stage == 1 || A.stage == 3) ? 4 : 2)) return hipErrorInvalidValue;
+    if (A.Kb % ((A.stage == 2 || A.stage == 4) ? 8 : (A.stage == 1 || A.stage == 3) ? 4 : 2))
+        return hipErrorInvalidValue;
+    if (A.stage == 4 && sizeof(T) != 4) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
+        if (A.stage == 4) {
+            const size_t lds = size_t(mbw) * A.Kb * 64 * sizeof(float);
+            if (lds > 65536) return hipErrorInvalidValue;
+            const dim3 g{unsigned((npanels + 3) / 4) * unsigned(nmg)}, b{256u};
+#define FR_LDSA(w)                                                                                   \
+    case w:                                                                                          \
+        opmul_ldsa_kernel<w, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+        break;
+            switch (mbw) {
+                FR_LDSA(1) FR_LDSA(2) FR_LDSA(3) FR_LDSA(4) FR_LDSA(5) FR_LDSA(6) FR_LDSA(7) FR_LDSA(8)
+                default: return hipErrorInvalidValue;
+            }
+#undef FR_LDSA
+            return hipGetLastError();
+        }
         if (A.stage == 1 || A.stage == 2) {
             if (nmg > 8) return hipErrorInvalidValue;
             const dim3 g{unsigned(npanels)}, b{unsigned(64 * nmg)};

@@ -160,7 +160,7 @@ def test_every_product_variant_gives_identical_bits(p, prec):
     M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r0])
     torch.cuda.synchronize()
     n = 0
-    for stage in ((0, 1, 2, 3) if prec == "fp32" else (0, 3)):
+    for stage in ((0, 1, 2, 3, 4) if prec == "fp32" else (0, 3)):
         for cap in (1, 2, 3, 4, 8):
             ok = True
             for t in (0, 1):
