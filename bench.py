@@ -78,7 +78,8 @@ def kernel_model(mesh, system):
     per_pair = (2 * 5 + (15 if ns else 0) + 2 * 5 + 5) * s + 8
     out["common_flux"] = {"flops": 0.0, "bytes": float(per_pair * npairs)}
     if ns:
-        out["common_solution"] = {"flops": 0.0, "bytes": float((2 * 5 + 2 * 5) * s * npairs + 8 * npairs)}
+        # beta = 1/2: the jump to the common solution is written on side L only
+        out["common_solution"] = {"flops": 0.0, "bytes": float((2 * 5 + 5) * s * npairs + 8 * npairs)}
     return out
 
 

@@ -4,16 +4,19 @@
 // Right-hand side per element type (paper Section 2.1: operator products with
 // constant operators plus point-wise kernels; Section 3.4: DG-type scheme):
 //   1  U_f  = M0 U                                   operator product
-//   2  C    = common LDG solution at paired flux points        (NS)
-//   3  Q~   = [G'_k | L_k] [U; C], G'_k = G_k - L_k M0,
-//             L_k = L diag(n_ref,k)                  operator product (NS)
+//   2  D    = C - U_f, the jump to the common LDG solution C at each
+//             paired flux point                                 (NS)
+//   3  Q~   = [G_k | L_k] [U; D], L_k = L diag(n_ref,k)  operator product (NS)
 //   4  Q    = adj^T Q~ / J;  F~ = adj (F_inv - F_vis)  point-wise
 //   5  Q_f  = M0 Q                                   operator product (NS)
 //   6  Fn*  = common transformed normal flux at paired flux points
-//   7  R~   = [G'_0 G'_1 G'_2 | L] [F~; Fn*]         operator product
+//   7  R~   = [G'_0 G'_1 G'_2 | L] [F~; Fn*],
+//             G'_k = G_k - L_k M0                    operator product
 //   8  R    = -R~ / J, fused with the Runge-Kutta register update
 // Step 7 folds the correction L (Fn* - n_ref . M0 F~) into the divergence
-// operator, so F~ is read once; step 3 folds L_k (C - M0 U) likewise.
+// operator, so F~ is read once.  Step 3 takes the jump D, which the interface
+// kernel forms directly (no cancellation between L C and L M0 U); a side whose
+// LDG weight is zero (beta = +-1/2) has D = 0 and is never written.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -250,8 +253,8 @@ frd::OpSplit fragment_split(const std::vector<double> &A, int M, int K, int form
     return op;
 }
 
-// Folded operators of one reference element:
-//   grad: rows (k, i): [G_k - L_k M0 | L_k]               (3 nu) x (nu + nf)
+// Operators of one reference element for the products of steps 3 and 7:
+//   grad: rows (k, i): [G_k | L_k]                        (3 nu) x (nu + nf)
 //   div:  row i: [G_0 - L_0 M0, G_1 - L_1 M0, G_2 - L_2 M0 | L]  nu x (3 nu + nf)
 void folded_ops(const frh::RefOps &R, std::vector<double> &grad, std::vector<double> &div) {
     const int nu = R.nu, nf = R.nf;
@@ -269,7 +272,7 @@ void folded_ops(const frh::RefOps &R, std::vector<double> &grad, std::vector<dou
     for (int k = 0; k < 3; ++k)
         for (int i = 0; i < nu; ++i) {
             double *row = &grad[(size_t(k) * nu + i) * Kg];
-            for (int j = 0; j < nu; ++j) row[j] = Gp[(size_t(k) * nu + i) * nu + j];
+            for (int j = 0; j < nu; ++j) row[j] = R.G[(size_t(k) * nu + i) * nu + j];
             for (int f = 0; f < nf; ++f) row[nu + f] = R.L[size_t(i) * nf + f] * R.nref[3 * f + k];
         }
     const int Kd = 3 * nu + nf;

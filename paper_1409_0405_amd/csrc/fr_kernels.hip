@@ -624,14 +624,23 @@ __global__ __launch_bounds__(256) void upts_kernel(UptsArgs<T> a) {
                 adj[k][0] * F[0][v] + adj[k][1] * F[1][v] + adj[k][2] * F[2][v];
 }
 
+// Per-type kernel argument of an element type t in {0, 1}, selected without
+// indexing the argument block (which would be a memory load per thread).
+template <typename P>
+__device__ __forceinline__ P pick(const P (&v)[2], int t) {
+    return t ? v[1] : v[0];
+}
+
 __device__ __forceinline__ void unpack(uint32_t s, int64_t &e, int &f, int &t) {
     e = s & 0xffffffu;
     f = (s >> 24) & 0x7f;
     t = s >> 31;
 }
 
-// Common solution of the LDG scheme at each paired flux point, written to
-// both sides: C = (1/2 - beta) U_L + (1/2 + beta) U_R.
+// Jump to the common solution of the LDG scheme at each paired flux point,
+// C = (1/2 - beta) U_L + (1/2 + beta) U_R, stored per side as D = C - U_f:
+//   D_L = (1/2 + beta) (U_R - U_L),   D_R = (1/2 - beta) (U_L - U_R).
+// A side whose weight is zero keeps the zeros the buffer was created with.
 template <typename T>
 __global__ __launch_bounds__(256) void common_solution_kernel(PairArgs<T> a) {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -640,15 +649,22 @@ __global__ __launch_bounds__(256) void common_solution_kernel(PairArgs<T> a) {
     int fL, fR, tL, tR;
     unpack(a.sideL[p], eL, fL, tL);
     unpack(a.sideR[p], eR, fR, tR);
-    const int64_t ldL = a.ld[tL], ldR = a.ld[tR];
-    const T wl = T(0.5) - a.beta, wr = T(0.5) + a.beta;
+    const int64_t ldL = pick(a.ld, tL), ldR = pick(a.ld, tR);
+    const T wL = T(0.5) + a.beta, wR = T(0.5) - a.beta;
+    const T *__restrict__ uL = pick(a.Uf, tL) + int64_t(fL) * 5 * ldL + eL;
+    const T *__restrict__ uR = pick(a.Uf, tR) + int64_t(fR) * 5 * ldR + eR;
+    T jump[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const int64_t oL = (int64_t(fL) * 5 + v) * ldL + eL;
-        const int64_t oR = (int64_t(fR) * 5 + v) * ldR + eR;
-        const T c = wl * a.Uf[tL][oL] + wr * a.Uf[tR][oR];
-        a.Cf[tL][oL] = c;
-        a.Cf[tR][oR] = c;
+    for (int v = 0; v < 5; ++v) jump[v] = uR[v * ldR] - uL[v * ldL];     // all loads first
+    if (wL != T(0)) {
+        T *dL = pick(a.Cf, tL) + int64_t(fL) * 5 * ldL + eL;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dL[v * ldL] = wL * jump[v];
+    }
+    if (wR != T(0)) {
+        T *dR = pick(a.Cf, tR) + int64_t(fR) * 5 * ldR + eR;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dR[v * ldR] = -wR * jump[v];
     }
 }
 
@@ -664,15 +680,32 @@ __global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
     int fL, fR, tL, tR;
     unpack(a.sideL[p], eL, fL, tL);
     unpack(a.sideR[p], eR, fR, tR);
-    const int64_t ldL = a.ld[tL], ldR = a.ld[tR];
+    const int64_t ldL = pick(a.ld, tL), ldR = pick(a.ld, tR);
     const int64_t P = a.npairs;
     const T n[3] = {a.geo[p], a.geo[P + p], a.geo[2 * P + p]};
     const T sL = a.geo[3 * P + p], sR = a.geo[4 * P + p];
     T uL[5], uR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        uL[v] = a.Uf[tL][(int64_t(fL) * 5 + v) * ldL + eL];
-        uR[v] = a.Uf[tR][(int64_t(fR) * 5 + v) * ldR + eR];
+        uL[v] = pick(a.Uf, tL)[(int64_t(fL) * 5 + v) * ldL + eL];
+        uR[v] = pick(a.Uf, tR)[(int64_t(fR) * 5 + v) * ldR + eR];
+    }
+    // gradients of the sides whose LDG weight is not zero, loaded together
+    // with the states (beta = +-1/2, the usual choice, needs one side only:
+    // the other term would be an exact zero)
+    const T wl = T(0.5) + a.beta, wr = T(0.5) - a.beta;
+    T qL[3][5], qR[3][5];
+    if (NS && wl != T(0)) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qL[j][v] = pick(a.Qf, tL)[(int64_t(fL) * 15 + j * 5 + v) * ldL + eL];
+    }
+    if (NS && wr != T(0)) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qR[j][v] = pick(a.Qf, tR)[(int64_t(fR) * 15 + j * 5 + v) * ldR + eR];
     }
     T FL[3][5], FR[3][5], pL, pR;
     euler_flux(uL, a.gamma, FL, pL);
@@ -688,30 +721,13 @@ __global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
                          n[2] * (FL[2][v] + FR[2][v])) -
                T(0.5) * lam * (uR[v] - uL[v]);
     if (NS) {
-        // a side whose weight is zero (beta = +-1/2, the usual LDG choice) is
-        // neither read nor evaluated: its term would be an exact zero
-        const T wl = T(0.5) + a.beta, wr = T(0.5) - a.beta;
         T FvL[3][5], FvR[3][5];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int v = 0; v < 5; ++v) FvL[j][v] = FvR[j][v] = T(0);
-        if (wl != T(0)) {
-            T q[3][5];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) q[j][v] = a.Qf[tL][(int64_t(fL) * 15 + j * 5 + v) * ldL + eL];
-            viscous_flux(uL, q, a.gamma, a.mu, a.prandtl, FvL);
-        }
-        if (wr != T(0)) {
-            T q[3][5];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) q[j][v] = a.Qf[tR][(int64_t(fR) * 15 + j * 5 + v) * ldR + eR];
-            viscous_flux(uR, q, a.gamma, a.mu, a.prandtl, FvR);
-        }
+        if (wl != T(0)) viscous_flux(uL, qL, a.gamma, a.mu, a.prandtl, FvL);
+        if (wr != T(0)) viscous_flux(uR, qR, a.gamma, a.mu, a.prandtl, FvR);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             T fv = 0;
@@ -722,8 +738,8 @@ __global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        a.Fn[tL][(int64_t(fL) * 5 + v) * ldL + eL] = sL * f[v];
-        a.Fn[tR][(int64_t(fR) * 5 + v) * ldR + eR] = -sR * f[v];
+        pick(a.Fn, tL)[(int64_t(fL) * 5 + v) * ldL + eL] = sL * f[v];
+        pick(a.Fn, tR)[(int64_t(fR) * 5 + v) * ldR + eR] = -sR * f[v];
     }
 }
 
