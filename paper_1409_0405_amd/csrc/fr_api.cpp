@@ -47,6 +47,7 @@ struct DevType {
     frd::Op<T> Aint, Agint, Agrad, Adiv;          // Agint: M0 for the gradients
     frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
+    T *jinv = nullptr;        // [nu][ld] 1 / J at the solution points (host FP64, rounded)
     T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
     T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
     T *reg[3] = {nullptr, nullptr, nullptr};
@@ -373,9 +374,13 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             for (size_t e = size_t(H.nelem); e < ld; ++e) g[k * ld + e] = H.geom[size_t(k) * H.nelem];
         FR_TRY(dev_upload(m, d, D.geom, cast<T>(g), s));
         FR_TRY(dev_upload(m, d, D.xi, cast<T>(R.upts), s));
-        std::vector<double> wJ(size_t(nu) * ld, 0.0);
+        std::vector<double> wJ(size_t(nu) * ld, 0.0), jinv(size_t(nu) * ld, 1.0);
         for (int i = 0; i < nu; ++i)
-            for (int64_t e = 0; e < H.nelem; ++e) wJ[i * ld + e] = R.w[i] * H.jdet[size_t(e) * nu + i];
+            for (int64_t e = 0; e < H.nelem; ++e) {
+                wJ[i * ld + e] = R.w[i] * H.jdet[size_t(e) * nu + i];
+                jinv[i * ld + e] = 1.0 / H.jdet[size_t(e) * nu + i];
+            }
+        FR_TRY(dev_upload(m, d, D.jinv, cast<T>(jinv), s));
         {
             void *q;
             FR_HIP(m, hipMalloc(&q, wJ.size() * sizeof(double)));
@@ -543,7 +548,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         FR_LAUNCH(m, 4 * t + frd::OP_DIV, s,
                   opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
-                           D.geom, D.xi, D.ld, D.nelem, D.nu,
+                           D.jinv, D.ld, D.nelem, D.nu,
                            so[t].per_elem_dt ? D.dte : nullptr};
         if (cl) {
             na.cy = cl->y;

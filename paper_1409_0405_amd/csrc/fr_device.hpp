@@ -107,8 +107,7 @@ struct NegArgs {
     T *acc;
     const T *base;
     T a, b;
-    const T *geom;
-    const T *xi;
+    const T *jinv;     // [nu][ld] 1 / J
     int64_t ld, nelem;
     int nu;
     const T *dte;      // per-element step size, or null

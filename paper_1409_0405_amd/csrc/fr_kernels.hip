@@ -750,8 +750,7 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
     const int i = blockIdx.y;
     if (e >= a.nelem) return;
     const int64_t ld = a.ld;
-    T adj[3][3];
-    const T Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    const T Jinv = a.jinv[int64_t(i) * ld + e];
     const T sc = a.dte ? a.dte[e] : T(1);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
