@@ -208,8 +208,9 @@ fr_status fr_autotune(fr_mesh mesh, void *stream);
  * FP64 and split BF16, 1..2 split FP16); stage 0 / 3 = direct B loads with
  * 2 / 4 K steps in flight, 1 / 2 = B staged through LDS in chunks of 4 / 8 K
  * steps (FP32 only, at most 8 row groups), 4 = the operator's row-group slice
- * held in LDS for four panels (FP32 only, at most 64 KiB of it); the split
- * forms have stage 0 only.  Results are bitwise the same for every variant.  Synchronous
+ * held in LDS for four panels (FP32 only, at most 64 KiB of it).  The split
+ * forms have stage 0 (each wavefront splits its B panel) and 1 (the panel's
+ * row groups, at most 8 and 64 KiB of parts, share the split B in LDS).  Results are bitwise the same for every variant.  Synchronous
  * (uploads the operator); FR_ERR_UNSUPPORTED for a combination the form
  * does not have. */
 fr_status fr_set_blocking(fr_mesh mesh, int32_t etype, int32_t op, int32_t cap, int32_t stage);

@@ -768,10 +768,15 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             frd::OpSplit best_sop;
             std::vector<std::pair<int, int>> cands;
             for (int cap : caps)
-                for (int stage = 0; stage < (split ? 1 : 5); ++stage) {
+                for (int stage = 0; stage < (split ? 2 : 5); ++stage) {
                     if (sizeof(T) != 4 && (stage == 1 || stage == 2 || stage == 4)) continue;
                     int nmg, mbw;
                     frd::row_groups(c.M, cap, nmg, mbw);
+                    if (split) {
+                        if (stage == 1 && (nmg > 8 || nmg * (fmt == 2 ? 2 : 3) * 4096 > 65536)) continue;
+                        cands.push_back({cap, stage});
+                        continue;
+                    }
                     if ((stage == 1 || stage == 2) && nmg > 8) continue;
                     if (stage == 4 && size_t(mbw) * ((((c.K + 3) / 4) + 7) / 8 * 8) * 256 > 65536) continue;
                     cands.push_back({cap, stage});
@@ -783,6 +788,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                 if (split) {
                     std::vector<uint16_t> parts[3];
                     sop = fragment_split(*c.A, c.M, c.K, fmt, parts, cap);
+                    sop.stage = stage;
                     for (int q = 0; q < 3; ++q) {
                         if (parts[q].empty()) continue;
                         void *p;
@@ -1126,11 +1132,14 @@ fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
     const int K = op == frd::OP_GRAD ? nu + nf : op == frd::OP_DIV ? 3 * nu + nf : nu;
     const bool split = m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16;
     if (split) {
-        if (stage) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
+        if (stage > 1) return fail(m, FR_ERR_UNSUPPORTED, "the split forms have stages 0 and 1");
         const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
         if (cap > (fmt == 2 ? 2 : 4)) return fail(m, FR_ERR_UNSUPPORTED, "row-block cap too large for this form");
         std::vector<uint16_t> parts[3];
         frd::OpSplit so = fragment_split(*A, M, K, fmt, parts, cap);
+        so.stage = stage;
+        if (stage == 1 && (so.nmg > 8 || so.nmg * (fmt == 2 ? 2 : 3) * 4096 > 65536))
+            return fail(m, FR_ERR_UNSUPPORTED, "too many row groups to share the split operand");
         for (int q = 0; q < 3; ++q) {
             if (parts[q].empty()) continue;
             void *p;

@@ -54,6 +54,10 @@ struct OpSplit {
     const uint16_t *part[3] = {nullptr, nullptr, nullptr};
     int M = 0, Kb = 0, nmg = 0, mbw = 0, format = 1;
     float inv_scale = 1.0f;
+    // 0 = every wavefront splits its B panel itself; 1 = the row groups of a
+    // panel (nmg <= 8, nmg * parts * 4 KiB <= 64 KiB) share the split B
+    // through LDS.  Both give identical bits.
+    int stage = 0;
 };
 // C = A [B1; B2] with the FP32 state B split on the fly into 16-bit parts
 // like A, products of the leading part pairs on the matrix cores, FP32

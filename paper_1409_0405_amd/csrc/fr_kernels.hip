@@ -489,6 +489,140 @@ __global__ __launch_bounds__(256) void opmul_split_kernel(OpSplit A, const float
     }
 }
 
+// Split-precision product with the split B shared through LDS.  One
+// workgroup per 64-column panel and one wavefront per row group (nmg waves).
+// K steps of 32 are taken in groups of nmg: in each group, wavefront w loads
+// and splits step (group * nmg + w) for the whole panel (the same per-lane
+// work as opmul_split_kernel does for every step) and leaves the parts in
+// LDS in matrix-operand order; then every wavefront multiplies all nmg steps
+// of the group from LDS.  The split work per wavefront drops by nmg, the next
+// group's rows are loaded while the current group is multiplied, and every
+// output sums the same products in the same order as opmul_split_kernel.
+template <int MBW, bool F16, int TAG>
+__global__ __launch_bounds__(512) void opmul_split_lds_kernel(OpSplit A, const float *__restrict__ B1,
+                                                              int64_t ldb1, int K1,
+                                                              const float *__restrict__ B2,
+                                                              int64_t ldb2, int K2,
+                                                              float *__restrict__ C, int64_t ldc) {
+    constexpr int NP = F16 ? 2 : 3;
+    constexpr int NACC = F16 ? 2 : 1;
+    extern __shared__ uintx4 Bs[];              // [nmg][NP][4][64]
+    const int nmg = int(blockDim.x >> 6);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t col = int64_t(blockIdx.x) * 64 + 4 * (lane & 15);
+    const int g = lane >> 4;
+    const int K = K1 + K2;
+    const int Kb = A.Kb;
+    const int mb0 = w * MBW;
+
+    auto row = [&](int k) -> floatx4 {
+        k = min(k, K - 1);
+        const float *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+        return *reinterpret_cast<const floatx4 *>(p + col);
+    };
+
+    floatx4 acc[NACC][MBW][4];
+#pragma unroll
+    for (int c = 0; c < NACC; ++c)
+#pragma unroll
+        for (int m = 0; m < MBW; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[c][m][n] = floatx4{0, 0, 0, 0};
+
+    const uintx4 *Ap[3];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+        Ap[q] = reinterpret_cast<const uintx4 *>(A.part[q]) + size_t(mb0) * Kb * 64 + lane;
+
+    const int ngroups = (Kb + nmg - 1) / nmg;
+    floatx4 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = row(32 * w + 8 * g + j);
+    uintx4 *mine = Bs + size_t(w) * NP * 4 * 64 + lane;
+    for (int gr = 0; gr < ngroups; ++gr) {
+        if (gr * nmg + w < Kb) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                uintx4 b[NP];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned pp[NP];
+                    split2<F16>(x[2 * q][n], x[2 * q + 1][n], pp);
+#pragma unroll
+                    for (int t = 0; t < NP; ++t) b[t][q] = pp[t];
+                }
+#pragma unroll
+                for (int t = 0; t < NP; ++t) mine[(t * 4 + n) * 64] = b[t];
+            }
+        }
+        const int kn = 32 * ((gr + 1) * nmg + w) + 8 * g;     // next group's rows (clamped)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = row(kn + j);
+        __syncthreads();
+        const int nc = min(nmg, Kb - gr * nmg);
+        // A fragments one K step ahead (the first of the group loaded here)
+        uintx4 an[MBW][NP];
+#pragma unroll
+        for (int m = 0; m < MBW; ++m)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) an[m][q] = opaque(Ap[q][(size_t(m) * Kb + gr * nmg) * 64]);
+        for (int c = 0; c < nc; ++c) {
+            const int kb = gr * nmg + c;
+            uintx4 ac[MBW][NP];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) ac[m][q] = an[m][q];
+            const int kq = min(kb + 1, Kb - 1);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) an[m][q] = Ap[q][(size_t(m) * Kb + kq) * 64];
+            const uintx4 *src = Bs + size_t(c) * NP * 4 * 64 + lane;
+            uintx4 b[NP][4];
+#pragma unroll
+            for (int t = 0; t < NP; ++t)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) b[t][n] = src[(t * 4 + n) * 64];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) {
+                const uintx4 *a = ac[m];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    if constexpr (F16) {
+                        acc[0][m][n] = mfma16x32<F16>(a[0], b[0][n], acc[0][m][n]);
+                        acc[1][m][n] = mfma16x32<F16>(a[0], b[1][n], acc[1][m][n]);
+                        acc[1][m][n] = mfma16x32<F16>(a[1], b[0][n], acc[1][m][n]);
+                    } else {
+                        floatx4 tt = mfma16x32<F16>(a[0], b[2][n], acc[0][m][n]);
+                        tt = mfma16x32<F16>(a[1], b[1][n], tt);
+                        tt = mfma16x32<F16>(a[2], b[0][n], tt);
+                        tt = mfma16x32<F16>(a[0], b[1][n], tt);
+                        tt = mfma16x32<F16>(a[1], b[0][n], tt);
+                        acc[0][m][n] = mfma16x32<F16>(a[0], b[0][n], tt);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const float is = A.inv_scale;
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rw = 16 * (mb0 + m) + 4 * g + r;
+            if (rw < A.M) {
+                floatx4 out;
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    out[n] = NACC == 2 ? acc[0][m][n][r] + acc[NACC - 1][m][n][r] * is : acc[0][m][n][r];
+                *reinterpret_cast<floatx4 *>(C + int64_t(rw) * ldc + col) = out;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Geometry at a solution point from the Jacobian coefficients.
 // Tet: constant columns c0..c2.  Prism: dx/dxi = A1 + C1 z,
@@ -921,6 +1055,21 @@ template <bool F16, int TAG>
 hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int K1,
                             const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
                             int64_t npanels, hipStream_t s) {
+    if (A.stage == 1) {
+        const size_t lds = size_t(A.nmg) * (F16 ? 2 : 3) * 4 * 64 * 16;
+        if (A.nmg > 8 || lds > 65536) return hipErrorInvalidValue;
+        const dim3 g{unsigned(npanels)}, b{unsigned(64 * A.nmg)};
+#define FR_SLDS(w)                                                                                       \
+    case w:                                                                                              \
+        opmul_split_lds_kernel<w, F16, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+        break;
+        switch (A.mbw) {
+            FR_SLDS(1) FR_SLDS(2) FR_SLDS(3) FR_SLDS(4)
+            default: return hipErrorInvalidValue;
+        }
+#undef FR_SLDS
+        return hipGetLastError();
+    }
     const int64_t nwaves = npanels * A.nmg;
     const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
 #define FR_MBW(w)                                                                           \

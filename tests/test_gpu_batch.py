@@ -143,7 +143,7 @@ def test_autotune_keeps_results_bitwise():
         assert torch.equal(r0[t], r1[t])
 
 
-@pytest.mark.parametrize("p,prec", ((2, "fp32"), (4, "fp32"), (3, "fp64")))
+@pytest.mark.parametrize("p,prec", ((2, "fp32"), (4, "fp32"), (3, "fp64"), (4, "split_bf16"), (3, "split_fp16")))
 def test_every_product_variant_gives_identical_bits(p, prec):
     """Row blocking (1..8 blocks of 16 rows per wavefront) and LDS staging of
     the B panel (chunks of 4 or 8 K steps) do not change any output's
@@ -160,7 +160,8 @@ def test_every_product_variant_gives_identical_bits(p, prec):
     M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r0])
     torch.cuda.synchronize()
     n = 0
-    for stage in ((0, 1, 2, 3, 4) if prec == "fp32" else (0, 3)):
+    stages = {"fp32": (0, 1, 2, 3, 4), "fp64": (0, 3)}.get(prec, (0, 1))
+    for stage in stages:
         for cap in (1, 2, 3, 4, 8):
             ok = True
             for t in (0, 1):
@@ -176,7 +177,7 @@ def test_every_product_variant_gives_identical_bits(p, prec):
             for t in (0, 1):
                 assert torch.equal(r0[t], r1[t]), (stage, cap, t)
             n += ok
-    assert n >= (10 if prec == "fp32" else 4)
+    assert n >= {"fp32": 10, "fp64": 4}.get(prec, 2)
 
 
 def test_batched_problems_match_oracle_fp32():
