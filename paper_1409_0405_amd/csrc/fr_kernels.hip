@@ -63,6 +63,16 @@ __device__ __forceinline__ V opaque(V x) {
     return x;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// operator products renumber them so that every XCD runs one contiguous range
+// of logical workgroups (the grid is a multiple of 8): the row groups of a
+// 64-column panel, split over neighbouring workgroups, then read the panel of
+// B through the same L2 instead of fetching it from HBM once per XCD.
+__device__ __forceinline__ unsigned xcd_block() {
+    return (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+}
+inline unsigned xcd_grid(int64_t nblocks) { return unsigned((nblocks + 7) / 8 * 8); }
+
 // ---------------------------------------------------------------------------
 // Operator product C = A [B1; B2] on the matrix cores.  TAG (4 * element type
 // + operator id) only names the instantiation, so that a profiler reports each
@@ -86,7 +96,7 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
                                                     int64_t npanels, int nmg) {
     using v4 = typename Vec4<T>::type;
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
     const int64_t panel = wid / nmg;
     const int mg = int(wid - panel * nmg);
     if (panel >= npanels) return;
@@ -164,13 +174,16 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
                                                         int64_t ldb1, int K1,
                                                         const float *__restrict__ B2,
                                                         int64_t ldb2, int K2,
-                                                        float *__restrict__ C, int64_t ldc) {
+                                                        float *__restrict__ C, int64_t ldc,
+                                                        int64_t npanels) {
     constexpr int NV = 64 * KS;                 // 16-byte vectors per chunk
+    const unsigned blk = xcd_block();
+    if (blk >= npanels) return;                 // whole workgroup: padding of the grid
     __shared__ floatx4 Bs[2][NV];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, mg = tid >> 6;
     const int krow = lane >> 4;
-    const int64_t col0 = int64_t(blockIdx.x) * 64;
+    const int64_t col0 = int64_t(blk) * 64;
     const int K = K1 + K2, Kb = A.Kb;
     const int nchunk = Kb / KS;
 
@@ -278,8 +291,9 @@ __global__ __launch_bounds__(256) void opmul_ldsa_kernel(Op<float> A, const floa
     extern __shared__ floatx4 As[];             // [MBW][Kb / 4][64]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int Kb = A.Kb, Kq = Kb / 4;
-    const int mg = int(blockIdx.x % unsigned(nmg));
-    const int64_t panel = int64_t(blockIdx.x / unsigned(nmg)) * 4 + w;
+    const unsigned blk = xcd_block();
+    const int mg = int(blk % unsigned(nmg));
+    const int64_t panel = int64_t(blk / unsigned(nmg)) * 4 + w;
     const int mb0 = mg * MBW;
     const floatx4 *Ag = reinterpret_cast<const floatx4 *>(A.frag) + size_t(mb0) * Kq * 64;
     for (int i = threadIdx.x; i < MBW * Kq * 64; i += 256) As[i] = Ag[i];
@@ -401,7 +415,7 @@ __global__ __launch_bounds__(256) void opmul_split_kernel(OpSplit A, const float
     constexpr int NP = F16 ? 2 : 3;       // parts per operand
     constexpr int NACC = F16 ? 2 : 1;
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
     const int64_t panel = wid / nmg;
     const int mg = int(wid - panel * nmg);
     if (panel >= npanels) return;
@@ -503,13 +517,16 @@ __global__ __launch_bounds__(512) void opmul_split_lds_kernel(OpSplit A, const f
                                                               int64_t ldb1, int K1,
                                                               const float *__restrict__ B2,
                                                               int64_t ldb2, int K2,
-                                                              float *__restrict__ C, int64_t ldc) {
+                                                              float *__restrict__ C, int64_t ldc,
+                                                              int64_t npanels) {
     constexpr int NP = F16 ? 2 : 3;
     constexpr int NACC = F16 ? 2 : 1;
     extern __shared__ uintx4 Bs[];              // [nmg][NP][4][64]
+    const unsigned blk = xcd_block();
+    if (blk >= npanels) return;                 // whole workgroup: padding of the grid
     const int nmg = int(blockDim.x >> 6);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t col = int64_t(blockIdx.x) * 64 + 4 * (lane & 15);
+    const int64_t col = int64_t(blk) * 64 + 4 * (lane & 15);
     const int g = lane >> 4;
     const int K = K1 + K2;
     const int Kb = A.Kb;
@@ -981,7 +998,7 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
         if (A.stage == 4) {
             const size_t lds = size_t(mbw) * A.Kb * 64 * sizeof(float);
             if (lds > 65536) return hipErrorInvalidValue;
-            const dim3 g{unsigned((npanels + 3) / 4) * unsigned(nmg)}, b{256u};
+            const dim3 g{xcd_grid((npanels + 3) / 4 * nmg)}, b{256u};
 #define FR_LDSA(w)                                                                                   \
     case w:                                                                                          \
         opmul_ldsa_kernel<w, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
@@ -995,13 +1012,13 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
         }
         if (A.stage == 1 || A.stage == 2) {
             if (nmg > 8) return hipErrorInvalidValue;
-            const dim3 g{unsigned(npanels)}, b{unsigned(64 * nmg)};
+            const dim3 g{xcd_grid(npanels)}, b{unsigned(64 * nmg)};
 #define FR_LDS(w)                                                                                  \
     case w:                                                                                        \
         if (A.stage == 2)                                                                          \
-            opmul_lds_kernel<w, TAG, 8><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+            opmul_lds_kernel<w, TAG, 8><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
         else                                                                                       \
-            opmul_lds_kernel<w, TAG, 4><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+            opmul_lds_kernel<w, TAG, 4><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
         break;
             switch (mbw) {
                 FR_LDS(1) FR_LDS(2) FR_LDS(3) FR_LDS(4) FR_LDS(5) FR_LDS(6) FR_LDS(7) FR_LDS(8)
@@ -1012,7 +1029,7 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
         }
     }
     const int64_t nwaves = npanels * nmg;
-    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
+    const dim3 grid(xcd_grid((nwaves + 3) / 4)), block(256);
 #define FR_MBW(w)                                                                                \
     case w:                                                                                      \
         if (A.stage == 3)                                                                        \
@@ -1058,10 +1075,10 @@ hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int
     if (A.stage == 1) {
         const size_t lds = size_t(A.nmg) * (F16 ? 2 : 3) * 4 * 64 * 16;
         if (A.nmg > 8 || lds > 65536) return hipErrorInvalidValue;
-        const dim3 g{unsigned(npanels)}, b{unsigned(64 * A.nmg)};
+        const dim3 g{xcd_grid(npanels)}, b{unsigned(64 * A.nmg)};
 #define FR_SLDS(w)                                                                                       \
     case w:                                                                                              \
-        opmul_split_lds_kernel<w, F16, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc);    \
+        opmul_split_lds_kernel<w, F16, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
         break;
         switch (A.mbw) {
             FR_SLDS(1) FR_SLDS(2) FR_SLDS(3) FR_SLDS(4)
@@ -1071,7 +1088,7 @@ hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int
         return hipGetLastError();
     }
     const int64_t nwaves = npanels * A.nmg;
-    const dim3 grid(unsigned((nwaves + 3) / 4)), block(256);
+    const dim3 grid(xcd_grid((nwaves + 3) / 4)), block(256);
 #define FR_MBW(w)                                                                           \
     case w:                                                                                 \
         opmul_split_kernel<w, F16, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, \
