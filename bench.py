@@ -112,6 +112,56 @@ def cpu_baseline(target_seconds):
                       f"({dof} DOF, {el:.1f} s; NumPy with its thread pools limited to one thread)"}
 
 
+def closure_form(steps, warmup, arrays, mach, mu, pr, stream):
+    """Cost of the learned closure in the order-1 residual on the full mixed
+    mesh: RK45[2R+] steps of the order-1 NS solve without and with the network
+    attached (BF16 and FP32 weights; seeded weights, unit statistics: the
+    timing does not depend on the trained values)."""
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import frlib, inputs
+    m = frlib.Mesh(arrays, 1, system="ns", precision="fp32", mu=mu, prandtl=pr, stream=stream)
+    dof = 0
+    for t in (0, 1):
+        q = m.query(t)
+        x = m.upts_coords(t)
+        U = inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=mach)
+        u = frlib.to_device_state(m, t, np.transpose(U, (1, 0, 2)).astype(np.float32))
+        m.set_solution(t, u.data_ptr(), stream)
+        torch.cuda.synchronize()
+        dof += q["nupts"] * q["nelem"] * 5
+    net = frlib.MLP(0)
+    stats = torch.cat([torch.zeros(120), torch.ones(120), torch.zeros(20),
+                       torch.full((20,), 1e-6)]).float().cuda()
+    dt = 1e-4
+    out = {"order": 1, "n_dof": dof}
+    for label, attach in (("plain", None), ("closure_bf16", True), ("closure_fp32", False)):
+        if attach is None:
+            m.closure_attach(None)
+        else:
+            m.closure_attach(net, stats.data_ptr(), bf16_weights=attach)
+        m.rk_step(frlib.FR_RK45_2RP, dt, max(warmup, 1), stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.rk_step(frlib.FR_RK45_2RP, dt, steps, stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[label] = {"ms_per_step": 1e3 * el / steps, "value": 5.0 * dof * steps / el / 1e9}
+    m.closure_attach(net, stats.data_ptr(), bf16_weights=True)
+    m.profile(True)
+    m.rk_step(frlib.FR_RK45_2RP, dt, 2, stream)
+    prof = m.profile_read()
+    m.profile(False)
+    m.closure_attach(None)
+    for k in ("closure_inputs", "closure_forward"):
+        ms, cnt = prof[k]
+        out[k + "_us_per_rhs"] = 1e3 * ms / 10 if cnt else None       # 2 steps x 5 stages
+    out["overhead_bf16"] = out["closure_bf16"]["ms_per_step"] / out["plain"]["ms_per_step"] - 1.0
+    out["unit"] = "GDOF/s per RHS"
+    m.close()
+    return out
+
+
 def batch_form(steps, warmup, cfl=0.2):
     """512 independent periodic Euler problems (vortex at a random centre,
     element counts log-uniform in [100, 20000], orders uniform in 1..4, half
@@ -174,6 +224,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variants", action="store_true",
+                    help="time every product variant of the prism corrected-gradient "
+                         "operator on this workload (one JSON line) instead of the bench")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -277,6 +330,30 @@ def main():
         del u, r
         return out
 
+    if args.variants:
+        # every (row blocks per wavefront, staging) variant of the dominant
+        # product, six RHS evaluations each; used with rocprofv3 --pmc to
+        # measure each variant's HBM traffic
+        u = [frlib.to_device_state(mesh, t, host_state[t]) for t in (0, 1)]
+        r = [frlib.state_tensor(mesh, t) for t in (0, 1)]
+        rows = []
+        for stage in (0, 1, 2, 3, 4):
+            for cap in (1, 2, 3, 4, 5, 6, 8):
+                try:
+                    mesh.set_blocking(1, 1, cap, stage)
+                except frlib.FrError:
+                    continue
+                mesh.profile(True)
+                for _ in range(6):
+                    mesh.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r], stream)
+                ms, cnt = mesh.profile_read()["grad_pri"]
+                mesh.profile(False)
+                nmg = -(-15 // cap)
+                rows.append({"cap": cap, "rows_blocks_per_wave": -(-15 // nmg), "stage": stage,
+                             "avg_us": 1e3 * ms / cnt})
+        print(json.dumps({"variants_grad_pri": rows}), flush=True)
+        return
+
     ms_per_step, value, drift, finite = timed(mesh, args.steps, args.warmup)
     print(f"fp32: {ms_per_step:.3f} ms/step, {value:.2f} GDOF/s per RHS, mass/energy drift {drift:.2e}",
           file=sys.stderr, flush=True)
@@ -357,6 +434,13 @@ def main():
             torch.cuda.empty_cache()
         print(f"fp32 rhs error {forms['fp32']['rhs_rel_l2_vs_fp64']}, state error "
               f"{forms['fp32']['state_rel_l2_vs_fp64']}", file=sys.stderr, flush=True)
+
+    if not args.no_forms:
+        mesh.close()
+        torch.cuda.empty_cache()
+        cf = closure_form(args.steps, args.warmup, arrays, mach, mu, pr, stream)
+        forms["closure_p1"] = cf
+        print(f"closure: {cf}", file=sys.stderr, flush=True)
 
     if not args.no_batch:
         mesh.close()

@@ -190,8 +190,9 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * operator products (op 0 interpolation to flux points, 1 corrected
  * gradient, 2 gradient interpolation, 3 divergence plus correction), 8 + etype
  * the solution-point flux kernel, 10 common solution, 11 common interface
- * flux, 12 + etype negdivconf with the Runge-Kutta update. */
-#define FR_PROF_NCLASS 14
+ * flux, 12 + etype negdivconf with the Runge-Kutta update, 14 closure
+ * inputs (moments and neighbour gathering), 15 closure network forward. */
+#define FR_PROF_NCLASS 16
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 

@@ -135,7 +135,7 @@ fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
 // Kernel classes of the profiler: 0..7 operator products (4 * type + op),
 // 8/9 solution-point kernel (tet/prism), 10 common solution, 11 common flux,
 // 12/13 negdivconf (tet/prism).
-constexpr int PROF_NCLASS = 14;
+constexpr int PROF_NCLASS = 16;
 constexpr size_t PROF_NONE = size_t(-1);
 
 size_t prof_begin(fr_mesh m, hipStream_t s) {
@@ -530,16 +530,17 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
     const Closure *cl = (m->closure && m->closure->params) ? m->closure.get() : nullptr;
     if (cl) {
+        const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
         for (int t = 0; t < 2; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
-            FR_HIP(m, frd::launch_moments<T>(U[t], nullptr, D.ld, D.nelem, D.nu, cl->Mom[t], cl->mom,
-                                             t ? d.t[0].nelem : 0, nullptr, s));
+            // feature-major moments, inputs and outputs: every access coalesced
+            FR_LAUNCH(m, 14, s, frd::launch_moments<T>(U[t], nullptr, D.ld, D.nelem, D.nu, cl->Mom[t], cl->mom,
+                                                       t ? d.t[0].nelem : 0, 1, ntot, nullptr, s));
         }
-        const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
-        FR_HIP(m, frd::launch_features(cl->mom, cl->nb, ntot, cl->stats, cl->feat, s));
-        FR_HIP(m, frd::launch_mlp_forward(cl->params, cl->params_bf16, cl->bf16, cl->feat, ntot,
-                                          cl->stats, false, cl->y, s));
+        FR_LAUNCH(m, 14, s, frd::launch_features(cl->mom, 1, ntot, cl->nb, ntot, cl->stats, cl->feat, 1, ntot, s));
+        FR_LAUNCH(m, 15, s, frd::launch_mlp_forward(cl->params, cl->params_bf16, cl->bf16, cl->feat, 1, ntot, ntot,
+                                                    cl->stats, false, cl->y, 1, ntot, s));
     }
     for (int t = 0; t < 2; ++t) {
         DevType<T> &D = d.t[t];
@@ -552,6 +553,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
                            so[t].per_elem_dt ? D.dte : nullptr};
         if (cl) {
             na.cy = cl->y;
+            na.cys = d.t[0].nelem + d.t[1].nelem;
             na.clift = cl->lift[t];
             na.goff = t ? d.t[0].nelem : 0;
         }
@@ -1520,7 +1522,8 @@ fr_status fr_mlp_get_params(fr_mlp n, float *host) {
 fr_status fr_mlp_forward(fr_mlp n, const float *x, int64_t count, const float *stats, float *y,
                          int32_t bf16_weights, void *stream) {
     if (!n || !x || !y || count < 0) return FR_ERR_INVALID_ARG;
-    FR_MHIP(n, frd::launch_mlp_forward(n->params, n->params_bf16, bf16_weights != 0, x, count, stats, true, y,
+    FR_MHIP(n, frd::launch_mlp_forward(n->params, n->params_bf16, bf16_weights != 0, x, frd::MLP_IN, 1, count,
+                                       stats, true, y, frd::MLP_OUT, 1,
                                        static_cast<hipStream_t>(stream)));
     return FR_OK;
 }
@@ -1628,14 +1631,14 @@ fr_status closure_tables(fr_mesh m) {
 
 template <typename T>
 fr_status closure_moments_impl(fr_mesh m, const void *const u[2], const void *const b[2], float *mom,
-                               const float *ystats, hipStream_t s) {
+                               int64_t rs, int64_t cs, const float *ystats, hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
     for (int t = 0; t < 2; ++t) {
         if (!d.t[t].nelem) continue;
         if (!u || !u[t] || (b && !b[t])) return fail(m, FR_ERR_INVALID_ARG, "null state");
         FR_HIP(m, frd::launch_moments<T>(static_cast<const T *>(u[t]), b ? static_cast<const T *>(b[t]) : nullptr,
                                          d.t[t].ld, d.t[t].nelem, d.t[t].nu, m->closure->Mom[t], mom,
-                                         t ? d.t[0].nelem : 0, ystats, s));
+                                         t ? d.t[0].nelem : 0, rs, cs, ystats, s));
     }
     return FR_OK;
 }
@@ -1649,8 +1652,8 @@ fr_status fr_closure_moments(fr_mesh m, const void *const u[2], float *mom, void
     if (!mom) return fail(m, FR_ERR_INVALID_ARG, "null output");
     if (fr_status st = closure_tables(m)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, nullptr, mom, nullptr, s)
-                                   : closure_moments_impl<double>(m, u, nullptr, mom, nullptr, s);
+    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, nullptr, mom, 20, 1, nullptr, s)
+                                   : closure_moments_impl<double>(m, u, nullptr, mom, 20, 1, nullptr, s);
 }
 
 fr_status fr_closure_targets(fr_mesh m, const void *const a[2], const void *const b[2], const float *stats,
@@ -1660,8 +1663,8 @@ fr_status fr_closure_targets(fr_mesh m, const void *const a[2], const void *cons
     if (fr_status st = closure_tables(m)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const float *ys = stats ? stats + 2 * frd::MLP_IN : nullptr;
-    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, a, b, out, ys, s)
-                                   : closure_moments_impl<double>(m, a, b, out, ys, s);
+    return m->precision != FR_FP64 ? closure_moments_impl<float>(m, a, b, out, 20, 1, ys, s)
+                                   : closure_moments_impl<double>(m, a, b, out, 20, 1, ys, s);
 }
 
 fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *stats, float *feat,
@@ -1670,11 +1673,12 @@ fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *st
     if (!feat) return fail(m, FR_ERR_INVALID_ARG, "null output");
     if (fr_status st = closure_tables(m)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    fr_status st = m->precision != FR_FP64 ? closure_moments_impl<float>(m, u, nullptr, m->closure->mom, nullptr, s)
-                                           : closure_moments_impl<double>(m, u, nullptr, m->closure->mom, nullptr, s);
+    const int64_t ntot = m->host.t[0].nelem + m->host.t[1].nelem;
+    fr_status st = m->precision != FR_FP64
+                       ? closure_moments_impl<float>(m, u, nullptr, m->closure->mom, 1, ntot, nullptr, s)
+                       : closure_moments_impl<double>(m, u, nullptr, m->closure->mom, 1, ntot, nullptr, s);
     if (st) return st;
-    FR_HIP(m, frd::launch_features(m->closure->mom, m->closure->nb, m->host.t[0].nelem + m->host.t[1].nelem,
-                                   stats, feat, s));
+    FR_HIP(m, frd::launch_features(m->closure->mom, 1, ntot, m->closure->nb, ntot, stats, feat, frd::MLP_IN, 1, s));
     return FR_OK;
 }
 

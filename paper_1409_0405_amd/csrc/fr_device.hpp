@@ -115,8 +115,9 @@ struct NegArgs {
     int64_t ld, nelem;
     int nu;
     const T *dte;      // per-element step size, or null
-    // learned closure: k += sum_a lift[i][a] y[goff + e][v * 4 + a]
+    // learned closure: k += sum_a lift[i][a] y[(v * 4 + a) * cys + goff + e]
     const float *cy = nullptr;
+    int64_t cys = 0;
     const float *clift = nullptr;   // [nu][4]
     int64_t goff = 0;
 };
@@ -146,11 +147,13 @@ constexpr int MLP_NSTATS = 2 * MLP_IN + 2 * MLP_OUT;   // mu_x, s_x, mu_y, s_y
 constexpr int MLP_GRAD_BLOCKS = 256;
 template <typename T>
 hipError_t launch_moments(const T *U, const T *B, int64_t ld, int64_t nelem, int nu, const float *Mom,
-                          float *mom, int64_t goff, const float *ystats, hipStream_t s);
-hipError_t launch_features(const float *mom, const int32_t *nb, int64_t ntot, const float *stats,
-                           float *feat, hipStream_t s);
-hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t n,
-                              const float *stats, bool norm_in, float *Y, hipStream_t s);
+                          float *mom, int64_t goff, int64_t rs, int64_t cs, const float *ystats,
+                          hipStream_t s);
+hipError_t launch_features(const float *mom, int64_t rs, int64_t cs, const int32_t *nb, int64_t ntot,
+                           const float *stats, float *feat, int64_t frs, int64_t fcs, hipStream_t s);
+hipError_t launch_mlp_forward(const float *P, const uint16_t *Pb, bool bf16, const float *X, int64_t xrs,
+                              int64_t xcs, int64_t n, const float *stats, bool norm_in, float *Y, int64_t yrs,
+                              int64_t ycs, hipStream_t s);
 hipError_t launch_mlp_grad(const float *P, const float *X, const float *Tg, const int32_t *idx, int64_t n,
                            const float *stats, float *partial, int nblk, float *grad, hipStream_t s);
 hipError_t launch_adam(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps,

@@ -908,9 +908,9 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
         const int64_t o = (int64_t(i) * 5 + v) * ld + e;
         T k = -a.Rt[o] * Jinv;
         if (a.cy) {
-            const float *y = a.cy + (a.goff + e) * 20 + v * 4;
+            const float *y = a.cy + (a.goff + e) + int64_t(v) * 4 * a.cys;
             const float *l = a.clift + i * 4;
-            k += T(l[0] * y[0] + l[1] * y[1] + l[2] * y[2] + l[3] * y[3]);
+            k += T(l[0] * y[0] + l[1] * y[a.cys] + l[2] * y[2 * a.cys] + l[3] * y[3 * a.cys]);
         }
         k *= sc;
         T accv = 0;

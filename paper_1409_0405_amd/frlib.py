@@ -43,7 +43,7 @@ MLP_NPARAM, MLP_NSTATS = 13204, 280
 PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
                 "upts_tet", "upts_pri", "common_solution", "common_flux",
-                "negdivconf_tet", "negdivconf_pri")
+                "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward")
 
 
 class FrError(RuntimeError):
