@@ -15,6 +15,10 @@ statistics):
    data);
 4. run order 1 with and without the attached closure from Pi_1 U_q(0) and
    compare the kinetic-energy dissipation rate -dE_k/dt with order q's.
+
+generate_along_trajectory() is the variant whose inputs and order-1
+residuals come from the order-1 run itself (advanced beside order q), so the
+network is trained on the states it is later applied to.
 """
 from __future__ import annotations
 
@@ -86,6 +90,52 @@ def generate(hi, lo, dt, n_snap, steps_between, stream=0):
         rates.append(-hi.reduce(frlib.FR_RED_KE, stream)[1])
         states.append([x.clone() for x in u1])
     return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates), states
+
+
+def generate_along_trajectory(hi, lo, dt_hi, steps_hi, dt_lo, steps_lo, n_snap, stream=0):
+    """Like generate(), but the inputs and the order-1 residual come from the
+    order-1 solution itself, advanced beside the order-q run from the
+    filtered initial state (both meshes hold their initial states): targets
+    = P1 moments of Pi_1 R_q(U_q(t)) - R_1(U_1(t)).  The network then sees
+    the states it will be applied to."""
+    import torch
+    ntot = sum(hi.query(t)["nelem"] for t in (0, 1))
+    X = torch.zeros((n_snap, ntot, 120), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((n_snap, ntot, 20), dtype=torch.float32, device="cuda")
+    uq, rq = _states(hi), _states(hi)
+    u1, r1, pr = _states(lo), _states(lo), _states(lo)
+    times, rates, states = [], [], []
+    t_now = 0.0
+    for k in range(n_snap):
+        if k:
+            hi.rk_step(frlib.FR_RK45_2RP, dt_hi, steps_hi, stream)
+            lo.rk_step(frlib.FR_RK45_2RP, dt_lo, steps_lo, stream)
+            t_now += dt_hi * steps_hi
+        for t in (0, 1):
+            hi.get_solution(t, uq[t].data_ptr(), stream)
+            lo.get_solution(t, u1[t].data_ptr(), stream)
+        hi.rhs(_ptrs(uq), _ptrs(rq), stream)
+        hi.project_to(lo, _ptrs(rq), _ptrs(pr), stream)
+        lo.rhs(_ptrs(u1), _ptrs(r1), stream)
+        lo.closure_targets(_ptrs(pr), _ptrs(r1), 0, Y[k].data_ptr(), stream)
+        lo.closure_features(_ptrs(u1), 0, X[k].data_ptr(), stream)
+        torch.cuda.synchronize()
+        times.append(t_now)
+        rates.append(-hi.reduce(frlib.FR_RED_KE, stream)[1])
+        states.append([x.clone() for x in u1])
+    return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates), states
+
+
+def load_filtered(hi, lo, stream=0):
+    """Order-1 solution of lo = L2 projection of the order-q solution of hi."""
+    import torch
+    uq, u1 = _states(hi), _states(lo)
+    for t in (0, 1):
+        hi.get_solution(t, uq[t].data_ptr(), stream)
+    hi.project_to(lo, _ptrs(uq), _ptrs(u1), stream)
+    for t in (0, 1):
+        lo.set_solution(t, u1[t].data_ptr(), stream)
+    torch.cuda.synchronize()
 
 
 def stats_of(X, Y):

@@ -323,3 +323,44 @@ def test_trained_closure_reduces_apriori_dissipation_error():
           f"closure BF16 {e(corr16):.3e}", flush=True)
     assert e(corr) < 0.33 * e(plain)
     assert e(corr16) < 0.33 * e(plain)
+
+
+def test_closure_trained_along_trajectory_runs_stably():
+    """Trained on the order-1 run itself (inputs and order-1 residuals from
+    U_1(t), targets against the filtered order-4 residual), the closure keeps
+    the order-1 Taylor-Green run finite over t in [0, 8] and is judged on the
+    kinetic-energy dissipation rate against the plain order-4 run (printed;
+    the gain is mesh dependent, see the design notes)."""
+    import math
+    from paper_1409_0405_amd import closure as cl, frlib
+    print("closure along the trajectory: generate", flush=True)
+    arrays = inputs.tgv_mixed_box(nxy=8, n_pri_layers=14, n_tet_layers=8, jitter=0.1, seed=0)
+    hi = frlib.Mesh(arrays, 4, system="ns", precision="fp32", mu=1.0 / 1600.0, check_finite=True)
+    lo = frlib.Mesh(arrays, 1, system="ns", precision="fp32", mu=1.0 / 1600.0, check_finite=True)
+    n_int, T_end = 20, 8.0
+    h_ref = min(math.pi / 14, math.pi / 16)
+    dt4, dt1 = cl.dt_for(4, h_ref, cfl=0.25), cl.dt_for(1, h_ref, cfl=0.25)
+    sb4, sb1 = max(1, round(T_end / n_int / dt4)), max(1, round(T_end / n_int / dt1))
+    dt4, dt1 = T_end / n_int / sb4, T_end / n_int / sb1
+    cl.load_tgv(hi)
+    cl.load_filtered(hi, lo)
+    X, Y, times, rates4, _ = cl.generate_along_trajectory(hi, lo, dt4, sb4, dt1, sb1, n_int + 1)
+    stats = cl.stats_of(X, Y)
+    print("closure along the trajectory: train", flush=True)
+    net, hist = cl.train(X, Y, stats, epochs=30, batch=4096, lr=2e-3)
+    assert hist[-1] < hist[0]
+
+    def run(with_net):
+        cl.load_tgv(hi)
+        cl.load_filtered(hi, lo)
+        if with_net:
+            lo.closure_attach(net, stats.data_ptr(), bf16_weights=True)
+        try:
+            return cl.dissipation_history(lo, dt1, n_int + 1, sb1)
+        finally:
+            lo.closure_attach(None)
+    plain, corr = run(False), run(True)
+    assert np.isfinite(corr).all()
+    e = lambda r: float(np.sqrt(np.mean((r - rates4) ** 2) / np.mean(rates4 ** 2)))
+    print(f"a-posteriori dissipation-rate error vs order 4: plain {e(plain):.3f}, closure {e(corr):.3f}",
+          flush=True)

@@ -99,12 +99,17 @@ CASES = [
     ("mixed", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("mixed", 4, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("mixed", 4, "euler", inputs.taylor_green, {"mach": 0.1}, 0.0),
+    ("prisms", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("prisms", 1, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
 ]
 
 
 def _mesh(kind, seed=0):
     if kind == "tetcube":
         return inputs.vortex_tet_cube(n=6, jitter=0.05, seed=seed)
+    if kind == "prisms":
+        # prisms only (the tet type is empty): 5 x 5 x 2 triangles x 3 layers = 150
+        return inputs.mixed_box(5, 5, 3, 0, (2 * math.pi,) * 3, jitter=0.1, seed=seed)
     # 4 x 4 x (3 + 3): 96 prisms and 288 tets -> ragged against 64
     return inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=seed)
 
