@@ -148,6 +148,19 @@ def measured_peaks():
             best = max(best, reps * 2.0 * m ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12)
             del x, y
         out[name] = best
+    # the vendor FP32 GEMM on the shape of the dominant product (prism
+    # corrected gradient: 225 x 180 operator, 552,960 columns), for comparison
+    A = torch.randn(225, 180, device="cuda")
+    B = torch.randn(180, 552960, device="cuda")
+    for _ in range(3):
+        torch.matmul(A, B)
+    e0.record()
+    for _ in range(10):
+        torch.matmul(A, B)
+    e1.record()
+    e1.synchronize()
+    out["vendor_sgemm_grad_pri_shape_us"] = e0.elapsed_time(e1) / 10 * 1e3
+    del A, B
     torch.cuda.empty_cache()
     return out
 
