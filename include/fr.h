@@ -156,6 +156,23 @@ fr_status fr_rhs(fr_mesh mesh, const void *const u_dev[2], void *const r_dev[2],
 fr_status fr_rk_step(fr_mesh mesh, int32_t scheme, double dt, int32_t n_steps,
                      void *stream);
 
+/* Adaptive RK45[2R+]: advance the solution register from state[0] (time) to
+ * t_end with error control by the scheme's embedded third-order solution
+ * (Section 3.4 names the scheme; the controller is this library's reading).
+ * Per attempt: e = dt sum_i (b_i - bhat_i) k_i accumulated in a third
+ * register; err = RMS over all values of e / (atol + rtol max(|u_old|,
+ * |u_new|)), summed in FP64 on the device; accepted if err <= 1.  Step size:
+ * accepted dt * clamp(0.9 err^(-0.7/4) err_prev^(0.4/4), 0.2, 5), err_prev =
+ * max(err, 1e-4); rejected (the step is undone) dt * clamp(0.9 err^(-1/4),
+ * 0.2, 1); the last step is cut to land on t_end exactly.
+ * state: in/out {t, dt (next proposed step), err_prev (1 to start)}.
+ * counts: out {accepted, rejected}.  Stops at t_end or after max_attempts
+ * attempts.  Synchronises the stream once per attempt.  Allocates the error
+ * register on first use.  FR_ERR_NONFINITE (step undone) if the error
+ * estimate is not finite. */
+fr_status fr_rk45_adaptive(fr_mesh mesh, double t_end, double state[3], double atol, double rtol,
+                           int32_t max_attempts, int32_t counts[2], void *stream);
+
 /* Global FP64 reductions over the mesh's solution register U (and, for the
  * residual items, over R(U), evaluated here).  Integrals use the element
  * quadrature: int f = sum_e sum_i w_i J_ei f_ei.  `what` selects one item:

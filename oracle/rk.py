@@ -93,3 +93,76 @@ def run(stepper, f, U, dt, n):
     for _ in range(n):
         U = stepper(f, U, dt)
     return U
+
+
+# ---------------------------------------------------------------------------
+# Adaptive RK45[2R+] (reading R10: the embedded third-order solution of the
+# scheme as error estimate, a PI step-size controller).
+#
+#   e = dt sum_i (b_i - bhat_i) k_i                    (u_4th - u_3rd)
+#   err = sqrt( mean over all values of (e / (atol + rtol max(|u_old|, |u_new|)))^2 )
+#   accept if err <= 1;  k = 4 (e = O(dt^4))
+#   accepted: fac = SAFETY err^(-0.7/k) err_prev^(0.4/k), err_prev = max(err, 1e-4)
+#   rejected: fac = SAFETY err^(-1/k), at most 1
+#   dt <- dt * min(FAC_MAX, max(FAC_MIN, fac)); the last step is cut to land on t_end.
+# ---------------------------------------------------------------------------
+ADAPT_K = 4.0
+ADAPT_SAFETY, ADAPT_FAC_MIN, ADAPT_FAC_MAX, ADAPT_ERR_FLOOR = 0.9, 0.2, 5.0, 1e-4
+
+
+def rk45_step_with_error(f, U, dt):
+    """One RK45[2R+] step in two-register form, plus the embedded error
+    e = u_4th - u_3rd accumulated stage by stage."""
+    q = dict(U)
+    r = dict(U)
+    e = {n: np.zeros_like(U[n]) for n in U}
+    for i in range(5):
+        k = f(r)
+        bi = float(RK45_B[i])
+        q = _axpy(dt * bi, k, q)
+        e = _axpy(dt * (bi - float(RK45_BHAT[i])), k, e)
+        if i < 4:
+            r = _axpy(dt * (float(RK45_A[i]) - bi), k, q)
+    return q, e
+
+
+def error_norm(e, u_old, u_new, atol, rtol):
+    num = 0.0
+    cnt = 0
+    for n in e:
+        sc = atol + rtol * np.maximum(np.abs(u_old[n]), np.abs(u_new[n]))
+        num += float(((e[n] / sc) ** 2).sum())
+        cnt += e[n].size
+    return np.sqrt(num / cnt)
+
+
+def controller(err, err_prev, accepted):
+    """Step-size factor of the PI controller (reading R10)."""
+    if accepted:
+        fac = ADAPT_FAC_MAX if err == 0.0 else \
+            ADAPT_SAFETY * err ** (-0.7 / ADAPT_K) * err_prev ** (0.4 / ADAPT_K)
+        return min(ADAPT_FAC_MAX, max(ADAPT_FAC_MIN, fac))
+    return min(1.0, max(ADAPT_FAC_MIN, ADAPT_SAFETY * err ** (-1.0 / ADAPT_K)))
+
+
+def rk45_adaptive(f, U, t, t_end, dt, atol, rtol, err_prev=1.0, max_attempts=100000):
+    """Advance from t to t_end; returns (U, t, dt, err_prev, n_accepted,
+    n_rejected, errors) with errors the error norm of every attempt."""
+    n_acc = n_rej = 0
+    errors = []
+    while t < t_end and n_acc + n_rej < max_attempts:
+        last = t + dt >= t_end
+        h = t_end - t if last else dt
+        V, e = rk45_step_with_error(f, U, h)
+        err = error_norm(e, U, V, atol, rtol)
+        errors.append(err)
+        if err <= 1.0:
+            fac = controller(err, err_prev, True)
+            U, t = V, (t_end if last else t + h)
+            err_prev = max(err, ADAPT_ERR_FLOOR)
+            dt = h * fac
+            n_acc += 1
+        else:
+            dt = h * controller(err, err_prev, False)
+            n_rej += 1
+    return U, t, dt, err_prev, n_acc, n_rej, errors

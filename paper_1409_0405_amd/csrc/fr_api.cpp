@@ -51,6 +51,7 @@ struct DevType {
     T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
     T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
     T *reg[3] = {nullptr, nullptr, nullptr};
+    T *ereg = nullptr;        // embedded error of the adaptive RK45 (allocated on first use)
     T *dte = nullptr;         // per-element step size (batched problems)
     double *wJ = nullptr;
 };
@@ -463,6 +464,9 @@ struct StageOut {
     const T *base = nullptr;
     T a = 0, b = 1;
     bool per_elem_dt = false;   // scale the stage by the per-element step size
+    T *err = nullptr;           // error register: err = (err_set ? 0 : err) + c k
+    T c = 0;
+    bool err_set = false;
 };
 
 // Operator product through the kernel of the mesh's precision.
@@ -551,6 +555,9 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.jinv, D.ld, D.nelem, D.nu,
                            so[t].per_elem_dt ? D.dte : nullptr};
+        na.err = so[t].err;
+        na.c = so[t].c;
+        na.err_set = so[t].err_set;
         if (cl) {
             na.cy = cl->y;
             na.cys = d.t[0].nelem + d.t[1].nelem;
@@ -613,23 +620,25 @@ fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
     return FR_OK;
 }
 
+// RK45[2R+] (Kennedy, Carpenter & Lewis 2000, RK4(3)5[2R+]C): sub-diagonal
+// a[i+1][i], weights b and the embedded third-order weights bhat.
+const double RK45_A[4] = {970286171893.0 / 4311952581923.0, 6584761158862.0 / 12103376702013.0,
+                          2251764453980.0 / 15575788980749.0, 26877169314380.0 / 34165994151039.0};
+const double RK45_B[5] = {1153189308089.0 / 22510343858157.0, 1772645290293.0 / 4653164025191.0,
+                          -1672844663538.0 / 4480602732383.0, 2114624349019.0 / 3568978502595.0,
+                          5198255086312.0 / 14908931495163.0};
+const double RK45_BHAT[5] = {1016888040809.0 / 7410784769900.0, 11231460423587.0 / 58533540763752.0,
+                             -1563879915014.0 / 6823010717585.0, 606302364029.0 / 971179775848.0,
+                             1097981568119.0 / 3980877426909.0};
+
 template <typename T>
 fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
                   bool per_elem_dt = false, bool allow_check = true) {
     Dev<T> &d = dev_of<T>(m);
     static const double rk4_a[4] = {0.5, 0.5, 1.0, 0.0};
     static const double rk4_b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
-    // RK45[2R+] (Kennedy, Carpenter & Lewis 2000, RK4(3)5[2R+]C): sub-diagonal
-    // a[i+1][i] and weights b; a[i][j] = b[j] for j < i-1.
-    static const double rk45_a[4] = {970286171893.0 / 4311952581923.0,
-                                     6584761158862.0 / 12103376702013.0,
-                                     2251764453980.0 / 15575788980749.0,
-                                     26877169314380.0 / 34165994151039.0};
-    static const double rk45_b[5] = {1153189308089.0 / 22510343858157.0,
-                                     1772645290293.0 / 4653164025191.0,
-                                     -1672844663538.0 / 4480602732383.0,
-                                     2114624349019.0 / 3568978502595.0,
-                                     5198255086312.0 / 14908931495163.0};
+    // RK45[2R+]: a[i][j] = b[j] for j < i-1, so two registers suffice
+    const double *rk45_a = RK45_A, *rk45_b = RK45_B;
     for (int step = 0; step < nsteps; ++step) {
         if (scheme == FR_FWD_EULER) {
             const T *U[2] = {d.t[0].reg[0], d.t[1].reg[0]};
@@ -687,6 +696,93 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
         if (st) return st;
         if (bad > 0) return fail(m, FR_ERR_NONFINITE, "non-finite value in the solution");
     }
+    return FR_OK;
+}
+
+// Adaptive RK45[2R+] (see fr_rk45_adaptive): registers reg[0] = solution q,
+// reg[1] = stage input r, reg[2] = the solution at the start of the step,
+// ereg = embedded error.
+template <typename T>
+fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol, double rtol,
+                           int max_attempts, int32_t counts[2], hipStream_t s) {
+    Dev<T> &d = dev_of<T>(m);
+    int64_t ndof = 0;
+    for (int t = 0; t < 2; ++t) {
+        DevType<T> &D = d.t[t];
+        if (!D.nelem) continue;
+        if (!D.ereg)
+            if (fr_status st = dev_alloc(m, d, D.ereg, size_t(D.nu) * 5 * D.ld)) return st;
+        ndof += int64_t(D.nu) * 5 * D.nelem;
+    }
+    constexpr double K = 4.0, SAFETY = 0.9, FAC_MIN = 0.2, FAC_MAX = 5.0, ERR_FLOOR = 1e-4;
+    double t = state[0], dt = state[1], err_prev = state[2];
+    counts[0] = counts[1] = 0;
+    while (t < t_end && counts[0] + counts[1] < max_attempts) {
+        const bool last = t + dt >= t_end;
+        const double h = last ? t_end - t : dt;
+        for (int ty = 0; ty < 2; ++ty)
+            if (d.t[ty].nelem)
+                FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[2], d.t[ty].reg[0], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
+        for (int st_i = 0; st_i < 5; ++st_i) {
+            const T *U[2];
+            StageOut<T> so[2];
+            for (int ty = 0; ty < 2; ++ty) {
+                U[ty] = st_i == 0 ? d.t[ty].reg[0] : d.t[ty].reg[1];
+                so[ty].acc = d.t[ty].reg[0];
+                so[ty].a = T(RK45_B[st_i] * h);
+                so[ty].out = st_i < 4 ? d.t[ty].reg[1] : nullptr;
+                so[ty].b = st_i < 4 ? T((RK45_A[st_i] - RK45_B[st_i]) * h) : T(0);
+                so[ty].err = d.t[ty].ereg;
+                so[ty].c = T((RK45_B[st_i] - RK45_BHAT[st_i]) * h);
+                so[ty].err_set = st_i == 0;
+            }
+            fr_status st = rhs_pipeline<T>(m, U, so, s);
+            if (st) return st;
+        }
+        // fused error norm: sum (e / (atol + rtol max(|u_old|, |u_new|)))^2 in FP64
+        double sum = 0;
+        for (int ty = 0; ty < 2; ++ty) {
+            DevType<T> &D = d.t[ty];
+            if (!D.nelem) continue;
+            frd::RedArgs<T> ra{D.reg[0], D.ereg, D.wJ, D.ld, D.nelem, D.nu, 6, d.partial};
+            ra.U0 = D.reg[2];
+            ra.atol = atol;
+            ra.rtol = rtol;
+            FR_HIP(m, frd::launch_reduce<T>(ra, s));
+            FR_HIP(m, frd::launch_reduce_final(d.partial, frd::RED_BLOCKS, d.red_out, s));
+            double hsum[8];
+            FR_HIP(m, hipMemcpyAsync(hsum, d.red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+            FR_HIP(m, hipStreamSynchronize(s));
+            sum += hsum[0];
+        }
+        const double err = std::sqrt(sum / double(ndof));
+        if (!std::isfinite(err)) {
+            for (int ty = 0; ty < 2; ++ty)
+                if (d.t[ty].nelem)
+                    FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[0], d.t[ty].reg[2], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
+            state[0] = t;
+            state[1] = dt;
+            state[2] = err_prev;
+            return fail(m, FR_ERR_NONFINITE, "non-finite error estimate; the step was undone");
+        }
+        if (err <= 1.0) {
+            double fac = err == 0.0 ? FAC_MAX : SAFETY * std::pow(err, -0.7 / K) * std::pow(err_prev, 0.4 / K);
+            fac = std::min(FAC_MAX, std::max(FAC_MIN, fac));
+            t = last ? t_end : t + h;
+            err_prev = std::max(err, ERR_FLOOR);
+            dt = h * fac;
+            counts[0] += 1;
+        } else {
+            for (int ty = 0; ty < 2; ++ty)
+                if (d.t[ty].nelem)
+                    FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[0], d.t[ty].reg[2], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
+            dt = h * std::min(1.0, std::max(FAC_MIN, SAFETY * std::pow(err, -1.0 / K)));
+            counts[1] += 1;
+        }
+    }
+    state[0] = t;
+    state[1] = dt;
+    state[2] = err_prev;
     return FR_OK;
 }
 
@@ -1057,6 +1153,18 @@ fr_status fr_rk_step(fr_mesh m, int32_t scheme, double dt, int32_t n_steps, void
     hipStream_t s = static_cast<hipStream_t>(stream);
     return m->precision != FR_FP64 ? rk_impl<float>(m, scheme, dt, n_steps, s)
                                    : rk_impl<double>(m, scheme, dt, n_steps, s);
+}
+
+fr_status fr_rk45_adaptive(fr_mesh m, double t_end, double state[3], double atol, double rtol,
+                           int32_t max_attempts, int32_t counts[2], void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!state || !counts) return fail(m, FR_ERR_INVALID_ARG, "null state or counts");
+    if (!(state[1] > 0) || !(state[2] > 0) || !(atol >= 0) || !(rtol >= 0) || !(atol + rtol > 0) ||
+        max_attempts < 0 || !std::isfinite(t_end) || !std::isfinite(state[0]))
+        return fail(m, FR_ERR_INVALID_ARG, "dt and err_prev must be positive, tolerances non-negative");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->precision != FR_FP64 ? rk_adaptive_impl<float>(m, t_end, state, atol, rtol, max_attempts, counts, s)
+                                   : rk_adaptive_impl<double>(m, t_end, state, atol, rtol, max_attempts, counts, s);
 }
 
 fr_status fr_reduce(fr_mesh m, int32_t what, double *out, void *stream) {

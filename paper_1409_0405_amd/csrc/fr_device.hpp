@@ -118,6 +118,10 @@ struct NegArgs {
     // learned closure: k += sum_a lift[i][a] y[(v * 4 + a) * cys + goff + e]
     const float *cy = nullptr;
     int64_t cys = 0;
+    // embedded error register of the adaptive RK45[2R+]: err = (stage 0 ? 0 : err) + c k
+    T *err = nullptr;
+    T c = 0;
+    bool err_set = false;
     const float *clift = nullptr;   // [nu][4]
     int64_t goff = 0;
 };
@@ -134,6 +138,9 @@ struct RedArgs {
     int64_t ld, nelem;
     int nu, what;
     double *partial;     // [nblocks][8]
+    // what 6 (error norm): sum (R / (atol + rtol max(|U0|, |U|)))^2
+    const T *U0 = nullptr;
+    double atol = 0, rtol = 0;
 };
 constexpr int RED_BLOCKS = 512;
 template <typename T>

@@ -913,6 +913,7 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
             k += T(l[0] * y[0] + l[1] * y[a.cys] + l[2] * y[2 * a.cys] + l[3] * y[3 * a.cys]);
         }
         k *= sc;
+        if (a.err) a.err[o] = (a.err_set ? T(0) : a.err[o]) + a.c * k;
         T accv = 0;
         if (a.acc) {
             accv = a.acc[o] + a.a * k;
@@ -949,6 +950,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(RedArgs<T> a) {
             s[1] += wJ * (vx * r[1] + vy * r[2] + vz * r[3] - 0.5 * v2 * r[0]);
         } else if (a.what == 5) {
             for (int v = 0; v < 5; ++v) s[0] += isfinite(u[v]) ? 0.0 : 1.0;
+        } else if (a.what == 6) {
+            for (int v = 0; v < 5; ++v) {
+                const double u0 = double(a.U0[(int64_t(i) * 5 + v) * a.ld + e]);
+                const double q = r[v] / (a.atol + a.rtol * fmax(fabs(u0), fabs(u[v])));
+                s[0] += q * q;
+            }
         }
     }
     __shared__ double sh[8][256];

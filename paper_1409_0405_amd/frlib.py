@@ -36,7 +36,7 @@ EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coord
             "fr_batch_last_error", "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_params",
             "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_get_grad", "fr_mlp_adam",
             "fr_mlp_last_error", "fr_project", "fr_closure_moments", "fr_closure_features",
-            "fr_closure_targets", "fr_set_blocking",
+            "fr_closure_targets", "fr_set_blocking", "fr_rk45_adaptive",
             "fr_closure_attach", "fr_last_error")
 MLP_NPARAM, MLP_NSTATS = 13204, 280
 
@@ -121,6 +121,7 @@ def lib():
         L.fr_closure_moments.argtypes = [vp, ctypes.POINTER(vp), vp, vp]
         L.fr_closure_features.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp]
         L.fr_set_blocking.argtypes = [vp, i32, i32, i32, i32]
+        L.fr_rk45_adaptive.argtypes = [vp, dbl, ctypes.POINTER(dbl), dbl, dbl, i32, ctypes.POINTER(i32), vp]
         L.fr_closure_targets.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
         L.fr_closure_attach.argtypes = [vp, vp, vp, i32]
         L.fr_last_error.argtypes = [vp]
@@ -237,6 +238,16 @@ class Mesh:
 
     def rk_step(self, scheme, dt, n_steps, stream=0):
         _check(lib().fr_rk_step(self.h, scheme, float(dt), int(n_steps), ctypes.c_void_p(stream)), self.h)
+
+    def rk45_adaptive(self, t_end, state, atol, rtol, max_attempts=1000000, stream=0):
+        """Adaptive RK45[2R+] to t_end; state = [t, dt, err_prev] (updated in
+        place); returns (accepted, rejected)."""
+        st = (ctypes.c_double * 3)(*[float(x) for x in state])
+        cnt = (ctypes.c_int32 * 2)()
+        _check(lib().fr_rk45_adaptive(self.h, float(t_end), st, float(atol), float(rtol), int(max_attempts), cnt,
+                                      ctypes.c_void_p(stream)), self.h)
+        state[:] = [st[0], st[1], st[2]]
+        return int(cnt[0]), int(cnt[1])
 
     def reduce(self, what, stream=0):
         out = np.zeros(8)

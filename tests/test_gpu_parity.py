@@ -211,6 +211,63 @@ def test_rk_steps_fp64_vortex(scheme):
     assert (err < 1e-12).all(), err
 
 
+def test_rk45_adaptive_fp64_vortex():
+    """Adaptive RK45[2R+] (embedded error, PI controller) on the small Euler
+    workload against the oracle's driver: the same accepted and rejected
+    attempts (two rejections from an oversized first step), the same final
+    time, step size and controller state, and the same solution to 1e-12.
+    Every error norm of the oracle run is far from the accept threshold 1,
+    so both sides take the same decisions."""
+    frlib = _lib()
+    print("rk45 adaptive fp64", flush=True)
+    arrays = inputs.vortex_tet_cube(n=6, jitter=0.05, seed=0)
+    p = 2
+    dt = _vortex_dt(6, p)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system="euler")
+    U0 = fr.initial_state(O, inputs.isentropic_vortex)
+    tol, t_end = 1e-6, 8 * dt
+    Uo, to, dto, epo, na, nr, errs = rk.rk45_adaptive(lambda V: fr.rhs(O, V, prm), U0, 0.0, t_end, 4 * dt, tol, tol)
+    assert min(abs(np.array(errs) - 1.0)) > 1e-3 and nr >= 1
+    M = frlib.Mesh(arrays, p, system="euler", precision="fp64", check_finite=True)
+    u = frlib.to_device_state(M, 0, np.transpose(U0["tet"], (1, 2, 0)))
+    M.set_solution(0, u.data_ptr())
+    state = [0.0, 4 * dt, 1.0]
+    acc, rej = M.rk45_adaptive(t_end, state, tol, tol)
+    out = frlib.state_tensor(M, 0)
+    M.get_solution(0, out.data_ptr())
+    torch.cuda.synchronize()
+    print(f"  accepted {acc} rejected {rej} (oracle {na}, {nr}); state {state} vs {[to, dto, epo]}", flush=True)
+    assert (acc, rej) == (na, nr)
+    assert state[0] == to
+    assert abs(state[1] - dto) < 1e-9 * dto and abs(state[2] - epo) < 1e-9 * epo
+    g = np.transpose(out[:, :, :O.types["tet"].nelem].cpu().numpy(), (2, 0, 1))
+    d = g - Uo["tet"]
+    err = np.sqrt((d ** 2).sum(axis=(0, 1)) / (Uo["tet"] ** 2).sum(axis=(0, 1)))
+    assert (err < 1e-12).all(), err
+
+
+def test_rk45_adaptive_fp32_ns_lands_on_t_end():
+    """FP32 NS on the mixed parity mesh: the adaptive driver reaches t_end
+    exactly, keeps the solution finite, and a second call continues from the
+    returned controller state."""
+    frlib = _lib()
+    arrays = _mesh("mixed")
+    O = om.build_mesh(arrays, 2)
+    U = _round32(_state(O, inputs.taylor_green, 3, mach=0.3))
+    M = frlib.Mesh(arrays, 2, system="ns", precision="fp32", mu=0.02, check_finite=True)
+    for t, n in enumerate(NAMES):
+        u = frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0)))
+        M.set_solution(t, u.data_ptr())
+    state = [0.0, 1e-3, 1.0]
+    a1, r1 = M.rk45_adaptive(0.02, state, 1e-5, 1e-5)
+    assert state[0] == 0.02 and a1 >= 1
+    a2, r2 = M.rk45_adaptive(0.05, state, 1e-5, 1e-5)
+    assert state[0] == 0.05 and a2 >= 1
+    with pytest.raises(frlib.FrError):
+        M.rk45_adaptive(0.1, [0.05, -1.0, 1.0], 1e-5, 1e-5)      # dt must be positive
+
+
 def test_reductions_fp64():
     """FP64 global sums: integral of U and of R(U) (discrete conservation) and
     the kinetic-energy rate, against the oracle's quadrature."""

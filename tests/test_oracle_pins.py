@@ -315,3 +315,58 @@ def test_rk45_two_register_matches_butcher():
     want = y0 + dt * sum(b[j] * k[j] for j in range(5))
     got = rk.rk45_step(f, {"y": y0}, dt)["y"]
     assert np.allclose(got, want, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive RK45[2R+] (reading R10)
+# ---------------------------------------------------------------------------
+
+def test_embedded_error_is_difference_of_butcher_solutions():
+    """The two-register error accumulation equals u(b) - u(bhat) of the
+    Butcher tableau, on a nonlinear system."""
+    from oracle import rk
+    A, b, bhat, c = rk.rk45_butcher()
+    f = lambda U: {"x": np.stack([U["x"][1], -np.sin(U["x"][0]) - 0.1 * U["x"][1]])}
+    U = {"x": np.array([1.2, -0.4])}
+    dt = 0.3
+    k = []
+    for i in range(5):
+        Y = U["x"] + dt * sum(A[i, j] * k[j] for j in range(i))
+        k.append(f({"x": Y})["x"])
+    ub = U["x"] + dt * sum(b[i] * k[i] for i in range(5))
+    uh = U["x"] + dt * sum(bhat[i] * k[i] for i in range(5))
+    q, e = rk.rk45_step_with_error(f, U, dt)
+    assert np.allclose(q["x"], ub, rtol=0, atol=1e-14)
+    assert np.allclose(e["x"], ub - uh, rtol=0, atol=1e-14)
+
+
+def test_embedded_error_is_third_order_local():
+    """e = O(dt^4) on y' = y: halving dt divides it by ~16."""
+    from oracle import rk
+    f = lambda U: {"y": U["y"]}
+    e1 = abs(rk.rk45_step_with_error(f, {"y": np.array([1.0])}, 0.2)[1]["y"][0])
+    e2 = abs(rk.rk45_step_with_error(f, {"y": np.array([1.0])}, 0.1)[1]["y"][0])
+    assert 13.0 < e1 / e2 < 19.0
+
+
+def test_adaptive_error_tracks_tolerance():
+    """On y' = -y + sin(3t) (exact solution known), the adaptive driver lands
+    on t_end, rejects nothing once settled, and its global error falls with
+    the tolerance and stays within a modest multiple of it."""
+    from oracle import rk
+    def exact(t):
+        # y' = -y + sin 3t, y(0) = 1
+        return (np.sin(3 * t) - 3 * np.cos(3 * t)) / 10 + 1.3 * np.exp(-t)
+    state = {"t": 0.0}
+    prev = None
+    for tol in (1e-4, 1e-6, 1e-8):
+        def f(U, _s=state):
+            return {"y": -U["y"] + np.sin(3 * U["ty"]), "ty": np.ones(1)}
+        U = {"y": np.array([1.0]), "ty": np.array([0.0])}
+        U, t, dt, ep, na, nr, errs = rk.rk45_adaptive(f, U, 0.0, 5.0, 0.01, tol, tol)
+        assert t == 5.0 and abs(U["ty"][0] - 5.0) < 1e-12
+        g = abs(U["y"][0] - exact(5.0))
+        assert g < 50 * tol
+        if prev is not None:
+            assert g < prev and na > prev_na
+        prev, prev_na = g, na
