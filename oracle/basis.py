@@ -145,6 +145,22 @@ def prism_basis(p, rst):
     return vals, np.stack([gr, gs, gt], axis=-1)
 
 
+def hex_basis(p, rst):
+    """Tensor Legendre basis L_i(r) L_j(s) L_k(t) on [-1, 1]^3 spanning
+    Q_p (degree <= p in each variable).  Values [n_pts][n_modes], gradients
+    [n_pts][n_modes][3]."""
+    rst = np.asarray(rst, dtype=np.float64)
+    vr, dr = line_basis(p, rst[:, 0])
+    vs, ds = line_basis(p, rst[:, 1])
+    vt, dt = line_basis(p, rst[:, 2])
+    n = len(rst)
+    vals = np.einsum("pi,pj,pk->pkji", vr, vs, vt).reshape(n, -1)
+    gr = np.einsum("pi,pj,pk->pkji", dr, vs, vt).reshape(n, -1)
+    gs = np.einsum("pi,pj,pk->pkji", vr, ds, vt).reshape(n, -1)
+    gt = np.einsum("pi,pj,pk->pkji", vr, vs, dt).reshape(n, -1)
+    return vals, np.stack([gr, gs, gt], axis=-1)
+
+
 # ---------------------------------------------------------------------------
 # Point sets (reading R1): symmetric interior sets built from 1-D
 # Gauss-Legendre nodes, solution points and face flux points alike.
@@ -206,6 +222,12 @@ def prism_points(p):
     return np.array([[r, s, zk] for zk in z for (r, s) in tri])
 
 
+def hex_points(p):
+    """Gauss-Legendre product set; index = (k (p+1) + j) (p+1) + i (r fastest)."""
+    x = gauss_legendre(p + 1)[0]
+    return np.array([[x[i], x[j], x[k]] for k in range(p + 1) for j in range(p + 1) for i in range(p + 1)])
+
+
 # ---------------------------------------------------------------------------
 # Quadrature (collapsed Gauss-Jacobi products)
 # ---------------------------------------------------------------------------
@@ -242,3 +264,12 @@ def prism_quadrature(deg):
     pts = np.array([[r, s, zk] for zk in z for (r, s) in tq])
     w = np.array([wk * wt for wk in wz for wt in tw])
     return pts, w
+
+
+def hex_quadrature(deg):
+    """Gauss-Legendre product rule on [-1, 1]^3 exact for degree <= deg in
+    each variable."""
+    x, w = gauss_legendre(deg // 2 + 2)
+    pts = np.array([[xi, xj, xk] for xk in x for xj in x for xi in x])
+    wt = np.array([wi * wj * wk for wk in w for wj in w for wi in w])
+    return pts, wt

@@ -34,8 +34,16 @@ SHAPES = [(N_H, N_IN), (N_H,), (N_H, N_H), (N_H,), (N_OUT, N_H), (N_OUT,)]
 N_PARAM = sum(int(np.prod(s)) for s in SHAPES)
 
 
+def _closure_type(name):
+    """The closure is defined on tets and prisms (the five-face neighbour
+    stencil); other types are refused."""
+    if name not in ("tet", "pri"):
+        raise ValueError(f"closure not defined on '{name}' elements")
+    return name
+
+
 def _quad(name, deg):
-    return basis.tet_quadrature(deg) if name == "tet" else basis.prism_quadrature(deg)
+    return basis.tet_quadrature(deg) if _closure_type(name) == "tet" else basis.prism_quadrature(deg)
 
 
 def _linear_basis(name, x):
@@ -55,7 +63,7 @@ def _linear_basis(name, x):
 def _lagrange_at(name, p, x):
     """Nodal Lagrange basis of order p evaluated at points x: [n_x][N_u]."""
     ref = elements.get(name, p)
-    bfn = basis.tet_basis if name == "tet" else basis.prism_basis
+    bfn = basis.tet_basis if _closure_type(name) == "tet" else basis.prism_basis
     return bfn(p, x)[0] @ np.linalg.inv(ref.V)
 
 
@@ -96,7 +104,7 @@ def face_neighbours(mesh):
     """Global element id (type-major) of the neighbour across each local
     face [n_total][5], -1 where the element has no such face; built from the
     oracle's own flux-point pairing."""
-    names = list(mesh.types)
+    names = [_closure_type(n) for n in mesh.types]
     ntot = sum(mesh.types[n].nelem for n in names)
     base, g = {}, 0
     for n in names:

@@ -39,9 +39,14 @@ PRI_VERTS = np.array([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0],
 # (1+t_j)/2 (d-a), index j * (p+1) + i.
 TET_FACES = [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]
 PRI_FACES = [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)]
+# Hexahedron [-1, 1]^3: vertices 0-3 counter-clockwise at t = -1, 4-7 above them
+HEX_VERTS = np.array([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [1.0, 1.0, -1.0], [-1.0, 1.0, -1.0],
+                      [-1.0, -1.0, 1.0], [1.0, -1.0, 1.0], [1.0, 1.0, 1.0], [-1.0, 1.0, 1.0]])
+HEX_FACES = [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]
 
 TET_VOLUME = 4.0 / 3.0
 PRI_VOLUME = 4.0
+HEX_VOLUME = 8.0
 
 
 def _outward_normal(verts, face, centroid):
@@ -137,19 +142,21 @@ class RefElement:
 
 
 def _basis_fn(name):
-    return {"tet": basis.tet_basis, "pri": basis.prism_basis}[name]
+    return {"tet": basis.tet_basis, "pri": basis.prism_basis, "hex": basis.hex_basis}[name]
 
 
 def _quad_fn(name):
-    return {"tet": basis.tet_quadrature, "pri": basis.prism_quadrature}[name]
+    return {"tet": basis.tet_quadrature, "pri": basis.prism_quadrature, "hex": basis.hex_quadrature}[name]
 
 
 def build(name, p):
-    """Build the reference element 'tet' or 'pri' at order p."""
+    """Build the reference element 'tet', 'pri' or 'hex' at order p."""
     if name == "tet":
         verts, faces, upts, vol = basis.TET_VERTS, TET_FACES, basis.tet_points(p), TET_VOLUME
     elif name == "pri":
         verts, faces, upts, vol = PRI_VERTS, PRI_FACES, basis.prism_points(p), PRI_VOLUME
+    elif name == "hex":
+        verts, faces, upts, vol = HEX_VERTS, HEX_FACES, basis.hex_points(p), HEX_VOLUME
     else:
         raise ValueError(name)
     centroid = verts.mean(axis=0)
@@ -210,6 +217,8 @@ def get(name, p):
 def nupts(name, p):
     if name == "tet":
         return (p + 1) * (p + 2) * (p + 3) // 6
+    if name == "hex":
+        return (p + 1) ** 3
     return (p + 1) ** 2 * (p + 2) // 2
 
 
@@ -217,4 +226,6 @@ def nfpts(name, p):
     tri = (p + 1) * (p + 2) // 2
     if name == "tet":
         return 4 * tri
+    if name == "hex":
+        return 6 * (p + 1) ** 2
     return 2 * tri + 3 * (p + 1) ** 2

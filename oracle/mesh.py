@@ -5,12 +5,13 @@ Test infrastructure (see ``oracle/__init__``).
 Paper, Section 2.1 and Section 3.3: elements of several types on one mixed
 unstructured grid; interfaces couple neighbouring elements only through
 data at their shared faces.  Geometry (reading R4): straight-sided
-elements, the tet affine and the prism mapped by its six-node shape
-functions (linear on the triangle times linear in t); the metric terms
-are evaluated exactly at every point from the mapping's derivatives.
+elements, the tet affine, the prism mapped by its six-node shape
+functions (linear on the triangle times linear in t) and the hexahedron
+by its eight-node trilinear ones; the metric terms are evaluated exactly
+at every point from the mapping's derivatives.
 
 Conventions used here and documented for the library alike:
-* global element id is type-major: tets 0..n_tet-1, then prisms;
+* global element id is type-major: tets 0..n_tet-1, then prisms, then hexahedra;
 * a face pair's side L is the (global id, local face) that sorts first;
 * flux points pair by physical position (after periodic unwrapping).
 """
@@ -22,7 +23,7 @@ import numpy as np
 
 from . import elements
 
-TYPES = ("tet", "pri")
+TYPES = ("tet", "pri", "hex")
 
 
 def shape_functions(name, x):
@@ -35,6 +36,15 @@ def shape_functions(name, x):
         N = np.stack([-(1 + r + s + t) / 2, (1 + r) / 2, (1 + s) / 2, (1 + t) / 2], -1)
         dN = np.array([[-0.5, -0.5, -0.5], [0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]])
         dN = np.broadcast_to(dN, (len(x), 4, 3)).copy()
+        return N, dN
+    if name == "hex":
+        # trilinear: N_a = (1 + r r_a)(1 + s s_a)(1 + t t_a) / 8
+        V = elements.HEX_VERTS
+        fr = 1 + r[:, None] * V[:, 0]
+        fs = 1 + s[:, None] * V[:, 1]
+        ft = 1 + t[:, None] * V[:, 2]
+        N = fr * fs * ft / 8
+        dN = np.stack([V[:, 0] * fs * ft, fr * V[:, 1] * ft, fr * fs * V[:, 2]], -1) / 8
         return N, dN
     l = [-(r + s) / 2, (1 + r) / 2, (1 + s) / 2]
     dl = [(-0.5 * one, -0.5 * one), (0.5 * one, zero), (zero, 0.5 * one)]
@@ -98,7 +108,7 @@ def build_mesh(mesh_arrays, p, tol=1e-9):
     gid0 = 0
     gid_base = {}
     for name in TYPES:
-        v = mesh_arrays[f"{name}_v"]
+        v = mesh_arrays.get(f"{name}_v", np.zeros((0, 0), np.int64))
         if len(v) == 0:
             continue
         ref = elements.get(name, p)

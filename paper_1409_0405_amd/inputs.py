@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs: periodic mixed prism/tet meshes and initial fields.
+"""Seeded synthetic inputs: periodic tet/prism/hex meshes and initial fields.
 
 This module holds input generation only (vertex lattices, jitter, element
 connectivity, closed-form initial conditions evaluated at given physical
@@ -14,6 +14,10 @@ Mesh arrays (all numpy, host memory):
 * ``pri_v``    int64   [n_prisms][6]    0-2 bottom triangle (counter-clockwise
                                         seen from above), 3-5 top, k+3 above k
 * ``pri_img``  int8    [n_prisms][6][3]
+* ``hex_v``    int64   [n_hex][8]       0-3 bottom quad (counter-clockwise seen
+                                        from above), 4-7 top, k+4 above k
+                                        (optional: absent means no hexahedra)
+* ``hex_img``  int8    [n_hex][8][3]
 * ``period``   float64 [3]
 
 Element order is chosen for locality of interface gathers: tets are numbered
@@ -152,8 +156,86 @@ def mixed_box(nx, ny, n_pri_layers, n_tet_layers, lengths, z_split=None,
     }
 
 
+def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0):
+    """Periodic box of nx x ny x nz cells holding all three element types
+    with conforming interfaces:
+
+    * cells ix <  x_split, iz <  z_split: hexahedra;
+    * cells ix >= x_split, iz <  z_split: prisms extruded along z (the x-y
+      quad split along (i,j)->(i+1,j+1)), meeting the hexahedra through
+      x-faces;
+    * cells ix <  x_split, iz >= z_split: prisms extruded along x (the y-z
+      quad split along (j,k)->(j+1,k+1)), meeting the hexahedra through
+      z-faces;
+    * cells ix >= x_split, iz >= z_split: Kuhn-split tets, meeting both
+      prism kinds through triangles whose diagonals match the Kuhn split.
+
+    ``x_split = nx, z_split = nz`` gives a pure hexahedral box,
+    ``x_split = 0`` the prism/tet layers of ``mixed_box``.  Vertices are
+    jittered by U(-a, a) times the cell size on each axis, drawn in vertex
+    id order (x fastest, then y, then z; per vertex x, y, z).
+
+    Element order: hexahedra (z, y, x) with x fastest; z-prisms triangle
+    major, then (z, y, x); x-prisms triangle-major, then (z, y, x); tets
+    shape-major, then (z, y, x).
+    """
+    Lx, Ly, Lz = (float(v) for v in lengths)
+    if not (0 <= x_split <= nx and 0 <= z_split <= nz) or min(nx, ny, nz) < 1:
+        raise ValueError("bad hybrid box split")
+    h = np.array([Lx / nx, Ly / ny, Lz / nz])
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    xyz = np.stack([ix, iy, iz], axis=-1).reshape(-1, 3) * h
+    if jitter:
+        rng = np.random.default_rng(seed)
+        xyz = xyz + jitter * rng.uniform(-1.0, 1.0, size=xyz.shape) * h
+    n = np.array([nx, ny, nz])
+
+    def corner(c, off):
+        k = c + np.asarray(off)[None, :]
+        vid = (np.mod(k[:, 2], nz) * ny + np.mod(k[:, 1], ny)) * nx + np.mod(k[:, 0], nx)
+        return vid, (k >= n[None, :]).astype(np.int8)
+
+    def cells(x0, x1, z0, z1):
+        cz, cy, cx = np.meshgrid(np.arange(z0, z1), np.arange(ny), np.arange(x0, x1), indexing="ij")
+        return np.stack([cx.reshape(-1), cy.reshape(-1), cz.reshape(-1)], axis=-1)
+
+    def build(cl, shapes, nv):
+        vs, ims = [], []
+        for shape in shapes:
+            sv, si = zip(*(corner(cl, off) for off in shape))
+            vs.append(np.stack(sv, axis=-1))
+            ims.append(np.stack(si, axis=1))
+        if not vs or len(cl) == 0:
+            return np.zeros((0, nv), np.int64), np.zeros((0, nv, 3), np.int8)
+        return np.concatenate(vs), np.concatenate(ims)
+
+    hex_shape = [[(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+                  (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]]
+    zpri = [[(a, b, dk) for dk in (0, 1) for (a, b) in tri] for tri in _QUAD_TRIS]
+    xpri = [[(di, a, b) for di in (0, 1) for (a, b) in tri] for tri in _QUAD_TRIS]
+    tets = [[tuple(o) for o in shape] for shape in _kuhn_shapes()]
+    hex_v, hex_img = build(cells(0, x_split, 0, z_split), hex_shape, 8)
+    pz_v, pz_img = build(cells(x_split, nx, 0, z_split), zpri, 6)
+    px_v, px_img = build(cells(0, x_split, z_split, nz), xpri, 6)
+    tet_v, tet_img = build(cells(x_split, nx, z_split, nz), tets, 4)
+    c = np.ascontiguousarray
+    return {
+        "xyz": c(xyz, dtype=np.float64),
+        "tet_v": c(tet_v, dtype=np.int64), "tet_img": c(tet_img, dtype=np.int8),
+        "pri_v": c(np.concatenate([pz_v, px_v]), dtype=np.int64),
+        "pri_img": c(np.concatenate([pz_img, px_img]), dtype=np.int8),
+        "hex_v": c(hex_v, dtype=np.int64), "hex_img": c(hex_img, dtype=np.int8),
+        "period": np.array([Lx, Ly, Lz], dtype=np.float64),
+    }
+
+
+def hex_box(n, lengths=(2.0 * math.pi,) * 3, jitter=0.0, seed=0):
+    """Periodic box of n^3 hexahedra (``hybrid_box`` with no other type)."""
+    return hybrid_box(n, n, n, n, n, lengths, jitter=jitter, seed=seed)
+
+
 def unwrapped(mesh, kind):
-    """Unwrapped vertex coordinates [n_elem][n_vert][3] of 'tet' or 'pri'."""
+    """Unwrapped vertex coordinates [n_elem][n_vert][3] of 'tet', 'pri' or 'hex'."""
     v = mesh[f"{kind}_v"]
     im = mesh[f"{kind}_img"].astype(np.float64)
     return mesh["xyz"][v] + im * mesh["period"]

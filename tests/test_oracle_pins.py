@@ -32,7 +32,7 @@ def _table2():
     return rows
 
 
-@pytest.mark.parametrize("row", [r for r in _table2() if r[0] in ("tet", "pri")])
+@pytest.mark.parametrize("row", _table2())
 def test_table2_operator_dims(row):
     name, p, nu, nf = row
     R = elements.get(name, p)
@@ -59,13 +59,23 @@ def test_point_sets_symmetric_interior_unisolvent(p):
         key = {tuple(np.round(b, 12)) for b in bary}
         for perm in itertools.permutations(range(n)):
             assert {tuple(np.round(b[list(perm)], 12)) for b in bary} == key
-    for name in ("tet", "pri"):
+    for name in ("tet", "pri", "hex"):
         R = elements.get(name, p)
         assert np.linalg.cond(R.V) < 50.0
+    # hexahedron: Gauss-Legendre tensor set, invariant under the 48 symmetries
+    # of the cube, strictly interior
+    H = elements.get("hex", p).upts
+    key = {tuple(np.round(x, 12)) for x in H}
+    for perm in itertools.permutations(range(3)):
+        for sg in itertools.product((-1, 1), repeat=3):
+            assert {tuple(np.round(x[list(perm)] * sg, 12) + 0.0) for x in H} == key
+    assert np.abs(H).max() < 1.0
 
 
 def _monomials(name, p):
     """Exponents (a, b, c) of x^a y^b z^c spanning the element's space."""
+    if name == "hex":
+        return list(itertools.product(range(p + 1), repeat=3))
     out = []
     for a in range(p + 1):
         for b in range(p + 1 - a):
@@ -76,7 +86,7 @@ def _monomials(name, p):
     return out
 
 
-@pytest.mark.parametrize("name", ["tet", "pri"])
+@pytest.mark.parametrize("name", ["tet", "pri", "hex"])
 @pytest.mark.parametrize("p", ORDERS)
 def test_interpolation_and_gradient_exact(name, p):
     R = elements.get(name, p)
@@ -149,7 +159,23 @@ def _pri_face_int(f, e):
     return 0.0 if a else 2.0 / (b + 1) * _zint(c)     # xi = -1
 
 
+def _hex_vol_int(e):          # exponents of (x, y, z) on [-1, 1]^3
+    return _zint(e[0]) * _zint(e[1]) * _zint(e[2])
+
+
+def _hex_face_int(f, e):
+    """Faces as in elements.HEX_FACES: t = -1, t = +1, s = -1, r = +1, s = +1, r = -1."""
+    a, b, c = e
+    axis, side = [(2, -1), (2, 1), (1, -1), (0, 1), (1, 1), (0, -1)][f]
+    out = 1.0
+    for k, ek in enumerate(e):
+        out *= float(side) ** ek if k == axis else _zint(ek)
+    return out
+
+
 def _lam_monos(name, p):
+    if name == "hex":
+        return _monomials("hex", p)
     out = []
     for a in range(p + 1):
         for b in range(p + 1 - a):
@@ -159,30 +185,36 @@ def _lam_monos(name, p):
 
 
 def _lam_eval(name, x, e):
+    if name == "hex":
+        return x[:, 0] ** e[0] * x[:, 1] ** e[1] * x[:, 2] ** e[2]
     if name == "tet":
         lam = _tet_lam(x)
         return lam[:, 1] ** e[0] * lam[:, 2] ** e[1] * lam[:, 3] ** e[2]
     return ((1 + x[:, 0]) / 2) ** e[0] * ((1 + x[:, 1]) / 2) ** e[1] * x[:, 2] ** e[2]
 
 
-@pytest.mark.parametrize("name", ["tet", "pri"])
+_VOL = {"tet": _tet_vol_int, "pri": _pri_vol_int, "hex": _hex_vol_int}
+_FACE = {"tet": _tet_face_int, "pri": _pri_face_int, "hex": _hex_face_int}
+
+
+@pytest.mark.parametrize("name", ["tet", "pri", "hex"])
 @pytest.mark.parametrize("p", ORDERS)
 def test_quadrature_weights_closed_form(name, p):
     R = elements.get(name, p)
-    vol = _tet_vol_int if name == "tet" else _pri_vol_int
+    vol = _VOL[name]
     assert abs(R.w.sum() - R.volume) < 1e-13
     for e in _lam_monos(name, p):
         assert abs(R.w @ _lam_eval(name, R.upts, e) - vol(e)) < 1e-13
 
 
-@pytest.mark.parametrize("name", ["tet", "pri"])
+@pytest.mark.parametrize("name", ["tet", "pri", "hex"])
 @pytest.mark.parametrize("p", ORDERS)
 def test_lift_identity_closed_form(name, p):
     """int phi (L g) = sum_f int_f phi g ds for phi in the solution space and
     g the face trace of a polynomial of the solution space."""
     R = elements.get(name, p)
-    vol = _tet_vol_int if name == "tet" else _pri_vol_int
-    face = _tet_face_int if name == "tet" else _pri_face_int
+    vol = _VOL[name]
+    face = _FACE[name]
     monos = _lam_monos(name, p)
     Vm = np.stack([_lam_eval(name, R.upts, e) for e in monos], -1)    # [N_u][n_monos]
     rng = np.random.default_rng(3)
