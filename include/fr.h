@@ -3,7 +3,7 @@
  *
  * The library evaluates the FR right-hand side of the compressible Euler and
  * Navier-Stokes equations (constant viscosity) on mixed tetrahedral / prismatic
- * periodic grids, and advances it with explicit Runge-Kutta schemes.  The
+ * / hexahedral periodic grids, and advances it with explicit Runge-Kutta schemes.  The
  * operations follow the paper "Heterogeneous Computing on Mixed Unstructured
  * Grids with PyFR" (Witherden, Vermeire, Vincent):
  *   - Section 2.1: an FR step is mostly products C <- c1 A B + c2 C of a
@@ -16,8 +16,8 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * Element types: FR_TET = 0, FR_PRI = 1.  Global element ids are type-major
- * (tets first).  Solution state per type is a device array laid out
+ * Element types: FR_TET = 0, FR_PRI = 1, FR_HEX = 2.  Global element ids are
+ * type-major (tets, then prisms, then hexahedra).  Solution state per type is a device array laid out
  * [n_upts][5][ld] of the mesh's scalar type (double for FR_FP64, float for
  * every other precision): point-major, then the conserved field (rho, rho u, rho v, rho w,
  * E), then the element index, fastest; ld >= n_elem is a multiple of 64 and
@@ -58,7 +58,9 @@ typedef enum {
     FR_ERR_NONFINITE = 6      /* FR_CHECK_FINITE found a NaN / Inf */
 } fr_status;
 
-typedef enum { FR_TET = 0, FR_PRI = 1 } fr_etype;
+typedef enum { FR_TET = 0, FR_PRI = 1, FR_HEX = 2 } fr_etype;
+/* Number of element types: arrays indexed by element type have this length. */
+#define FR_NTYPES 3
 typedef enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 } fr_system;
 /* FR_SPLIT_BF16 / FR_SPLIT_FP16: FP32 state and point-wise arithmetic; the
  * operator products run on the 16-bit matrix cores with both operands split
@@ -87,9 +89,16 @@ typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
  * xyz        [n_vertices][3] vertex coordinates.
  * tet_v      [n_tets][4] vertex ids; prism vertex ids pri_v [n_prisms][6] list
  *            the bottom triangle 0-2 (counter-clockwise seen from above) and
- *            then the top 3-5, vertex k+3 above vertex k.
- * tet_img, pri_img  periodic image shift per element vertex [..][n][3] (int8,
- *            unwrapped vertex = xyz[v] + img * period), or NULL for none.
+ *            then the top 3-5, vertex k+3 above vertex k; hexahedron vertex
+ *            ids hex_v [n_hex][8] list the bottom quad 0-3 (counter-clockwise
+ *            seen from above) and then the top 4-7, vertex k+4 above vertex k
+ *            (trilinear map; Table 2 gives its operator sizes).
+ * tet_img, pri_img, hex_img  periodic image shift per element vertex
+ *            [..][n][3] (int8, unwrapped vertex = xyz[v] + img * period), or
+ *            NULL for none.
+ *            At most 2^22 - 1 elements of each type; faces between elements
+ *            must be conforming (a hexahedron meets prisms through their
+ *            quadrilateral faces).
  * period     box lengths of the periodic directions (used with the images).
  */
 typedef struct {
@@ -107,6 +116,9 @@ typedef struct {
     const int64_t *pri_v;
     const int8_t *pri_img;
     double period[3];
+    int64_t n_hex;
+    const int64_t *hex_v;
+    const int8_t *hex_img;
 } fr_mesh_desc;
 
 /* Build operators (FP64 on the host), geometry and the interface pairing,
@@ -145,7 +157,7 @@ fr_status fr_get_solution(fr_mesh mesh, int32_t etype, void *u_dev, void *stream
  * point-wise kernels, Section 3.4 scheme).  u_dev[t] / r_dev[t] are the
  * caller's device states of type t ([n_upts][5][ld]); entries of types the
  * mesh does not have are ignored and may be NULL.  r_dev must not alias u_dev. */
-fr_status fr_rhs(fr_mesh mesh, const void *const u_dev[2], void *const r_dev[2],
+fr_status fr_rhs(fr_mesh mesh, const void *const u_dev[FR_NTYPES], void *const r_dev[FR_NTYPES],
                  void *stream);
 
 /* Advance the mesh's solution register n_steps steps of size dt with the
@@ -204,12 +216,14 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * fr_profile_read waits for the recorded events, writes per kernel class the
  * summed duration in milliseconds and the launch count (arrays of
  * FR_PROF_NCLASS), and clears the records.  Classes: 4 * etype + op for the
- * operator products (op 0 interpolation to flux points, 1 corrected
- * gradient, 2 gradient interpolation, 3 divergence plus correction), 8 + etype
- * the solution-point flux kernel, 10 common solution, 11 common interface
- * flux, 12 + etype negdivconf with the Runge-Kutta update, 14 closure
- * inputs (moments and neighbour gathering), 15 closure network forward. */
-#define FR_PROF_NCLASS 16
+ * operator products of tets and prisms (op 0 interpolation to flux points, 1
+ * corrected gradient, 2 gradient interpolation, 3 divergence plus
+ * correction), 8 + etype the solution-point flux kernel, 10 common solution,
+ * 11 common interface flux, 12 + etype negdivconf with the Runge-Kutta
+ * update, 14 closure inputs (moments and neighbour gathering), 15 closure
+ * network forward; hexahedra: 16 + op the products, 20 the solution-point
+ * kernel, 21 negdivconf. */
+#define FR_PROF_NCLASS 22
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 
@@ -313,16 +327,19 @@ const char *fr_mlp_last_error(fr_mlp net);
 /* L2 projection (reference element) of a state of mesh src, order p, to the
  * order q of mesh dst; both meshes have the same elements and scalar type.
  * States [n_upts][5][ld] of each mesh.  Allocates its operators on first use. */
-fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void *const u_dst[2],
-                     void *stream);
+fr_status fr_project(fr_mesh src, const void *const u_src[FR_NTYPES], fr_mesh dst,
+                     void *const u_dst[FR_NTYPES], void *stream);
 /* P1 moments [n_tet + n_pri][20] of a state, and the network inputs
- * [n_tet + n_pri][120] (normalised with stats_dev unless NULL). */
-fr_status fr_closure_moments(fr_mesh mesh, const void *const u_dev[2], float *mom_dev, void *stream);
-fr_status fr_closure_features(fr_mesh mesh, const void *const u_dev[2], const float *stats_dev,
+ * [n_tet + n_pri][120] (normalised with stats_dev unless NULL).  The closure
+ * is defined on tet and prism meshes: a mesh with hexahedra gives
+ * FR_ERR_UNSUPPORTED here and in fr_closure_targets / fr_closure_attach
+ * (entry FR_HEX of the state arrays is ignored). */
+fr_status fr_closure_moments(fr_mesh mesh, const void *const u_dev[FR_NTYPES], float *mom_dev, void *stream);
+fr_status fr_closure_features(fr_mesh mesh, const void *const u_dev[FR_NTYPES], const float *stats_dev,
                               float *feat_dev, void *stream);
 /* Network targets [n_tet + n_pri][20]: P1 moments of a_dev - b_dev,
  * normalised as (m - mu_y) / s_y with stats_dev unless NULL. */
-fr_status fr_closure_targets(fr_mesh mesh, const void *const a_dev[2], const void *const b_dev[2],
+fr_status fr_closure_targets(fr_mesh mesh, const void *const a_dev[FR_NTYPES], const void *const b_dev[FR_NTYPES],
                              const float *stats_dev, float *out_dev, void *stream);
 /* Attach (net != NULL) or detach (net == NULL) the closure: every later
  * fr_rhs / fr_rk_step of this mesh adds the lifted network correction to the

@@ -58,7 +58,7 @@ struct DevType {
 
 template <typename T>
 struct Dev : DevBase {
-    DevType<T> t[2];
+    DevType<T> t[frh::NTYPE];
     uint32_t *sideL = nullptr, *sideR = nullptr;
     T *pgeo = nullptr;
     int64_t npairs = 0;
@@ -133,10 +133,15 @@ fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
-// Kernel classes of the profiler: 0..7 operator products (4 * type + op),
-// 8/9 solution-point kernel (tet/prism), 10 common solution, 11 common flux,
-// 12/13 negdivconf (tet/prism).
-constexpr int PROF_NCLASS = 16;
+// Kernel classes of the profiler: 0..7 operator products (4 * type + op) of
+// tets and prisms, 8/9 solution-point kernel (tet/prism), 10 common solution,
+// 11 common flux, 12/13 negdivconf (tet/prism), 14/15 closure, 16..19
+// hexahedron products (16 + op), 20 hexahedron solution-point kernel, 21
+// hexahedron negdivconf.
+constexpr int PROF_NCLASS = FR_PROF_NCLASS;
+constexpr int prof_op(int t, int op) { return t < 2 ? 4 * t + op : 16 + op; }
+constexpr int prof_upts(int t) { return t < 2 ? 8 + t : 20; }
+constexpr int prof_neg(int t) { return t < 2 ? 12 + t : 21; }
 constexpr size_t PROF_NONE = size_t(-1);
 
 size_t prof_begin(fr_mesh m, hipStream_t s) {
@@ -320,7 +325,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
     do {                          \
         if ((st = (x))) return st; \
     } while (0)
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         const frh::TypeHost &H = m->host.t[t];
         DevType<T> &D = d.t[t];
         D.nelem = H.nelem;
@@ -482,15 +487,16 @@ hipError_t opmul(fr_mesh m, int tag, const frd::Op<T> &A, const frd::OpSplit &S,
 }
 
 template <typename T>
-fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], hipStream_t s) {
+fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T> so[frh::NTYPE],
+                       hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
     const bool ns = m->system == FR_NAVIER_STOKES;
     const T gamma = T(m->gamma), mu = T(m->mu), pr = T(m->prandtl);
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
-        FR_LAUNCH(m, 4 * t + frd::OP_INTERP, s,
+        FR_LAUNCH(m, prof_op(t, frd::OP_INTERP), s,
                   opmul<T>(m, 4 * t + frd::OP_INTERP, D.Aint, D.Sint, U[t], w5, D.nu, nullptr, 0, 0, D.Uf, w5, w5, s));
     }
     frd::PairArgs<T> pa{};
@@ -498,7 +504,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
     pa.sideR = d.sideR;
     pa.geo = d.pgeo;
     pa.npairs = d.npairs;
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         pa.Uf[t] = d.t[t].Uf;
         pa.Qf[t] = d.t[t].Qf;
         pa.Cf[t] = d.t[t].Cf;
@@ -512,22 +518,22 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
     pa.tau = T(m->tau);
     if (ns) {
         FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < frh::NTYPE; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
             const int64_t w5 = 5 * D.ld;
-            FR_LAUNCH(m, 4 * t + frd::OP_GRAD, s,
+            FR_LAUNCH(m, prof_op(t, frd::OP_GRAD), s,
                       opmul<T>(m, 4 * t + frd::OP_GRAD, D.Agrad, D.Sgrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
         }
     }
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         frd::UptsArgs<T> ua{U[t], D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu, gamma, mu, pr};
-        FR_LAUNCH(m, 8 + t, s, frd::launch_upts<T>(t, ns, ua, s));
+        FR_LAUNCH(m, prof_upts(t), s, frd::launch_upts<T>(t, ns, ua, s));
         if (ns) {
             const int64_t w15 = 15 * D.ld;
-            FR_LAUNCH(m, 4 * t + frd::OP_GRADINTERP, s,
+            FR_LAUNCH(m, prof_op(t, frd::OP_GRADINTERP), s,
                       opmul<T>(m, 4 * t + frd::OP_GRADINTERP, D.Agint, D.Sgint, D.Q, w15, D.nu, nullptr, 0, 0, D.Qf, w15, w15, s));
         }
     }
@@ -535,7 +541,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
     const Closure *cl = (m->closure && m->closure->params) ? m->closure.get() : nullptr;
     if (cl) {
         const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 2; ++t) {   // the closure covers tets and prisms only
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
             // feature-major moments, inputs and outputs: every access coalesced
@@ -546,11 +552,11 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         FR_LAUNCH(m, 15, s, frd::launch_mlp_forward(cl->params, cl->params_bf16, cl->bf16, cl->feat, 1, ntot, ntot,
                                                     cl->stats, false, cl->y, 1, ntot, s));
     }
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
-        FR_LAUNCH(m, 4 * t + frd::OP_DIV, s,
+        FR_LAUNCH(m, prof_op(t, frd::OP_DIV), s,
                   opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.jinv, D.ld, D.nelem, D.nu,
@@ -558,13 +564,13 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
         na.err = so[t].err;
         na.c = so[t].c;
         na.err_set = so[t].err_set;
-        if (cl) {
+        if (cl && t < 2) {
             na.cy = cl->y;
             na.cys = d.t[0].nelem + d.t[1].nelem;
             na.clift = cl->lift[t];
             na.goff = t ? d.t[0].nelem : 0;
         }
-        FR_LAUNCH(m, 12 + t, s, frd::launch_negdivconf<T>(t, na, s));
+        FR_LAUNCH(m, prof_neg(t), s, frd::launch_negdivconf<T>(t, na, s));
     }
     return FR_OK;
 }
@@ -572,10 +578,10 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[2], const StageOut<T> so[2], 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 template <typename T>
-fr_status rhs_entry(fr_mesh m, const void *const u[2], void *const r[2], hipStream_t s) {
-    const T *U[2] = {nullptr, nullptr};
-    StageOut<T> so[2];
-    for (int t = 0; t < 2; ++t) {
+fr_status rhs_entry(fr_mesh m, const void *const u[FR_NTYPES], void *const r[FR_NTYPES], hipStream_t s) {
+    const T *U[frh::NTYPE] = {nullptr, nullptr, nullptr};
+    StageOut<T> so[frh::NTYPE];
+    for (int t = 0; t < frh::NTYPE; ++t) {
         if (!m->host.t[t].nelem) continue;
         if (!u || !r || !u[t] || !r[t]) return fail(m, FR_ERR_INVALID_ARG, "null state pointer");
         if (!aligned(u[t], 4 * sizeof(T)) || !aligned(r[t], 4 * sizeof(T)))
@@ -594,14 +600,13 @@ fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
     std::vector<double> tot(8, 0.0);
     const bool needR = what == 2 || what == 3 || what == 4;
     if (needR) {
-        const T *U[2] = {d.t[0].reg[0], d.t[1].reg[0]};
-        StageOut<T> so[2];
-        so[0].out = d.t[0].R;
-        so[1].out = d.t[1].R;
+        const T *U[frh::NTYPE] = {d.t[0].reg[0], d.t[1].reg[0], d.t[2].reg[0]};
+        StageOut<T> so[frh::NTYPE];
+        for (int t = 0; t < frh::NTYPE; ++t) so[t].out = d.t[t].R;
         fr_status st = rhs_pipeline<T>(m, U, so, s);
         if (st) return st;
     }
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, d.partial};
@@ -641,9 +646,9 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
     const double *rk45_a = RK45_A, *rk45_b = RK45_B;
     for (int step = 0; step < nsteps; ++step) {
         if (scheme == FR_FWD_EULER) {
-            const T *U[2] = {d.t[0].reg[0], d.t[1].reg[0]};
-            StageOut<T> so[2];
-            for (int t = 0; t < 2; ++t) {
+            const T *U[frh::NTYPE] = {d.t[0].reg[0], d.t[1].reg[0], d.t[2].reg[0]};
+            StageOut<T> so[frh::NTYPE];
+            for (int t = 0; t < frh::NTYPE; ++t) {
                 so[t].acc = d.t[t].reg[0];
                 so[t].a = T(dt);
                 so[t].per_elem_dt = per_elem_dt;
@@ -651,14 +656,14 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
             fr_status st = rhs_pipeline<T>(m, U, so, s);
             if (st) return st;
         } else if (scheme == FR_RK4) {
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < frh::NTYPE; ++t)
                 if (d.t[t].nelem)
                     FR_HIP(m, frd::launch_copy<T>(d.t[t].reg[2], d.t[t].reg[0],
                                                   int64_t(d.t[t].nu) * 5 * d.t[t].ld, s));
             for (int st_i = 0; st_i < 4; ++st_i) {
-                const T *U[2];
-                StageOut<T> so[2];
-                for (int t = 0; t < 2; ++t) {
+                const T *U[frh::NTYPE];
+                StageOut<T> so[frh::NTYPE];
+                for (int t = 0; t < frh::NTYPE; ++t) {
                     U[t] = st_i == 0 ? d.t[t].reg[0] : d.t[t].reg[1];
                     so[t].acc = d.t[t].reg[2];
                     so[t].a = T(rk4_b[st_i] * dt);
@@ -670,12 +675,12 @@ fr_status rk_impl(fr_mesh m, int scheme, double dt, int nsteps, hipStream_t s,
                 fr_status st = rhs_pipeline<T>(m, U, so, s);
                 if (st) return st;
             }
-            for (int t = 0; t < 2; ++t) std::swap(d.t[t].reg[0], d.t[t].reg[2]);
+            for (int t = 0; t < frh::NTYPE; ++t) std::swap(d.t[t].reg[0], d.t[t].reg[2]);
         } else if (scheme == FR_RK45_2RP) {
             for (int st_i = 0; st_i < 5; ++st_i) {
-                const T *U[2];
-                StageOut<T> so[2];
-                for (int t = 0; t < 2; ++t) {
+                const T *U[frh::NTYPE];
+                StageOut<T> so[frh::NTYPE];
+                for (int t = 0; t < frh::NTYPE; ++t) {
                     U[t] = st_i == 0 ? d.t[t].reg[0] : d.t[t].reg[1];
                     so[t].acc = d.t[t].reg[0];
                     so[t].a = T(rk45_b[st_i] * dt);
@@ -707,7 +712,7 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
                            int max_attempts, int32_t counts[2], hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
     int64_t ndof = 0;
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         if (!D.ereg)
@@ -720,13 +725,13 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
     while (t < t_end && counts[0] + counts[1] < max_attempts) {
         const bool last = t + dt >= t_end;
         const double h = last ? t_end - t : dt;
-        for (int ty = 0; ty < 2; ++ty)
+        for (int ty = 0; ty < frh::NTYPE; ++ty)
             if (d.t[ty].nelem)
                 FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[2], d.t[ty].reg[0], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
         for (int st_i = 0; st_i < 5; ++st_i) {
-            const T *U[2];
-            StageOut<T> so[2];
-            for (int ty = 0; ty < 2; ++ty) {
+            const T *U[frh::NTYPE];
+            StageOut<T> so[frh::NTYPE];
+            for (int ty = 0; ty < frh::NTYPE; ++ty) {
                 U[ty] = st_i == 0 ? d.t[ty].reg[0] : d.t[ty].reg[1];
                 so[ty].acc = d.t[ty].reg[0];
                 so[ty].a = T(RK45_B[st_i] * h);
@@ -741,7 +746,7 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
         }
         // fused error norm: sum (e / (atol + rtol max(|u_old|, |u_new|)))^2 in FP64
         double sum = 0;
-        for (int ty = 0; ty < 2; ++ty) {
+        for (int ty = 0; ty < frh::NTYPE; ++ty) {
             DevType<T> &D = d.t[ty];
             if (!D.nelem) continue;
             frd::RedArgs<T> ra{D.reg[0], D.ereg, D.wJ, D.ld, D.nelem, D.nu, 6, d.partial};
@@ -757,7 +762,7 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
         }
         const double err = std::sqrt(sum / double(ndof));
         if (!std::isfinite(err)) {
-            for (int ty = 0; ty < 2; ++ty)
+            for (int ty = 0; ty < frh::NTYPE; ++ty)
                 if (d.t[ty].nelem)
                     FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[0], d.t[ty].reg[2], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
             state[0] = t;
@@ -773,7 +778,7 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
             dt = h * fac;
             counts[0] += 1;
         } else {
-            for (int ty = 0; ty < 2; ++ty)
+            for (int ty = 0; ty < frh::NTYPE; ++ty)
                 if (d.t[ty].nelem)
                     FR_HIP(m, frd::launch_copy<T>(d.t[ty].reg[0], d.t[ty].reg[2], int64_t(d.t[ty].nu) * 5 * d.t[ty].ld, s));
             dt = h * std::min(1.0, std::max(FAC_MIN, SAFETY * std::pow(err, -1.0 / K)));
@@ -788,7 +793,7 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
 
 fr_status check_mesh(fr_mesh m, int etype, bool need_device) {
     if (!m) return FR_ERR_INVALID_ARG;
-    if (etype != 0 && etype != 1) return fail(m, FR_ERR_INVALID_ARG, "unknown element type");
+    if (etype < 0 || etype >= frh::NTYPE) return fail(m, FR_ERR_INVALID_ARG, "unknown element type");
     if (need_device && !m->device) return fail(m, FR_ERR_INVALID_ARG, "mesh was created validate-only");
     return FR_OK;
 }
@@ -826,7 +831,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
     if (split) caps = fmt == 2 ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
     else caps = sizeof(T) == 4 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 4};
     fr_status st = FR_OK;
-    for (int t = 0; t < 2 && !st; ++t) {
+    for (int t = 0; t < frh::NTYPE && !st; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const frh::RefOps &R = m->host.t[t].ops;
@@ -937,7 +942,8 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                 *c.sdst = best_sop;
             else
                 *c.dst = best_op;
-            report += (t ? "pri" : "tet") + std::string(" op") + std::to_string(c.op) + " cap " +
+            static const char *const short_name[frh::NTYPE] = {"tet", "pri", "hex"};
+            report += short_name[t] + std::string(" op") + std::to_string(c.op) + " cap " +
                       std::to_string(best_cap) + " stage " + std::to_string(best_stage) + " " +
                       std::to_string(best / 3 * 1e3) + " us; ";
         }
@@ -957,8 +963,8 @@ struct fr_batch_s {
     std::unique_ptr<fr_mesh_s> group[4];     // one merged mesh per order p = 1..4
     struct Prob {
         int g = 0;
-        int64_t off[2] = {0, 0}, ne[2] = {0, 0}, ld[2] = {0, 0};
-        int nu[2] = {0, 0};
+        int64_t off[frh::NTYPE] = {}, ne[frh::NTYPE] = {}, ld[frh::NTYPE] = {};
+        int nu[frh::NTYPE] = {};
     };
     std::vector<Prob> prob;
     hipStream_t stream = nullptr;             // stream the step graph replays on
@@ -997,7 +1003,7 @@ fr_status bfail(fr_batch b, fr_status st, const std::string &msg) {
 template <typename T>
 fr_status batch_alloc_dt(fr_mesh m) {
     Dev<T> &d = dev_of<T>(m);
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         if (!d.t[t].nelem) continue;
         FR_HIP(m, hipMalloc(reinterpret_cast<void **>(&d.t[t].dte), size_t(d.t[t].ld) * sizeof(T)));
         d.allocs.push_back(d.t[t].dte);
@@ -1016,6 +1022,14 @@ T *group_dte(fr_mesh m, int t) {
     return dev_of<T>(m).t[t].dte;
 }
 
+// Host tables of one mesh description.
+bool build_host(const fr_mesh_desc &d, frh::MeshHost &h, std::string &err) {
+    const int64_t ne[frh::NTYPE] = {d.n_tets, d.n_prisms, d.n_hex};
+    const int64_t *const conn[frh::NTYPE] = {d.tet_v, d.pri_v, d.hex_v};
+    const int8_t *const img[frh::NTYPE] = {d.tet_img, d.pri_img, d.hex_img};
+    return frh::build_mesh_host(d.order, d.n_vertices, d.xyz, ne, conn, img, d.period, h, err);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1030,9 +1044,9 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
         return fail(nullptr, FR_ERR_INVALID_ARG, "unknown system");
     if (desc->precision < FR_FP32 || desc->precision > FR_SPLIT_FP16)
         return fail(nullptr, FR_ERR_UNSUPPORTED, "unsupported precision");
-    if (desc->n_vertices <= 0 || !desc->xyz || desc->n_tets < 0 || desc->n_prisms < 0 ||
-        (desc->n_tets && !desc->tet_v) || (desc->n_prisms && !desc->pri_v) ||
-        desc->n_tets + desc->n_prisms == 0)
+    if (desc->n_vertices <= 0 || !desc->xyz || desc->n_tets < 0 || desc->n_prisms < 0 || desc->n_hex < 0 ||
+        (desc->n_tets && !desc->tet_v) || (desc->n_prisms && !desc->pri_v) || (desc->n_hex && !desc->hex_v) ||
+        desc->n_tets + desc->n_prisms + desc->n_hex == 0)
         return fail(nullptr, FR_ERR_INVALID_ARG, "empty or inconsistent mesh arrays");
     if (!(desc->gamma > 1) || desc->mu < 0 ||
         (desc->system == FR_NAVIER_STOKES && !(desc->prandtl > 0)))
@@ -1049,10 +1063,7 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
     m->tau = desc->ldg_tau;
     std::string err;
     try {
-        if (!frh::build_mesh_host(desc->order, desc->n_vertices, desc->xyz, desc->n_tets,
-                                  desc->tet_v, desc->tet_img, desc->n_prisms, desc->pri_v,
-                                  desc->pri_img, desc->period, m->host, err))
-            return fail(nullptr, FR_ERR_BAD_MESH, err);
+        if (!build_host(*desc, m->host, err)) return fail(nullptr, FR_ERR_BAD_MESH, err);
     } catch (const std::exception &ex) {
         return fail(nullptr, FR_ERR_BAD_MESH, ex.what());
     }
@@ -1141,7 +1152,7 @@ fr_status fr_get_solution(fr_mesh m, int32_t etype, void *u, void *stream) {
                                    : copy_state<double>(m, etype, u, nullptr, false, s);
 }
 
-fr_status fr_rhs(fr_mesh m, const void *const u[2], void *const r[2], void *stream) {
+fr_status fr_rhs(fr_mesh m, const void *const u[FR_NTYPES], void *const r[FR_NTYPES], void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return m->precision != FR_FP64 ? rhs_entry<float>(m, u, r, s) : rhs_entry<double>(m, u, r, s);
@@ -1333,14 +1344,13 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
         frh::MeshHost h;
         std::string err;
         try {
-            if (!frh::build_mesh_host(d.order, d.n_vertices, d.xyz, d.n_tets, d.tet_v, d.tet_img,
-                                      d.n_prisms, d.pri_v, d.pri_img, d.period, h, err))
+            if (!build_host(d, h, err))
                 return bfail(nullptr, FR_ERR_BAD_MESH, "problem " + std::to_string(i) + ": " + err);
         } catch (const std::exception &ex) {
             return bfail(nullptr, FR_ERR_BAD_MESH, ex.what());
         }
         b->prob[i].g = d.order - 1;
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < frh::NTYPE; ++t) {
             b->prob[i].ne[t] = h.t[t].nelem;
             b->prob[i].ld[t] = h.t[t].ld;
             b->prob[i].nu[t] = frh::n_upts(t, d.order);
@@ -1361,12 +1371,12 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
         m->prandtl = d0.prandtl;
         m->beta = d0.ldg_beta;
         m->tau = d0.ldg_tau;
-        std::vector<std::array<int64_t, 2>> off;
+        std::vector<std::array<int64_t, frh::NTYPE>> off;
         std::string err;
         if (!frh::merge_meshes(parts[g], m->host, off, err)) return bfail(nullptr, FR_ERR_BAD_MESH, err);
         parts[g].clear();
         for (size_t j = 0; j < members[g].size(); ++j)
-            for (int t = 0; t < 2; ++t) b->prob[members[g][j]].off[t] = off[j][t];
+            for (int t = 0; t < frh::NTYPE; ++t) b->prob[members[g][j]].off[t] = off[j][t];
         m->create_stream = s;
         fr_status st = m->precision != FR_FP64 ? setup_device<float>(m.get(), s) : setup_device<double>(m.get(), s);
         if (!st) st = m->precision != FR_FP64 ? batch_alloc_dt<float>(m.get()) : batch_alloc_dt<double>(m.get());
@@ -1396,7 +1406,7 @@ fr_status fr_batch_destroy(fr_batch b) {
 fr_status fr_batch_query(fr_batch b, int32_t problem, int32_t etype, int64_t *n_elem, int32_t *n_upts,
                          int64_t *ld) {
     if (!b) return FR_ERR_INVALID_ARG;
-    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+    if (problem < 0 || problem >= b->n || etype < 0 || etype >= frh::NTYPE)
         return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
     const auto &P = b->prob[problem];
     if (n_elem) *n_elem = P.ne[etype];
@@ -1408,7 +1418,7 @@ fr_status fr_batch_query(fr_batch b, int32_t problem, int32_t etype, int64_t *n_
 static fr_status batch_copy(fr_batch b, int problem, int etype, void *dst, const void *src, bool to_reg,
                             hipStream_t s) {
     if (!b) return FR_ERR_INVALID_ARG;
-    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+    if (problem < 0 || problem >= b->n || etype < 0 || etype >= frh::NTYPE)
         return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
     const auto &P = b->prob[problem];
     if (!P.ne[etype]) return FR_OK;
@@ -1428,7 +1438,7 @@ static fr_status batch_copy(fr_batch b, int problem, int etype, void *dst, const
 
 fr_status fr_batch_upts_coords(fr_batch b, int32_t problem, int32_t etype, double *xyz) {
     if (!b || !xyz) return FR_ERR_INVALID_ARG;
-    if (problem < 0 || problem >= b->n || etype < 0 || etype > 1)
+    if (problem < 0 || problem >= b->n || etype < 0 || etype >= frh::NTYPE)
         return bfail(b, FR_ERR_INVALID_ARG, "problem or element type out of range");
     const auto &P = b->prob[problem];
     if (!P.ne[etype]) return FR_OK;
@@ -1457,7 +1467,7 @@ fr_status fr_batch_set_dt(fr_batch b, const double *dt_host, void *stream) {
     for (int g = 0; g < 4; ++g) {
         fr_mesh m = b->group[g].get();
         if (!m) continue;
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < frh::NTYPE; ++t) {
             const int64_t ld = m->host.t[t].ld;
             if (!ld) continue;
             std::vector<double> h(size_t(ld), 0.0);
@@ -1669,14 +1679,14 @@ fr_status fr_mlp_adam(fr_mlp n, float lr, void *stream) {
 
 const char *fr_mlp_last_error(fr_mlp n) { return n ? n->err.c_str() : g_create_error.c_str(); }
 
-fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void *const u_dst[2],
+fr_status fr_project(fr_mesh src, const void *const u_src[FR_NTYPES], fr_mesh dst, void *const u_dst[FR_NTYPES],
                      void *stream) {
     if (fr_status st = check_mesh(src, 0, true)) return st;
     if (fr_status st = check_mesh(dst, 0, true)) return st;
     if ((src->precision == FR_FP64) != (dst->precision == FR_FP64))
         return fail(src, FR_ERR_INVALID_ARG, "projection between meshes of different scalar types");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < frh::NTYPE; ++t) {
         const int64_t ne = src->host.t[t].nelem;
         if (ne != dst->host.t[t].nelem) return fail(src, FR_ERR_INVALID_ARG, "meshes differ in element counts");
         if (!ne) continue;
@@ -1717,6 +1727,8 @@ fr_status fr_project(fr_mesh src, const void *const u_src[2], fr_mesh dst, void 
 
 namespace {
 fr_status closure_tables(fr_mesh m) {
+    if (m->host.t[2].nelem)
+        return fail(m, FR_ERR_UNSUPPORTED, "the closure is defined on tet and prism meshes only");
     if (m->closure) return FR_OK;
     auto c = std::make_unique<Closure>();
     const int64_t ntot = m->host.t[0].nelem + m->host.t[1].nelem;
@@ -1726,7 +1738,7 @@ fr_status closure_tables(fr_mesh m) {
     FR_HIP(m, upload_vec(c->allocs, z, c->mom));
     FR_HIP(m, upload_vec(c->allocs, z, c->y));
     FR_HIP(m, upload_vec(c->allocs, zf, c->feat));
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 2; ++t) {   // tets and prisms (hexahedra refused above)
         if (!m->host.t[t].nelem) continue;
         const std::vector<double> Mo = frh::build_moments(t, m->order), Li = frh::build_lift(t, m->order);
         FR_HIP(m, upload_vec(c->allocs, std::vector<float>(Mo.begin(), Mo.end()), c->Mom[t]));
@@ -1738,10 +1750,10 @@ fr_status closure_tables(fr_mesh m) {
 }
 
 template <typename T>
-fr_status closure_moments_impl(fr_mesh m, const void *const u[2], const void *const b[2], float *mom,
+fr_status closure_moments_impl(fr_mesh m, const void *const u[FR_NTYPES], const void *const b[FR_NTYPES], float *mom,
                                int64_t rs, int64_t cs, const float *ystats, hipStream_t s) {
     Dev<T> &d = dev_of<T>(m);
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 2; ++t) {   // tets and prisms (hexahedra refused by closure_tables)
         if (!d.t[t].nelem) continue;
         if (!u || !u[t] || (b && !b[t])) return fail(m, FR_ERR_INVALID_ARG, "null state");
         FR_HIP(m, frd::launch_moments<T>(static_cast<const T *>(u[t]), b ? static_cast<const T *>(b[t]) : nullptr,
@@ -1755,7 +1767,7 @@ fr_status closure_moments_impl(fr_mesh m, const void *const u[2], const void *co
 
 extern "C" {
 
-fr_status fr_closure_moments(fr_mesh m, const void *const u[2], float *mom, void *stream) {
+fr_status fr_closure_moments(fr_mesh m, const void *const u[FR_NTYPES], float *mom, void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     if (!mom) return fail(m, FR_ERR_INVALID_ARG, "null output");
     if (fr_status st = closure_tables(m)) return st;
@@ -1764,7 +1776,8 @@ fr_status fr_closure_moments(fr_mesh m, const void *const u[2], float *mom, void
                                    : closure_moments_impl<double>(m, u, nullptr, mom, 20, 1, nullptr, s);
 }
 
-fr_status fr_closure_targets(fr_mesh m, const void *const a[2], const void *const b[2], const float *stats,
+fr_status fr_closure_targets(fr_mesh m, const void *const a[FR_NTYPES], const void *const b[FR_NTYPES],
+                             const float *stats,
                              float *out, void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     if (!out || !b) return fail(m, FR_ERR_INVALID_ARG, "null argument");
@@ -1775,7 +1788,7 @@ fr_status fr_closure_targets(fr_mesh m, const void *const a[2], const void *cons
                                    : closure_moments_impl<double>(m, a, b, out, 20, 1, ys, s);
 }
 
-fr_status fr_closure_features(fr_mesh m, const void *const u[2], const float *stats, float *feat,
+fr_status fr_closure_features(fr_mesh m, const void *const u[FR_NTYPES], const float *stats, float *feat,
                               void *stream) {
     if (fr_status st = check_mesh(m, 0, true)) return st;
     if (!feat) return fail(m, FR_ERR_INVALID_ARG, "null output");

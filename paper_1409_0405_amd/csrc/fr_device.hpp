@@ -9,6 +9,7 @@
 namespace frd {
 
 constexpr int NVAR = 5;
+constexpr int NTYPE = 3;   // 0 tet, 1 prism, 2 hexahedron
 
 // Fragment-ordered operator for the MFMA product kernel: element
 // [mb][kb][lane] holds A[16 mb + lane % 16][4 kb + lane / 16], zero padded to
@@ -39,7 +40,7 @@ inline void row_groups(int M, int cap, int &nmg, int &mbw) {
 // C[M][ncols] = A[M][K1 + K2] . [B1 (K1 rows); B2 (K2 rows)], row strides
 // ldb1, ldb2, ldc (elements); ncols a multiple of 64.  tag = 4 * element type +
 // operator (0 interpolation, 1 gradient, 2 gradient interpolation, 3
-// divergence) names the kernel instantiation.
+// divergence), 0..11, names the kernel instantiation.
 enum { OP_INTERP = 0, OP_GRAD = 1, OP_GRADINTERP = 2, OP_DIV = 3 };
 template <typename T>
 hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
@@ -67,8 +68,8 @@ hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_
                               int64_t ncols, hipStream_t s);
 
 // Point-wise work at the solution points of one element type (ETYPE 0 tet,
-// 1 prism): physical gradient Q from the reference gradient Qt (NS) and the
-// transformed flux Ft = adj (F_inv - F_vis).
+// 1 prism, 2 hexahedron): physical gradient Q from the reference gradient Qt
+// (NS) and the transformed flux Ft = adj (F_inv - F_vis).
 template <typename T>
 struct UptsArgs {
     const T *U;        // [nu][5][ld]
@@ -87,14 +88,14 @@ hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s);
 // Interface work on the paired flux points.
 template <typename T>
 struct PairArgs {
-    const uint32_t *sideL, *sideR;   // elem | fpt << 24 | type << 31
+    const uint32_t *sideL, *sideR;   // elem | fpt << 22 | type << 30
     const T *geo;                    // [5][npairs]: nx, ny, nz, sL, sR
     int64_t npairs;
-    const T *Uf[2];                  // [nf][5][ld]
-    const T *Qf[2];                  // [nf][15][ld]
-    T *Cf[2];                        // [nf][5][ld]
-    T *Fn[2];                        // [nf][5][ld]
-    int64_t ld[2];
+    const T *Uf[NTYPE];              // [nf][5][ld]
+    const T *Qf[NTYPE];              // [nf][15][ld]
+    T *Cf[NTYPE];                    // [nf][5][ld]
+    T *Fn[NTYPE];                    // [nf][5][ld]
+    int64_t ld[NTYPE];
     T gamma, mu, prandtl, beta, tau;
 };
 template <typename T>

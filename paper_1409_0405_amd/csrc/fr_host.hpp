@@ -10,6 +10,11 @@
 namespace frh {
 
 constexpr int NVAR = 5;
+constexpr int NTYPE = 3;          // 0 tet, 1 prism, 2 hexahedron
+constexpr int ELEM_BITS = 22;     // side word: elem | fpt << 22 | type << 30
+constexpr int64_t MAX_ELEM = int64_t(1) << ELEM_BITS;
+
+inline const char *type_name(int t) { return t == 0 ? "tet" : (t == 1 ? "prism" : "hex"); }
 
 // Reference element of one type at one order, built in extended precision and
 // stored as double.  Point / face conventions:
@@ -20,8 +25,12 @@ constexpr int NVAR = 5;
 //    enumeration i3, i2, i1 (outer to inner);
 //  * prism solution points: Gauss-Legendre layer in zeta (outer) x triangle
 //    set (inner);
+//  * hexahedron [-1,1]^3 (vertices 0-3 counter-clockwise at zeta = -1, k+4
+//    above k): Gauss-Legendre tensor points, index (k(p+1) + j)(p+1) + i
+//    with xi fastest;
 //  * faces: tet (0,1,2) (0,1,3) (0,2,3) (1,2,3); prism (0,1,2) (3,4,5)
-//    (0,1,4,3) (1,2,5,4) (2,0,3,5); triangle-face points l0 a + l1 b + l2 c;
+//    (0,1,4,3) (1,2,5,4) (2,0,3,5); hexahedron (0,1,2,3) (4,5,6,7) (0,1,5,4)
+//    (1,2,6,5) (2,3,7,6) (3,0,4,7); triangle-face points l0 a + l1 b + l2 c;
 //    quad-face points a + (1+s_i)/2 (b-a) + (1+t_j)/2 (d-a), index j(p+1)+i.
 struct RefOps {
     int etype = 0, p = 0, nu = 0, nf = 0;
@@ -62,7 +71,10 @@ void ref_vertex(int etype, int v, double out[3]);
 // Jacobian coefficient vectors of one element from its (unwrapped) vertices:
 // tet  -> 9 values: columns dx/dxi, dx/deta, dx/dzeta (constant);
 // prism-> 15 values: A1, B1, C0, C1, C2 with dx/dxi = A1 + C1 z,
-//         dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.
+//         dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y;
+// hex  -> 21 values: c1..c7 of the trilinear map x = c0 + c1 r + c2 s + c3 t
+//         + c4 rs + c5 rt + c6 st + c7 rst, so dx/dr = c1 + c4 s + c5 t + c7 st,
+//         dx/ds = c2 + c4 r + c6 t + c7 rt, dx/dt = c3 + c5 r + c6 s + c7 rs.
 int n_geom(int etype);
 void geom_coeffs(int etype, const double *X, double *c);
 // Jacobian matrix columns at a reference point from the coefficients.
@@ -72,7 +84,7 @@ void map_point(int etype, const double *X, const double *xi, double out[3]);
 
 struct PairTable {
     // one entry per paired flux point, sorted by (type L, fpt L, elem L)
-    std::vector<uint32_t> sideL, sideR;   // elem | fpt << 24 | type << 31
+    std::vector<uint32_t> sideL, sideR;   // elem | fpt << 22 | type << 30
     std::vector<double> nhat;             // [n][3] unit normal out of side L
     std::vector<double> sL, sR;           // |adj^T n_ref| on each side
 };
@@ -87,29 +99,34 @@ struct TypeHost {
 
 struct MeshHost {
     int p = 0;
-    TypeHost t[2];
+    TypeHost t[NTYPE];
     PairTable pairs;
     double volume = 0;
 };
 
 // Neighbour across each local face, global type-major element id
-// [n_tet + n_pri][5], -1 where the element has no such face.
+// [n_tet + n_pri][5], -1 where the element has no such face (tets and prisms
+// only: the caller refuses meshes with hexahedra).
 std::vector<int32_t> face_neighbours(const MeshHost &m);
 
 // Builds geometry and pairing; returns false with a message on a bad mesh.
-bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet,
-                     const int64_t *tet_v, const int8_t *tet_img, int64_t npri,
-                     const int64_t *pri_v, const int8_t *pri_img, const double period[3],
-                     MeshHost &m, std::string &err);
+// Per type t: nelem[t] elements, connectivity conn[t] [nelem][n_verts(t)],
+// periodic images img[t] (may be null).
+bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
+                     const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
+                     const double period[3], MeshHost &m, std::string &err);
 
 // Merge independent meshes of one order into one element array per type.
 // Element indices of each part are offset by the elements of the parts
 // before it (elem_off[part][type]); the pairing stays within each part.
 bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
-                  std::vector<std::array<int64_t, 2>> &elem_off, std::string &err);
+                  std::vector<std::array<int64_t, NTYPE>> &elem_off, std::string &err);
 
 inline uint32_t pack_side(int64_t e, int f, int t) {
-    return uint32_t(e) | (uint32_t(f) << 24) | (uint32_t(t) << 31);
+    return uint32_t(e) | (uint32_t(f) << ELEM_BITS) | (uint32_t(t) << 30);
 }
+inline int64_t side_elem(uint32_t s) { return int64_t(s & ((1u << ELEM_BITS) - 1)); }
+inline int side_fpt(uint32_t s) { return int((s >> ELEM_BITS) & 0xffu); }
+inline int side_type(uint32_t s) { return int(s >> 30); }
 
 }  // namespace frh

@@ -643,7 +643,9 @@ __global__ __launch_bounds__(512) void opmul_split_lds_kernel(OpSplit A, const f
 // ---------------------------------------------------------------------------
 // Geometry at a solution point from the Jacobian coefficients.
 // Tet: constant columns c0..c2.  Prism: dx/dxi = A1 + C1 z,
-// dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.
+// dx/deta = B1 + C2 z, dx/dzeta = C0 + C1 x + C2 y.  Hexahedron (trilinear
+// map, coefficients c1..c7): dx/dr = c1 + c4 s + c5 t + c7 st,
+// dx/ds = c2 + c4 r + c6 t + c7 rt, dx/dt = c3 + c5 r + c6 s + c7 rs.
 // adj[k][j] = J dxi_k/dx_j (rows are cross products of the columns).
 // ---------------------------------------------------------------------------
 template <typename T, int ET>
@@ -655,6 +657,18 @@ __device__ __forceinline__ T metric(const T *__restrict__ g, int64_t ld, int64_t
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int d = 0; d < 3; ++d) c[k][d] = g[(3 * k + d) * ld + e];
+    } else if (ET == 2) {
+        const T r = xi[0], sv = xi[1], t = xi[2];
+        const T st = sv * t, rt = r * t, rs = r * sv;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T c1 = g[d * ld + e], c2 = g[(3 + d) * ld + e], c3 = g[(6 + d) * ld + e];
+            const T c4 = g[(9 + d) * ld + e], c5 = g[(12 + d) * ld + e], c6 = g[(15 + d) * ld + e];
+            const T c7 = g[(18 + d) * ld + e];
+            c[0][d] = c1 + c4 * sv + c5 * t + c7 * st;
+            c[1][d] = c2 + c4 * r + c6 * t + c7 * rt;
+            c[2][d] = c3 + c5 * r + c6 * sv + c7 * rs;
+        }
     } else {
         const T x = xi[0], y = xi[1], z = xi[2];
 #pragma unroll
@@ -775,17 +789,19 @@ __global__ __launch_bounds__(256) void upts_kernel(UptsArgs<T> a) {
                 adj[k][0] * F[0][v] + adj[k][1] * F[1][v] + adj[k][2] * F[2][v];
 }
 
-// Per-type kernel argument of an element type t in {0, 1}, selected without
-// indexing the argument block (which would be a memory load per thread).
+// Per-type kernel argument of an element type t in {0, 1, 2}, selected
+// without indexing the argument block (which would be a memory load per
+// thread).
 template <typename P>
-__device__ __forceinline__ P pick(const P (&v)[2], int t) {
-    return t ? v[1] : v[0];
+__device__ __forceinline__ P pick(const P (&v)[NTYPE], int t) {
+    return t == 0 ? v[0] : (t == 1 ? v[1] : v[2]);
 }
 
+// Side word: element (22 bits) | flux point << 22 (8 bits) | type << 30.
 __device__ __forceinline__ void unpack(uint32_t s, int64_t &e, int &f, int &t) {
-    e = s & 0xffffffu;
-    f = (s >> 24) & 0x7f;
-    t = s >> 31;
+    e = s & 0x3fffffu;
+    f = (s >> 22) & 0xff;
+    t = s >> 30;
 }
 
 // Jump to the common solution of the LDG scheme at each paired flux point,
@@ -1070,6 +1086,7 @@ hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int 
     case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, s);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
+        FR_TAG(8) FR_TAG(9) FR_TAG(10) FR_TAG(11)
         default: return hipErrorInvalidValue;
     }
 #undef FR_TAG
@@ -1121,6 +1138,7 @@ hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_
                              : launch_split_tag<false, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
+        FR_TAG(8) FR_TAG(9) FR_TAG(10) FR_TAG(11)
         default: return hipErrorInvalidValue;
     }
 #undef FR_TAG
@@ -1132,9 +1150,12 @@ hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s) 
     if (etype == 0) {
         if (ns) upts_kernel<T, 0, true><<<grid, block, 0, s>>>(a);
         else upts_kernel<T, 0, false><<<grid, block, 0, s>>>(a);
-    } else {
+    } else if (etype == 1) {
         if (ns) upts_kernel<T, 1, true><<<grid, block, 0, s>>>(a);
         else upts_kernel<T, 1, false><<<grid, block, 0, s>>>(a);
+    } else {
+        if (ns) upts_kernel<T, 2, true><<<grid, block, 0, s>>>(a);
+        else upts_kernel<T, 2, false><<<grid, block, 0, s>>>(a);
     }
     return hipGetLastError();
 }
@@ -1159,7 +1180,8 @@ template <typename T>
 hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s) {
     const dim3 grid(unsigned((a.nelem + 255) / 256), unsigned(a.nu)), block(256);
     if (etype == 0) negdivconf_kernel<T, 0><<<grid, block, 0, s>>>(a);
-    else negdivconf_kernel<T, 1><<<grid, block, 0, s>>>(a);
+    else if (etype == 1) negdivconf_kernel<T, 1><<<grid, block, 0, s>>>(a);
+    else negdivconf_kernel<T, 2><<<grid, block, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -1,10 +1,10 @@
 // Element geometry, face matching and flux-point pairing (host).
 //
-// Paper, Sections 2.1 and 3.3: a mixed unstructured grid of tets and prisms;
-// elements interact only through their shared faces.  Straight-sided
-// elements: the tet map is affine, the prism map is linear on the triangle
-// times linear in zeta, and the metric terms are evaluated exactly from the
-// map's derivatives.
+// Paper, Sections 2.1 and 3.3: a mixed unstructured grid of tets, prisms and
+// hexahedra; elements interact only through their shared faces.
+// Straight-sided elements: the tet map is affine, the prism map is linear on
+// the triangle times linear in zeta, the hexahedron map trilinear, and the
+// metric terms are evaluated exactly from the map's derivatives.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -15,10 +15,30 @@
 
 namespace frh {
 
-int n_geom(int etype) { return etype == 0 ? 9 : 15; }
+int n_geom(int etype) { return etype == 0 ? 9 : (etype == 1 ? 15 : 21); }
+
+// Reference vertex signs of the hexahedron (vertices 0-3 at zeta = -1
+// counter-clockwise, k+4 above k).
+static const int HEX_SIGN[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                   {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 
 void geom_coeffs(int etype, const double *X, double *c) {
     auto V = [&](int v, int d) { return X[3 * v + d]; };
+    if (etype == 2) {
+        // c_k = sum_a m_k(r_a, s_a, t_a) X_a / 8 for the monomials
+        // m = r, s, t, rs, rt, st, rst
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 7; ++k) {
+                double acc = 0;
+                for (int a = 0; a < 8; ++a) {
+                    const int r = HEX_SIGN[a][0], sg = HEX_SIGN[a][1], t = HEX_SIGN[a][2];
+                    const int m[7] = {r, sg, t, r * sg, r * t, sg * t, r * sg * t};
+                    acc += m[k] * V(a, d);
+                }
+                c[3 * k + d] = acc / 8;
+            }
+        return;
+    }
     if (etype == 0) {
         for (int d = 0; d < 3; ++d) {
             c[d] = 0.5 * (V(1, d) - V(0, d));
@@ -43,8 +63,14 @@ void geom_coeffs(int etype, const double *X, double *c) {
 }
 
 void jac_at(int etype, const double *c, const double *xi, double col[3][3]) {
+    const double r = xi[0], sg = xi[1], t = xi[2];
     for (int d = 0; d < 3; ++d) {
-        if (etype == 0) {
+        if (etype == 2) {
+            auto C = [&](int k) { return c[3 * (k - 1) + d]; };
+            col[0][d] = C(1) + C(4) * sg + C(5) * t + C(7) * sg * t;
+            col[1][d] = C(2) + C(4) * r + C(6) * t + C(7) * r * t;
+            col[2][d] = C(3) + C(5) * r + C(6) * sg + C(7) * r * sg;
+        } else if (etype == 0) {
             col[0][d] = c[d];
             col[1][d] = c[3 + d];
             col[2][d] = c[6 + d];
@@ -57,9 +83,12 @@ void jac_at(int etype, const double *c, const double *xi, double col[3][3]) {
 }
 
 void map_point(int etype, const double *X, const double *xi, double out[3]) {
-    double N[6];
+    double N[8];
     int nv = n_verts(etype);
-    if (etype == 0) {
+    if (etype == 2) {
+        for (int a = 0; a < 8; ++a)
+            N[a] = (1 + HEX_SIGN[a][0] * xi[0]) * (1 + HEX_SIGN[a][1] * xi[1]) * (1 + HEX_SIGN[a][2] * xi[2]) / 8;
+    } else if (etype == 0) {
         N[0] = -(1 + xi[0] + xi[1] + xi[2]) / 2;
         N[1] = (1 + xi[0]) / 2;
         N[2] = (1 + xi[1]) / 2;
@@ -102,22 +131,18 @@ struct FaceRec {
 
 }  // namespace
 
-bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const int64_t *tet_v,
-                     const int8_t *tet_img, int64_t npri, const int64_t *pri_v,
-                     const int8_t *pri_img, const double period[3], MeshHost &m,
-                     std::string &err) {
+bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
+                     const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
+                     const double period[3], MeshHost &m, std::string &err) {
     m.p = p;
-    const int64_t nelem[2] = {ntet, npri};
-    const int64_t *conn[2] = {tet_v, pri_v};
-    const int8_t *img[2] = {tet_img, pri_img};
     m.volume = 0;
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NTYPE; ++t) {
         TypeHost &T = m.t[t];
         T.nelem = nelem[t];
         T.ld = (T.nelem + 63) / 64 * 64;
         if (T.nelem == 0) continue;
-        if (T.nelem >= (int64_t(1) << 24)) {
-            err = "too many elements of one type (limit 2^24)";
+        if (T.nelem >= MAX_ELEM) {
+            err = "too many elements of one type (limit 2^22)";
             return false;
         }
         T.ops = ref_cached(t, p);
@@ -130,7 +155,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
             for (int a = 0; a < nvt; ++a) {
                 int64_t v = conn[t][e * nvt + a];
                 if (v < 0 || v >= nv) {
-                    err = "vertex id out of range in " + std::string(t ? "prism " : "tet ") +
+                    err = "vertex id out of range in " + std::string(type_name(t)) + " " +
                           std::to_string(e);
                     return false;
                 }
@@ -139,7 +164,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
                     X[3 * a + d] = xyz[3 * v + d] + sh;
                 }
             }
-            double c[15];
+            double c[21];
             geom_coeffs(t, X, c);
             for (int k = 0; k < ng; ++k) T.geom[size_t(k) * T.nelem + e] = c[k];
             // J > 0 at every solution and flux point
@@ -149,7 +174,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
                 jac_at(t, c, xi, col);
                 double J = adjugate(col, adj);
                 if (!(J > 0)) {
-                    err = std::string("non-positive Jacobian in ") + (t ? "prism " : "tet ") +
+                    err = std::string("non-positive Jacobian in ") + type_name(t) + " " +
                           std::to_string(e);
                     return false;
                 }
@@ -163,8 +188,8 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
 
     // faces keyed by their sorted vertex ids
     std::vector<FaceRec> recs;
-    int64_t gbase[2] = {0, ntet};
-    for (int t = 0; t < 2; ++t) {
+    int64_t gbase[NTYPE] = {0, nelem[0], nelem[0] + nelem[1]};
+    for (int t = 0; t < NTYPE; ++t) {
         const TypeHost &T = m.t[t];
         if (!T.nelem) continue;
         const auto &faces = faces_of(t);
@@ -238,12 +263,11 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
         const int fa0 = TA.ops.face_off[A.face], fa1 = TA.ops.face_off[A.face + 1];
         const int fb0 = TB.ops.face_off[B.face], fb1 = TB.ops.face_off[B.face + 1];
         if (fa1 - fa0 != fb1 - fb0) {
-            err = "non-conforming face between " + std::string(A.type ? "prism " : "tet ") +
-                  std::to_string(A.elem) + " and " + (B.type ? "prism " : "tet ") +
-                  std::to_string(B.elem);
+            err = "non-conforming face between " + std::string(type_name(A.type)) + " " +
+                  std::to_string(A.elem) + " and " + type_name(B.type) + " " + std::to_string(B.elem);
             return false;
         }
-        double ca[15], cb[15];
+        double ca[21], cb[21];
         for (int k = 0; k < n_geom(A.type); ++k) ca[k] = TA.geom[size_t(k) * TA.nelem + A.elem];
         for (int k = 0; k < n_geom(B.type); ++k) cb[k] = TB.geom[size_t(k) * TB.nelem + B.elem];
         std::vector<char> used(fb1 - fb0, 0);
@@ -265,8 +289,8 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
             }
             if (std::sqrt(bd) > tol || used[best - fb0]) {
                 err = "flux points do not coincide on the face between " +
-                      std::string(A.type ? "prism " : "tet ") + std::to_string(A.elem) + " and " +
-                      (B.type ? "prism " : "tet ") + std::to_string(B.elem);
+                      std::string(type_name(A.type)) + " " + std::to_string(A.elem) + " and " +
+                      type_name(B.type) + " " + std::to_string(B.elem);
                 return false;
             }
             used[best - fb0] = 1;
@@ -302,7 +326,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
             size_t y = x + 1;
             while (y < j && (done[y - i] || !same_face(recs[x], recs[y]))) ++y;
             if (y == j) {
-                err = "unmatched face: " + std::string(recs[x].type ? "prism " : "tet ") +
+                err = "unmatched face: " + std::string(type_name(recs[x].type)) + " " +
                       std::to_string(recs[x].elem) + " face " + std::to_string(recs[x].face);
                 return false;
             }
@@ -314,7 +338,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, int64_t ntet, const i
 
     // order by (type L, flux point L, element L) for coalesced side-L access
     auto keyL = [](uint32_t s) {
-        return (uint64_t(s >> 31) << 40) | (uint64_t((s >> 24) & 0x7f) << 32) | (s & 0xffffff);
+        return (uint64_t(side_type(s)) << 40) | (uint64_t(side_fpt(s)) << 32) | uint64_t(side_elem(s));
     };
     std::sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
     PairTable &P = m.pairs;
@@ -338,10 +362,9 @@ std::vector<int32_t> face_neighbours(const MeshHost &m) {
     const int64_t nt = m.t[0].nelem, ntot = nt + m.t[1].nelem;
     std::vector<int32_t> nb(size_t(ntot) * 5, -1);
     auto info = [&](uint32_t s, int64_t &g, int &f) {
-        const int t = int(s >> 31);
-        const int64_t e = s & 0xffffffu;
-        g = (t ? nt : 0) + e;
-        f = m.t[t].ops.fface[(s >> 24) & 0x7f];
+        const int t = side_type(s);
+        g = (t ? nt : 0) + side_elem(s);
+        f = m.t[t].ops.fface[side_fpt(s)];
     };
     for (size_t j = 0; j < m.pairs.sideL.size(); ++j) {
         int64_t gl, gr;
@@ -355,15 +378,15 @@ std::vector<int32_t> face_neighbours(const MeshHost &m) {
 }
 
 bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
-                  std::vector<std::array<int64_t, 2>> &elem_off, std::string &err) {
+                  std::vector<std::array<int64_t, NTYPE>> &elem_off, std::string &err) {
     if (parts.empty()) {
         err = "no meshes to merge";
         return false;
     }
     out = MeshHost();
     out.p = parts[0].p;
-    elem_off.assign(parts.size(), {0, 0});
-    for (int t = 0; t < 2; ++t) {
+    elem_off.assign(parts.size(), std::array<int64_t, NTYPE>{});
+    for (int t = 0; t < NTYPE; ++t) {
         int64_t n = 0;
         for (size_t i = 0; i < parts.size(); ++i) {
             if (parts[i].p != out.p) {
@@ -374,8 +397,8 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
             n += parts[i].t[t].nelem;
             if (parts[i].t[t].nelem && !out.t[t].ops.nu) out.t[t].ops = parts[i].t[t].ops;
         }
-        if (n >= (int64_t(1) << 24)) {
-            err = "too many elements of one type in a merged batch (limit 2^24)";
+        if (n >= MAX_ELEM) {
+            err = "too many elements of one type in a merged batch (limit 2^22)";
             return false;
         }
         TypeHost &T = out.t[t];
@@ -400,9 +423,8 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
     };
     std::vector<PP> pp;
     auto shift = [&](uint32_t side, size_t i) {
-        const int t = int(side >> 31);
-        const int64_t e = int64_t(side & 0xffffffu) + elem_off[i][t];
-        return pack_side(e, int((side >> 24) & 0x7f), t);
+        const int t = side_type(side);
+        return pack_side(side_elem(side) + elem_off[i][t], side_fpt(side), t);
     };
     for (size_t i = 0; i < parts.size(); ++i) {
         const PairTable &P = parts[i].pairs;
@@ -412,7 +434,7 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
         out.volume += parts[i].volume;
     }
     auto keyL = [](uint32_t s) {
-        return (uint64_t(s >> 31) << 40) | (uint64_t((s >> 24) & 0x7f) << 32) | (s & 0xffffff);
+        return (uint64_t(side_type(s)) << 40) | (uint64_t(side_fpt(s)) << 32) | uint64_t(side_elem(s));
     };
     std::stable_sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
     PairTable &T = out.pairs;

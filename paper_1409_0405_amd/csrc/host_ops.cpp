@@ -2,7 +2,7 @@
 //
 // Paper, Section 2.1: an FR step is mostly products of constant operator
 // matrices with state matrices; Table 2 gives the dimensions of the
-// volume-to-surface interpolation operator M0.  The correction is the DG lift
+// volume-to-surface interpolation operator M0 for tets, prisms and hexahedra.  The correction is the DG lift
 // (Section 3.4: "a DG scheme"), built in the reference element.
 //
 // Construction route: a monomial basis phi_a, its Vandermonde matrix at the
@@ -114,13 +114,15 @@ ld ipow(ld x, int e) {
 
 // Monomial basis of the element space: tet X^a Y^b Z^c (a+b+c <= p), prism
 // X^a Y^b t^c (a+b <= p, c <= p), with X = (1+xi)/2, Y = (1+eta)/2,
-// Z = (1+zeta)/2 and t = zeta.
+// Z = (1+zeta)/2 and t = zeta; hexahedron xi^a eta^b zeta^c (a, b, c <= p),
+// centred monomials (the tensor Vandermonde's condition number is the
+// product of the 1-D ones, small on [-1, 1]).
 struct Monos {
     int etype, p;
     std::vector<int> e;   // [n][3]
     Monos(int et, int pp) : etype(et), p(pp) {
         for (int a = 0; a <= p; ++a)
-            for (int b = 0; a + b <= p; ++b)
+            for (int b = 0; b <= (etype == 2 ? p : p - a); ++b)
                 for (int c = 0; c <= (etype == 0 ? p - a - b : p); ++c) {
                     e.push_back(a);
                     e.push_back(b);
@@ -130,16 +132,17 @@ struct Monos {
     int n() const { return int(e.size() / 3); }
     // values [n] and gradient [3][n] at reference point x
     void eval(const ld *x, ld *val, ld *grad) const {
-        ld X = (1 + x[0]) / 2, Y = (1 + x[1]) / 2;
+        const bool hex = etype == 2;
+        ld X = hex ? x[0] : (1 + x[0]) / 2, Y = hex ? x[1] : (1 + x[1]) / 2;
         ld Z = etype == 0 ? (1 + x[2]) / 2 : x[2];
-        ld dZ = etype == 0 ? ld(0.5) : ld(1);
+        ld dXY = hex ? ld(1) : ld(0.5), dZ = etype == 0 ? ld(0.5) : ld(1);
         for (int m = 0; m < n(); ++m) {
             int a = e[3 * m], b = e[3 * m + 1], c = e[3 * m + 2];
             ld va = ipow(X, a), vb = ipow(Y, b), vc = ipow(Z, c);
             val[m] = va * vb * vc;
             if (grad) {
-                grad[m] = (a ? a * ipow(X, a - 1) * ld(0.5) : 0) * vb * vc;
-                grad[n() + m] = va * (b ? b * ipow(Y, b - 1) * ld(0.5) : 0) * vc;
+                grad[m] = (a ? a * ipow(X, a - 1) * dXY : 0) * vb * vc;
+                grad[n() + m] = va * (b ? b * ipow(Y, b - 1) * dXY : 0) * vc;
                 grad[2 * n() + m] = va * vb * (c ? c * ipow(Z, c - 1) * dZ : 0);
             }
         }
@@ -150,7 +153,10 @@ const ld TET_V[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
 const ld PRI_V[6][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1},
                         {-1, -1, 1},  {1, -1, 1},  {-1, 1, 1}};
 
-const ld *vert(int etype, int v) { return etype == 0 ? TET_V[v] : PRI_V[v]; }
+const ld HEX_V[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                        {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+const ld *vert(int etype, int v) { return etype == 0 ? TET_V[v] : (etype == 1 ? PRI_V[v] : HEX_V[v]); }
 
 // Triangle barycentrics of the order-p set.
 std::vector<ld> tri_bary(int p) {
@@ -192,7 +198,12 @@ void volume_rule(int etype, int n, std::vector<ld> &pts, std::vector<ld> &wts) {
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
                 ld a = x[i], b = x[j], c = x[k];
-                if (etype == 0) {
+                if (etype == 2) {
+                    pts.push_back(a);
+                    pts.push_back(b);
+                    pts.push_back(c);
+                    wts.push_back(w[i] * w[j] * w[k]);
+                } else if (etype == 0) {
                     pts.push_back((1 + a) * (1 - b) * (1 - c) / 4 - 1);
                     pts.push_back((1 + b) * (1 - c) / 2 - 1);
                     pts.push_back(c);
@@ -316,11 +327,13 @@ struct FaceLagrange {
 }  // namespace
 
 int n_upts(int etype, int p) {
+    if (etype == 2) return (p + 1) * (p + 1) * (p + 1);
     return etype == 0 ? (p + 1) * (p + 2) * (p + 3) / 6 : (p + 1) * (p + 1) * (p + 2) / 2;
 }
 
 int n_fpts(int etype, int p) {
     int tri = (p + 1) * (p + 2) / 2;
+    if (etype == 2) return 6 * (p + 1) * (p + 1);
     return etype == 0 ? 4 * tri : 2 * tri + 3 * (p + 1) * (p + 1);
 }
 
@@ -328,10 +341,12 @@ const std::vector<std::vector<int>> &faces_of(int etype) {
     static const std::vector<std::vector<int>> tet = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
     static const std::vector<std::vector<int>> pri = {
         {0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
-    return etype == 0 ? tet : pri;
+    static const std::vector<std::vector<int>> hex = {
+        {0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+    return etype == 0 ? tet : (etype == 1 ? pri : hex);
 }
 
-int n_verts(int etype) { return etype == 0 ? 4 : 6; }
+int n_verts(int etype) { return etype == 0 ? 4 : (etype == 1 ? 6 : 8); }
 
 void ref_vertex(int etype, int v, double out[3]) {
     for (int d = 0; d < 3; ++d) out[d] = double(vert(etype, v)[d]);
@@ -355,6 +370,16 @@ RefOps build_ref(int etype, int p) {
                 for (int a = 0; a < 4; ++a) s += b[4 * i + a] * TET_V[a][d];
                 up.push_back(s);
             }
+    } else if (etype == 2) {
+        std::vector<ld> x, w;
+        gauss_legendre(p + 1, x, w);
+        for (int k = 0; k <= p; ++k)
+            for (int j = 0; j <= p; ++j)
+                for (int i = 0; i <= p; ++i) {
+                    up.push_back(x[i]);
+                    up.push_back(x[j]);
+                    up.push_back(x[k]);
+                }
     } else {
         auto b = tri_bary(p);
         std::vector<ld> z, w;

@@ -18,7 +18,9 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfr.so")
 
 FR_OK, FR_ERR_INVALID_ARG, FR_ERR_BAD_MESH, FR_ERR_UNSUPPORTED = 0, 1, 2, 3
 FR_ERR_OUT_OF_MEMORY, FR_ERR_DEVICE, FR_ERR_NONFINITE = 4, 5, 6
-FR_TET, FR_PRI = 0, 1
+FR_TET, FR_PRI, FR_HEX = 0, 1, 2
+NTYPES = 3
+TYPE_NAMES = ("tet", "pri", "hex")
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_FP32, FR_FP64, FR_SPLIT_BF16, FR_SPLIT_FP16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FR_FP32, "fp64": FR_FP64, "split_bf16": FR_SPLIT_BF16,
@@ -43,7 +45,8 @@ MLP_NPARAM, MLP_NSTATS = 13204, 280
 PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
                 "upts_tet", "upts_pri", "common_solution", "common_flux",
-                "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward")
+                "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward",
+                "interp_hex", "grad_hex", "gradinterp_hex", "div_hex", "upts_hex", "negdivconf_hex")
 
 
 class FrError(RuntimeError):
@@ -64,6 +67,8 @@ class fr_mesh_desc(ctypes.Structure):
         ("n_prisms", ctypes.c_int64), ("pri_v", ctypes.POINTER(ctypes.c_int64)),
         ("pri_img", ctypes.POINTER(ctypes.c_int8)),
         ("period", ctypes.c_double * 3),
+        ("n_hex", ctypes.c_int64), ("hex_v", ctypes.POINTER(ctypes.c_int64)),
+        ("hex_img", ctypes.POINTER(ctypes.c_int8)),
     ]
 
 
@@ -143,6 +148,16 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def _type_ptrs(ptrs):
+    """Per-type device pointers (tet, prism, hexahedron) as the C array the
+    ABI takes; missing trailing entries are NULL."""
+    ptrs = list(ptrs or [])
+    if len(ptrs) > NTYPES:
+        raise ValueError("more pointers than element types")
+    ptrs += [0] * (NTYPES - len(ptrs))
+    return (ctypes.c_void_p * NTYPES)(*[ctypes.c_void_p(p or 0) for p in ptrs])
+
+
 def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4, mu=0.0,
               prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False, check_finite=False):
     """fr_mesh_desc for the generator's mesh arrays; the numpy arrays it points
@@ -158,7 +173,9 @@ def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=
     ti = np.ascontiguousarray(mesh_arrays["tet_img"], dtype=np.int8)
     pv = np.ascontiguousarray(mesh_arrays["pri_v"], dtype=np.int64)
     pi = np.ascontiguousarray(mesh_arrays["pri_img"], dtype=np.int8)
-    keep += [xyz, tv, ti, pv, pi]
+    hv = np.ascontiguousarray(mesh_arrays.get("hex_v", np.zeros((0, 8))), dtype=np.int64)
+    hi = np.ascontiguousarray(mesh_arrays.get("hex_img", np.zeros((0, 8, 3))), dtype=np.int8)
+    keep += [xyz, tv, ti, pv, pi, hv, hi]
     d.n_vertices = len(xyz)
     d.xyz = _ptr(xyz, ctypes.c_double)
     d.n_tets = len(tv)
@@ -167,6 +184,9 @@ def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=
     d.n_prisms = len(pv)
     d.pri_v = _ptr(pv, ctypes.c_int64) if len(pv) else None
     d.pri_img = _ptr(pi, ctypes.c_int8) if len(pv) else None
+    d.n_hex = len(hv)
+    d.hex_v = _ptr(hv, ctypes.c_int64) if len(hv) else None
+    d.hex_img = _ptr(hi, ctypes.c_int8) if len(hv) else None
     for k in range(3):
         d.period[k] = float(mesh_arrays["period"][k])
     return d
@@ -232,8 +252,8 @@ class Mesh:
         _check(lib().fr_get_solution(self.h, etype, ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)), self.h)
 
     def rhs(self, u_ptrs, r_ptrs, stream=0):
-        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
-        R = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in r_ptrs])
+        U = _type_ptrs(u_ptrs)
+        R = _type_ptrs(r_ptrs)
         _check(lib().fr_rhs(self.h, U, R, ctypes.c_void_p(stream)), self.h)
 
     def rk_step(self, scheme, dt, n_steps, stream=0):
@@ -267,16 +287,16 @@ class Mesh:
 
     def project_to(self, dst, u_ptrs, v_ptrs, stream=0):
         """L2-project a state of this mesh onto mesh dst (same elements)."""
-        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
-        V = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in v_ptrs])
+        U = _type_ptrs(u_ptrs)
+        V = _type_ptrs(v_ptrs)
         _check(lib().fr_project(self.h, U, dst.h, V, ctypes.c_void_p(stream)), self.h)
 
     def closure_moments(self, u_ptrs, mom_ptr, stream=0):
-        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        U = _type_ptrs(u_ptrs)
         _check(lib().fr_closure_moments(self.h, U, ctypes.c_void_p(mom_ptr), ctypes.c_void_p(stream)), self.h)
 
     def closure_features(self, u_ptrs, stats_ptr, feat_ptr, stream=0):
-        U = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in u_ptrs])
+        U = _type_ptrs(u_ptrs)
         _check(lib().fr_closure_features(self.h, U, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(feat_ptr),
                                          ctypes.c_void_p(stream)), self.h)
 
@@ -284,8 +304,8 @@ class Mesh:
         _check(lib().fr_set_blocking(self.h, int(etype), int(op), int(cap), int(stage)), self.h)
 
     def closure_targets(self, a_ptrs, b_ptrs, stats_ptr, out_ptr, stream=0):
-        A = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in a_ptrs])
-        B = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(p or 0) for p in b_ptrs])
+        A = _type_ptrs(a_ptrs)
+        B = _type_ptrs(b_ptrs)
         _check(lib().fr_closure_targets(self.h, A, B, ctypes.c_void_p(stats_ptr or 0), ctypes.c_void_p(out_ptr),
                                         ctypes.c_void_p(stream)), self.h)
 

@@ -34,11 +34,14 @@ def test_library_exports_declared_symbols():
         assert ctypes.cast(getattr(so, name), ctypes.c_void_p).value
 
 
+def _hybrid(seed=2):
+    return inputs.hybrid_box(4, 3, 4, 2, 2, (6.0, 7.0, 5.5), jitter=0.12, seed=seed)
+
+
 @pytest.mark.parametrize("p", (1, 2, 3, 4))
 def test_operators_match_oracle(p):
-    arrays = inputs.small_mixed_box(nxy=3, n_pri_layers=2, n_tet_layers=2, jitter=0.1)
-    M = frlib.Mesh(arrays, p, system="ns", validate_only=True)
-    for t, name in enumerate(("tet", "pri")):
+    M = frlib.Mesh(_hybrid(), p, system="ns", validate_only=True)
+    for t, name in enumerate(frlib.TYPE_NAMES):
         R = elements.get(name, p)
         assert np.abs(M.operator(t, 0) - R.M0).max() < 1e-13
         for k in range(3):
@@ -47,11 +50,16 @@ def test_operators_match_oracle(p):
         assert np.abs(M.operator(t, 5)[0] - R.w).max() < 1e-13
 
 
-def test_upts_coords_match_oracle():
-    arrays = inputs.small_mixed_box(nxy=3, n_pri_layers=2, n_tet_layers=2, jitter=0.1, seed=3)
+@pytest.mark.parametrize("which", ["mixed", "hybrid"])
+def test_upts_coords_match_oracle(which):
+    arrays = (inputs.small_mixed_box(nxy=3, n_pri_layers=2, n_tet_layers=2, jitter=0.1, seed=3)
+              if which == "mixed" else _hybrid(3))
     M = frlib.Mesh(arrays, 3, validate_only=True)
     O = om.build_mesh(arrays, 3)
-    for t, name in enumerate(("tet", "pri")):
+    for t, name in enumerate(frlib.TYPE_NAMES):
+        if name not in O.types:
+            assert M.query(t)["nelem"] == 0
+            continue
         x = M.upts_coords(t)
         assert np.abs(x - np.transpose(O.types[name].x_upts, (1, 2, 0))).max() < 1e-13
         q = M.query(t)
@@ -63,6 +71,15 @@ def test_full_size_mesh_validates():
     M = frlib.Mesh(inputs.tgv_mixed_box(), 4, system="ns", validate_only=True)
     assert M.query(0)["nelem"] == 196608 and M.query(1)["nelem"] == 110592
     assert M.query(1)["nupts"] == 75 and M.query(1)["nfpts"] == 105
+
+
+def test_hex_box_sizes_validate():
+    """Table 2 sizes of the hexahedron at p = 4 and the element count of a
+    periodic hexahedral box."""
+    M = frlib.Mesh(inputs.hex_box(12, jitter=0.1), 4, system="ns", validate_only=True)
+    q = M.query(frlib.FR_HEX)
+    assert (q["nelem"], q["nupts"], q["nfpts"]) == (1728, 125, 150)
+    assert M.query(frlib.FR_TET)["nelem"] == 0 and M.query(frlib.FR_PRI)["nelem"] == 0
 
 
 def _expect(status, fn):
@@ -93,6 +110,18 @@ def test_error_codes():
     _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(bad, 2, validate_only=True))
     # unknown system / bad constants
     _expect(frlib.FR_ERR_INVALID_ARG, lambda: frlib.Mesh(good, 2, validate_only=True, gamma=0.5))
+    # inverted hexahedron: swap bottom and top
+    bad = {k: v.copy() for k, v in _hybrid().items()}
+    bad["hex_v"][5] = bad["hex_v"][5][[4, 5, 6, 7, 0, 1, 2, 3]]
+    bad["hex_img"][5] = bad["hex_img"][5][[4, 5, 6, 7, 0, 1, 2, 3]]
+    msg = _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(bad, 2, validate_only=True))
+    assert "hex 5" in msg
+    # a hexahedron face meeting two triangles is non-conforming: drop the
+    # prism layer between hexahedra and tets
+    hyb = _hybrid()
+    nz_pri = len(hyb["pri_v"]) // 2                      # z-prisms come first
+    bad = dict(hyb, pri_v=hyb["pri_v"][:nz_pri], pri_img=hyb["pri_img"][:nz_pri])
+    _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(bad, 2, validate_only=True))
     # validate-only meshes refuse device work
     M = frlib.Mesh(good, 2, validate_only=True)
     _expect(frlib.FR_ERR_INVALID_ARG, lambda: M.rk_step(frlib.FR_RK4, 1e-3, 1))

@@ -364,3 +364,20 @@ def test_closure_trained_along_trajectory_runs_stably():
     e = lambda r: float(np.sqrt(np.mean((r - rates4) ** 2) / np.mean(rates4 ** 2)))
     print(f"a-posteriori dissipation-rate error vs order 4: plain {e(plain):.3f}, closure {e(corr):.3f}",
           flush=True)
+
+
+def test_closure_refuses_hexahedra():
+    """The closure's neighbour stencil covers tets and prisms: on a mesh with
+    hexahedra the closure entry points report FR_ERR_UNSUPPORTED."""
+    frlib = _lib()
+    arrays = inputs.hybrid_box(4, 3, 4, 2, 2, (2 * np.pi,) * 3, jitter=0.1, seed=1)
+    M = frlib.Mesh(arrays, 1, system="ns", precision="fp32", mu=0.02)
+    net = frlib.MLP(seed=0)
+    stats = torch.ones(frlib.MLP_NSTATS, dtype=torch.float32, device="cuda")
+    ntot = sum(M.query(t)["nelem"] for t in range(3))
+    mom = torch.zeros((ntot, 20), dtype=torch.float32, device="cuda")
+    for call in (lambda: M.closure_attach(net, stats.data_ptr(), bf16_weights=True),
+                 lambda: M.closure_moments([0, 0, 0], mom.data_ptr())):
+        with pytest.raises(frlib.FrError) as ei:
+            call()
+        assert ei.value.status == frlib.FR_ERR_UNSUPPORTED

@@ -19,7 +19,7 @@ from paper_1409_0405_amd import inputs
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-NAMES = ("tet", "pri")
+NAMES = ("tet", "pri", "hex")
 
 
 def _lib():
@@ -41,7 +41,7 @@ def _round32(U):
 def _gpu_rhs(M, O, U):
     frlib = _lib()
     u, r = [], []
-    for t in (0, 1):
+    for t in range(len(NAMES)):
         if NAMES[t] in O.types:
             u.append(frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))))
         else:
@@ -51,7 +51,7 @@ def _gpu_rhs(M, O, U):
           [x.data_ptr() if x is not None else 0 for x in r])
     torch.cuda.synchronize()
     out = {}
-    for t in (0, 1):
+    for t in range(len(NAMES)):
         if r[t] is not None:
             ne = O.types[NAMES[t]].nelem
             out[NAMES[t]] = np.transpose(r[t][:, :, :ne].cpu().numpy().astype(np.float64), (2, 0, 1))
@@ -101,6 +101,11 @@ CASES = [
     ("mixed", 4, "euler", inputs.taylor_green, {"mach": 0.1}, 0.0),
     ("prisms", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("prisms", 1, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("hex", 2, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("hex", 4, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("hybrid", 1, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("hybrid", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("hybrid", 4, "euler", inputs.taylor_green, {"mach": 0.1}, 0.0),
 ]
 
 
@@ -110,6 +115,13 @@ def _mesh(kind, seed=0):
     if kind == "prisms":
         # prisms only (the tet type is empty): 5 x 5 x 2 triangles x 3 layers = 150
         return inputs.mixed_box(5, 5, 3, 0, (2 * math.pi,) * 3, jitter=0.1, seed=seed)
+    if kind == "hex":
+        # 5^3 = 125 jittered hexahedra (ragged against 64)
+        return inputs.hex_box(5, jitter=0.12, seed=seed)
+    if kind == "hybrid":
+        # all three types, conforming: 36 hexahedra, 144 prisms (both
+        # orientations), 216 tets
+        return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed)
     # 4 x 4 x (3 + 3): 96 prisms and 288 tets -> ragged against 64
     return inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=seed)
 
@@ -151,12 +163,13 @@ def test_rhs_fp32_parity(case):
     assert (err < tol).all(), (err, tol)
 
 
-@pytest.mark.parametrize("p,system", [(2, "ns"), (4, "ns"), (3, "euler")])
-def test_interface_intermediates_fp64(p, system):
+@pytest.mark.parametrize("kind,p,system", [("mixed", 2, "ns"), ("mixed", 4, "ns"), ("mixed", 3, "euler"),
+                                           ("hybrid", 3, "ns")])
+def test_interface_intermediates_fp64(kind, p, system):
     """State at flux points, common normal flux and (NS) the gradient at flux
     points, element by element."""
-    print(f"intermediates p{p} {system}", flush=True)
-    arrays = _mesh("mixed", seed=2)
+    print(f"intermediates {kind} p{p} {system}", flush=True)
+    arrays = _mesh(kind, seed=2)
     O = om.build_mesh(arrays, p)
     prm = fr.Params(system=system, mu=0.02)
     U = _state(O, inputs.taylor_green, 4, mach=0.3)
@@ -166,7 +179,8 @@ def test_interface_intermediates_fp64(p, system):
     _gpu_rhs(M, O, U)
     items = [(0, "Uf", 5), (1, "Fn", 5)] + ([(2, "Qf", 15)] if system == "ns" else [])
     for which, key, nv in items:
-        for t, n in enumerate(NAMES):
+        for n in O.types:
+            t = NAMES.index(n)
             q = M.query(t)
             buf = torch.zeros((q["nfpts"], nv, q["ld"]), dtype=torch.float64, device="cuda")
             M.intermediate(t, which, buf.data_ptr())
@@ -209,6 +223,35 @@ def test_rk_steps_fp64_vortex(scheme):
     err = np.sqrt((d ** 2).sum(axis=(0, 1)) / (Uo["tet"] ** 2).sum(axis=(0, 1)))
     print("  field errors", err, flush=True)
     assert (err < 1e-12).all(), err
+
+
+def test_rk45_steps_fp64_hybrid():
+    """Five fixed RK45[2R+] steps of NS on the three-type box (p = 2) against
+    the oracle's stepper, every type to 1e-12."""
+    frlib = _lib()
+    print("rk45 hybrid fp64", flush=True)
+    arrays = _mesh("hybrid", seed=1)
+    p, mu, nsteps = 2, 0.02, 5
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system="ns", mu=mu)
+    U0 = _state(O, inputs.taylor_green, 5, mach=0.3)
+    dt = 0.2 * (2 * math.pi / 6) / ((1 + 1 / 0.3) * (2 * p + 1))
+    Uo = rk.run(rk.rk45_step, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp64", mu=mu, check_finite=True)
+    for n in O.types:
+        t = NAMES.index(n)
+        M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U0[n], (1, 2, 0))).data_ptr())
+    M.rk_step(frlib.FR_RK45_2RP, dt, nsteps)
+    for n in O.types:
+        t = NAMES.index(n)
+        out = frlib.state_tensor(M, t)
+        M.get_solution(t, out.data_ptr())
+        torch.cuda.synchronize()
+        g = np.transpose(out[:, :, :O.types[n].nelem].cpu().numpy(), (2, 0, 1))
+        d = g - Uo[n]
+        err = np.sqrt((d ** 2).sum(axis=(0, 1)) / (Uo[n] ** 2).sum(axis=(0, 1)))
+        print(f"  {n} field errors", err, flush=True)
+        assert (err < 1e-12).all(), (n, err)
 
 
 def test_rk45_adaptive_fp64_vortex():
@@ -256,7 +299,8 @@ def test_rk45_adaptive_fp32_ns_lands_on_t_end():
     O = om.build_mesh(arrays, 2)
     U = _round32(_state(O, inputs.taylor_green, 3, mach=0.3))
     M = frlib.Mesh(arrays, 2, system="ns", precision="fp32", mu=0.02, check_finite=True)
-    for t, n in enumerate(NAMES):
+    for n in O.types:
+        t = NAMES.index(n)
         u = frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0)))
         M.set_solution(t, u.data_ptr())
     state = [0.0, 1e-3, 1.0]
@@ -268,18 +312,20 @@ def test_rk45_adaptive_fp32_ns_lands_on_t_end():
         M.rk45_adaptive(0.1, [0.05, -1.0, 1.0], 1e-5, 1e-5)      # dt must be positive
 
 
-def test_reductions_fp64():
+@pytest.mark.parametrize("kind", ["mixed", "hybrid"])
+def test_reductions_fp64(kind):
     """FP64 global sums: integral of U and of R(U) (discrete conservation) and
     the kinetic-energy rate, against the oracle's quadrature."""
     frlib = _lib()
-    arrays = _mesh("mixed", seed=5)
+    arrays = _mesh(kind, seed=5)
     p, mu = 3, 0.02
     O = om.build_mesh(arrays, p)
     prm = fr.Params(system="ns", mu=mu)
     U = _state(O, inputs.taylor_green, 9, mach=0.3)
     Ro = fr.rhs(O, U, prm)
     M = frlib.Mesh(arrays, p, system="ns", precision="fp64", mu=mu)
-    for t, n in enumerate(NAMES):
+    for n in O.types:
+        t = NAMES.index(n)
         u = frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0)))
         M.set_solution(t, u.data_ptr())
     torch.cuda.synchronize()
@@ -295,11 +341,12 @@ def test_reductions_fp64():
     assert abs(dke - reduce.kinetic_energy_rate(O, U, Ro)) < 1e-9 * abs(dke)
 
 
-def test_freestream_and_conservation_fp32_mixed():
+@pytest.mark.parametrize("kind", ["mixed", "hybrid"])
+def test_freestream_and_conservation_fp32(kind):
     """Uniform flow gives zero residual (up to FP32 rounding of the flux
     magnitude); the FP64 conservation sum of R(U) vanishes."""
     frlib = _lib()
-    arrays = _mesh("mixed", seed=6)
+    arrays = _mesh(kind, seed=6)
     p = 4
     O = om.build_mesh(arrays, p)
     M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.01)

@@ -18,11 +18,14 @@ from paper_1409_0405_amd import inputs
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-NAMES = ("tet", "pri")
+NAMES = ("tet", "pri", "hex")
 
 
-def _setup(p, mach=0.3, seed=3):
-    arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=0)
+def _setup(p, mach=0.3, seed=3, kind="mixed"):
+    if kind == "hybrid":
+        arrays = inputs.hybrid_box(6, 4, 6, 3, 3, (2 * np.pi,) * 3, jitter=0.1, seed=0)
+    else:
+        arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=0)
     O = om.build_mesh(arrays, p)
     U = fr.initial_state(O, inputs.taylor_green, mach=mach)
     for n in U:
@@ -32,12 +35,13 @@ def _setup(p, mach=0.3, seed=3):
 
 def _rhs(M, O, U):
     from paper_1409_0405_amd import frlib
-    u = [frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))) for t in (0, 1)]
-    r = [frlib.state_tensor(M, t) for t in (0, 1)]
-    M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r])
+    ts = [NAMES.index(n) for n in O.types]
+    u = {t: frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))) for t in ts}
+    r = {t: frlib.state_tensor(M, t) for t in ts}
+    M.rhs([u[t].data_ptr() if t in u else 0 for t in range(3)], [r[t].data_ptr() if t in r else 0 for t in range(3)])
     torch.cuda.synchronize()
     return {NAMES[t]: np.transpose(r[t][:, :, :O.types[NAMES[t]].nelem].cpu().numpy().astype(np.float64),
-                                   (2, 0, 1)) for t in (0, 1)}
+                                   (2, 0, 1)) for t in ts}
 
 
 def _err(G, R):
@@ -50,11 +54,12 @@ def _err(G, R):
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
-@pytest.mark.parametrize("p,system", [(1, "ns"), (2, "euler"), (3, "ns"), (4, "ns")])
-def test_split_rhs_parity(prec, p, system):
+@pytest.mark.parametrize("kind,p,system", [("mixed", 1, "ns"), ("mixed", 2, "euler"), ("mixed", 3, "ns"),
+                                           ("mixed", 4, "ns"), ("hybrid", 4, "ns")])
+def test_split_rhs_parity(prec, kind, p, system):
     from paper_1409_0405_amd import frlib
-    print(f"{prec} p{p} {system}", flush=True)
-    arrays, O, U = _setup(p)
+    print(f"{prec} {kind} p{p} {system}", flush=True)
+    arrays, O, U = _setup(p, kind=kind)
     prm = fr.Params(system=system, mu=0.02)
     Ro = fr.rhs(O, U, prm)
     M = frlib.Mesh(arrays, p, system=system, precision=prec, mu=0.02)
@@ -73,11 +78,11 @@ def test_split_rk45_steps(prec):
     dt = 0.3 * (2 * np.pi / 4 / 3) / ((1 + 1 / 0.3) * (2 * p + 1))
     Uo = rk.run(rk.rk45_step, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
     M = frlib.Mesh(arrays, p, system="ns", precision=prec, mu=mu, check_finite=True)
-    for t, n in enumerate(NAMES):
+    for t, n in enumerate(NAMES[:2]):
         M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U0[n], (1, 2, 0))).data_ptr())
     M.rk_step(frlib.FR_RK45_2RP, dt, nsteps)
     G = {}
-    for t, n in enumerate(NAMES):
+    for t, n in enumerate(NAMES[:2]):
         out = frlib.state_tensor(M, t)
         M.get_solution(t, out.data_ptr())
         torch.cuda.synchronize()
