@@ -57,9 +57,11 @@ def kernel_model(mesh, system):
     out = {}
     s = 4
     npairs = 0
-    for t, name in ((0, "tet"), (1, "pri")):
+    for t, name in ((0, "tet"), (1, "pri"), (2, "hex")):
         q = mesh.query(t)
         E, nu, nf = q["nelem"], q["nupts"], q["nfpts"]
+        if not E:
+            continue
         npairs += E * nf
         cols5 = 5 * E
         ops = {"interp": (nf, nu, cols5), "div": (nu, 3 * nu + nf, cols5)}
@@ -68,7 +70,7 @@ def kernel_model(mesh, system):
             ops["gradinterp"] = (nf, nu, 3 * cols5)
         for op, (M, K, n) in ops.items():
             out[f"{op}_{name}"] = {"flops": 2.0 * M * K * n, "bytes": s * (K + M) * n}
-        ng = 9 if t == 0 else 15
+        ng = (9, 15, 21)[t]
         pt = (5 + (15 + 15 if ns else 0) + 15) * nu * E * s + ng * E * s
         out[f"upts_{name}"] = {"flops": 0.0, "bytes": float(pt)}
         out[f"negdivconf_{name}"] = {"flops": 0.0, "bytes": float((5 + 5 + 5) * nu * E * s + ng * E * s)}
@@ -265,6 +267,85 @@ def batch_form(steps, warmup, cfl=0.2):
     return out
 
 
+def roofline_of(model, avg_s, k):
+    """Roofline entry of kernel class k from its algorithmic model and
+    average launch duration."""
+    mdl = model[k]
+    if mdl["flops"] and mdl["flops"] / mdl["bytes"] > RIDGE:
+        roof = {"bound": "mfma", "achieved": mdl["flops"] / avg_s / 1e12, "peak": 157.3, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": mdl["bytes"] / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    return roof
+
+
+def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=0.3, p=4):
+    """Another mesh of the same physics (NS Taylor-Green, p = 4, FP32,
+    autotuned): RK45[2R+] steps timed like the main workload, then a
+    per-kernel profile and the dominant kernel's roofline."""
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import frlib, inputs
+    m = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=mu, prandtl=pr, stream=stream)
+    report = m.autotune(stream)
+    print(f"autotune {name}: {report}", file=sys.stderr, flush=True)
+    types, dof, counts = [], 0, {}
+    for t in range(3):
+        q = m.query(t)
+        if not q["nelem"]:
+            continue
+        x = m.upts_coords(t)
+        U = np.transpose(inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=mach), (1, 0, 2)).astype(np.float32)
+        u = frlib.to_device_state(m, t, U)
+        m.set_solution(t, u.data_ptr(), stream)
+        torch.cuda.synchronize()
+        del u
+        types.append(t)
+        dof += 5 * q["nupts"] * q["nelem"]
+        counts[frlib.TYPE_NAMES[t]] = q["nelem"]
+    dt = cfl * h_ref / ((1.0 + 1.0 / mach) * (2 * p + 1))
+
+    def step():
+        m.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
+        return m.reduce(frlib.FR_RED_INT_U, stream)
+    i0 = step()
+    for _ in range(max(warmup - 1, 0)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        i1 = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"elements": counts, "n_dof": dof, "ms_per_step": 1e3 * el / steps,
+           "value": 5.0 * dof * steps / el / 1e9, "unit": "GDOF/s per RHS",
+           "finite": bool(np.all(np.isfinite(i1))),
+           "mass_energy_drift": float(np.max(np.abs(i1 - i0)[[0, 4]] / np.abs(i0)[[0, 4]]))}
+    nprof = max(3, min(steps, 10))
+    m.profile(True)
+    for _ in range(nprof):
+        m.rk_step(frlib.FR_RK45_2RP, dt, 1, stream)
+    prof = m.profile_read()
+    m.profile(False)
+    model = kernel_model(m, "ns")
+    rows = sorted(((ms, k, cnt) for k, (ms, cnt) in prof.items() if cnt), reverse=True)
+    tot = sum(r[0] for r in rows)
+    kern = {}
+    for ms, k, cnt in rows:
+        avg = ms / cnt * 1e-3
+        kern[k] = {"share": ms / tot, "avg_us": avg * 1e6}
+        if k in model:
+            kern[k].update(roofline_of(model, avg, k))
+    ms, k, cnt = rows[0]
+    out["roofline"] = dict(roofline_of(model, ms / cnt * 1e-3, k), kernel=k, avg_launch_us=1e3 * ms / cnt,
+                           share_of_step=ms / tot)
+    out["kernels"] = kern
+    m.close()
+    del m
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +359,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--no-hex", action="store_true", help="skip the hexahedral and three-type workloads")
     ap.add_argument("--variants", action="store_true",
                     help="time every product variant of the prism corrected-gradient "
                          "operator on this workload (one JSON line) instead of the bench")
@@ -522,6 +604,23 @@ def main():
         forms = forms or {}
         forms["batch_512_euler"] = bf
         print(f"batch: {bf}", file=sys.stderr, flush=True)
+
+    if not args.no_hex:
+        mesh.close()
+        torch.cuda.empty_cache()
+        forms = forms or {}
+        L = 2 * math.pi
+        hx = workload_form("hex", inputs.hex_box(50, jitter=0.10, seed=0), L / 50, args.steps, args.warmup,
+                           mach, mu, pr, stream)
+        hx["workload"] = "periodic [0,2pi)^3, 50^3 hexahedra (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32"
+        forms["hex_p4"] = hx
+        print(f"hex: {hx}", file=sys.stderr, flush=True)
+        hy = workload_form("hybrid", inputs.hybrid_box(48, 48, 48, 24, 24, (L, L, L), jitter=0.10, seed=0),
+                           L / 48, args.steps, args.warmup, mach, mu, pr, stream)
+        hy["workload"] = ("periodic [0,2pi)^3, 48^3 cells: hexahedra | z-prisms below, x-prisms | Kuhn tets "
+                          "above (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32")
+        forms["hybrid_p4"] = hy
+        print(f"hybrid: {hy}", file=sys.stderr, flush=True)
 
     peaks = None
     if not args.no_peaks:
