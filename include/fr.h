@@ -144,7 +144,9 @@ fr_status fr_upts_coords(fr_mesh mesh, int32_t etype, double *xyz_host);
 /* Copy a host-built FP64 operator of one element type to a host array of
  * rows*cols doubles, row-major.  which: 0 = M0 (n_fpts x n_upts), 1..3 =
  * gradient d/dxi_k (n_upts x n_upts), 4 = correction lift L (n_upts x n_fpts),
- * 5 = quadrature weights (1 x n_upts).  out may be NULL to query the shape. */
+ * 5 = quadrature weights (1 x n_upts), 6 = outward unit normals of the
+ * reference faces at the flux points (n_fpts x 3).  out may be NULL to query
+ * the shape. */
 fr_status fr_operator(fr_mesh mesh, int32_t etype, int32_t which, double *out,
                       int32_t *rows, int32_t *cols);
 
@@ -240,9 +242,13 @@ fr_status fr_autotune(fr_mesh mesh, void *stream);
  * FP64 and split BF16, 1..2 split FP16); stage 0 / 3 = direct B loads with
  * 2 / 4 K steps in flight, 1 / 2 = B staged through LDS in chunks of 4 / 8 K
  * steps (FP32 only, at most 8 row groups), 4 = the operator's row-group slice
- * held in LDS for four panels (FP32 only, at most 64 KiB of it).  The split
- * forms have stage 0 (each wavefront splits its B panel) and 1 (the panel's
- * row groups, at most 8 and 64 KiB of parts, share the split B in LDS).  Results are bitwise the same for every variant.  Synchronous
+ * held in LDS for four panels (FP32 only, at most 64 KiB of it), 5 = direct
+ * loads over only the K steps where the row group's operator fragments are
+ * nonzero (the structural zeros of prisms and hexahedra; at most 4 row
+ * blocks per wavefront).  The split forms have stage 0 (each wavefront splits
+ * its B panel) and 1 (the panel's row groups, at most 8 and 64 KiB of parts,
+ * share the split B in LDS).  Results are bitwise the same for every variant
+ * (for finite states).  Synchronous
  * (uploads the operator); FR_ERR_UNSUPPORTED for a combination the form
  * does not have. */
 fr_status fr_set_blocking(fr_mesh mesh, int32_t etype, int32_t op, int32_t cap, int32_t stage);

@@ -172,19 +172,64 @@ void prof_end(fr_mesh m, size_t i, int cls, hipStream_t s) {
         prof_end(m, pi_, cls, s);              \
     } while (0)
 
-// Fragment order for the MFMA product kernel (see frd::Op).
+// Fragment order for the MFMA product kernel (see frd::Op).  Stage 5 also
+// fills idx = [koff (nmg + 1) | klist] and compacts f per row group.
+// Row order for the step-list product: groups of `gsize` rows filled
+// greedily, each next row the one adding the fewest K steps (of 4 columns)
+// to the group's union (ties: lowest row), so that rows touching the same
+// columns (one layer of a prism, one line of a hexahedron) share a group.
+std::vector<int> cluster_rows(const std::vector<double> &A, int M, int K, int gsize) {
+    const int Kb = (K + 3) / 4;
+    std::vector<std::vector<char>> mask(M, std::vector<char>(Kb, 0));
+    for (int r = 0; r < M; ++r)
+        for (int c = 0; c < K; ++c)
+            if (A[size_t(r) * K + c] != 0.0) mask[r][c / 4] = 1;
+    std::vector<char> used(M, 0);
+    std::vector<int> order;
+    while (int(order.size()) < M) {
+        std::vector<char> uni(Kb, 0);
+        for (int n = 0; n < gsize && int(order.size()) < M; ++n) {
+            int best = -1, best_add = 1 << 30;
+            for (int r = 0; r < M; ++r) {
+                if (used[r]) continue;
+                int add = 0;
+                for (int kb = 0; kb < Kb; ++kb) add += mask[r][kb] && !uni[kb];
+                if (add < best_add) {
+                    best_add = add;
+                    best = r;
+                }
+            }
+            used[best] = 1;
+            order.push_back(best);
+            for (int kb = 0; kb < Kb; ++kb) uni[kb] |= mask[best][kb];
+        }
+    }
+    return order;
+}
+
 template <typename T>
-frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &f, int cap = 0,
-                    int stage = 0) {
+frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T> &f, int cap = 0,
+                    int stage = 0, std::vector<int32_t> *idx = nullptr) {
     frd::Op<T> op;
     op.M = M;
     op.stage = stage;
+    // stage 5: rows permuted into clustered groups (perm[r'] = source row)
+    std::vector<int> perm;
+    std::vector<double> Aperm;
+    const std::vector<double> &A = stage == 5 ? Aperm : A_in;
     // an even number of K steps; a multiple of the chunk (4 or 8 steps) when
     // the B panel is staged through LDS
     const int kmul = (stage == 2 || stage == 4) ? 8 : (stage == 1 || stage == 3) ? 4 : 2;
     op.Kb = ((K + 3) / 4 + kmul - 1) / kmul * kmul;
     frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
+    if (stage == 5) {
+        perm = cluster_rows(A_in, M, K, 16 * op.mbw);
+        Aperm.resize(size_t(M) * K);
+        for (int r = 0; r < M; ++r)
+            std::copy(A_in.begin() + size_t(perm[r]) * K, A_in.begin() + size_t(perm[r] + 1) * K,
+                      Aperm.begin() + size_t(r) * K);
+    }
     f.assign(size_t(Mb) * op.Kb * 64, T(0));
     // stage 4 groups four K steps per lane: [mb][Kb / 4][lane][4]
     for (int mb = 0; mb < Mb; ++mb)
@@ -195,7 +240,61 @@ frd::Op<T> fragment(const std::vector<double> &A, int M, int K, std::vector<T> &
                                              : (size_t(mb) * op.Kb + kb) * 64 + l;
                 if (r < M && c < K) f[at] = T(A[size_t(r) * K + c]);
             }
+    if (stage == 5) {
+        std::vector<T> dense;
+        dense.swap(f);
+        std::vector<int32_t> koff(op.nmg + 1), klist;
+        for (int g = 0; g < op.nmg; ++g) {
+            koff[g] = int32_t(klist.size());
+            std::vector<int> ks;
+            for (int kb = 0; kb < op.Kb; ++kb) {
+                bool nz = false;
+                for (int m = 0; m < op.mbw && !nz; ++m)
+                    for (int l = 0; l < 64 && !nz; ++l)
+                        nz = dense[(size_t(g * op.mbw + m) * op.Kb + kb) * 64 + l] != T(0);
+                if (nz) ks.push_back(kb);
+            }
+            const size_t nreal = ks.size();
+            if (ks.empty()) ks.push_back(0);
+            while (ks.size() % 2) ks.push_back(ks.back());
+            for (size_t j = 0; j < ks.size(); ++j) {
+                klist.push_back(ks[j]);
+                for (int m = 0; m < op.mbw; ++m)
+                    for (int l = 0; l < 64; ++l)
+                        f.push_back(j < nreal ? dense[(size_t(g * op.mbw + m) * op.Kb + ks[j]) * 64 + l] : T(0));
+            }
+        }
+        koff[op.nmg] = int32_t(klist.size());
+        if (idx) {
+            idx->assign(koff.begin(), koff.end());
+            idx->insert(idx->end(), klist.begin(), klist.end());
+            for (int r = 0; r < Mb * 16; ++r) idx->push_back(r < M ? perm[r] : -1);
+        }
+    }
     return op;
+}
+
+// Device copy of a fragment array (and, stage 5, its step lists); the
+// allocations are appended to `allocs`.
+template <typename T>
+hipError_t upload_op(frd::Op<T> &op, const std::vector<T> &f, const std::vector<int32_t> &idx,
+                     std::vector<void *> &allocs) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(f.size(), 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    allocs.push_back(p);
+    if ((e = hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    op.frag = static_cast<T *>(p);
+    if (op.stage == 5) {
+        if ((e = hipMalloc(&p, idx.size() * sizeof(int32_t))) != hipSuccess) return e;
+        allocs.push_back(p);
+        if ((e = hipMemcpy(p, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        op.koff = static_cast<int32_t *>(p);
+        op.klist = op.koff + op.nmg + 1;
+        op.rowmap = op.klist + idx[op.nmg];
+    }
+    return hipSuccess;
 }
 
 // 16-bit parts of an operator for the split-precision product kernel (see
@@ -871,10 +970,11 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             frd::OpSplit best_sop;
             std::vector<std::pair<int, int>> cands;
             for (int cap : caps)
-                for (int stage = 0; stage < (split ? 2 : 5); ++stage) {
+                for (int stage = 0; stage < (split ? 2 : 6); ++stage) {
                     if (sizeof(T) != 4 && (stage == 1 || stage == 2 || stage == 4)) continue;
                     int nmg, mbw;
                     frd::row_groups(c.M, cap, nmg, mbw);
+                    if (stage == 5 && mbw > 4) continue;
                     if (split) {
                         if (stage == 1 && (nmg > 8 || nmg * (fmt == 2 ? 2 : 3) * 4096 > 65536)) continue;
                         cands.push_back({cap, stage});
@@ -902,12 +1002,9 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                     }
                 } else {
                     std::vector<T> f;
-                    op = fragment<T>(*c.A, c.M, c.K, f, cap, stage);
-                    void *p;
-                    FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
-                    FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
-                    op.frag = static_cast<T *>(p);
-                    mine.push_back(p);
+                    std::vector<int32_t> idx;
+                    op = fragment<T>(*c.A, c.M, c.K, f, cap, stage, &idx);
+                    FR_HIP(m, upload_op(op, f, idx, mine));
                 }
                 auto run = [&]() -> hipError_t {
                     if constexpr (std::is_same<T, float>::value) {
@@ -1128,6 +1225,7 @@ fr_status fr_operator(fr_mesh m, int32_t etype, int32_t which, double *out, int3
         case 1: case 2: case 3: src = R.G.data() + size_t(which - 1) * R.nu * R.nu; r = R.nu; c = R.nu; break;
         case 4: src = R.L.data(); r = R.nu; c = R.nf; break;
         case 5: src = R.w.data(); r = 1; c = R.nu; break;
+        case 6: src = R.nref.data(); r = R.nf; c = 3; break;
         default: return fail(m, FR_ERR_INVALID_ARG, "unknown operator");
     }
     if (rows) *rows = r;
@@ -1277,16 +1375,15 @@ fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
     const bool lds = stage == 1 || stage == 2 || stage == 4;
     if (lds && sizeof(T) != 4) return fail(m, FR_ERR_UNSUPPORTED, "LDS staging is for the FP32 product only");
     std::vector<T> f;
-    frd::Op<T> o = fragment<T>(*A, M, K, f, cap, stage);
+    std::vector<int32_t> idx;
+    frd::Op<T> o = fragment<T>(*A, M, K, f, cap, stage, &idx);
     if ((stage == 1 || stage == 2) && o.nmg > 8)
         return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
     if (stage == 4 && size_t(o.mbw) * o.Kb * 256 > 65536)
         return fail(m, FR_ERR_UNSUPPORTED, "operator slice too large for LDS");
-    void *p;
-    FR_HIP(m, hipMalloc(&p, f.size() * sizeof(T)));
-    d.allocs.push_back(p);
-    FR_HIP(m, hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice));
-    o.frag = static_cast<T *>(p);
+    if (stage == 5 && o.mbw > 4)
+        return fail(m, FR_ERR_UNSUPPORTED, "the step-list product takes at most 4 row blocks per wavefront");
+    FR_HIP(m, upload_op(o, f, idx, d.allocs));
     frd::Op<T> *dst[4] = {&D.Aint, &D.Agrad, &D.Agint, &D.Adiv};
     *dst[op] = o;
     return FR_OK;
@@ -1297,8 +1394,8 @@ extern "C" {
 
 fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
-    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 4)
-        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..4");
+    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 5)
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..5");
     if (!m->host.t[etype].nelem) return FR_OK;
     return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
                                    : set_blocking_impl<double>(m, etype, op, cap, stage);

@@ -24,9 +24,16 @@ struct Op {
     // B staged through LDS in chunks of 4 / 8 K steps (nmg <= 8); 4 (FP32
     // only) = the row group's A slice sits in LDS, shared by four panels
     // (fragments grouped by four K steps, mbw * Kb * 256 bytes <= 64 KiB).
-    // Kb is a multiple of 2, 4, 8, 4, 8 respectively.  All variants give
-    // identical bits.
+    // Kb is a multiple of 2, 4, 8, 4, 8 respectively.  5 = like 0, but each
+    // row group walks only the K steps where one of its fragments is nonzero:
+    // klist[koff[g] .. koff[g+1]) lists them (padded to an even count with
+    // zero fragments), and frag holds the group's fragments compacted in that
+    // order, [step][mbw][lane] (mbw <= 4).  The rows are permuted so that
+    // rows touching the same columns share a group: fragment row r' is
+    // operator row rowmap[r'] (-1 for padding).  All variants give identical
+    // bits for finite B (skipped products are exact zeros).
     int stage = 0;
+    const int32_t *klist = nullptr, *koff = nullptr, *rowmap = nullptr;
 };
 
 // Row grouping of an M-row operator: at most `cap` blocks of 16 rows per

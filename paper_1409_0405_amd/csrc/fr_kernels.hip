@@ -160,6 +160,89 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Operator product over the nonzero K steps of each row group only.  The
+// operators of tensor-product elements are mostly structural zeros (a row of
+// a hexahedron's derivative touches one line of points, a prism's in-layer
+// derivative one triangle layer), so a row group of MBW x 16 rows needs only
+// a fraction of the K steps: the group's step list (shared by the wavefront,
+// read through scalar loads) drives the same pipelined loop as opmul_kernel
+// with D = 2 steps in flight, over fragments stored compacted per group.
+// Rows are grouped by the columns they touch and written back through a row
+// map.  The products left out are exact zeros, so every output keeps the bits
+// of the dense kernels.
+// ---------------------------------------------------------------------------
+template <typename T, int MBW, int TAG>
+__global__ __launch_bounds__(256) void opmul_sparse_kernel(Op<T> A, const T *__restrict__ B1,
+                                                           int64_t ldb1, int K1,
+                                                           const T *__restrict__ B2, int64_t ldb2,
+                                                           int K2, T *__restrict__ C, int64_t ldc,
+                                                           int64_t npanels, int nmg) {
+    using v4 = typename Vec4<T>::type;
+    constexpr int D = 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t panel = wid / nmg;
+    const int mg = int(wid - panel * nmg);
+    if (panel >= npanels) return;
+    const int mb0 = mg * MBW;
+    const int64_t col = panel * 64 + 4 * (lane & 15);
+    const int krow = lane >> 4;
+    const int K = K1 + K2;
+    const int s0 = A.koff[mg];
+    const int ns = A.koff[mg + 1] - s0;       // even, >= 2
+    const int32_t *__restrict__ kl = A.klist + s0;
+
+    auto bptr = [&](int kb) -> const v4 * {
+        const int k = min(4 * kb + krow, K - 1);
+        const T *p = k < K1 ? B1 + int64_t(k) * ldb1 : B2 + int64_t(k - K1) * ldb2;
+        return reinterpret_cast<const v4 *>(p + col);
+    };
+
+    v4 acc[MBW][4];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = v4{0, 0, 0, 0};
+
+    const T *Af = A.frag + size_t(s0) * MBW * 64 + lane;
+    T a[D][MBW];
+    v4 b[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        b[d] = opaque(*bptr(kl[d]));
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) a[d][m] = opaque(Af[(size_t(d) * MBW + m) * 64]);
+    }
+    for (int st = 0; st < ns; st += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) {
+                acc[m][0] = mfma16(a[d][m], b[d][0], acc[m][0]);
+                acc[m][1] = mfma16(a[d][m], b[d][1], acc[m][1]);
+                acc[m][2] = mfma16(a[d][m], b[d][2], acc[m][2]);
+                acc[m][3] = mfma16(a[d][m], b[d][3], acc[m][3]);
+            }
+            const int sn = min(st + d + D, ns - 1);
+            b[d] = *bptr(kl[sn]);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) a[d][m] = Af[(size_t(sn) * MBW + m) * 64];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = A.rowmap[16 * (mb0 + m) + acc_row<T>(krow, r)];
+            if (row >= 0) {
+                v4 out = v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+                *reinterpret_cast<v4 *>(C + int64_t(row) * ldc + col) = out;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP32 operator product with the B panel staged through LDS.  One workgroup
 // per 64-column panel and one wavefront per row group (nmg waves): the group
 // loads B cooperatively in chunks of KS K steps (4 KS rows x 64 columns,
@@ -1053,6 +1136,19 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
     }
     const int64_t nwaves = npanels * nmg;
     const dim3 grid(xcd_grid((nwaves + 3) / 4)), block(256);
+    if (A.stage == 5) {
+        if (!A.klist || !A.koff || !A.rowmap) return hipErrorInvalidValue;
+#define FR_SPARSE(w)                                                                                       \
+    case w:                                                                                                \
+        opmul_sparse_kernel<T, w, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+        break;
+        switch (mbw) {
+            FR_SPARSE(1) FR_SPARSE(2) FR_SPARSE(3) FR_SPARSE(4)
+            default: return hipErrorInvalidValue;
+        }
+#undef FR_SPARSE
+        return hipGetLastError();
+    }
 #define FR_MBW(w)                                                                                \
     case w:                                                                                      \
         if (A.stage == 3)                                                                        \

@@ -514,6 +514,20 @@ RefOps build_ref(int etype, int p) {
     }
 
     auto todbl = [](const std::vector<ld> &v) { return std::vector<double>(v.begin(), v.end()); };
+    // Entries that vanish analytically (the tensor structure of prisms and
+    // hexahedra, symmetries of the point sets) come out of the Vandermonde
+    // route as rounding residue below 1e-12 of the operator's largest entry,
+    // while every genuine entry is above 1e-4 of it: set the residue to zero
+    // so that the structural zeros are exact.
+    auto chop = [](std::vector<ld> &v, size_t begin, size_t end) {
+        ld mx = 0;
+        for (size_t i = begin; i < end; ++i) mx = std::max(mx, std::fabs(v[i]));
+        for (size_t i = begin; i < end; ++i)
+            if (std::fabs(v[i]) <= ld(1e-10) * mx) v[i] = 0;
+    };
+    chop(M0, 0, M0.size());
+    for (int k = 0; k < 3; ++k) chop(G, size_t(k) * nu * nu, size_t(k + 1) * nu * nu);
+    chop(L, 0, L.size());
     R.upts = todbl(up);
     R.fpts = todbl(fp);
     R.M0 = todbl(M0);

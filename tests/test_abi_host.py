@@ -48,6 +48,7 @@ def test_operators_match_oracle(p):
             assert np.abs(M.operator(t, 1 + k) - R.G[k]).max() < 5e-13
         assert np.abs(M.operator(t, 4) - R.L).max() < 1e-12
         assert np.abs(M.operator(t, 5)[0] - R.w).max() < 1e-13
+        assert np.abs(M.operator(t, 6) - R.norm_ref).max() < 1e-15
 
 
 @pytest.mark.parametrize("which", ["mixed", "hybrid"])

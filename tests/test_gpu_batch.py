@@ -143,41 +143,50 @@ def test_autotune_keeps_results_bitwise():
         assert torch.equal(r0[t], r1[t])
 
 
-@pytest.mark.parametrize("p,prec", ((2, "fp32"), (4, "fp32"), (3, "fp64"), (4, "split_bf16"), (3, "split_fp16")))
-def test_every_product_variant_gives_identical_bits(p, prec):
-    """Row blocking (1..8 blocks of 16 rows per wavefront) and LDS staging of
-    the B panel (chunks of 4 or 8 K steps) do not change any output's
+@pytest.mark.parametrize("kind,p,prec", (("mixed", 2, "fp32"), ("mixed", 4, "fp32"), ("mixed", 3, "fp64"),
+                                         ("mixed", 4, "split_bf16"), ("mixed", 3, "split_fp16"),
+                                         ("hybrid", 4, "fp32"), ("hybrid", 3, "fp64")))
+def test_every_product_variant_gives_identical_bits(kind, p, prec):
+    """Row blocking (1..8 blocks of 16 rows per wavefront), LDS staging of
+    the B panel (chunks of 4 or 8 K steps), the LDS-resident operator slice
+    and the walk over nonzero K steps only do not change any output's
     accumulation order: every variant reproduces the default residual bit
-    for bit.  The mesh's element counts are ragged against 64."""
+    for bit.  The meshes' element counts are ragged against 64."""
     from paper_1409_0405_amd import frlib
-    arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=2)
+    if kind == "hybrid":
+        arrays = inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2)
+    else:
+        arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=2)
+    names = ("tet", "pri", "hex")
     O = om.build_mesh(arrays, p)
     U = fr.initial_state(O, inputs.taylor_green, mach=0.3)
     M = frlib.Mesh(arrays, p, system="ns", precision=prec, mu=0.02)
-    u = [frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0))) for t, n in enumerate(NAMES)]
-    r0 = [frlib.state_tensor(M, t) for t in (0, 1)]
-    r1 = [frlib.state_tensor(M, t) for t in (0, 1)]
-    M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r0])
+    ts = [names.index(n) for n in O.types]
+    u = {t: frlib.to_device_state(M, t, np.transpose(U[names[t]], (1, 2, 0))) for t in ts}
+    r0 = {t: frlib.state_tensor(M, t) for t in ts}
+    r1 = {t: frlib.state_tensor(M, t) for t in ts}
+    ptr = lambda d: [d[t].data_ptr() if t in d else 0 for t in range(3)]
+    M.rhs(ptr(u), ptr(r0))
     torch.cuda.synchronize()
     n = 0
-    stages = {"fp32": (0, 1, 2, 3, 4), "fp64": (0, 3)}.get(prec, (0, 1))
+    stages = {"fp32": (0, 1, 2, 3, 4, 5), "fp64": (0, 3, 5)}.get(prec, (0, 1))
     for stage in stages:
         for cap in (1, 2, 3, 4, 8):
             ok = True
-            for t in (0, 1):
+            for t in ts:
                 for op in range(4):
                     try:
                         M.set_blocking(t, op, cap, stage)
                     except frlib.FrError as e:
                         assert e.status == frlib.FR_ERR_UNSUPPORTED, str(e)
                         ok = False
-            print(f"p={p} stage={stage} cap={cap}", flush=True)
-            M.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r1])
+            print(f"{kind} p={p} stage={stage} cap={cap}", flush=True)
+            M.rhs(ptr(u), ptr(r1))
             torch.cuda.synchronize()
-            for t in (0, 1):
+            for t in ts:
                 assert torch.equal(r0[t], r1[t]), (stage, cap, t)
             n += ok
-    assert n >= {"fp32": 10, "fp64": 4}.get(prec, 2)
+    assert n >= {"fp32": 12, "fp64": 6}.get(prec, 2)
 
 
 def test_batched_problems_match_oracle_fp32():
