@@ -16,7 +16,9 @@ scheme evaluated here is (readings R2, R3, R5, R6):
   a4  Q_f = M0 Q                                   gradient at flux points (NS)
   a5  F~ = adj (F_inv(U) - F_vis(U, Q))            transformed flux
   a6  Fn* = s [Rusanov(U_L, U_R; n) + LDG viscous] common normal flux,
-      side L stores +, side R stores - (each with its own s = |adj^T n_ref|)
+      side L stores +, side R stores - (each with its own s = |adj^T n_ref|);
+      at boundary points (wall, far field) the boundary and ghost states of
+      reading R11 stand in for side R
   a7  R~ = sum_k G_k F~_k + L (Fn* - n_ref . M0 F~)
   a8  R = -R~ / J
 
@@ -45,6 +47,8 @@ class Params:
     prandtl: float = 0.71
     beta: float = 0.5
     tau: float = 0.1
+    t_wall: float = 1.0                                  # wall temperature p / rho
+    farfield: tuple = (1.0, 0.0, 0.0, 0.0, 1.0 / 1.4)    # free stream (rho, u, v, w, p)
 
 
 def to_lib(U, ld=None):
@@ -100,6 +104,11 @@ def rhs(mesh: Mesh, U: dict, prm: Params, want=None):
         Cg = np.zeros_like(Ufg)
         Cg[mesh.pair_L] = Cp
         Cg[mesh.pair_R] = Cp
+        if len(mesh.bnd_idx):
+            # boundary points: the common solution is the boundary state
+            Ub, _ = physics.boundary_states(Ufg[mesh.bnd_idx].T, mesh.bnd_nhat.T, mesh.bnd_kind,
+                                            prm.gamma, prm.t_wall, prm.farfield)
+            Cg[mesh.bnd_idx] = Ub.T
         C = _scatter(mesh, Cg)
         # a3: corrected reference gradient, then physical gradient
         Q = {}
@@ -135,6 +144,11 @@ def rhs(mesh: Mesh, U: dict, prm: Params, want=None):
     Fng = np.zeros_like(Ufg)
     Fng[mesh.pair_L] = (mesh.pair_sL * fn).T
     Fng[mesh.pair_R] = -(mesh.pair_sR * fn).T
+    if len(mesh.bnd_idx):
+        QB = np.moveaxis(_gather(mesh, Qf)[mesh.bnd_idx], 0, -1) if ns else None
+        fb = physics.boundary_flux(Ufg[mesh.bnd_idx].T, QB, mesh.bnd_nhat.T, mesh.bnd_kind, prm.gamma,
+                                   prm.t_wall, prm.farfield, ns, prm.mu, prm.prandtl, prm.tau)
+        Fng[mesh.bnd_idx] = (mesh.bnd_s * fb).T
     Fn = _scatter(mesh, Fng)
 
     # a7, a8: divergence plus correction, then -1/J

@@ -13,7 +13,9 @@ at every point from the mapping's derivatives.
 Conventions used here and documented for the library alike:
 * global element id is type-major: tets 0..n_tet-1, then prisms, then hexahedra;
 * a face pair's side L is the (global id, local face) that sorts first;
-* flux points pair by physical position (after periodic unwrapping).
+* flux points pair by physical position (after periodic unwrapping);
+* faces listed as boundary faces (wall or far field, reading R11) pair with
+  nothing: their flux points form the boundary point list.
 """
 from __future__ import annotations
 
@@ -97,6 +99,10 @@ class Mesh:
     pair_nhat: np.ndarray  # [n_pairs][3] unit normal pointing out of side L
     pair_sL: np.ndarray    # [n_pairs] |adj^T n_ref| on side L
     pair_sR: np.ndarray    # [n_pairs]
+    bnd_idx: np.ndarray = None    # [n_bnd] global flux index of boundary points
+    bnd_nhat: np.ndarray = None   # [n_bnd][3] outward unit normal
+    bnd_s: np.ndarray = None      # [n_bnd] |adj^T n_ref|
+    bnd_kind: np.ndarray = None   # [n_bnd] 1 wall, 2 far field
 
 
 def build_mesh(mesh_arrays, p, tol=1e-9):
@@ -126,12 +132,26 @@ def build_mesh(mesh_arrays, p, tol=1e-9):
         fpt_offset[name] = off
         off += tg.nelem * tg.ref.nfpts
 
+    # Boundary faces (reading R11): [n][4] = (type index, element, local face,
+    # kind); they take part in no pairing
+    bnd = set()
+    bfaces = np.asarray(mesh_arrays.get("bfaces", np.zeros((0, 4), np.int64)), dtype=np.int64).reshape(-1, 4)
+    for ti, e, fi, kind in bfaces:
+        name = TYPES[ti]
+        if name not in types or not (0 <= e < types[name].nelem) or not (0 <= fi < len(types[name].ref.faces)):
+            raise ValueError(f"boundary face ({ti}, {e}, {fi}) does not exist")
+        if kind not in (1, 2) or (name, e, fi) in bnd:
+            raise ValueError(f"bad or repeated boundary face ({ti}, {e}, {fi})")
+        bnd.add((name, int(e), int(fi)))
+
     # Face matching by sorted global vertex ids
     faces = {}
     for name, tg in types.items():
         for fi, face in enumerate(tg.ref.faces):
             keys = np.sort(tg.verts[:, list(face)], axis=1)
             for e in range(tg.nelem):
+                if (name, e, fi) in bnd:
+                    continue
                 faces.setdefault(tuple(keys[e]), []).append((gid_base[name] + e, fi, name, e))
     pL, pR, nh, sL, sR = [], [], [], [], []
     scale = max(np.ptp(mesh_arrays["xyz"], axis=0).max(), 1.0)
@@ -185,8 +205,19 @@ def build_mesh(mesh_arrays, p, tol=1e-9):
             nh.append(n / s)
             sL.append(s)
             sR.append(np.linalg.norm(B.n_fpts[eb, jj]))
+    bi, bn, bs, bk = [], [], [], []
+    for ti, e, fi, kind in sorted(map(tuple, bfaces)):
+        name = TYPES[ti]
+        tg = types[name]
+        for j in range(tg.ref.face_offsets[fi], tg.ref.face_offsets[fi] + _nface(tg.ref, fi)):
+            n = tg.n_fpts[e, j]
+            bi.append(fpt_offset[name] + e * tg.ref.nfpts + j)
+            bs.append(np.linalg.norm(n))
+            bn.append(n / bs[-1])
+            bk.append(kind)
     return Mesh(p, types, fpt_offset, off, np.array(pL), np.array(pR), np.array(nh),
-                np.array(sL), np.array(sR))
+                np.array(sL), np.array(sR), np.array(bi, dtype=np.int64),
+                np.array(bn).reshape(-1, 3), np.array(bs), np.array(bk, dtype=np.int64))
 
 
 def _nface(ref, f):

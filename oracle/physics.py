@@ -98,3 +98,87 @@ def ldg_common_viscous(FvL, FvR, UL, UR, n, beta, tau):
     F_inv - F_vis:  -[(1/2 + beta) FvL + (1/2 - beta) FvR].n + tau (UL - UR)."""
     fv = (0.5 + beta) * FvL + (0.5 - beta) * FvR
     return -normal_flux(fv, n) + tau * (UL - UR)
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions (reading R11).  The paper applies a no-slip isothermal
+# wall at the body and Riemann-invariant conditions at the far field without
+# defining them; both are imposed weakly through a boundary state Ub (used
+# for the LDG common solution and the viscous flux) and a ghost state (the
+# right state of the Rusanov flux).  Temperature is p / rho throughout.
+# ---------------------------------------------------------------------------
+
+def wall_states(UL, gamma, t_wall):
+    """No-slip isothermal wall: Ub = (rho_L, 0, 0, 0, rho_L t_wall/(gamma-1));
+    ghost = (rho_L, -rho_L v_L, rho_L t_wall/(gamma-1) + rho_L |v_L|^2/2),
+    the interior velocity mirrored (average zero) at the wall temperature."""
+    rho, v, _ = primitives(UL, gamma)
+    eint = rho * t_wall / (gamma - 1.0)
+    Ub = np.zeros_like(UL)
+    Ub[0] = rho
+    Ub[4] = eint
+    G = np.empty_like(UL)
+    G[0] = rho
+    G[1:4] = -UL[1:4]
+    G[4] = eint + 0.5 * rho * (v * v).sum(axis=0)
+    return Ub, G
+
+
+def farfield_state(UL, n, gamma, free):
+    """Riemann-invariant far field for the free stream free = (rho, u, v, w, p)
+    and the outward unit normal n: the outgoing invariant v.n + 2c/(gamma-1)
+    from the interior, the incoming v.n - 2c/(gamma-1) from the free stream;
+    entropy p/rho^gamma and tangential velocity from the interior where the
+    boundary normal velocity points out of the domain (outflow), else from
+    the free stream.  Returns the boundary state (also the ghost state)."""
+    rho, v, p = primitives(UL, gamma)
+    rf = free[0]
+    vf = np.asarray(free[1:4], dtype=np.float64).reshape((3,) + (1,) * (UL.ndim - 1))
+    pf = free[4]
+    vnL = (v * n).sum(axis=0)
+    vnf = (vf * n).sum(axis=0)
+    cL = np.sqrt(gamma * p / rho)
+    cf = np.sqrt(gamma * pf / rf)
+    rp = vnL + 2.0 * cL / (gamma - 1.0)
+    rm = vnf - 2.0 * cf / (gamma - 1.0)
+    vnb = 0.5 * (rp + rm)
+    cb = 0.25 * (gamma - 1.0) * (rp - rm)
+    out = vnb > 0
+    ent = np.where(out, p / rho ** gamma, pf / rf ** gamma)
+    vt = np.where(out, v - vnL * n, vf - vnf * n)
+    rhob = (cb * cb / (gamma * ent)) ** (1.0 / (gamma - 1.0))
+    pb = rhob * cb * cb / gamma
+    vb = vt + vnb * n
+    Ub = np.empty_like(UL)
+    Ub[0] = rhob
+    Ub[1:4] = rhob * vb
+    Ub[4] = pb / (gamma - 1.0) + 0.5 * rhob * (vb * vb).sum(axis=0)
+    return Ub
+
+
+BC_WALL, BC_FARFIELD = 1, 2
+
+
+def boundary_states(UL, n, kind, gamma, t_wall, free):
+    """(Ub, ghost) per boundary point; kind 1 wall, 2 far field."""
+    Ub = np.empty_like(UL)
+    G = np.empty_like(UL)
+    w = kind == BC_WALL
+    if w.any():
+        Ub[:, w], G[:, w] = wall_states(UL[:, w], gamma, t_wall)
+    f = kind == BC_FARFIELD
+    if f.any():
+        Ub[:, f] = farfield_state(UL[:, f], n[:, f], gamma, free)
+        G[:, f] = Ub[:, f]
+    return Ub, G
+
+
+def boundary_flux(UL, QL, n, kind, gamma, t_wall, free, ns, mu=0.0, prandtl=0.71, tau=0.1):
+    """Common normal flux out of the domain at boundary points, in the sign
+    of the total flux F_inv - F_vis: Rusanov(UL, ghost; n), and for
+    Navier-Stokes - F_vis(Ub, Q_L).n + tau (U_L - Ub)."""
+    Ub, G = boundary_states(UL, n, kind, gamma, t_wall, free)
+    fn = rusanov(UL, G, n, gamma)
+    if ns:
+        fn = fn - normal_flux(viscous_flux(Ub, QL, gamma, mu, prandtl), n) + tau * (UL - Ub)
+    return fn

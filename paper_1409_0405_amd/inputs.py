@@ -18,7 +18,10 @@ Mesh arrays (all numpy, host memory):
                                         from above), 4-7 top, k+4 above k
                                         (optional: absent means no hexahedra)
 * ``hex_img``  int8    [n_hex][8][3]
-* ``period``   float64 [3]
+* ``period``   float64 [3]                 0 for a direction that is not periodic
+* ``bfaces``   int64   [n][4]          optional boundary faces: (type 0 tet / 1
+                                        prism / 2 hex, element, local face,
+                                        kind 1 wall / 2 far field)
 
 Element order is chosen for locality of interface gathers: tets are numbered
 shape-major (the six Kuhn shapes of a cube are six blocks, cubes run fastest
@@ -156,7 +159,17 @@ def mixed_box(nx, ny, n_pri_layers, n_tet_layers, lengths, z_split=None,
     }
 
 
-def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0):
+# Local faces of each element type (vertex positions within the element), in
+# the order the mesh format numbers them; used only to name boundary faces.
+LOCAL_FACES = {
+    "tet": [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)],
+    "pri": [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
+    "hex": [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)],
+}
+BC_WALL, BC_FARFIELD = 1, 2
+
+
+def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0, y_bc=None):
     """Periodic box of nx x ny x nz cells holding all three element types
     with conforming interfaces:
 
@@ -175,6 +188,11 @@ def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0):
     jittered by U(-a, a) times the cell size on each axis, drawn in vertex
     id order (x fastest, then y, then z; per vertex x, y, z).
 
+    ``y_bc`` = "wall" or "farfield" makes y bounded instead of periodic: the
+    planes y = 0 and y = Ly are boundaries of that kind (their vertices keep
+    y exact), listed in ``bfaces`` [n][4] = (type 0 tet / 1 prism / 2 hex,
+    element, local face, kind 1 wall / 2 far field), and period[1] is 0.
+
     Element order: hexahedra (z, y, x) with x fastest; z-prisms triangle
     major, then (z, y, x); x-prisms triangle-major, then (z, y, x); tets
     shape-major, then (z, y, x).
@@ -182,17 +200,25 @@ def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0):
     Lx, Ly, Lz = (float(v) for v in lengths)
     if not (0 <= x_split <= nx and 0 <= z_split <= nz) or min(nx, ny, nz) < 1:
         raise ValueError("bad hybrid box split")
+    if y_bc not in (None, "wall", "farfield"):
+        raise ValueError("y_bc must be None, 'wall' or 'farfield'")
     h = np.array([Lx / nx, Ly / ny, Lz / nz])
-    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    nyv = ny + 1 if y_bc else ny                   # vertex rows in y
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(nyv), np.arange(nx), indexing="ij")
     xyz = np.stack([ix, iy, iz], axis=-1).reshape(-1, 3) * h
     if jitter:
         rng = np.random.default_rng(seed)
-        xyz = xyz + jitter * rng.uniform(-1.0, 1.0, size=xyz.shape) * h
-    n = np.array([nx, ny, nz])
+        r = jitter * rng.uniform(-1.0, 1.0, size=xyz.shape) * h
+        if y_bc:
+            on_bnd = (iy.reshape(-1) == 0) | (iy.reshape(-1) == ny)
+            r[on_bnd, 1] = 0.0
+        xyz = xyz + r
+    n = np.array([nx, ny if not y_bc else 1 << 30, nz])
 
     def corner(c, off):
         k = c + np.asarray(off)[None, :]
-        vid = (np.mod(k[:, 2], nz) * ny + np.mod(k[:, 1], ny)) * nx + np.mod(k[:, 0], nx)
+        ky = k[:, 1] if y_bc else np.mod(k[:, 1], ny)
+        vid = (np.mod(k[:, 2], nz) * nyv + ky) * nx + np.mod(k[:, 0], nx)
         return vid, (k >= n[None, :]).astype(np.int8)
 
     def cells(x0, x1, z0, z1):
@@ -219,19 +245,31 @@ def hybrid_box(nx, ny, nz, x_split, z_split, lengths, jitter=0.0, seed=0):
     px_v, px_img = build(cells(0, x_split, z_split, nz), xpri, 6)
     tet_v, tet_img = build(cells(x_split, nx, z_split, nz), tets, 4)
     c = np.ascontiguousarray
-    return {
+    out = {
         "xyz": c(xyz, dtype=np.float64),
         "tet_v": c(tet_v, dtype=np.int64), "tet_img": c(tet_img, dtype=np.int8),
         "pri_v": c(np.concatenate([pz_v, px_v]), dtype=np.int64),
         "pri_img": c(np.concatenate([pz_img, px_img]), dtype=np.int8),
         "hex_v": c(hex_v, dtype=np.int64), "hex_img": c(hex_img, dtype=np.int8),
-        "period": np.array([Lx, Ly, Lz], dtype=np.float64),
+        "period": np.array([Lx, 0.0 if y_bc else Ly, Lz], dtype=np.float64),
     }
+    if y_bc:
+        kind = BC_WALL if y_bc == "wall" else BC_FARFIELD
+        rows = []
+        for ti, name in enumerate(("tet", "pri", "hex")):
+            ky = (out[f"{name}_v"] // nx) % nyv                  # vertex row of each element vertex
+            for fi, face in enumerate(LOCAL_FACES[name]):
+                fk = ky[:, list(face)]
+                hit = np.flatnonzero((fk == 0).all(axis=1) | (fk == ny).all(axis=1))
+                rows += [(ti, int(e), fi, kind) for e in hit]
+        out["bfaces"] = np.array(rows, dtype=np.int64).reshape(-1, 4)
+    return out
 
 
-def hex_box(n, lengths=(2.0 * math.pi,) * 3, jitter=0.0, seed=0):
-    """Periodic box of n^3 hexahedra (``hybrid_box`` with no other type)."""
-    return hybrid_box(n, n, n, n, n, lengths, jitter=jitter, seed=seed)
+def hex_box(n, lengths=(2.0 * math.pi,) * 3, jitter=0.0, seed=0, y_bc=None):
+    """Box of n^3 hexahedra (``hybrid_box`` with no other type), periodic
+    unless ``y_bc`` bounds it in y."""
+    return hybrid_box(n, n, n, n, n, lengths, jitter=jitter, seed=seed, y_bc=y_bc)
 
 
 def unwrapped(mesh, kind):
