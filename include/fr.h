@@ -70,6 +70,10 @@ typedef enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 } fr_system;
 typedef enum { FR_FP32 = 0, FR_FP64 = 1, FR_SPLIT_BF16 = 2, FR_SPLIT_FP16 = 3 } fr_precision;
 typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
 
+/* fr_mesh_desc.bfaces kinds */
+#define FR_BC_WALL 1
+#define FR_BC_FARFIELD 2
+
 /* fr_mesh_desc.flags */
 #define FR_VALIDATE_ONLY 0x1u  /* build host-side tables only; no device work */
 #define FR_CHECK_FINITE 0x2u   /* fr_rk_step ends with a finiteness check */
@@ -99,7 +103,30 @@ typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
  *            At most 2^22 - 1 elements of each type; faces between elements
  *            must be conforming (a hexahedron meets prisms through their
  *            quadrilateral faces).
- * period     box lengths of the periodic directions (used with the images).
+ * period     box lengths of the periodic directions (used with the images);
+ *            0 for a direction that is not periodic.
+ * bfaces     [n_bfaces][4] boundary faces: (element type, element index,
+ *            local face, kind FR_BC_WALL / FR_BC_FARFIELD), or NULL.  Local
+ *            faces by vertex positions: tet (0,1,2) (0,1,3) (0,2,3) (1,2,3);
+ *            prism (0,1,2) (3,4,5) (0,1,4,3) (1,2,5,4) (2,0,3,5); hexahedron
+ *            (0,1,2,3) (4,5,6,7) (0,1,5,4) (1,2,6,5) (2,3,7,6) (3,0,4,7).
+ *            Every face that meets no other element must be listed.
+ *            Section 3.2 names the two kinds (no-slip isothermal wall at the
+ *            body, Riemann invariants at the far field); both are imposed
+ *            weakly through a boundary state Ub (the LDG common solution and
+ *            the state of the viscous flux, with the interior gradient) and a
+ *            ghost state (the right state of the Rusanov flux), temperature
+ *            meaning p / rho:
+ *              wall: Ub = (rho, 0, 0, 0, rho t_wall / (gamma - 1)), ghost =
+ *                the interior velocity mirrored at the wall temperature;
+ *              far field: v.n and the sound speed from the outgoing invariant
+ *                of the interior and the incoming one of the free stream,
+ *                entropy and tangential velocity from the upwind side;
+ *                ghost = Ub.
+ *            The common flux adds, for Navier-Stokes, -Fv(Ub, Q).n +
+ *            ldg_tau (U - Ub).
+ * t_wall     wall temperature p / rho (> 0 when there are wall faces).
+ * farfield   free stream (rho, u, v, w, p) of the far-field faces.
  */
 typedef struct {
     int32_t order;
@@ -119,6 +146,10 @@ typedef struct {
     int64_t n_hex;
     const int64_t *hex_v;
     const int8_t *hex_img;
+    int64_t n_bfaces;
+    const int64_t *bfaces;
+    double t_wall;
+    double farfield[5];
 } fr_mesh_desc;
 
 /* Build operators (FP64 on the host), geometry and the interface pairing,
@@ -220,9 +251,9 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * FR_PROF_NCLASS), and clears the records.  Classes: 4 * etype + op for the
  * operator products of tets and prisms (op 0 interpolation to flux points, 1
  * corrected gradient, 2 gradient interpolation, 3 divergence plus
- * correction), 8 + etype the solution-point flux kernel, 10 common solution,
- * 11 common interface flux, 12 + etype negdivconf with the Runge-Kutta
- * update, 14 closure inputs (moments and neighbour gathering), 15 closure
+ * correction), 8 + etype the solution-point flux kernel, 10 common solution
+ * (and the boundary states), 11 common interface flux (and the boundary
+ * flux), 12 + etype negdivconf with the Runge-Kutta update, 14 closure inputs (moments and neighbour gathering), 15 closure
  * network forward; hexahedra: 16 + op the products, 20 the solution-point
  * kernel, 21 negdivconf. */
 #define FR_PROF_NCLASS 22

@@ -62,6 +62,10 @@ struct Dev : DevBase {
     uint32_t *sideL = nullptr, *sideR = nullptr;
     T *pgeo = nullptr;
     int64_t npairs = 0;
+    uint32_t *bside = nullptr;      // boundary points
+    T *bgeo = nullptr;              // [4][nb]
+    int8_t *bkind = nullptr;
+    int64_t nb = 0;
     double *partial = nullptr, *red_out = nullptr;
     std::vector<void *> allocs;
     ~Dev() override {
@@ -102,6 +106,7 @@ struct fr_mesh_s {
     int order = 0, system = 0, precision = 0;
     uint32_t flags = 0;
     double gamma = 1.4, mu = 0, prandtl = 0.72, beta = 0.5, tau = 0.1;
+    double t_wall = 1.0, farfield[5] = {1.0, 0.0, 0.0, 0.0, 1.0 / 1.4};
     frh::MeshHost host;
     hipStream_t create_stream = nullptr;
     bool device = false;
@@ -542,6 +547,27 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
     }
     FR_TRY(dev_upload(m, d, d.pgeo, pg, s));
     {
+        const frh::BndTable &B = m->host.bnd;
+        d.nb = int64_t(B.side.size());
+        void *q;
+        FR_HIP(m, hipMalloc(&q, std::max<size_t>(B.side.size(), 1) * 4));
+        d.allocs.push_back(q);
+        d.bside = static_cast<uint32_t *>(q);
+        FR_HIP(m, hipMalloc(&q, std::max<size_t>(B.kind.size(), 1)));
+        d.allocs.push_back(q);
+        d.bkind = static_cast<int8_t *>(q);
+        if (d.nb) {
+            FR_HIP(m, hipMemcpy(d.bside, B.side.data(), B.side.size() * 4, hipMemcpyHostToDevice));
+            FR_HIP(m, hipMemcpy(d.bkind, B.kind.data(), B.kind.size(), hipMemcpyHostToDevice));
+        }
+        std::vector<T> bg(4 * size_t(d.nb));
+        for (int64_t i = 0; i < d.nb; ++i) {
+            for (int k = 0; k < 3; ++k) bg[size_t(k) * d.nb + i] = T(B.nhat[3 * i + k]);
+            bg[3 * size_t(d.nb) + i] = T(B.s[i]);
+        }
+        FR_TRY(dev_upload(m, d, d.bgeo, bg, s));
+    }
+    {
         void *q;
         FR_HIP(m, hipMalloc(&q, frd::RED_BLOCKS * 8 * sizeof(double)));
         d.allocs.push_back(q);
@@ -615,8 +641,27 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     pa.prandtl = pr;
     pa.beta = T(m->beta);
     pa.tau = T(m->tau);
+    frd::BndArgs<T> ba{};
+    ba.side = d.bside;
+    ba.geo = d.bgeo;
+    ba.kind = d.bkind;
+    ba.nb = d.nb;
+    for (int t = 0; t < frh::NTYPE; ++t) {
+        ba.Uf[t] = d.t[t].Uf;
+        ba.Qf[t] = d.t[t].Qf;
+        ba.Cf[t] = d.t[t].Cf;
+        ba.Fn[t] = d.t[t].Fn;
+        ba.ld[t] = d.t[t].ld;
+    }
+    ba.gamma = gamma;
+    ba.mu = mu;
+    ba.prandtl = pr;
+    ba.tau = T(m->tau);
+    ba.t_wall = T(m->t_wall);
+    for (int k = 0; k < 5; ++k) ba.free[k] = T(m->farfield[k]);
     if (ns) {
         FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
+        if (d.nb) FR_LAUNCH(m, 10, s, frd::launch_boundary_solution<T>(ba, s));
         for (int t = 0; t < frh::NTYPE; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
@@ -637,6 +682,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
         }
     }
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
+    if (d.nb) FR_LAUNCH(m, 11, s, frd::launch_boundary_flux<T>(ns, ba, s));
     const Closure *cl = (m->closure && m->closure->params) ? m->closure.get() : nullptr;
     if (cl) {
         const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
@@ -1124,7 +1170,8 @@ bool build_host(const fr_mesh_desc &d, frh::MeshHost &h, std::string &err) {
     const int64_t ne[frh::NTYPE] = {d.n_tets, d.n_prisms, d.n_hex};
     const int64_t *const conn[frh::NTYPE] = {d.tet_v, d.pri_v, d.hex_v};
     const int8_t *const img[frh::NTYPE] = {d.tet_img, d.pri_img, d.hex_img};
-    return frh::build_mesh_host(d.order, d.n_vertices, d.xyz, ne, conn, img, d.period, h, err);
+    return frh::build_mesh_host(d.order, d.n_vertices, d.xyz, ne, conn, img, d.period, d.n_bfaces, d.bfaces, h,
+                                err);
 }
 
 }  // namespace
@@ -1148,6 +1195,15 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
     if (!(desc->gamma > 1) || desc->mu < 0 ||
         (desc->system == FR_NAVIER_STOKES && !(desc->prandtl > 0)))
         return fail(nullptr, FR_ERR_INVALID_ARG, "invalid physical constants");
+    if (desc->n_bfaces < 0 || (desc->n_bfaces && !desc->bfaces))
+        return fail(nullptr, FR_ERR_INVALID_ARG, "inconsistent boundary face list");
+    for (int64_t i = 0; i < desc->n_bfaces; ++i) {
+        const int64_t kind = desc->bfaces[4 * i + 3];
+        if (kind == FR_BC_WALL && !(desc->t_wall > 0))
+            return fail(nullptr, FR_ERR_INVALID_ARG, "wall faces need a positive wall temperature");
+        if (kind == FR_BC_FARFIELD && !(desc->farfield[0] > 0 && desc->farfield[4] > 0))
+            return fail(nullptr, FR_ERR_INVALID_ARG, "far-field faces need a positive free-stream density and pressure");
+    }
     auto m = std::make_unique<fr_mesh_s>();
     m->order = desc->order;
     m->system = desc->system;
@@ -1158,6 +1214,8 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
     m->prandtl = desc->prandtl;
     m->beta = desc->ldg_beta;
     m->tau = desc->ldg_tau;
+    m->t_wall = desc->t_wall;
+    for (int k = 0; k < 5; ++k) m->farfield[k] = desc->farfield[k];
     std::string err;
     try {
         if (!build_host(*desc, m->host, err)) return fail(nullptr, FR_ERR_BAD_MESH, err);
@@ -1417,9 +1475,11 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
     const fr_mesh_desc &d0 = descs[0];
     for (int i = 0; i < n; ++i) {
         const fr_mesh_desc &d = descs[i];
+        bool same_bc = d.t_wall == d0.t_wall;
+        for (int k = 0; k < 5; ++k) same_bc = same_bc && d.farfield[k] == d0.farfield[k];
         if (d.system != d0.system || d.precision != d0.precision || d.gamma != d0.gamma ||
             d.mu != d0.mu || d.prandtl != d0.prandtl || d.ldg_beta != d0.ldg_beta ||
-            d.ldg_tau != d0.ldg_tau)
+            d.ldg_tau != d0.ldg_tau || !same_bc)
             return bfail(nullptr, FR_ERR_INVALID_ARG,
                          "problem " + std::to_string(i) + ": system, precision and constants must match");
         if (d.order < 1 || d.order > 4)
@@ -1468,6 +1528,8 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
         m->prandtl = d0.prandtl;
         m->beta = d0.ldg_beta;
         m->tau = d0.ldg_tau;
+        m->t_wall = d0.t_wall;
+        for (int k = 0; k < 5; ++k) m->farfield[k] = d0.farfield[k];
         std::vector<std::array<int64_t, frh::NTYPE>> off;
         std::string err;
         if (!frh::merge_meshes(parts[g], m->host, off, err)) return bfail(nullptr, FR_ERR_BAD_MESH, err);

@@ -110,6 +110,32 @@ hipError_t launch_common_solution(const PairArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_common_flux(bool ns, const PairArgs<T> &a, hipStream_t s);
 
+// Boundary flux points (no-slip isothermal wall, kind 1; Riemann-invariant
+// far field, kind 2), imposed weakly: a boundary state Ub (the LDG common
+// solution and the state of the viscous flux) and a ghost state (the right
+// state of the Rusanov flux) from the interior trace.
+template <typename T>
+struct BndArgs {
+    const uint32_t *side;            // elem | fpt << 22 | type << 30
+    const T *geo;                    // [4][nb]: nx, ny, nz (outward unit normal), s
+    const int8_t *kind;              // [nb]
+    int64_t nb;
+    const T *Uf[NTYPE];
+    const T *Qf[NTYPE];
+    T *Cf[NTYPE];
+    T *Fn[NTYPE];
+    int64_t ld[NTYPE];
+    T gamma, mu, prandtl, tau;
+    T t_wall;                        // wall temperature p / rho
+    T free[5];                       // free stream rho, u, v, w, p
+};
+// Cf = Ub - U_f at each boundary point (NS).
+template <typename T>
+hipError_t launch_boundary_solution(const BndArgs<T> &a, hipStream_t s);
+// Fn = s [Rusanov(U_f, ghost; n) (- Fv(Ub, Q_f).n + tau (U_f - Ub))].
+template <typename T>
+hipError_t launch_boundary_flux(bool ns, const BndArgs<T> &a, hipStream_t s);
+
 // k = -Rt / J at each solution point (times dte[e] if given), then
 //   acc += a k (if acc), out = (base ? base : (acc ? acc : 0)) + b k (if out).
 template <typename T>

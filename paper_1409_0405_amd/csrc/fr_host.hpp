@@ -89,6 +89,15 @@ struct PairTable {
     std::vector<double> sL, sR;           // |adj^T n_ref| on each side
 };
 
+// Boundary flux points (faces listed as wall or far field), sorted like the
+// pairs by (type, flux point, element).
+struct BndTable {
+    std::vector<uint32_t> side;           // elem | fpt << 22 | type << 30
+    std::vector<double> nhat;             // [n][3] outward unit normal
+    std::vector<double> s;                // |adj^T n_ref|
+    std::vector<int8_t> kind;             // 1 wall, 2 far field
+};
+
 struct TypeHost {
     int64_t nelem = 0, ld = 0;
     RefOps ops;
@@ -101,6 +110,7 @@ struct MeshHost {
     int p = 0;
     TypeHost t[NTYPE];
     PairTable pairs;
+    BndTable bnd;
     double volume = 0;
 };
 
@@ -111,10 +121,12 @@ std::vector<int32_t> face_neighbours(const MeshHost &m);
 
 // Builds geometry and pairing; returns false with a message on a bad mesh.
 // Per type t: nelem[t] elements, connectivity conn[t] [nelem][n_verts(t)],
-// periodic images img[t] (may be null).
+// periodic images img[t] (may be null).  Boundary faces bfaces [nbf][4] =
+// (type, element, local face, kind 1 wall / 2 far field) pair with nothing.
 bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
                      const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
-                     const double period[3], MeshHost &m, std::string &err);
+                     const double period[3], int64_t nbf, const int64_t *bfaces, MeshHost &m,
+                     std::string &err);
 
 // Merge independent meshes of one order into one element array per type.
 // Element indices of each part are offset by the elements of the parts

@@ -993,6 +993,118 @@ __global__ __launch_bounds__(256) void common_flux_kernel(PairArgs<T> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Boundary points.  Wall (kind 1): Ub = (rho, 0, 0, 0, rho T_w / (gamma - 1)),
+// ghost = (rho, -rho v, rho T_w / (gamma - 1) + rho |v|^2 / 2), the interior
+// velocity mirrored at the wall temperature.  Far field (kind 2): the
+// outgoing invariant v.n + 2c/(gamma-1) of the interior and the incoming
+// v.n - 2c/(gamma-1) of the free stream fix v.n and c; entropy p/rho^gamma
+// and tangential velocity come from the interior where the flow leaves the
+// domain, else from the free stream; the ghost is Ub.  Temperature is p/rho.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void boundary_states(const T u[5], const T n[3], int kind, const BndArgs<T> &a,
+                                                T ub[5], T gh[5]) {
+    const T g1 = a.gamma - T(1);
+    const T rinv = T(1) / u[0];
+    if (kind == 1) {
+        const T eint = u[0] * a.t_wall / g1;
+        const T ke = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * rinv;
+        ub[0] = u[0];
+        ub[1] = ub[2] = ub[3] = T(0);
+        ub[4] = eint;
+        gh[0] = u[0];
+        gh[1] = -u[1];
+        gh[2] = -u[2];
+        gh[3] = -u[3];
+        gh[4] = eint + ke;
+        return;
+    }
+    const T v[3] = {u[1] * rinv, u[2] * rinv, u[3] * rinv};
+    const T p = g1 * (u[4] - T(0.5) * (u[1] * v[0] + u[2] * v[1] + u[3] * v[2]));
+    const T vnL = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    const T vnf = a.free[1] * n[0] + a.free[2] * n[1] + a.free[3] * n[2];
+    const T cL = sqrt(a.gamma * p * rinv), cf = sqrt(a.gamma * a.free[4] / a.free[0]);
+    const T rp = vnL + T(2) * cL / g1, rm = vnf - T(2) * cf / g1;
+    const T vnb = T(0.5) * (rp + rm), cb = T(0.25) * g1 * (rp - rm);
+    const bool out = vnb > T(0);
+    const T ent = out ? p / pow(u[0], a.gamma) : a.free[4] / pow(a.free[0], a.gamma);
+    T vb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vb[d] = (out ? v[d] - vnL * n[d] : a.free[1 + d] - vnf * n[d]) + vnb * n[d];
+    const T rhob = pow(cb * cb / (a.gamma * ent), T(1) / g1);
+    const T pb = rhob * cb * cb / a.gamma;
+    ub[0] = rhob;
+    ub[1] = rhob * vb[0];
+    ub[2] = rhob * vb[1];
+    ub[3] = rhob * vb[2];
+    ub[4] = pb / g1 + T(0.5) * rhob * (vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gh[k] = ub[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void boundary_solution_kernel(BndArgs<T> a) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.nb) return;
+    int64_t e;
+    int f, t;
+    unpack(a.side[p], e, f, t);
+    const int64_t ld = pick(a.ld, t);
+    const T n[3] = {a.geo[p], a.geo[a.nb + p], a.geo[2 * a.nb + p]};
+    T u[5], ub[5], gh[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = pick(a.Uf, t)[(int64_t(f) * 5 + v) * ld + e];
+    boundary_states(u, n, int(a.kind[p]), a, ub, gh);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) pick(a.Cf, t)[(int64_t(f) * 5 + v) * ld + e] = ub[v] - u[v];
+}
+
+template <typename T, bool NS>
+__global__ __launch_bounds__(256) void boundary_flux_kernel(BndArgs<T> a) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.nb) return;
+    int64_t e;
+    int f, t;
+    unpack(a.side[p], e, f, t);
+    const int64_t ld = pick(a.ld, t);
+    const int64_t nb = a.nb;
+    const T n[3] = {a.geo[p], a.geo[nb + p], a.geo[2 * nb + p]};
+    const T sc = a.geo[3 * nb + p];
+    T u[5], ub[5], gh[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = pick(a.Uf, t)[(int64_t(f) * 5 + v) * ld + e];
+    T q[3][5];
+    if (NS) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[j][v] = pick(a.Qf, t)[(int64_t(f) * 15 + j * 5 + v) * ld + e];
+    }
+    boundary_states(u, n, int(a.kind[p]), a, ub, gh);
+    T FL[3][5], FR[3][5], pL, pR;
+    euler_flux(u, a.gamma, FL, pL);
+    euler_flux(gh, a.gamma, FR, pR);
+    const T vnL = (u[1] * n[0] + u[2] * n[1] + u[3] * n[2]) / u[0];
+    const T vnR = (gh[1] * n[0] + gh[2] * n[1] + gh[3] * n[2]) / gh[0];
+    const T lam = fmax(fabs(vnL) + sqrt(a.gamma * pL / u[0]), fabs(vnR) + sqrt(a.gamma * pR / gh[0]));
+    T fl[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+        fl[v] = T(0.5) * (n[0] * (FL[0][v] + FR[0][v]) + n[1] * (FL[1][v] + FR[1][v]) +
+                          n[2] * (FL[2][v] + FR[2][v])) -
+                T(0.5) * lam * (gh[v] - u[v]);
+    if (NS) {
+        T Fv[3][5];
+        viscous_flux(ub, q, a.gamma, a.mu, a.prandtl, Fv);
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            fl[v] += -(n[0] * Fv[0][v] + n[1] * Fv[1][v] + n[2] * Fv[2][v]) + a.tau * (u[v] - ub[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) pick(a.Fn, t)[(int64_t(f) * 5 + v) * ld + e] = sc * fl[v];
+}
+
 // R = -Rt / J at each solution point, fused with a Runge-Kutta register update.
 template <typename T, int ET>
 __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
@@ -1273,6 +1385,22 @@ hipError_t launch_common_flux(bool ns, const PairArgs<T> &a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_boundary_solution(const BndArgs<T> &a, hipStream_t s) {
+    if (!a.nb) return hipSuccess;
+    boundary_solution_kernel<T><<<unsigned((a.nb + 255) / 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_boundary_flux(bool ns, const BndArgs<T> &a, hipStream_t s) {
+    if (!a.nb) return hipSuccess;
+    const unsigned g = unsigned((a.nb + 255) / 256);
+    if (ns) boundary_flux_kernel<T, true><<<g, 256, 0, s>>>(a);
+    else boundary_flux_kernel<T, false><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s) {
     const dim3 grid(unsigned((a.nelem + 255) / 256), unsigned(a.nu)), block(256);
     if (etype == 0) negdivconf_kernel<T, 0><<<grid, block, 0, s>>>(a);
@@ -1306,6 +1434,8 @@ hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s) {
     template hipError_t launch_upts<T>(int, bool, const UptsArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_solution<T>(const PairArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_flux<T>(bool, const PairArgs<T> &, hipStream_t);        \
+    template hipError_t launch_boundary_solution<T>(const BndArgs<T> &, hipStream_t);         \
+    template hipError_t launch_boundary_flux<T>(bool, const BndArgs<T> &, hipStream_t);       \
     template hipError_t launch_negdivconf<T>(int, const NegArgs<T> &, hipStream_t);           \
     template hipError_t launch_reduce<T>(const RedArgs<T> &, hipStream_t);                    \
     template hipError_t launch_copy<T>(T *, const T *, int64_t, hipStream_t);

@@ -133,7 +133,8 @@ struct FaceRec {
 
 bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
                      const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
-                     const double period[3], MeshHost &m, std::string &err) {
+                     const double period[3], int64_t nbf, const int64_t *bfaces, MeshHost &m,
+                     std::string &err) {
     m.p = p;
     m.volume = 0;
     for (int t = 0; t < NTYPE; ++t) {
@@ -186,6 +187,34 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         }
     }
 
+    // boundary faces: validated, then left out of the matching
+    std::vector<std::array<int64_t, 4>> bl;
+    if (nbf < 0 || (nbf && !bfaces)) {
+        err = "bad boundary face list";
+        return false;
+    }
+    for (int64_t i = 0; i < nbf; ++i) {
+        const int64_t *b = bfaces + 4 * i;
+        if (b[0] < 0 || b[0] >= NTYPE || b[1] < 0 || b[1] >= m.t[b[0]].nelem || b[2] < 0 ||
+            b[2] >= int64_t(faces_of(int(b[0])).size()) || (b[3] != 1 && b[3] != 2)) {
+            err = "boundary face " + std::to_string(i) + " names no face of the mesh or an unknown kind";
+            return false;
+        }
+        bl.push_back({b[0], b[1], b[2], b[3]});
+    }
+    std::sort(bl.begin(), bl.end());
+    for (size_t i = 1; i < bl.size(); ++i)
+        if (bl[i][0] == bl[i - 1][0] && bl[i][1] == bl[i - 1][1] && bl[i][2] == bl[i - 1][2]) {
+            err = "boundary face listed twice: " + std::string(type_name(int(bl[i][0]))) + " " +
+                  std::to_string(bl[i][1]) + " face " + std::to_string(bl[i][2]);
+            return false;
+        }
+    auto is_bnd = [&](int t, int64_t e, int f) {
+        const std::array<int64_t, 4> key{t, e, f, 0};
+        auto it = std::lower_bound(bl.begin(), bl.end(), key);
+        return it != bl.end() && (*it)[0] == t && (*it)[1] == e && (*it)[2] == f;
+    };
+
     // faces keyed by their sorted vertex ids
     std::vector<FaceRec> recs;
     int64_t gbase[NTYPE] = {0, nelem[0], nelem[0] + nelem[1]};
@@ -196,6 +225,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         const int nvt = n_verts(t);
         for (int64_t e = 0; e < T.nelem; ++e)
             for (size_t f = 0; f < faces.size(); ++f) {
+                if (!bl.empty() && is_bnd(t, e, int(f))) continue;
                 FaceRec r;
                 r.key = {-1, -1, -1, -1};
                 for (size_t a = 0; a < faces[f].size(); ++a) r.key[a] = conn[t][e * nvt + faces[f][a]];
@@ -341,6 +371,46 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         return (uint64_t(side_type(s)) << 40) | (uint64_t(side_fpt(s)) << 32) | uint64_t(side_elem(s));
     };
     std::sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
+
+    // boundary points: outward normal adj^T n_ref at each flux point of the face
+    {
+        struct BP {
+            uint32_t side;
+            double n[3], s;
+            int8_t kind;
+        };
+        std::vector<BP> bp;
+        for (const auto &b : bl) {
+            const int t = int(b[0]);
+            const TypeHost &T = m.t[t];
+            double c[21];
+            for (int k = 0; k < n_geom(t); ++k) c[k] = T.geom[size_t(k) * T.nelem + b[1]];
+            for (int j = T.ops.face_off[b[2]]; j < T.ops.face_off[b[2] + 1]; ++j) {
+                double col[3][3], adj[3][3], nn[3];
+                jac_at(t, c, &T.ops.fpts[3 * j], col);
+                adjugate(col, adj);
+                for (int jd = 0; jd < 3; ++jd) {
+                    nn[jd] = 0;
+                    for (int k = 0; k < 3; ++k) nn[jd] += adj[k][jd] * T.ops.nref[3 * j + k];
+                }
+                BP q;
+                q.side = pack_side(b[1], j, t);
+                q.s = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+                for (int d = 0; d < 3; ++d) q.n[d] = nn[d] / q.s;
+                q.kind = int8_t(b[3]);
+                bp.push_back(q);
+            }
+        }
+        std::sort(bp.begin(), bp.end(), [&](const BP &a, const BP &b) { return keyL(a.side) < keyL(b.side); });
+        BndTable &B = m.bnd;
+        B = BndTable();
+        for (const BP &q : bp) {
+            B.side.push_back(q.side);
+            for (int d = 0; d < 3; ++d) B.nhat.push_back(q.n[d]);
+            B.s.push_back(q.s);
+            B.kind.push_back(q.kind);
+        }
+    }
     PairTable &P = m.pairs;
     const size_t n = pp.size();
     P.sideL.resize(n);
@@ -426,17 +496,34 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
         const int t = side_type(side);
         return pack_side(side_elem(side) + elem_off[i][t], side_fpt(side), t);
     };
+    struct BP {
+        uint32_t side;
+        double n[3], s;
+        int8_t kind;
+    };
+    std::vector<BP> bp;
     for (size_t i = 0; i < parts.size(); ++i) {
         const PairTable &P = parts[i].pairs;
         for (size_t j = 0; j < P.sideL.size(); ++j)
             pp.push_back({shift(P.sideL[j], i), shift(P.sideR[j], i),
                           {P.nhat[3 * j], P.nhat[3 * j + 1], P.nhat[3 * j + 2]}, P.sL[j], P.sR[j]});
+        const BndTable &B = parts[i].bnd;
+        for (size_t j = 0; j < B.side.size(); ++j)
+            bp.push_back({shift(B.side[j], i), {B.nhat[3 * j], B.nhat[3 * j + 1], B.nhat[3 * j + 2]}, B.s[j],
+                          B.kind[j]});
         out.volume += parts[i].volume;
     }
     auto keyL = [](uint32_t s) {
         return (uint64_t(side_type(s)) << 40) | (uint64_t(side_fpt(s)) << 32) | uint64_t(side_elem(s));
     };
     std::stable_sort(pp.begin(), pp.end(), [&](const PP &a, const PP &b) { return keyL(a.L) < keyL(b.L); });
+    std::stable_sort(bp.begin(), bp.end(), [&](const BP &a, const BP &b) { return keyL(a.side) < keyL(b.side); });
+    for (const BP &q : bp) {
+        out.bnd.side.push_back(q.side);
+        for (int d = 0; d < 3; ++d) out.bnd.nhat.push_back(q.n[d]);
+        out.bnd.s.push_back(q.s);
+        out.bnd.kind.push_back(q.kind);
+    }
     PairTable &T = out.pairs;
     T.sideL.resize(pp.size());
     T.sideR.resize(pp.size());

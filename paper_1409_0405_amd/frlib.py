@@ -27,6 +27,7 @@ PRECISIONS = {"fp32": FR_FP32, "fp64": FR_FP64, "split_bf16": FR_SPLIT_BF16,
               "split_fp16": FR_SPLIT_FP16}
 FR_RK4, FR_RK45_2RP, FR_FWD_EULER = 0, 1, 2
 FR_VALIDATE_ONLY, FR_CHECK_FINITE = 0x1, 0x2
+FR_BC_WALL, FR_BC_FARFIELD = 1, 2
 FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
 
 EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coords",
@@ -69,6 +70,8 @@ class fr_mesh_desc(ctypes.Structure):
         ("period", ctypes.c_double * 3),
         ("n_hex", ctypes.c_int64), ("hex_v", ctypes.POINTER(ctypes.c_int64)),
         ("hex_img", ctypes.POINTER(ctypes.c_int8)),
+        ("n_bfaces", ctypes.c_int64), ("bfaces", ctypes.POINTER(ctypes.c_int64)),
+        ("t_wall", ctypes.c_double), ("farfield", ctypes.c_double * 5),
     ]
 
 
@@ -159,7 +162,8 @@ def _type_ptrs(ptrs):
 
 
 def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4, mu=0.0,
-              prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False, check_finite=False):
+              prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False, check_finite=False,
+              t_wall=1.0, farfield=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4)):
     """fr_mesh_desc for the generator's mesh arrays; the numpy arrays it points
     into are appended to ``keep`` (they must outlive the create call)."""
     d = fr_mesh_desc()
@@ -187,6 +191,13 @@ def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=
     d.n_hex = len(hv)
     d.hex_v = _ptr(hv, ctypes.c_int64) if len(hv) else None
     d.hex_img = _ptr(hi, ctypes.c_int8) if len(hv) else None
+    bf = np.ascontiguousarray(mesh_arrays.get("bfaces", np.zeros((0, 4))), dtype=np.int64).reshape(-1, 4)
+    keep.append(bf)
+    d.n_bfaces = len(bf)
+    d.bfaces = _ptr(bf, ctypes.c_int64) if len(bf) else None
+    d.t_wall = float(t_wall)
+    for k in range(5):
+        d.farfield[k] = float(farfield[k])
     for k in range(3):
         d.period[k] = float(mesh_arrays["period"][k])
     return d
@@ -197,10 +208,10 @@ class Mesh:
 
     def __init__(self, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4,
                  mu=0.0, prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False,
-                 check_finite=False, stream=0):
+                 check_finite=False, stream=0, t_wall=1.0, farfield=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4)):
         self._keep = []
         d = make_desc(self._keep, mesh_arrays, order, system, precision, gamma, mu, prandtl,
-                      ldg_beta, ldg_tau, validate_only, check_finite)
+                      ldg_beta, ldg_tau, validate_only, check_finite, t_wall, farfield)
         h = ctypes.c_void_p()
         _check(lib().fr_mesh_create(ctypes.byref(d), ctypes.c_void_p(stream), ctypes.byref(h)))
         self.h = h

@@ -123,6 +123,16 @@ def test_error_codes():
     nz_pri = len(hyb["pri_v"]) // 2                      # z-prisms come first
     bad = dict(hyb, pri_v=hyb["pri_v"][:nz_pri], pri_img=hyb["pri_img"][:nz_pri])
     _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(bad, 2, validate_only=True))
+    # bounded box: a boundary face left unlisted, listed twice, or naming no face
+    wall = inputs.hybrid_box(4, 3, 4, 2, 2, (6.0, 7.0, 5.5), jitter=0.1, seed=1, y_bc="wall")
+    frlib.Mesh(wall, 2, validate_only=True)
+    for bf in (wall["bfaces"][1:], np.concatenate([wall["bfaces"], wall["bfaces"][:1]]),
+               np.concatenate([wall["bfaces"][1:], [[2, 10 ** 6, 0, 1]]])):
+        _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(dict(wall, bfaces=bf), 2, validate_only=True))
+    _expect(frlib.FR_ERR_INVALID_ARG, lambda: frlib.Mesh(wall, 2, validate_only=True, t_wall=-1.0))
+    far = inputs.hybrid_box(4, 3, 4, 2, 2, (6.0, 7.0, 5.5), jitter=0.1, seed=1, y_bc="farfield")
+    _expect(frlib.FR_ERR_INVALID_ARG,
+            lambda: frlib.Mesh(far, 2, validate_only=True, farfield=(0.0, 0.0, 0.0, 0.0, 1.0)))
     # validate-only meshes refuse device work
     M = frlib.Mesh(good, 2, validate_only=True)
     _expect(frlib.FR_ERR_INVALID_ARG, lambda: M.rk_step(frlib.FR_RK4, 1e-3, 1))

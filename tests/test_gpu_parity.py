@@ -106,7 +106,17 @@ CASES = [
     ("hybrid", 1, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("hybrid", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("hybrid", 4, "euler", inputs.taylor_green, {"mach": 0.1}, 0.0),
+    ("wallbox", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("wallbox", 1, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("farbox", 2, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("farbox", 4, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
 ]
+
+# Boundary data of the bounded boxes, on the scale of the Taylor-Green state
+# at Mach 0.3 (rho0 = 1, p0 = 1 / (gamma Ma^2)): wall temperature p0 / rho0,
+# a free stream crossing the far-field planes.
+P0 = 1.0 / (1.4 * 0.09)
+BC = {"wallbox": {"t_wall": P0}, "farbox": {"farfield": (1.0, 0.2, 0.3, -0.1, P0)}}
 
 
 def _mesh(kind, seed=0):
@@ -122,6 +132,10 @@ def _mesh(kind, seed=0):
         # all three types, conforming: 36 hexahedra, 144 prisms (both
         # orientations), 216 tets
         return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed)
+    if kind in ("wallbox", "farbox"):
+        # the three-type box bounded in y by walls or far-field planes
+        return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed,
+                                 y_bc="wall" if kind == "wallbox" else "farfield")
     # 4 x 4 x (3 + 3): 96 prisms and 288 tets -> ragged against 64
     return inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=seed)
 
@@ -136,10 +150,10 @@ def test_rhs_fp64_parity(case):
     print(f"case {_ids(case)} fp64", flush=True)
     arrays = _mesh(kind)
     O = om.build_mesh(arrays, p)
-    prm = fr.Params(system=system, mu=mu)
+    prm = fr.Params(system=system, mu=mu, **BC.get(kind, {}))
     U = _state(O, ic, 3, **kw)
     Ro = fr.rhs(O, U, prm)
-    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=mu)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=mu, **BC.get(kind, {}))
     Rg = _gpu_rhs(M, O, U)
     err = _field_errors(Rg, Ro)
     print("  field errors", err, flush=True)
@@ -152,10 +166,10 @@ def test_rhs_fp32_parity(case):
     print(f"case {_ids(case)} fp32", flush=True)
     arrays = _mesh(kind)
     O = om.build_mesh(arrays, p)
-    prm = fr.Params(system=system, mu=mu)
+    prm = fr.Params(system=system, mu=mu, **BC.get(kind, {}))
     U = _round32(_state(O, ic, 3, **kw))
     Ro = fr.rhs(O, U, prm)
-    M = _lib().Mesh(arrays, p, system=system, precision="fp32", mu=mu)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp32", mu=mu, **BC.get(kind, {}))
     Rg = _gpu_rhs(M, O, U)
     err = _field_errors(Rg, Ro)
     tol = _fp32_tol(O, U, prm)
@@ -164,18 +178,18 @@ def test_rhs_fp32_parity(case):
 
 
 @pytest.mark.parametrize("kind,p,system", [("mixed", 2, "ns"), ("mixed", 4, "ns"), ("mixed", 3, "euler"),
-                                           ("hybrid", 3, "ns")])
+                                           ("hybrid", 3, "ns"), ("wallbox", 2, "ns"), ("farbox", 3, "ns")])
 def test_interface_intermediates_fp64(kind, p, system):
     """State at flux points, common normal flux and (NS) the gradient at flux
     points, element by element."""
     print(f"intermediates {kind} p{p} {system}", flush=True)
     arrays = _mesh(kind, seed=2)
     O = om.build_mesh(arrays, p)
-    prm = fr.Params(system=system, mu=0.02)
+    prm = fr.Params(system=system, mu=0.02, **BC.get(kind, {}))
     U = _state(O, inputs.taylor_green, 4, mach=0.3)
     want = {}
     fr.rhs(O, U, prm, want=want)
-    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=0.02)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp64", mu=0.02, **BC.get(kind, {}))
     _gpu_rhs(M, O, U)
     items = [(0, "Uf", 5), (1, "Fn", 5)] + ([(2, "Qf", 15)] if system == "ns" else [])
     for which, key, nv in items:
@@ -252,6 +266,38 @@ def test_rk45_steps_fp64_hybrid():
         err = np.sqrt((d ** 2).sum(axis=(0, 1)) / (Uo[n] ** 2).sum(axis=(0, 1)))
         print(f"  {n} field errors", err, flush=True)
         assert (err < 1e-12).all(), (n, err)
+
+
+@pytest.mark.parametrize("kind", ["wallbox", "farbox"])
+def test_boundary_flux_balance_fp64(kind):
+    """FP64 library: the integral of R(U) equals minus the boundary flux
+    summed with the reference face weights (the oracle's quantities), and no
+    mass crosses a wall."""
+    frlib = _lib()
+    arrays = _mesh(kind, seed=4)
+    p, mu = 3, 0.02
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system="ns", mu=mu, **BC[kind])
+    U = _state(O, inputs.taylor_green, 2, mach=0.3)
+    want = {}
+    Ro = fr.rhs(O, U, prm, want=want)
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp64", mu=mu, **BC[kind])
+    for n in O.types:
+        t = NAMES.index(n)
+        M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0))).data_ptr())
+    torch.cuda.synchronize()
+    ir = M.reduce(frlib.FR_RED_INT_R)
+    om_ = np.zeros(O.nfpts_total)
+    for n, tg in O.types.items():
+        o = O.fpt_offset[n]
+        om_[o:o + tg.nelem * tg.ref.nfpts] = np.tile(tg.ref.w @ tg.ref.L, tg.nelem)
+    Fn = np.concatenate([want["Fn"][n].reshape(-1, 5) for n in O.types])
+    bflux = (om_[O.bnd_idx, None] * Fn[O.bnd_idx]).sum(axis=0)
+    scale = reduce.integral(O, {n: np.abs(Ro[n]) for n in Ro})
+    print(f"  integral R {ir}, boundary flux {bflux}", flush=True)
+    assert np.all(np.abs(ir + bflux) <= 1e-11 * scale), (ir, bflux)
+    if kind == "wallbox":
+        assert abs(ir[0]) <= 1e-11 * scale[0]
 
 
 def test_rk45_adaptive_fp64_vortex():
