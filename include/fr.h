@@ -127,6 +127,17 @@ typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
  *            ldg_tau (U - Ub).
  * t_wall     wall temperature p / rho (> 0 when there are wall faces).
  * farfield   free stream (rho, u, v, w, p) of the far-field faces.
+ * tet_q, pri_q, hex_q  quadratically curved elements of that type (Section
+ *            3.3): [n][nq][3] unwrapped positions of the nodes of each
+ *            element's order-2 lattice, or NULL for straight-sided elements.
+ *            nq = 10 tet, lattice (a, b, c) with a + b + c <= 2; 18 prism,
+ *            (a, b) with a + b <= 2 times c <= 2; 27 hexahedron, (a, b, c)
+ *            <= 2; node at reference point (-1 + a, -1 + b, -1 + c), c
+ *            outermost and a innermost.  The geometry is the quadratic
+ *            Lagrange interpolant of the nodes; the vertex nodes must agree
+ *            with xyz (and the images), neighbours must share face nodes.
+ *            The metric terms are then stored per solution point (9 + 1
+ *            values).
  */
 typedef struct {
     int32_t order;
@@ -150,6 +161,7 @@ typedef struct {
     const int64_t *bfaces;
     double t_wall;
     double farfield[5];
+    const double *tet_q, *pri_q, *hex_q;
 } fr_mesh_desc;
 
 /* Build operators (FP64 on the host), geometry and the interface pairing,

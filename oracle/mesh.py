@@ -8,7 +8,9 @@ data at their shared faces.  Geometry (reading R4): straight-sided
 elements, the tet affine, the prism mapped by its six-node shape
 functions (linear on the triangle times linear in t) and the hexahedron
 by its eight-node trilinear ones; the metric terms are evaluated exactly
-at every point from the mapping's derivatives.
+at every point from the mapping's derivatives.  Curved elements (Section
+3.3, reading R12) replace the straight map by the quadratic Lagrange map of
+nodes on the element's order-2 lattice.
 
 Conventions used here and documented for the library alike:
 * global element id is type-major: tets 0..n_tet-1, then prisms, then hexahedra;
@@ -26,6 +28,52 @@ import numpy as np
 from . import elements
 
 TYPES = ("tet", "pri", "hex")
+
+
+def quadratic_nodes(name):
+    """Reference coordinates of the quadratic geometry nodes (reading R12):
+    the order-2 lattice of the element, tet (a, b, c) with a + b + c <= 2,
+    prism (a, b) with a + b <= 2 times k <= 2, hexahedron (i, j, k) <= 2,
+    at -1 + index on each axis; enumerated with the last axis outermost and
+    the first innermost."""
+    out = []
+    for c in range(3):
+        for b in range(3 if name != "tet" else 3 - c):
+            for a in range(3 - b - (c if name == "tet" else 0) if name != "hex" else 3):
+                out.append((-1.0 + a, -1.0 + b, -1.0 + c))
+    return np.array(out)
+
+
+def _quadratic_monomials(name):
+    if name == "hex":
+        return [(a, b, c) for a in range(3) for b in range(3) for c in range(3)]
+    if name == "pri":
+        return [(a, b, c) for a in range(3) for b in range(3 - a) for c in range(3)]
+    return [(a, b, c) for a in range(3) for b in range(3 - a) for c in range(3 - a - b)]
+
+
+def _mono_eval(monos, x):
+    V = np.stack([x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c for a, b, c in monos], -1)
+    dV = np.zeros(V.shape + (3,))
+    for m, e in enumerate(monos):
+        for k in range(3):
+            if e[k]:
+                ee = list(e)
+                ee[k] -= 1
+                dV[:, m, k] = e[k] * x[:, 0] ** ee[0] * x[:, 1] ** ee[1] * x[:, 2] ** ee[2]
+    return V, dV
+
+
+def quadratic_shape_functions(name, x):
+    """Lagrange shape functions of the quadratic geometry nodes (values
+    [n_pts][n_nodes], reference derivatives [n_pts][n_nodes][3]): the
+    element's order-2 space (P2, P2 x P2 in zeta, Q2) interpolating at
+    quadratic_nodes."""
+    monos = _quadratic_monomials(name)
+    Vn, _ = _mono_eval(monos, quadratic_nodes(name))
+    Vinv = np.linalg.inv(Vn)
+    V, dV = _mono_eval(monos, np.asarray(x, dtype=np.float64))
+    return V @ Vinv, np.einsum("pmk,mn->pnk", dV, Vinv)
 
 
 def shape_functions(name, x):
@@ -73,10 +121,11 @@ class TypeGeom:
     n_fpts: np.ndarray     # [E][N_f][3]  adj^T n_ref (physical normal scaled)
 
 
-def geometry(name, ref, X):
-    """Physical positions, Jacobian determinant and adjugate at the points."""
+def geometry(name, ref, X, curved=False):
+    """Physical positions, Jacobian determinant and adjugate at the points;
+    X are the element's vertices, or with curved=True its quadratic nodes."""
     def at(pts):
-        N, dN = shape_functions(name, pts)
+        N, dN = quadratic_shape_functions(name, pts) if curved else shape_functions(name, pts)
         x = np.einsum("pa,eai->epi", N, X)
         Jm = np.einsum("pak,eai->epik", dN, X)          # dx_i / dxi_k
         J = np.linalg.det(Jm)
@@ -119,7 +168,12 @@ def build_mesh(mesh_arrays, p, tol=1e-9):
             continue
         ref = elements.get(name, p)
         X = mesh_arrays["xyz"][v] + mesh_arrays[f"{name}_img"].astype(np.float64) * mesh_arrays["period"]
-        xu, xf, Ju, adju, nf = geometry(name, ref, X)
+        Xq = mesh_arrays.get(f"{name}_q")
+        if Xq is not None and len(Xq):
+            # quadratically curved elements (reading R12): unwrapped node positions
+            xu, xf, Ju, adju, nf = geometry(name, ref, np.asarray(Xq, dtype=np.float64), curved=True)
+        else:
+            xu, xf, Ju, adju, nf = geometry(name, ref, X)
         if (Ju <= 0).any():
             bad = int(np.argwhere((Ju <= 0).any(axis=1))[0, 0])
             raise ValueError(f"non-positive Jacobian in {name} element {bad}")

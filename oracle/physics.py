@@ -101,9 +101,9 @@ def ldg_common_viscous(FvL, FvR, UL, UR, n, beta, tau):
 
 
 # ---------------------------------------------------------------------------
-# Boundary conditions (reading R11).  The paper applies a no-slip isothermal
-# wall at the body and Riemann-invariant conditions at the far field without
-# defining them; both are imposed weakly through a boundary state Ub (used
+# Boundary conditions (reading R11).  Section 3.2 applies a no-slip
+# isothermal wall at the body and Riemann-invariant conditions at the far
+# field without defining them; both are imposed weakly through a boundary state Ub (used
 # for the LDG common solution and the viscous flux) and a ghost state (the
 # right state of the Rusanov flux).  Temperature is p / rho throughout.
 # ---------------------------------------------------------------------------

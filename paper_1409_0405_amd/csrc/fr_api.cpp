@@ -48,6 +48,7 @@ struct DevType {
     frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
     T *jinv = nullptr;        // [nu][ld] 1 / J at the solution points (host FP64, rounded)
+    T *padj = nullptr;        // [9][nu][ld] adjugate at the solution points (curved types only)
     T *Uf = nullptr, *Cf = nullptr, *Qt = nullptr, *Q = nullptr, *Qf = nullptr;
     T *Ft = nullptr, *Fn = nullptr, *Rt = nullptr, *R = nullptr;
     T *reg[3] = {nullptr, nullptr, nullptr};
@@ -491,6 +492,22 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
                 jinv[i * ld + e] = 1.0 / H.jdet[size_t(e) * nu + i];
             }
         FR_TRY(dev_upload(m, d, D.jinv, cast<T>(jinv), s));
+        if (!H.Xq.empty()) {
+            // curved: adj[k][j] = (col[k1] x col[k2])_j per solution point
+            std::vector<double> pa(9 * size_t(nu) * ld, 0.0);
+            for (int i = 0; i < nu; ++i)
+                for (size_t e = 0; e < ld; ++e) {
+                    double col[3][3];
+                    frh::elem_jac(H, t, int64_t(e < size_t(H.nelem) ? e : 0), &R.upts[3 * i], col);
+                    for (int k = 0; k < 3; ++k) {
+                        const double *a1 = col[(k + 1) % 3], *a2 = col[(k + 2) % 3];
+                        const double c3[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2],
+                                              a1[0] * a2[1] - a1[1] * a2[0]};
+                        for (int j = 0; j < 3; ++j) pa[(size_t(3 * k + j) * nu + i) * ld + e] = c3[j];
+                    }
+                }
+            FR_TRY(dev_upload(m, d, D.padj, cast<T>(pa), s));
+        }
         {
             void *q;
             FR_HIP(m, hipMalloc(&q, wJ.size() * sizeof(double)));
@@ -674,6 +691,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         frd::UptsArgs<T> ua{U[t], D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu, gamma, mu, pr};
+        ua.padj = D.padj;
+        ua.pjinv = D.jinv;
         FR_LAUNCH(m, prof_upts(t), s, frd::launch_upts<T>(t, ns, ua, s));
         if (ns) {
             const int64_t w15 = 15 * D.ld;
@@ -1170,8 +1189,9 @@ bool build_host(const fr_mesh_desc &d, frh::MeshHost &h, std::string &err) {
     const int64_t ne[frh::NTYPE] = {d.n_tets, d.n_prisms, d.n_hex};
     const int64_t *const conn[frh::NTYPE] = {d.tet_v, d.pri_v, d.hex_v};
     const int8_t *const img[frh::NTYPE] = {d.tet_img, d.pri_img, d.hex_img};
-    return frh::build_mesh_host(d.order, d.n_vertices, d.xyz, ne, conn, img, d.period, d.n_bfaces, d.bfaces, h,
-                                err);
+    const double *const quad[frh::NTYPE] = {d.tet_q, d.pri_q, d.hex_q};
+    return frh::build_mesh_host(d.order, d.n_vertices, d.xyz, ne, conn, img, quad, d.period, d.n_bfaces,
+                                d.bfaces, h, err);
 }
 
 }  // namespace
@@ -1260,11 +1280,11 @@ fr_status fr_upts_coords(fr_mesh m, int32_t etype, double *xyz) {
     if (!xyz) return fail(m, FR_ERR_INVALID_ARG, "null output");
     const frh::TypeHost &H = m->host.t[etype];
     if (!H.nelem) return FR_OK;
-    const int nu = H.ops.nu, nvt = frh::n_verts(etype);
+    const int nu = H.ops.nu;
     for (int i = 0; i < nu; ++i)
         for (int64_t e = 0; e < H.nelem; ++e) {
             double x[3];
-            frh::map_point(etype, &H.X[size_t(e) * nvt * 3], &H.ops.upts[3 * i], x);
+            frh::elem_point(H, etype, e, &H.ops.upts[3 * i], x);
             for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * H.nelem + e] = x[d];
         }
     return FR_OK;
@@ -1602,11 +1622,11 @@ fr_status fr_batch_upts_coords(fr_batch b, int32_t problem, int32_t etype, doubl
     const auto &P = b->prob[problem];
     if (!P.ne[etype]) return FR_OK;
     const frh::TypeHost &H = b->group[P.g]->host.t[etype];
-    const int nu = H.ops.nu, nvt = frh::n_verts(etype);
+    const int nu = H.ops.nu;
     for (int i = 0; i < nu; ++i)
         for (int64_t e = 0; e < P.ne[etype]; ++e) {
             double x[3];
-            frh::map_point(etype, &H.X[size_t(P.off[etype] + e) * nvt * 3], &H.ops.upts[3 * i], x);
+            frh::elem_point(H, etype, P.off[etype] + e, &H.ops.upts[3 * i], x);
             for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * P.ne[etype] + e] = x[d];
         }
     return FR_OK;

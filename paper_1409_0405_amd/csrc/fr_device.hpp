@@ -88,6 +88,9 @@ struct UptsArgs {
     int64_t ld, nelem;
     int nu;
     T gamma, mu, prandtl;
+    // curved elements: adjugate [9][nu][ld] (entry 3k + j = J dxi_k/dx_j)
+    // and 1 / J [nu][ld] per point, used instead of geom when padj is set
+    const T *padj = nullptr, *pjinv = nullptr;
 };
 template <typename T>
 hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s);

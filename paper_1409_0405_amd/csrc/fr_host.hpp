@@ -82,6 +82,13 @@ void jac_at(int etype, const double *c, const double *xi, double col[3][3]);
 // Physical position of a reference point.
 void map_point(int etype, const double *X, const double *xi, double out[3]);
 
+// Quadratically curved geometry: nodes on the element's order-2 lattice
+// (tet (a,b,c) a+b+c <= 2, prism (a,b) a+b <= 2 times c <= 2, hexahedron
+// (a,b,c) <= 2; reference coordinates -1 + index; c outermost, a innermost)
+// and their Lagrange shape functions N [nq], reference derivatives dN [nq][3].
+int n_qnodes(int etype);
+void quad_shape(int etype, const double *xi, double *N, double *dN);
+
 struct PairTable {
     // one entry per paired flux point, sorted by (type L, fpt L, elem L)
     std::vector<uint32_t> sideL, sideR;   // elem | fpt << 22 | type << 30
@@ -102,6 +109,7 @@ struct TypeHost {
     int64_t nelem = 0, ld = 0;
     RefOps ops;
     std::vector<double> X;       // [nelem][nverts][3] unwrapped vertices
+    std::vector<double> Xq;      // [nelem][nq][3] quadratic nodes (curved types), else empty
     std::vector<double> geom;    // [n_geom][nelem]
     std::vector<double> jdet;    // [nelem][nu] Jacobian determinant at upts
 };
@@ -120,13 +128,19 @@ struct MeshHost {
 std::vector<int32_t> face_neighbours(const MeshHost &m);
 
 // Builds geometry and pairing; returns false with a message on a bad mesh.
+// Jacobian columns and physical position of element e of type t at a
+// reference point (straight or curved geometry).
+void elem_jac(const TypeHost &T, int t, int64_t e, const double *xi, double col[3][3]);
+void elem_point(const TypeHost &T, int t, int64_t e, const double *xi, double out[3]);
+
 // Per type t: nelem[t] elements, connectivity conn[t] [nelem][n_verts(t)],
-// periodic images img[t] (may be null).  Boundary faces bfaces [nbf][4] =
-// (type, element, local face, kind 1 wall / 2 far field) pair with nothing.
+// periodic images img[t] (may be null), quadratic nodes quad[t] [nelem][nq][3]
+// (null: straight-sided).  Boundary faces bfaces [nbf][4] = (type, element,
+// local face, kind 1 wall / 2 far field) pair with nothing.
 bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
                      const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
-                     const double period[3], int64_t nbf, const int64_t *bfaces, MeshHost &m,
-                     std::string &err);
+                     const double *const quad[NTYPE], const double period[3], int64_t nbf,
+                     const int64_t *bfaces, MeshHost &m, std::string &err);
 
 // Merge independent meshes of one order into one element array per type.
 // Element indices of each part are offset by the elements of the parts

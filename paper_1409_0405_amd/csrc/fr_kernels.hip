@@ -836,8 +836,16 @@ __global__ __launch_bounds__(256) void upts_kernel(UptsArgs<T> a) {
     const int i = blockIdx.y;
     if (e >= a.nelem) return;
     const int64_t ld = a.ld;
-    T adj[3][3];
-    const T J = metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    T adj[3][3], Jinv;
+    if (a.padj) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * a.nu + i) * ld + e];
+        Jinv = a.pjinv[int64_t(i) * ld + e];
+    } else {
+        Jinv = T(1) / metric<T, ET>(a.geom, ld, e, a.xi + 3 * i, adj);
+    }
     T u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = a.U[(int64_t(i) * 5 + v) * ld + e];
@@ -850,7 +858,6 @@ __global__ __launch_bounds__(256) void upts_kernel(UptsArgs<T> a) {
 #pragma unroll
             for (int v = 0; v < 5; ++v)
                 qt[k][v] = a.Qt[((int64_t(k) * a.nu + i) * 5 + v) * ld + e];
-        const T Jinv = T(1) / J;
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll

@@ -106,6 +106,40 @@ void map_point(int etype, const double *X, const double *xi, double out[3]) {
     }
 }
 
+void elem_jac(const TypeHost &T, int t, int64_t e, const double *xi, double col[3][3]) {
+    if (!T.Xq.empty()) {
+        const int nq = n_qnodes(t);
+        double N[27], dN[81];
+        quad_shape(t, xi, N, dN);
+        const double *Xq = &T.Xq[size_t(e) * nq * 3];
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) {
+                double s = 0;
+                for (int a = 0; a < nq; ++a) s += dN[3 * a + k] * Xq[3 * a + d];
+                col[k][d] = s;
+            }
+        return;
+    }
+    double c[21];
+    for (int k = 0; k < n_geom(t); ++k) c[k] = T.geom[size_t(k) * T.nelem + e];
+    jac_at(t, c, xi, col);
+}
+
+void elem_point(const TypeHost &T, int t, int64_t e, const double *xi, double out[3]) {
+    if (!T.Xq.empty()) {
+        const int nq = n_qnodes(t);
+        double N[27];
+        quad_shape(t, xi, N, nullptr);
+        const double *Xq = &T.Xq[size_t(e) * nq * 3];
+        for (int d = 0; d < 3; ++d) {
+            out[d] = 0;
+            for (int a = 0; a < nq; ++a) out[d] += N[a] * Xq[3 * a + d];
+        }
+        return;
+    }
+    map_point(t, &T.X[size_t(e) * n_verts(t) * 3], xi, out);
+}
+
 namespace {
 
 void cross3(const double *a, const double *b, double *c) {
@@ -133,8 +167,8 @@ struct FaceRec {
 
 bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[NTYPE],
                      const int64_t *const conn[NTYPE], const int8_t *const img[NTYPE],
-                     const double period[3], int64_t nbf, const int64_t *bfaces, MeshHost &m,
-                     std::string &err) {
+                     const double *const quad[NTYPE], const double period[3], int64_t nbf,
+                     const int64_t *bfaces, MeshHost &m, std::string &err) {
     m.p = p;
     m.volume = 0;
     for (int t = 0; t < NTYPE; ++t) {
@@ -149,6 +183,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         T.ops = ref_cached(t, p);
         const int nvt = n_verts(t), ng = n_geom(t), nu = T.ops.nu, nf = T.ops.nf;
         T.X.resize(size_t(T.nelem) * nvt * 3);
+        if (quad && quad[t]) T.Xq.assign(quad[t], quad[t] + size_t(T.nelem) * n_qnodes(t) * 3);
         T.geom.assign(size_t(ng) * T.nelem, 0);
         T.jdet.resize(size_t(T.nelem) * nu);
         for (int64_t e = 0; e < T.nelem; ++e) {
@@ -172,7 +207,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
             for (int i = 0; i < nu + nf; ++i) {
                 const double *xi = i < nu ? &T.ops.upts[3 * i] : &T.ops.fpts[3 * (i - nu)];
                 double col[3][3], adj[3][3];
-                jac_at(t, c, xi, col);
+                elem_jac(T, t, e, xi, col);
                 double J = adjugate(col, adj);
                 if (!(J > 0)) {
                     err = std::string("non-positive Jacobian in ") + type_name(t) + " " +
@@ -297,18 +332,15 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
                   std::to_string(A.elem) + " and " + type_name(B.type) + " " + std::to_string(B.elem);
             return false;
         }
-        double ca[21], cb[21];
-        for (int k = 0; k < n_geom(A.type); ++k) ca[k] = TA.geom[size_t(k) * TA.nelem + A.elem];
-        for (int k = 0; k < n_geom(B.type); ++k) cb[k] = TB.geom[size_t(k) * TB.nelem + B.elem];
         std::vector<char> used(fb1 - fb0, 0);
         double xbs[25][3];
         for (int jb = fb0; jb < fb1; ++jb) {
-            map_point(B.type, XB, &TB.ops.fpts[3 * jb], xbs[jb - fb0]);
+            elem_point(TB, B.type, B.elem, &TB.ops.fpts[3 * jb], xbs[jb - fb0]);
             for (int d = 0; d < 3; ++d) xbs[jb - fb0][d] += shift[d];
         }
         for (int ja = fa0; ja < fa1; ++ja) {
             double xa[3];
-            map_point(A.type, XA, &TA.ops.fpts[3 * ja], xa);
+            elem_point(TA, A.type, A.elem, &TA.ops.fpts[3 * ja], xa);
             int best = -1;
             double bd = 1e300;
             for (int jb = fb0; jb < fb1; ++jb) {
@@ -328,13 +360,13 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
             q.L = pack_side(A.elem, ja, A.type);
             q.R = pack_side(B.elem, best, B.type);
             double col[3][3], adj[3][3], nA[3], nB[3];
-            jac_at(A.type, ca, &TA.ops.fpts[3 * ja], col);
+            elem_jac(TA, A.type, A.elem, &TA.ops.fpts[3 * ja], col);
             adjugate(col, adj);
             for (int jd = 0; jd < 3; ++jd) {
                 nA[jd] = 0;
                 for (int k = 0; k < 3; ++k) nA[jd] += adj[k][jd] * TA.ops.nref[3 * ja + k];
             }
-            jac_at(B.type, cb, &TB.ops.fpts[3 * best], col);
+            elem_jac(TB, B.type, B.elem, &TB.ops.fpts[3 * best], col);
             adjugate(col, adj);
             for (int jd = 0; jd < 3; ++jd) {
                 nB[jd] = 0;
@@ -383,11 +415,9 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         for (const auto &b : bl) {
             const int t = int(b[0]);
             const TypeHost &T = m.t[t];
-            double c[21];
-            for (int k = 0; k < n_geom(t); ++k) c[k] = T.geom[size_t(k) * T.nelem + b[1]];
             for (int j = T.ops.face_off[b[2]]; j < T.ops.face_off[b[2] + 1]; ++j) {
                 double col[3][3], adj[3][3], nn[3];
-                jac_at(t, c, &T.ops.fpts[3 * j], col);
+                elem_jac(T, t, b[1], &T.ops.fpts[3 * j], col);
                 adjugate(col, adj);
                 for (int jd = 0; jd < 3; ++jd) {
                     nn[jd] = 0;
@@ -475,12 +505,23 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
         T.nelem = n;
         T.ld = (n + 63) / 64 * 64;
         if (!n) continue;
+        int ncurved = 0, nparts = 0;
+        for (const auto &P : parts)
+            if (P.t[t].nelem) {
+                ++nparts;
+                ncurved += !P.t[t].Xq.empty();
+            }
+        if (ncurved && ncurved != nparts) {
+            err = "merged meshes of one order must be all curved or all straight for each type";
+            return false;
+        }
         const int ng = n_geom(t);
         T.geom.assign(size_t(ng) * n, 0.0);
         for (size_t i = 0; i < parts.size(); ++i) {
             const TypeHost &P = parts[i].t[t];
             if (!P.nelem) continue;
             T.X.insert(T.X.end(), P.X.begin(), P.X.end());
+            T.Xq.insert(T.Xq.end(), P.Xq.begin(), P.Xq.end());
             T.jdet.insert(T.jdet.end(), P.jdet.begin(), P.jdet.end());
             for (int k = 0; k < ng; ++k)
                 std::copy(P.geom.begin() + size_t(k) * P.nelem, P.geom.begin() + size_t(k + 1) * P.nelem,

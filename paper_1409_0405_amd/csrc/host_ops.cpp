@@ -650,6 +650,77 @@ std::vector<double> build_projection(int etype, int p, int q) {
     return std::vector<double>(P.begin(), P.end());
 }
 
+int n_qnodes(int etype) { return etype == 0 ? 10 : (etype == 1 ? 18 : 27); }
+
+namespace {
+// Order-2 geometry basis of one type: monomials xi^a eta^b zeta^c of the
+// element's order-2 space and the inverse of their Vandermonde matrix at the
+// lattice nodes.
+struct QuadBasis {
+    int nq = 0;
+    std::vector<int> e;       // [nq][3] monomial exponents
+    std::vector<ld> Vinv;     // [nq][nq]
+};
+
+QuadBasis make_quad_basis(int etype) {
+    QuadBasis B;
+    for (int a = 0; a <= 2; ++a)
+        for (int b = 0; b <= (etype == 2 ? 2 : 2 - a); ++b)
+            for (int c = 0; c <= (etype == 0 ? 2 - a - b : 2); ++c) {
+                B.e.push_back(a);
+                B.e.push_back(b);
+                B.e.push_back(c);
+            }
+    B.nq = int(B.e.size() / 3);
+    std::vector<ld> nodes;
+    for (int c = 0; c <= 2; ++c)
+        for (int b = 0; b <= (etype == 0 ? 2 - c : 2); ++b)
+            for (int a = 0; a <= (etype == 2 ? 2 : (etype == 0 ? 2 - b - c : 2 - b)); ++a) {
+                nodes.push_back(a - 1);
+                nodes.push_back(b - 1);
+                nodes.push_back(c - 1);
+            }
+    if (int(nodes.size() / 3) != B.nq) throw std::runtime_error("quadratic lattice size");
+    B.Vinv.assign(size_t(B.nq) * B.nq, 0);
+    for (int i = 0; i < B.nq; ++i)
+        for (int m = 0; m < B.nq; ++m)
+            B.Vinv[size_t(i) * B.nq + m] =
+                ipow(nodes[3 * i], B.e[3 * m]) * ipow(nodes[3 * i + 1], B.e[3 * m + 1]) * ipow(nodes[3 * i + 2], B.e[3 * m + 2]);
+    invert(B.Vinv, B.nq);
+    return B;
+}
+
+const QuadBasis &quad_basis(int etype) {
+    static const QuadBasis b[3] = {make_quad_basis(0), make_quad_basis(1), make_quad_basis(2)};
+    return b[etype];
+}
+}  // namespace
+
+void quad_shape(int etype, const double *xi, double *N, double *dN) {
+    const QuadBasis &B = quad_basis(etype);
+    const int nq = B.nq;
+    ld v[27], d[3][27];
+    for (int m = 0; m < nq; ++m) {
+        const int a = B.e[3 * m], b = B.e[3 * m + 1], c = B.e[3 * m + 2];
+        const ld x = xi[0], y = xi[1], z = xi[2];
+        v[m] = ipow(x, a) * ipow(y, b) * ipow(z, c);
+        d[0][m] = a ? a * ipow(x, a - 1) * ipow(y, b) * ipow(z, c) : 0;
+        d[1][m] = b ? b * ipow(x, a) * ipow(y, b - 1) * ipow(z, c) : 0;
+        d[2][m] = c ? c * ipow(x, a) * ipow(y, b) * ipow(z, c - 1) : 0;
+    }
+    for (int n = 0; n < nq; ++n) {
+        ld s = 0, g[3] = {0, 0, 0};
+        for (int m = 0; m < nq; ++m) {
+            const ld w = B.Vinv[size_t(m) * nq + n];
+            s += v[m] * w;
+            for (int k = 0; k < 3; ++k) g[k] += d[k][m] * w;
+        }
+        if (N) N[n] = double(s);
+        if (dN)
+            for (int k = 0; k < 3; ++k) dN[3 * n + k] = double(g[k]);
+    }
+}
+
 const RefOps &ref_cached(int etype, int p) {
     static std::mutex mu;
     static std::map<std::pair<int, int>, RefOps> cache;

@@ -72,6 +72,8 @@ class fr_mesh_desc(ctypes.Structure):
         ("hex_img", ctypes.POINTER(ctypes.c_int8)),
         ("n_bfaces", ctypes.c_int64), ("bfaces", ctypes.POINTER(ctypes.c_int64)),
         ("t_wall", ctypes.c_double), ("farfield", ctypes.c_double * 5),
+        ("tet_q", ctypes.POINTER(ctypes.c_double)), ("pri_q", ctypes.POINTER(ctypes.c_double)),
+        ("hex_q", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -195,6 +197,12 @@ def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=
     keep.append(bf)
     d.n_bfaces = len(bf)
     d.bfaces = _ptr(bf, ctypes.c_int64) if len(bf) else None
+    for kind, nq in (("tet", 10), ("pri", 18), ("hex", 27)):
+        q = mesh_arrays.get(f"{kind}_q")
+        if q is not None and len(q):
+            q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, nq, 3)
+            keep.append(q)
+            setattr(d, f"{kind}_q", _ptr(q, ctypes.c_double))
     d.t_wall = float(t_wall)
     for k in range(5):
         d.farfield[k] = float(farfield[k])

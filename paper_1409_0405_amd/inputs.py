@@ -272,6 +272,71 @@ def hex_box(n, lengths=(2.0 * math.pi,) * 3, jitter=0.0, seed=0, y_bc=None):
     return hybrid_box(n, n, n, n, n, lengths, jitter=jitter, seed=seed, y_bc=y_bc)
 
 
+def _order2_lattice(kind):
+    """Reference coordinates of an element's order-2 node lattice, the node
+    order of the mesh format's quadratic geometry: tet (a, b, c) with
+    a + b + c <= 2, prism (a, b) with a + b <= 2 times c <= 2, hexahedron
+    (a, b, c) <= 2; coordinates -1 + index; c outermost, a innermost."""
+    pts = []
+    for c in range(3):
+        nb = 3 - c if kind == "tet" else 3
+        for b in range(nb):
+            na = 3 if kind == "hex" else (3 - b - c if kind == "tet" else 3 - b)
+            for a in range(na):
+                pts.append((a - 1.0, b - 1.0, c - 1.0))
+    return np.array(pts)
+
+
+def _straight_points(kind, X, r):
+    """Positions of reference points r [n][3] under the straight-sided map of
+    elements with unwrapped vertices X [E][nv][3] -> [E][n][3]."""
+    x, y, z = r[:, 0], r[:, 1], r[:, 2]
+    if kind == "tet":
+        W = np.stack([-(1 + x + y + z) / 2, (1 + x) / 2, (1 + y) / 2, (1 + z) / 2], -1)
+    elif kind == "pri":
+        tri = [-(x + y) / 2, (1 + x) / 2, (1 + y) / 2]
+        W = np.stack([t * (1 - z) / 2 for t in tri] + [t * (1 + z) / 2 for t in tri], -1)
+    else:
+        sg = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                       [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+        W = np.prod(1 + r[:, None, :] * sg[None], axis=-1) / 8
+    return np.einsum("na,eai->eni", W, X)
+
+
+def curve(mesh, amp=0.02):
+    """Quadratically curved version of a straight mesh: every element gets
+    the nodes of its order-2 lattice (``tet_q`` [E][10][3], ``pri_q``
+    [E][18][3], ``hex_q`` [E][27][3], unwrapped), placed by the straight map
+    and then moved by the smooth deformation x_i += amp L_i prod_{j != i}
+    sin(2 pi x_j / L_j), periodic in the periodic directions (a bounded
+    direction i instead gets a factor sin(pi x_i / L_i) so its boundary
+    planes stay flat).  Vertices move with the same deformation, so shared
+    nodes coincide and faces stay conforming."""
+    per = np.asarray(mesh["period"], dtype=np.float64)
+    ext = np.where(per > 0, per, mesh["xyz"].max(axis=0) - mesh["xyz"].min(axis=0))
+
+    def phi(x):
+        s = np.sin(2 * np.pi * x / ext)
+        out = x.copy()
+        for i in range(3):
+            j, k = [d for d in range(3) if d != i]
+            d = amp * ext[i] * s[..., j] * s[..., k]
+            if per[i] == 0:
+                d = d * np.sin(np.pi * x[..., i] / ext[i])
+            out[..., i] = x[..., i] + d
+        return out
+
+    out = dict(mesh)
+    out["xyz"] = phi(np.asarray(mesh["xyz"], dtype=np.float64))
+    for kind in ("tet", "pri", "hex"):
+        v = mesh.get(f"{kind}_v")
+        if v is None or not len(v):
+            continue
+        X = mesh["xyz"][v] + mesh[f"{kind}_img"].astype(np.float64) * per
+        out[f"{kind}_q"] = np.ascontiguousarray(phi(_straight_points(kind, X, _order2_lattice(kind))))
+    return out
+
+
 def unwrapped(mesh, kind):
     """Unwrapped vertex coordinates [n_elem][n_vert][3] of 'tet', 'pri' or 'hex'."""
     v = mesh[f"{kind}_v"]

@@ -74,6 +74,17 @@ def test_full_size_mesh_validates():
     assert M.query(1)["nupts"] == 75 and M.query(1)["nfpts"] == 105
 
 
+@pytest.mark.parametrize("p", (1, 4))
+def test_curved_coordinates_and_operators_match_oracle(p):
+    """Quadratically curved three-type box: solution-point positions from the
+    library's quadratic map equal the oracle's."""
+    arrays = inputs.curve(_hybrid(4), 0.03)
+    M = frlib.Mesh(arrays, p, system="ns", validate_only=True)
+    O = om.build_mesh(arrays, p)
+    for t, name in enumerate(frlib.TYPE_NAMES):
+        assert np.abs(M.upts_coords(t) - np.transpose(O.types[name].x_upts, (1, 2, 0))).max() < 1e-12
+
+
 def test_hex_box_sizes_validate():
     """Table 2 sizes of the hexahedron at p = 4 and the element count of a
     periodic hexahedral box."""

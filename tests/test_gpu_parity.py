@@ -110,13 +110,16 @@ CASES = [
     ("wallbox", 1, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
     ("farbox", 2, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
     ("farbox", 4, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("curved", 2, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
+    ("curved", 4, "euler", inputs.taylor_green, {"mach": 0.3}, 0.0),
+    ("curvedwall", 3, "ns", inputs.taylor_green, {"mach": 0.3}, 0.02),
 ]
 
 # Boundary data of the bounded boxes, on the scale of the Taylor-Green state
 # at Mach 0.3 (rho0 = 1, p0 = 1 / (gamma Ma^2)): wall temperature p0 / rho0,
 # a free stream crossing the far-field planes.
 P0 = 1.0 / (1.4 * 0.09)
-BC = {"wallbox": {"t_wall": P0}, "farbox": {"farfield": (1.0, 0.2, 0.3, -0.1, P0)}}
+BC = {"wallbox": {"t_wall": P0}, "farbox": {"farfield": (1.0, 0.2, 0.3, -0.1, P0)}, "curvedwall": {"t_wall": P0}}
 
 
 def _mesh(kind, seed=0):
@@ -132,6 +135,11 @@ def _mesh(kind, seed=0):
         # all three types, conforming: 36 hexahedra, 144 prisms (both
         # orientations), 216 tets
         return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed)
+    if kind in ("curved", "curvedwall"):
+        # quadratically curved three-type box (smooth periodic deformation),
+        # periodic or bounded by walls in y
+        return inputs.curve(inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed,
+                                              y_bc="wall" if kind == "curvedwall" else None), 0.03)
     if kind in ("wallbox", "farbox"):
         # the three-type box bounded in y by walls or far-field planes
         return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=seed,
@@ -178,7 +186,8 @@ def test_rhs_fp32_parity(case):
 
 
 @pytest.mark.parametrize("kind,p,system", [("mixed", 2, "ns"), ("mixed", 4, "ns"), ("mixed", 3, "euler"),
-                                           ("hybrid", 3, "ns"), ("wallbox", 2, "ns"), ("farbox", 3, "ns")])
+                                           ("hybrid", 3, "ns"), ("wallbox", 2, "ns"), ("farbox", 3, "ns"),
+                                           ("curved", 4, "ns")])
 def test_interface_intermediates_fp64(kind, p, system):
     """State at flux points, common normal flux and (NS) the gradient at flux
     points, element by element."""
