@@ -38,13 +38,113 @@ RIDGE = PEAK_FP32_MFMA / PEAK_HBM
 
 # HBM bytes per launch measured with rocprofv3 --pmc on this workload
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors read off the state
-# copies of known size), per kernel class and operator-product variant
-# (16-row blocks per wavefront, staging); profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md.
-# A variant not listed here reports traffic null.
+# copies of known size), keyed (kernel class, 16-row blocks per wavefront,
+# stage) for the products and (class, 0, 0) for the point-wise kernels;
+# profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md.  A variant not listed here
+# reports traffic null.
 MEASURED_TRAFFIC = {
-    ("grad_pri", 4, 0): 898.3e6,
-    ("grad_pri", 2, 1): 900.8e6,
+    ('common_flux', 0, 0): 1966.1e6,
+    ('common_solution', 0, 0): 795.8e6,
+    ('div_pri', 5, 0): 901.6e6,
+    ('div_tet', 3, 0): 787.0e6,
+    ('grad_pri', 1, 0): 897.2e6,
+    ('grad_pri', 1, 3): 897.3e6,
+    ('grad_pri', 1, 4): 897.6e6,
+    ('grad_pri', 1, 5): 903.0e6,
+    ('grad_pri', 2, 0): 897.4e6,
+    ('grad_pri', 2, 1): 899.3e6,
+    ('grad_pri', 2, 2): 901.2e6,
+    ('grad_pri', 2, 3): 897.6e6,
+    ('grad_pri', 2, 4): 898.3e6,
+    ('grad_pri', 2, 5): 913.4e6,
+    ('grad_pri', 3, 0): 898.6e6,
+    ('grad_pri', 3, 1): 899.3e6,
+    ('grad_pri', 3, 2): 901.2e6,
+    ('grad_pri', 3, 3): 903.2e6,
+    ('grad_pri', 3, 4): 901.1e6,
+    ('grad_pri', 3, 5): 938.0e6,
+    ('grad_pri', 4, 0): 898.8e6,
+    ('grad_pri', 4, 1): 900.3e6,
+    ('grad_pri', 4, 2): 905.3e6,
+    ('grad_pri', 4, 3): 898.2e6,
+    ('grad_pri', 4, 4): 906.2e6,
+    ('grad_pri', 4, 5): 903.5e6,
+    ('grad_pri', 5, 0): 903.8e6,
+    ('grad_pri', 5, 1): 899.7e6,
+    ('grad_pri', 5, 2): 905.4e6,
+    ('grad_pri', 5, 3): 910.3e6,
+    ('grad_pri', 5, 4): 908.0e6,
+    ('grad_pri', 8, 0): 907.7e6,
+    ('grad_pri', 8, 1): 903.2e6,
+    ('grad_pri', 8, 2): 2182.8e6,
+    ('grad_pri', 8, 3): 902.9e6,
+    ('grad_tet', 7, 0): 788.0e6,
+    ('gradinterp_pri', 1, 0): 1194.7e6,
+    ('gradinterp_pri', 1, 1): 1194.7e6,
+    ('gradinterp_pri', 1, 2): 1194.7e6,
+    ('gradinterp_pri', 1, 3): 1194.8e6,
+    ('gradinterp_pri', 1, 4): 1194.8e6,
+    ('gradinterp_pri', 1, 5): 1200.9e6,
+    ('gradinterp_pri', 2, 0): 1194.7e6,
+    ('gradinterp_pri', 2, 1): 1194.8e6,
+    ('gradinterp_pri', 2, 2): 1194.9e6,
+    ('gradinterp_pri', 2, 3): 1194.8e6,
+    ('gradinterp_pri', 2, 4): 1194.9e6,
+    ('gradinterp_pri', 2, 5): 1207.0e6,
+    ('gradinterp_pri', 3, 0): 1194.8e6,
+    ('gradinterp_pri', 3, 1): 1195.0e6,
+    ('gradinterp_pri', 3, 2): 1195.0e6,
+    ('gradinterp_pri', 3, 3): 1195.0e6,
+    ('gradinterp_pri', 3, 4): 1195.6e6,
+    ('gradinterp_pri', 3, 5): 1199.3e6,
+    ('gradinterp_pri', 4, 0): 1194.9e6,
+    ('gradinterp_pri', 4, 1): 1195.0e6,
+    ('gradinterp_pri', 4, 2): 1195.1e6,
+    ('gradinterp_pri', 4, 3): 1194.9e6,
+    ('gradinterp_pri', 4, 4): 1195.4e6,
+    ('gradinterp_pri', 4, 5): 1198.0e6,
+    ('gradinterp_pri', 7, 0): 1195.5e6,
+    ('gradinterp_pri', 7, 1): 1195.3e6,
+    ('gradinterp_pri', 7, 2): 2030.7e6,
+    ('gradinterp_pri', 7, 3): 1197.2e6,
+    ('gradinterp_pri', 7, 4): 1196.8e6,
+    ('gradinterp_tet', 4, 0): 1120.8e6,
+    ('interp_pri', 7, 0): 399.1e6,
+    ('interp_tet', 4, 0): 373.8e6,
+    ('negdivconf_pri', 0, 0): 365.0e6,
+    ('negdivconf_tet', 0, 0): 302.8e6,
+    ('upts_pri', 0, 0): 1811.4e6,
+    ('upts_tet', 0, 0): 1570.3e6,
 }
+
+
+PRODUCT_OPS = {"interp": 0, "grad": 1, "gradinterp": 2, "div": 3}
+TYPE_SHORT = ("tet", "pri", "hex")
+
+
+def product_row_blocks(mesh, k):
+    """16-row blocks of the operator of product kernel class k ('grad_pri',
+    ...), and its (element type, operator) indices; None for other kernels."""
+    op, _, name = k.partition("_")
+    if op not in PRODUCT_OPS or name not in TYPE_SHORT:
+        return None
+    t = TYPE_SHORT.index(name)
+    q = mesh.query(t)
+    M = {"interp": q["nfpts"], "gradinterp": q["nfpts"], "grad": 3 * q["nupts"], "div": q["nupts"]}[op]
+    return -(-M // 16), t, PRODUCT_OPS[op]
+
+
+def variant_of(mesh, k, report):
+    """(rows blocks per wavefront, stage) the autotuner chose for product k."""
+    rb = product_row_blocks(mesh, k)
+    if rb is None:
+        return None
+    Mb, t, op = rb
+    m_ = re.search(rf"{TYPE_SHORT[t]} op{op} cap (\d+) stage (\d+)", report or "")
+    if not m_:
+        return None
+    nmg = -(-Mb // int(m_.group(1)))
+    return -(-Mb // nmg), int(m_.group(2))
 
 
 def operator_nnz(mesh, t):
@@ -380,9 +480,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-hex", action="store_true", help="skip the hexahedral and three-type workloads")
+    ap.add_argument("--workload", choices=("mixed", "hex", "hybrid"), default="mixed",
+                    help="hex / hybrid: run only that workload's form (for profiling) and print it")
     ap.add_argument("--variants", action="store_true",
-                    help="time every product variant of the prism corrected-gradient "
-                         "operator on this workload (one JSON line) instead of the bench")
+                    help="time every variant of the prism corrected-gradient and gradient-"
+                         "interpolation products on this workload (one JSON line) instead of the bench")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -399,6 +501,25 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     mu, mach, pr, p = 1.0 / 1600.0, 0.1, 0.71, 4
+    L = 2 * math.pi
+
+    def hex_form():
+        hx = workload_form("hex", inputs.hex_box(50, jitter=0.10, seed=0), L / 50, args.steps, args.warmup,
+                           mach, mu, pr, stream)
+        hx["workload"] = "periodic [0,2pi)^3, 50^3 hexahedra (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32"
+        return hx
+
+    def hybrid_form():
+        hy = workload_form("hybrid", inputs.hybrid_box(48, 48, 48, 24, 24, (L, L, L), jitter=0.10, seed=0),
+                           L / 48, args.steps, args.warmup, mach, mu, pr, stream)
+        hy["workload"] = ("periodic [0,2pi)^3, 48^3 cells: hexahedra | z-prisms below, x-prisms | Kuhn tets "
+                          "above (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32")
+        return hy
+
+    if args.workload != "mixed":
+        print(json.dumps({"form": args.workload, **(hex_form() if args.workload == "hex" else hybrid_form())}),
+              flush=True)
+        return
     arrays = inputs.tgv_mixed_box()
 
     tuned = {}
@@ -487,27 +608,32 @@ def main():
         return out
 
     if args.variants:
-        # every (row blocks per wavefront, staging) variant of the dominant
-        # product, six RHS evaluations each; used with rocprofv3 --pmc to
-        # measure each variant's HBM traffic
+        # every (row blocks per wavefront, staging) variant of the two largest
+        # prism products, six RHS evaluations each; used with rocprofv3 --pmc
+        # to measure each variant's HBM traffic
         u = [frlib.to_device_state(mesh, t, host_state[t]) for t in (0, 1)]
         r = [frlib.state_tensor(mesh, t) for t in (0, 1)]
-        rows = []
-        for stage in (0, 1, 2, 3, 4):
-            for cap in (1, 2, 3, 4, 5, 6, 8):
-                try:
-                    mesh.set_blocking(1, 1, cap, stage)
-                except frlib.FrError:
-                    continue
-                mesh.profile(True)
-                for _ in range(6):
-                    mesh.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r], stream)
-                ms, cnt = mesh.profile_read()["grad_pri"]
-                mesh.profile(False)
-                nmg = -(-15 // cap)
-                rows.append({"cap": cap, "rows_blocks_per_wave": -(-15 // nmg), "stage": stage,
-                             "avg_us": 1e3 * ms / cnt})
-        print(json.dumps({"variants_grad_pri": rows}), flush=True)
+        out_v = {}
+        for k in ("grad_pri", "gradinterp_pri"):
+            Mb, t, op = product_row_blocks(mesh, k)
+            rows = []
+            for stage in (0, 1, 2, 3, 4, 5):
+                print(f"variants {k} stage {stage}", file=sys.stderr, flush=True)
+                for cap in (1, 2, 3, 4, 5, 6, 8):
+                    try:
+                        mesh.set_blocking(t, op, cap, stage)
+                    except frlib.FrError:
+                        continue
+                    mesh.profile(True)
+                    for _ in range(6):
+                        mesh.rhs([x.data_ptr() for x in u], [x.data_ptr() for x in r], stream)
+                    ms, cnt = mesh.profile_read()[k]
+                    mesh.profile(False)
+                    nmg = -(-Mb // cap)
+                    rows.append({"cap": cap, "rows_blocks_per_wave": -(-Mb // nmg), "stage": stage,
+                                 "avg_us": 1e3 * ms / cnt})
+            out_v[k] = rows
+        print(json.dumps({"variants": out_v}), flush=True)
         return
 
     ms_per_step, value, drift, finite = timed(mesh, args.steps, args.warmup)
@@ -560,13 +686,10 @@ def main():
             roof = {"bound": "hbm", "achieved": mdl["bytes"] / avg / 1e9, "peak": 8000.0,
                     "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
-        m_ = re.search(r"pri op1 cap (\d+) stage (\d+)", tuned.get("fp32", "")) if k == "grad_pri" else None
-        if m_:
-            cap_, stage_ = int(m_.group(1)), int(m_.group(2))
-            nmg_ = -(-15 // cap_)                  # 225 rows = 15 blocks of 16
-            roof["variant"] = {"rows_blocks_per_wave": -(-15 // nmg_), "stage": stage_}
-            roof["traffic"] = MEASURED_TRAFFIC.get((k, -(-15 // nmg_), stage_))
+        vt = variant_of(mesh, k, tuned.get("fp32", ""))
+        if vt:
+            roof["variant"] = {"rows_blocks_per_wave": vt[0], "stage": vt[1]}
+        roof["traffic"] = MEASURED_TRAFFIC.get((k,) + (vt or (0, 0)))
         roof["kernel"] = k
         roof["avg_launch_us"] = avg * 1e6
         roof["share_of_step"] = ms / tot
@@ -629,16 +752,10 @@ def main():
         mesh.close()
         torch.cuda.empty_cache()
         forms = forms or {}
-        L = 2 * math.pi
-        hx = workload_form("hex", inputs.hex_box(50, jitter=0.10, seed=0), L / 50, args.steps, args.warmup,
-                           mach, mu, pr, stream)
-        hx["workload"] = "periodic [0,2pi)^3, 50^3 hexahedra (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32"
+        hx = hex_form()
         forms["hex_p4"] = hx
         print(f"hex: {hx}", file=sys.stderr, flush=True)
-        hy = workload_form("hybrid", inputs.hybrid_box(48, 48, 48, 24, 24, (L, L, L), jitter=0.10, seed=0),
-                           L / 48, args.steps, args.warmup, mach, mu, pr, stream)
-        hy["workload"] = ("periodic [0,2pi)^3, 48^3 cells: hexahedra | z-prisms below, x-prisms | Kuhn tets "
-                          "above (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32")
+        hy = hybrid_form()
         forms["hybrid_p4"] = hy
         print(f"hybrid: {hy}", file=sys.stderr, flush=True)
 
