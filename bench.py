@@ -205,6 +205,20 @@ def kernel_model(mesh, system):
     return out
 
 
+def boundary_points(arrays, p):
+    """Flux points on the listed boundary faces (order p): (p+1)(p+2)/2 per
+    triangle, (p+1)^2 per quadrilateral."""
+    from paper_1409_0405_amd import inputs
+    bf = arrays.get("bfaces")
+    if bf is None:
+        return 0
+    n = 0
+    for t, _, f, _ in bf:
+        nv = len(inputs.LOCAL_FACES[("tet", "pri", "hex")[t]][f])
+        n += (p + 1) * (p + 2) // 2 if nv == 3 else (p + 1) ** 2
+    return n
+
+
 def cpu_baseline(target_seconds):
     """The FP64 oracle on a bounded sample of the same workload (same mesh
     structure, order and physics, fewer elements)."""
@@ -399,14 +413,15 @@ def roofline_of(model, avg_s, k):
     return roof
 
 
-def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=0.3, p=4):
+def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=0.3, p=4, **mesh_kw):
     """Another mesh of the same physics (NS Taylor-Green, p = 4, FP32,
     autotuned): RK45[2R+] steps timed like the main workload, then a
-    per-kernel profile and the dominant kernel's roofline."""
+    per-kernel profile and the dominant kernel's roofline.  mesh_kw: boundary
+    data (t_wall, farfield) of bounded meshes."""
     import numpy as np
     import torch
     from paper_1409_0405_amd import frlib, inputs
-    m = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=mu, prandtl=pr, stream=stream)
+    m = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=mu, prandtl=pr, stream=stream, **mesh_kw)
     report = m.autotune(stream)
     print(f"autotune {name}: {report}", file=sys.stderr, flush=True)
     types, dof, counts = [], 0, {}
@@ -448,6 +463,11 @@ def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=
     prof = m.profile_read()
     m.profile(False)
     model = kernel_model(m, "ns")
+    nbp = boundary_points(arrays, p)
+    if nbp:
+        # boundary points: state and gradient traces in, the jump and the flux out
+        model["boundary_solution"] = {"flops": 0.0, "bytes": float(4 * (5 + 5) * nbp + 17 * nbp)}
+        model["boundary_flux"] = {"flops": 0.0, "bytes": float(4 * (5 + 15 + 5) * nbp + 17 * nbp)}
     rows = sorted(((ms, k, cnt) for k, (ms, cnt) in prof.items() if cnt), reverse=True)
     tot = sum(r[0] for r in rows)
     kern = {}
@@ -480,8 +500,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-hex", action="store_true", help="skip the hexahedral and three-type workloads")
-    ap.add_argument("--workload", choices=("mixed", "hex", "hybrid"), default="mixed",
-                    help="hex / hybrid: run only that workload's form (for profiling) and print it")
+    ap.add_argument("--workload", choices=("mixed", "hex", "hybrid", "curved_wall"), default="mixed",
+                    help="hex / hybrid / curved_wall: run only that workload's form (for profiling) and print it")
     ap.add_argument("--variants", action="store_true",
                     help="time every variant of the prism corrected-gradient and gradient-"
                          "interpolation products on this workload (one JSON line) instead of the bench")
@@ -516,9 +536,18 @@ def main():
                           "above (jitter 10 %), NS TGV Re1600 Ma0.1, p=4, FP32")
         return hy
 
+    def curved_wall_form():
+        # walls at the Taylor-Green temperature p0 / rho0 = 1 / (gamma Ma^2)
+        cw = workload_form("curved_wall", inputs.curve(inputs.hybrid_box(48, 48, 48, 24, 24, (L, L, L), jitter=0.05,
+                                                                        seed=0, y_bc="wall"), 0.02),
+                           L / 48, args.steps, args.warmup, mach, mu, pr, stream, t_wall=1.0 / (1.4 * mach * mach))
+        cw["workload"] = ("the 48^3-cell three-type box bounded by no-slip isothermal walls at y = 0, 2pi and "
+                          "quadratically curved (deformation amplitude 2 %, jitter 5 %), NS TGV Re1600 Ma0.1, p=4, FP32")
+        return cw
+
     if args.workload != "mixed":
-        print(json.dumps({"form": args.workload, **(hex_form() if args.workload == "hex" else hybrid_form())}),
-              flush=True)
+        form = {"hex": hex_form, "hybrid": hybrid_form, "curved_wall": curved_wall_form}[args.workload]
+        print(json.dumps({"form": args.workload, **form()}), flush=True)
         return
     arrays = inputs.tgv_mixed_box()
 
@@ -758,6 +787,9 @@ def main():
         hy = hybrid_form()
         forms["hybrid_p4"] = hy
         print(f"hybrid: {hy}", file=sys.stderr, flush=True)
+        cw = curved_wall_form()
+        forms["curved_wall_p4"] = cw
+        print(f"curved wall: {cw}", file=sys.stderr, flush=True)
 
     peaks = None
     if not args.no_peaks:

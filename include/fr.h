@@ -263,12 +263,12 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * FR_PROF_NCLASS), and clears the records.  Classes: 4 * etype + op for the
  * operator products of tets and prisms (op 0 interpolation to flux points, 1
  * corrected gradient, 2 gradient interpolation, 3 divergence plus
- * correction), 8 + etype the solution-point flux kernel, 10 common solution
- * (and the boundary states), 11 common interface flux (and the boundary
- * flux), 12 + etype negdivconf with the Runge-Kutta update, 14 closure inputs (moments and neighbour gathering), 15 closure
+ * correction), 8 + etype the solution-point flux kernel, 10 common solution,
+ * 11 common interface flux, 12 + etype negdivconf with the Runge-Kutta
+ * update, 14 closure inputs (moments and neighbour gathering), 15 closure
  * network forward; hexahedra: 16 + op the products, 20 the solution-point
- * kernel, 21 negdivconf. */
-#define FR_PROF_NCLASS 22
+ * kernel, 21 negdivconf; 22 boundary states, 23 boundary flux. */
+#define FR_PROF_NCLASS 24
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 

@@ -143,7 +143,7 @@ fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
 // tets and prisms, 8/9 solution-point kernel (tet/prism), 10 common solution,
 // 11 common flux, 12/13 negdivconf (tet/prism), 14/15 closure, 16..19
 // hexahedron products (16 + op), 20 hexahedron solution-point kernel, 21
-// hexahedron negdivconf.
+// hexahedron negdivconf, 22 / 23 boundary states / boundary flux.
 constexpr int PROF_NCLASS = FR_PROF_NCLASS;
 constexpr int prof_op(int t, int op) { return t < 2 ? 4 * t + op : 16 + op; }
 constexpr int prof_upts(int t) { return t < 2 ? 8 + t : 20; }
@@ -498,7 +498,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             for (int i = 0; i < nu; ++i)
                 for (size_t e = 0; e < ld; ++e) {
                     double col[3][3];
-                    frh::elem_jac(H, t, int64_t(e < size_t(H.nelem) ? e : 0), &R.upts[3 * i], col);
+                    frh::elem_jac_at(H, t, int64_t(e < size_t(H.nelem) ? e : 0), false, i, col);
                     for (int k = 0; k < 3; ++k) {
                         const double *a1 = col[(k + 1) % 3], *a2 = col[(k + 2) % 3];
                         const double c3[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2],
@@ -678,7 +678,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     for (int k = 0; k < 5; ++k) ba.free[k] = T(m->farfield[k]);
     if (ns) {
         FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
-        if (d.nb) FR_LAUNCH(m, 10, s, frd::launch_boundary_solution<T>(ba, s));
+        if (d.nb) FR_LAUNCH(m, 22, s, frd::launch_boundary_solution<T>(ba, s));
         for (int t = 0; t < frh::NTYPE; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
@@ -701,7 +701,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
         }
     }
     FR_LAUNCH(m, 11, s, frd::launch_common_flux<T>(ns, pa, s));
-    if (d.nb) FR_LAUNCH(m, 11, s, frd::launch_boundary_flux<T>(ns, ba, s));
+    if (d.nb) FR_LAUNCH(m, 23, s, frd::launch_boundary_flux<T>(ns, ba, s));
     const Closure *cl = (m->closure && m->closure->params) ? m->closure.get() : nullptr;
     if (cl) {
         const int64_t ntot = d.t[0].nelem + d.t[1].nelem;
@@ -1284,7 +1284,7 @@ fr_status fr_upts_coords(fr_mesh m, int32_t etype, double *xyz) {
     for (int i = 0; i < nu; ++i)
         for (int64_t e = 0; e < H.nelem; ++e) {
             double x[3];
-            frh::elem_point(H, etype, e, &H.ops.upts[3 * i], x);
+            frh::elem_point_at(H, etype, e, false, i, x);
             for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * H.nelem + e] = x[d];
         }
     return FR_OK;
@@ -1626,7 +1626,7 @@ fr_status fr_batch_upts_coords(fr_batch b, int32_t problem, int32_t etype, doubl
     for (int i = 0; i < nu; ++i)
         for (int64_t e = 0; e < P.ne[etype]; ++e) {
             double x[3];
-            frh::elem_point(H, etype, P.off[etype] + e, &H.ops.upts[3 * i], x);
+            frh::elem_point_at(H, etype, P.off[etype] + e, false, i, x);
             for (int d = 0; d < 3; ++d) xyz[(size_t(i) * 3 + d) * P.ne[etype] + e] = x[d];
         }
     return FR_OK;

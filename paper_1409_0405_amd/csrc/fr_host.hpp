@@ -110,6 +110,9 @@ struct TypeHost {
     RefOps ops;
     std::vector<double> X;       // [nelem][nverts][3] unwrapped vertices
     std::vector<double> Xq;      // [nelem][nq][3] quadratic nodes (curved types), else empty
+    // curved types: shape functions and reference derivatives of the nodes at
+    // the solution points [nu][nq], [nu][nq][3] and flux points [nf][nq], [nf][nq][3]
+    std::vector<double> qN_u, qdN_u, qN_f, qdN_f;
     std::vector<double> geom;    // [n_geom][nelem]
     std::vector<double> jdet;    // [nelem][nu] Jacobian determinant at upts
 };
@@ -132,6 +135,12 @@ std::vector<int32_t> face_neighbours(const MeshHost &m);
 // reference point (straight or curved geometry).
 void elem_jac(const TypeHost &T, int t, int64_t e, const double *xi, double col[3][3]);
 void elem_point(const TypeHost &T, int t, int64_t e, const double *xi, double out[3]);
+// The same at solution point i (flux = false) or flux point i (flux = true),
+// from tabulated shape functions for curved types.
+void elem_jac_at(const TypeHost &T, int t, int64_t e, bool flux, int i, double col[3][3]);
+void elem_point_at(const TypeHost &T, int t, int64_t e, bool flux, int i, double out[3]);
+// Fill the tables above (curved types).
+void tabulate_quad(TypeHost &T, int t);
 
 // Per type t: nelem[t] elements, connectivity conn[t] [nelem][n_verts(t)],
 // periodic images img[t] (may be null), quadratic nodes quad[t] [nelem][nq][3]

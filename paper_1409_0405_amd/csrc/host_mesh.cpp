@@ -140,6 +140,46 @@ void elem_point(const TypeHost &T, int t, int64_t e, const double *xi, double ou
     map_point(t, &T.X[size_t(e) * n_verts(t) * 3], xi, out);
 }
 
+void tabulate_quad(TypeHost &T, int t) {
+    const int nq = n_qnodes(t), nu = T.ops.nu, nf = T.ops.nf;
+    T.qN_u.assign(size_t(nu) * nq, 0);
+    T.qdN_u.assign(size_t(nu) * nq * 3, 0);
+    T.qN_f.assign(size_t(nf) * nq, 0);
+    T.qdN_f.assign(size_t(nf) * nq * 3, 0);
+    for (int i = 0; i < nu; ++i) quad_shape(t, &T.ops.upts[3 * i], &T.qN_u[size_t(i) * nq], &T.qdN_u[size_t(i) * nq * 3]);
+    for (int i = 0; i < nf; ++i) quad_shape(t, &T.ops.fpts[3 * i], &T.qN_f[size_t(i) * nq], &T.qdN_f[size_t(i) * nq * 3]);
+}
+
+void elem_jac_at(const TypeHost &T, int t, int64_t e, bool flux, int i, double col[3][3]) {
+    if (T.Xq.empty()) {
+        elem_jac(T, t, e, flux ? &T.ops.fpts[3 * i] : &T.ops.upts[3 * i], col);
+        return;
+    }
+    const int nq = n_qnodes(t);
+    const double *dN = (flux ? T.qdN_f.data() : T.qdN_u.data()) + size_t(i) * nq * 3;
+    const double *Xq = &T.Xq[size_t(e) * nq * 3];
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) {
+            double s = 0;
+            for (int a = 0; a < nq; ++a) s += dN[3 * a + k] * Xq[3 * a + d];
+            col[k][d] = s;
+        }
+}
+
+void elem_point_at(const TypeHost &T, int t, int64_t e, bool flux, int i, double out[3]) {
+    if (T.Xq.empty()) {
+        elem_point(T, t, e, flux ? &T.ops.fpts[3 * i] : &T.ops.upts[3 * i], out);
+        return;
+    }
+    const int nq = n_qnodes(t);
+    const double *N = (flux ? T.qN_f.data() : T.qN_u.data()) + size_t(i) * nq;
+    const double *Xq = &T.Xq[size_t(e) * nq * 3];
+    for (int d = 0; d < 3; ++d) {
+        out[d] = 0;
+        for (int a = 0; a < nq; ++a) out[d] += N[a] * Xq[3 * a + d];
+    }
+}
+
 namespace {
 
 void cross3(const double *a, const double *b, double *c) {
@@ -183,7 +223,10 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         T.ops = ref_cached(t, p);
         const int nvt = n_verts(t), ng = n_geom(t), nu = T.ops.nu, nf = T.ops.nf;
         T.X.resize(size_t(T.nelem) * nvt * 3);
-        if (quad && quad[t]) T.Xq.assign(quad[t], quad[t] + size_t(T.nelem) * n_qnodes(t) * 3);
+        if (quad && quad[t]) {
+            T.Xq.assign(quad[t], quad[t] + size_t(T.nelem) * n_qnodes(t) * 3);
+            tabulate_quad(T, t);
+        }
         T.geom.assign(size_t(ng) * T.nelem, 0);
         T.jdet.resize(size_t(T.nelem) * nu);
         for (int64_t e = 0; e < T.nelem; ++e) {
@@ -205,9 +248,8 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
             for (int k = 0; k < ng; ++k) T.geom[size_t(k) * T.nelem + e] = c[k];
             // J > 0 at every solution and flux point
             for (int i = 0; i < nu + nf; ++i) {
-                const double *xi = i < nu ? &T.ops.upts[3 * i] : &T.ops.fpts[3 * (i - nu)];
                 double col[3][3], adj[3][3];
-                elem_jac(T, t, e, xi, col);
+                elem_jac_at(T, t, e, i >= nu, i < nu ? i : i - nu, col);
                 double J = adjugate(col, adj);
                 if (!(J > 0)) {
                     err = std::string("non-positive Jacobian in ") + type_name(t) + " " +
@@ -335,12 +377,12 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
         std::vector<char> used(fb1 - fb0, 0);
         double xbs[25][3];
         for (int jb = fb0; jb < fb1; ++jb) {
-            elem_point(TB, B.type, B.elem, &TB.ops.fpts[3 * jb], xbs[jb - fb0]);
+            elem_point_at(TB, B.type, B.elem, true, jb, xbs[jb - fb0]);
             for (int d = 0; d < 3; ++d) xbs[jb - fb0][d] += shift[d];
         }
         for (int ja = fa0; ja < fa1; ++ja) {
             double xa[3];
-            elem_point(TA, A.type, A.elem, &TA.ops.fpts[3 * ja], xa);
+            elem_point_at(TA, A.type, A.elem, true, ja, xa);
             int best = -1;
             double bd = 1e300;
             for (int jb = fb0; jb < fb1; ++jb) {
@@ -360,13 +402,13 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
             q.L = pack_side(A.elem, ja, A.type);
             q.R = pack_side(B.elem, best, B.type);
             double col[3][3], adj[3][3], nA[3], nB[3];
-            elem_jac(TA, A.type, A.elem, &TA.ops.fpts[3 * ja], col);
+            elem_jac_at(TA, A.type, A.elem, true, ja, col);
             adjugate(col, adj);
             for (int jd = 0; jd < 3; ++jd) {
                 nA[jd] = 0;
                 for (int k = 0; k < 3; ++k) nA[jd] += adj[k][jd] * TA.ops.nref[3 * ja + k];
             }
-            elem_jac(TB, B.type, B.elem, &TB.ops.fpts[3 * best], col);
+            elem_jac_at(TB, B.type, B.elem, true, best, col);
             adjugate(col, adj);
             for (int jd = 0; jd < 3; ++jd) {
                 nB[jd] = 0;
@@ -417,7 +459,7 @@ bool build_mesh_host(int p, int64_t nv, const double *xyz, const int64_t nelem[N
             const TypeHost &T = m.t[t];
             for (int j = T.ops.face_off[b[2]]; j < T.ops.face_off[b[2] + 1]; ++j) {
                 double col[3][3], adj[3][3], nn[3];
-                elem_jac(T, t, b[1], &T.ops.fpts[3 * j], col);
+                elem_jac_at(T, t, b[1], true, j, col);
                 adjugate(col, adj);
                 for (int jd = 0; jd < 3; ++jd) {
                     nn[jd] = 0;
@@ -522,6 +564,12 @@ bool merge_meshes(const std::vector<MeshHost> &parts, MeshHost &out,
             if (!P.nelem) continue;
             T.X.insert(T.X.end(), P.X.begin(), P.X.end());
             T.Xq.insert(T.Xq.end(), P.Xq.begin(), P.Xq.end());
+            if (!P.Xq.empty() && T.qN_u.empty()) {
+                T.qN_u = P.qN_u;
+                T.qdN_u = P.qdN_u;
+                T.qN_f = P.qN_f;
+                T.qdN_f = P.qdN_f;
+            }
             T.jdet.insert(T.jdet.end(), P.jdet.begin(), P.jdet.end());
             for (int k = 0; k < ng; ++k)
                 std::copy(P.geom.begin() + size_t(k) * P.nelem, P.geom.begin() + size_t(k + 1) * P.nelem,

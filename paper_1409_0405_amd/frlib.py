@@ -47,7 +47,8 @@ PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "interp_pri", "grad_pri", "gradinterp_pri", "div_pri",
                 "upts_tet", "upts_pri", "common_solution", "common_flux",
                 "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward",
-                "interp_hex", "grad_hex", "gradinterp_hex", "div_hex", "upts_hex", "negdivconf_hex")
+                "interp_hex", "grad_hex", "gradinterp_hex", "div_hex", "upts_hex", "negdivconf_hex",
+                "boundary_solution", "boundary_flux")
 
 
 class FrError(RuntimeError):
