@@ -1,0 +1,213 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (FP32, autotuned; and the FP64 build), on sampled elements.
+
+The oracle cannot evaluate a 307,200-element mesh in a test, but the
+Navier-Stokes residual of an element depends only on the states within two
+face-neighbour layers: its own gradient on the common solutions at its faces
+(neighbours' traces), the common viscous flux on the gradient of the
+neighbour on side L (whose common solutions involve the second layer).  So
+for each sampled element a patch of the mesh (the element and two layers of
+neighbours, away from the periodic seams) is cut out and evaluated by the
+oracle, with the patch's outer faces listed as boundary faces (they change
+only the outer layer's own residual).  Patch elements keep the full mesh's
+order, so the side L of every face is the same.  The sampled elements'
+residuals must match the full-size GPU evaluation.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as om, physics
+from paper_1409_0405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ("tet", "pri", "hex")
+MU, PR, MACH = 1.0 / 1600.0, 0.71, 0.3
+
+
+def _neighbours(arrays):
+    """Face-neighbour lists over global type-major element ids."""
+    keys, owner = [], []
+    base = 0
+    for name in NAMES:
+        v = arrays.get(f"{name}_v")
+        if v is None or not len(v):
+            continue
+        for face in inputs.LOCAL_FACES[name]:
+            k = np.sort(v[:, list(face)], axis=1)
+            if k.shape[1] == 3:
+                k = np.concatenate([np.full((len(k), 1), -1), k], axis=1)
+            keys.append(k)
+            owner.append(base + np.arange(len(v)))
+        base += len(v)
+    keys = np.concatenate(keys)
+    owner = np.concatenate(owner)
+    _, inv = np.unique(keys, axis=0, return_inverse=True)
+    order = np.argsort(inv.ravel(), kind="stable")
+    inv = inv.ravel()[order]
+    own = owner[order]
+    nb = [[] for _ in range(base)]
+    same = inv[1:] == inv[:-1]
+    for a, b in zip(own[:-1][same], own[1:][same]):
+        nb[a].append(b)
+        nb[b].append(a)
+    return nb, base
+
+
+def _patch(arrays, centre, nb):
+    """Mesh arrays of the element `centre` and two neighbour layers (global
+    type-major ids kept in order), outer faces listed as far-field faces."""
+    sel = {centre}
+    ring = {centre}
+    for _ in range(2):
+        ring = {n for e in ring for n in nb[e]} - sel
+        sel |= ring
+    sel = np.array(sorted(sel))
+    counts = [len(arrays.get(f"{n}_v", [])) for n in NAMES]
+    starts = np.cumsum([0] + counts)
+    out = {"period": np.zeros(3)}
+    vids = []
+    local = {}
+    for t, name in enumerate(NAMES):
+        g = sel[(sel >= starts[t]) & (sel < starts[t + 1])] - starts[t]
+        v = arrays[f"{name}_v"][g] if counts[t] else np.zeros((0, 4 if t == 0 else 6 if t == 1 else 8), np.int64)
+        if counts[t]:
+            assert not arrays[f"{name}_img"][g].any(), "patch crosses a periodic seam"
+        out[f"{name}_v"] = v
+        out[f"{name}_img"] = np.zeros(v.shape + (3,), np.int8)
+        vids.append(v.ravel())
+        for i, e in enumerate(g):
+            local[starts[t] + e] = (t, i)
+    uv, inv = np.unique(np.concatenate(vids), return_inverse=True)
+    out["xyz"] = arrays["xyz"][uv]
+    o = 0
+    for name in NAMES:
+        n = out[f"{name}_v"].size
+        out[f"{name}_v"] = inv[o:o + n].reshape(out[f"{name}_v"].shape)
+        o += n
+    # outer faces: faces of the patch with no partner inside it
+    keyset = {}
+    for t, name in enumerate(NAMES):
+        for e, verts in enumerate(out[f"{name}_v"]):
+            for fi, face in enumerate(inputs.LOCAL_FACES[name]):
+                keyset.setdefault(tuple(sorted(verts[list(face)])), []).append((t, e, fi))
+    out["bfaces"] = np.array([(t, e, fi, inputs.BC_FARFIELD) for lst in keyset.values() if len(lst) == 1
+                              for (t, e, fi) in lst], dtype=np.int64).reshape(-1, 4)
+    return out, local[centre]
+
+
+def _interior_sample(arrays, nb, n, seed, types):
+    """Seeded elements of the given types whose two-layer neighbourhood
+    touches no periodic seam."""
+    rng = np.random.default_rng(seed)
+    counts = [len(arrays.get(f"{nm}_v", [])) for nm in NAMES]
+    starts = np.cumsum([0] + counts)
+    seam = np.zeros(starts[-1], bool)
+    for t, nm in enumerate(NAMES):
+        if counts[t]:
+            seam[starts[t]:starts[t + 1]] = arrays[f"{nm}_img"].reshape(counts[t], -1).any(axis=1)
+    out = []
+    for t in types:
+        cand = rng.permutation(np.arange(starts[t], starts[t + 1]))
+        got = 0
+        for e in cand:
+            ring, sel = {e}, {e}
+            for _ in range(2):
+                ring = {m for x in ring for m in nb[x]} - sel
+                sel |= ring
+            if not seam[list(sel)].any():
+                out.append(int(e))
+                got += 1
+                if got == n:
+                    break
+    return out
+
+
+def _full_state(M, frlib, seed):
+    """TGV (Ma 0.3) with seeded 1 % noise at the library's solution points,
+    [n_upts][5][E] per type, in the mesh's precision."""
+    U = {}
+    for t in range(3):
+        q = M.query(t)
+        if not q["nelem"]:
+            continue
+        x = M.upts_coords(t)
+        u = np.transpose(inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=MACH), (1, 0, 2))
+        u = u * inputs.random_perturbation(u.shape, seed + t, 0.01)
+        if M.precision != "fp64":
+            u = u.astype(np.float32).astype(np.float64)
+        U[t] = u
+    return U
+
+
+@pytest.mark.parametrize("workload,prec", [("mixed", "fp32"), ("mixed", "fp64"), ("hex", "fp32")])
+def test_full_size_sampled_elements_match_oracle(workload, prec):
+    from paper_1409_0405_amd import frlib
+    arrays = inputs.tgv_mixed_box() if workload == "mixed" else inputs.hex_box(50, jitter=0.10, seed=0)
+    print(f"full size {workload} {prec}: building", flush=True)
+    M = frlib.Mesh(arrays, 4, system="ns", precision=prec, mu=MU, prandtl=PR)
+    if prec == "fp32":
+        M.autotune()
+    U = _full_state(M, frlib, 7)
+    u = {t: frlib.to_device_state(M, t, U[t]) for t in U}
+    r = {t: frlib.state_tensor(M, t) for t in U}
+    M.rhs([u[t].data_ptr() if t in u else 0 for t in range(3)], [r[t].data_ptr() if t in r else 0 for t in range(3)])
+    torch.cuda.synchronize()
+    R = {t: r[t].double().cpu().numpy() for t in r}
+    del u, r
+    M.close()
+    torch.cuda.empty_cache()
+    print("  sampling patches", flush=True)
+    nb, ntot = _neighbours(arrays)
+    counts = [len(arrays.get(f"{nm}_v", [])) for nm in NAMES]
+    starts = np.cumsum([0] + counts)
+    types = [t for t in range(3) if counts[t]]
+    sample = _interior_sample(arrays, nb, 6 if workload == "mixed" else 8, 3, types)
+    prm = fr.Params(system="ns", mu=MU, prandtl=PR)
+    num = np.zeros(5)
+    den = np.zeros(5)
+    mag = np.zeros(5)
+    for g in sample:
+        t = int(np.searchsorted(starts, g, side="right") - 1)
+        pa, (tc, ic) = _patch(arrays, g, nb)
+        O = om.build_mesh(pa, 4)
+        # the patch's states, from the full arrays, in the oracle's layout
+        Up = _patch_state(U, g, nb, starts, O)
+        Ro = fr.rhs(O, Up, prm)
+        want = Ro[NAMES[tc]][ic]                      # [N_u][5]
+        got = R[t][:, :, g - starts[t]]               # [N_u][5]
+        num += ((got - want) ** 2).sum(axis=0)
+        den += (want ** 2).sum(axis=0)
+        # error scale of an FP32 evaluation at this element: |F| (p+1)^2 / h
+        Ue = np.moveaxis(Up[NAMES[tc]][ic], 1, 0)
+        F = np.abs(physics.inviscid_flux(Ue, 1.4)).max(axis=0)
+        h = np.cbrt(O.types[NAMES[tc]].J_upts[ic])
+        mag += ((F * 25 / h[None]) ** 2).sum(axis=1)
+    err = np.sqrt(num / den)
+    tol = 1e-11 if prec == "fp64" else 16 * 2.0 ** -24 * np.sqrt(mag / den)
+    print(f"  {len(sample)} elements, field errors {err}, tol {tol}", flush=True)
+    assert (err < tol).all(), (err, tol)
+
+
+def _patch_state(U, g, nb, starts, O):
+    """States of the patch around g (layout [E][N_u][5] per type) from the
+    full per-type arrays U[t] [N_u][5][E], in the patch's element order."""
+    sel = sorted(_ring2(g, nb))
+    Up = {}
+    for tt, name in enumerate(NAMES):
+        if name not in O.types:
+            continue
+        ids = np.array([e - starts[tt] for e in sel if starts[tt] <= e < starts[tt + 1]], dtype=np.int64)
+        Up[name] = np.transpose(U[tt][:, :, ids], (2, 0, 1))
+    return Up
+
+
+def _ring2(g, nb):
+    sel, ring = {g}, {g}
+    for _ in range(2):
+        ring = {m for x in ring for m in nb[x]} - sel
+        sel |= ring
+    return sel
