@@ -1,6 +1,6 @@
 """Learned subgrid closure: training data from the solver's own high-order
 runs, training with the library's network kernels, and its a-posteriori
-judgement on the kinetic-energy dissipation rate.
+assessment on the kinetic-energy dissipation rate.
 
 Pipeline (every numerical step runs in libfr; torch only holds device
 memory; host numpy only draws the shuffles and forms the normalisation

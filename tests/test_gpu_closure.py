@@ -283,10 +283,10 @@ def test_trained_closure_reduces_apriori_dissipation_error():
     0.1) brings the kinetic-energy dissipation rate of the order-1 residual
     at the filtered states of held-out snapshots much closer to the order-4
     rate than the order-1 residual without it; BF16 weights at inference
-    keep that gain.  Judged against the plain order-4 solve."""
+    keep that gain.  Measured against the plain order-4 solve."""
     import math
     from paper_1409_0405_amd import closure as cl, frlib
-    print("closure judge: generate", flush=True)
+    print("closure vs order 4: generate", flush=True)
     arrays = inputs.tgv_mixed_box(nxy=8, n_pri_layers=14, n_tet_layers=8, jitter=0.1, seed=0)
     hi, lo = cl.tgv_meshes(arrays)
     n_snap, T_end = 21, 8.0
@@ -304,7 +304,7 @@ def test_trained_closure_reduces_apriori_dissipation_error():
     Xtr, Ytr = X[rows(train_s)].contiguous(), Y[rows(train_s)].contiguous()
     Xte, Yte = X[rows(test_s)].contiguous(), Y[rows(test_s)].contiguous()
     stats = cl.stats_of(Xtr, Ytr)
-    print("closure judge: train", flush=True)
+    print("closure vs order 4: train", flush=True)
     net, hist = cl.train(Xtr, Ytr, stats, epochs=40, batch=4096, lr=2e-3)
     assert hist[-1] < 0.6 * hist[0]
     # held-out targets: the network explains a good part of their variance
@@ -328,7 +328,7 @@ def test_trained_closure_reduces_apriori_dissipation_error():
 def test_closure_trained_along_trajectory_runs_stably():
     """Trained on the order-1 run itself (inputs and order-1 residuals from
     U_1(t), targets against the filtered order-4 residual), the closure keeps
-    the order-1 Taylor-Green run finite over t in [0, 8] and is judged on the
+    the order-1 Taylor-Green run finite over t in [0, 8] and is measured on the
     kinetic-energy dissipation rate against the plain order-4 run (printed;
     the gain is mesh dependent, see the design notes)."""
     import math
