@@ -157,3 +157,20 @@ def test_two_cell_periodic_mesh_validates():
     O = om.build_mesh(arrays, 2)
     for t, name in enumerate(("tet", "pri")):
         assert np.abs(M.upts_coords(t) - np.transpose(O.types[name].x_upts, (1, 2, 0))).max() < 1e-13
+
+
+def test_size_limits_and_degenerate_meshes():
+    """The per-type element limit of the side word (2^22 - 1), an empty mesh,
+    and a periodic direction one cell wide (a face would pair with itself):
+    all refused with an error, never built."""
+    base = inputs.hex_box(2)
+    empty = dict(base, hex_v=np.zeros((0, 8), np.int64), hex_img=np.zeros((0, 8, 3), np.int8))
+    _expect(frlib.FR_ERR_INVALID_ARG, lambda: frlib.Mesh(empty, 2, validate_only=True))
+    n = 1 << 22
+    big = dict(base, hex_v=np.zeros((n, 8), np.int64), hex_img=np.zeros((n, 8, 3), np.int8))
+    msg = _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(big, 1, validate_only=True))
+    assert "too many elements" in msg
+    del big
+    _expect(frlib.FR_ERR_BAD_MESH, lambda: frlib.Mesh(inputs.hex_box(1), 2, validate_only=True))
+    with pytest.raises(ValueError):
+        om.build_mesh(inputs.hex_box(1), 2)
