@@ -657,7 +657,7 @@ def main():
         for k in ("grad_pri", "gradinterp_pri"):
             Mb, t, op = product_row_blocks(mesh, k)
             rows = []
-            for stage in (0, 1, 2, 3, 4, 5):
+            for stage in (0, 1, 2, 3, 4, 5, 6):
                 print(f"variants {k} stage {stage}", file=sys.stderr, flush=True)
                 for cap in (1, 2, 3, 4, 5, 6, 8):
                     try:

@@ -288,7 +288,8 @@ fr_status fr_autotune(fr_mesh mesh, void *stream);
  * held in LDS for four panels (FP32 only, at most 64 KiB of it), 5 = direct
  * loads over only the K steps where the row group's operator fragments are
  * nonzero (the structural zeros of prisms and hexahedra; at most 4 row
- * blocks per wavefront).  The split forms have stage 0 (each wavefront splits
+ * blocks per wavefront), 6 = the same with 4 instead of 2 K steps of loads
+ * in flight.  The split forms have stage 0 (each wavefront splits
  * its B panel) and 1 (the panel's row groups, at most 8 and 64 KiB of parts,
  * share the split B in LDS).  Results are bitwise the same for every variant
  * (for finite states).  Synchronous

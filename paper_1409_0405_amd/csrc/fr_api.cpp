@@ -219,17 +219,19 @@ frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T
     frd::Op<T> op;
     op.M = M;
     op.stage = stage;
-    // stage 5: rows permuted into clustered groups (perm[r'] = source row)
+    // stages 5 and 6 (step lists): rows permuted into clustered groups
+    // (perm[r'] = source row)
+    const bool steps = stage == 5 || stage == 6;
     std::vector<int> perm;
     std::vector<double> Aperm;
-    const std::vector<double> &A = stage == 5 ? Aperm : A_in;
+    const std::vector<double> &A = steps ? Aperm : A_in;
     // an even number of K steps; a multiple of the chunk (4 or 8 steps) when
     // the B panel is staged through LDS
     const int kmul = (stage == 2 || stage == 4) ? 8 : (stage == 1 || stage == 3) ? 4 : 2;
     op.Kb = ((K + 3) / 4 + kmul - 1) / kmul * kmul;
     frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
-    if (stage == 5) {
+    if (steps) {
         perm = cluster_rows(A_in, M, K, 16 * op.mbw);
         Aperm.resize(size_t(M) * K);
         for (int r = 0; r < M; ++r)
@@ -246,7 +248,10 @@ frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T
                                              : (size_t(mb) * op.Kb + kb) * 64 + l;
                 if (r < M && c < K) f[at] = T(A[size_t(r) * K + c]);
             }
-    if (stage == 5) {
+    if (steps) {
+        // each list padded with zero fragments to a multiple of the steps the
+        // kernel keeps in flight (2 for stage 5, 4 for stage 6)
+        const size_t mult = stage == 6 ? 4 : 2;
         std::vector<T> dense;
         dense.swap(f);
         std::vector<int32_t> koff(op.nmg + 1), klist;
@@ -262,7 +267,7 @@ frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T
             }
             const size_t nreal = ks.size();
             if (ks.empty()) ks.push_back(0);
-            while (ks.size() % 2) ks.push_back(ks.back());
+            while (ks.size() % mult) ks.push_back(ks.back());
             for (size_t j = 0; j < ks.size(); ++j) {
                 klist.push_back(ks[j]);
                 for (int m = 0; m < op.mbw; ++m)
@@ -280,7 +285,7 @@ frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T
     return op;
 }
 
-// Device copy of a fragment array (and, stage 5, its step lists); the
+// Device copy of a fragment array (and, stages 5 and 6, its step lists); the
 // allocations are appended to `allocs`.
 template <typename T>
 hipError_t upload_op(frd::Op<T> &op, const std::vector<T> &f, const std::vector<int32_t> &idx,
@@ -291,7 +296,7 @@ hipError_t upload_op(frd::Op<T> &op, const std::vector<T> &f, const std::vector<
     allocs.push_back(p);
     if ((e = hipMemcpy(p, f.data(), f.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess) return e;
     op.frag = static_cast<T *>(p);
-    if (op.stage == 5) {
+    if (op.stage == 5 || op.stage == 6) {
         if ((e = hipMalloc(&p, idx.size() * sizeof(int32_t))) != hipSuccess) return e;
         allocs.push_back(p);
         if ((e = hipMemcpy(p, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
@@ -1035,11 +1040,11 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
             frd::OpSplit best_sop;
             std::vector<std::pair<int, int>> cands;
             for (int cap : caps)
-                for (int stage = 0; stage < (split ? 2 : 6); ++stage) {
+                for (int stage = 0; stage < (split ? 2 : 7); ++stage) {
                     if (sizeof(T) != 4 && (stage == 1 || stage == 2 || stage == 4)) continue;
                     int nmg, mbw;
                     frd::row_groups(c.M, cap, nmg, mbw);
-                    if (stage == 5 && mbw > 4) continue;
+                    if ((stage == 5 || stage == 6) && mbw > 4) continue;
                     if (split) {
                         if (stage == 1 && (nmg > 8 || nmg * (fmt == 2 ? 2 : 3) * 4096 > 65536)) continue;
                         cands.push_back({cap, stage});
@@ -1459,7 +1464,7 @@ fr_status set_blocking_impl(fr_mesh m, int t, int op, int cap, int stage) {
         return fail(m, FR_ERR_UNSUPPORTED, "LDS staging needs at most 8 row groups");
     if (stage == 4 && size_t(o.mbw) * o.Kb * 256 > 65536)
         return fail(m, FR_ERR_UNSUPPORTED, "operator slice too large for LDS");
-    if (stage == 5 && o.mbw > 4)
+    if ((stage == 5 || stage == 6) && o.mbw > 4)
         return fail(m, FR_ERR_UNSUPPORTED, "the step-list product takes at most 4 row blocks per wavefront");
     FR_HIP(m, upload_op(o, f, idx, d.allocs));
     frd::Op<T> *dst[4] = {&D.Aint, &D.Agrad, &D.Agint, &D.Adiv};
@@ -1472,8 +1477,8 @@ extern "C" {
 
 fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
-    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 5)
-        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..5");
+    if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 6)
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..6");
     if (!m->host.t[etype].nelem) return FR_OK;
     return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
                                    : set_blocking_impl<double>(m, etype, op, cap, stage);

@@ -28,7 +28,9 @@ struct Op {
     // row group walks only the K steps where one of its fragments is nonzero:
     // klist[koff[g] .. koff[g+1]) lists them (padded to an even count with
     // zero fragments), and frag holds the group's fragments compacted in that
-    // order, [step][mbw][lane] (mbw <= 4).  The rows are permuted so that
+    // order, [step][mbw][lane] (mbw <= 4).  6 = 5 with 4 steps of loads in
+    // flight instead of 2 (lists padded to a multiple of 4).  The rows are
+    // permuted so that
     // rows touching the same columns share a group: fragment row r' is
     // operator row rowmap[r'] (-1 for padding).  All variants give identical
     // bits for finite B (skipped products are exact zeros).

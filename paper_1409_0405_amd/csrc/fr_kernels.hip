@@ -166,19 +166,19 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 // derivative one triangle layer), so a row group of MBW x 16 rows needs only
 // a fraction of the K steps: the group's step list (shared by the wavefront,
 // read through scalar loads) drives the same pipelined loop as opmul_kernel
-// with D = 2 steps in flight, over fragments stored compacted per group.
+// with D = 2 or 4 steps in flight (the list is padded with zero fragments to a
+// multiple of D), over fragments stored compacted per group.
 // Rows are grouped by the columns they touch and written back through a row
 // map.  The products left out are exact zeros, so every output keeps the bits
 // of the dense kernels.
 // ---------------------------------------------------------------------------
-template <typename T, int MBW, int TAG>
+template <typename T, int MBW, int TAG, int D>
 __global__ __launch_bounds__(256) void opmul_sparse_kernel(Op<T> A, const T *__restrict__ B1,
                                                            int64_t ldb1, int K1,
                                                            const T *__restrict__ B2, int64_t ldb2,
                                                            int K2, T *__restrict__ C, int64_t ldc,
                                                            int64_t npanels, int nmg) {
     using v4 = typename Vec4<T>::type;
-    constexpr int D = 2;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
     const int64_t panel = wid / nmg;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void opmul_sparse_kernel(Op<T> A, const T *__r
     const int krow = lane >> 4;
     const int K = K1 + K2;
     const int s0 = A.koff[mg];
-    const int ns = A.koff[mg + 1] - s0;       // even, >= 2
+    const int ns = A.koff[mg + 1] - s0;       // a multiple of D, >= D
     const int32_t *__restrict__ kl = A.klist + s0;
 
     auto bptr = [&](int kb) -> const v4 * {
@@ -1255,11 +1255,14 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
     }
     const int64_t nwaves = npanels * nmg;
     const dim3 grid(xcd_grid((nwaves + 3) / 4)), block(256);
-    if (A.stage == 5) {
+    if (A.stage == 5 || A.stage == 6) {
         if (!A.klist || !A.koff || !A.rowmap) return hipErrorInvalidValue;
 #define FR_SPARSE(w)                                                                                       \
     case w:                                                                                                \
-        opmul_sparse_kernel<T, w, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+        if (A.stage == 6)                                                                                  \
+            opmul_sparse_kernel<T, w, TAG, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+        else                                                                                               \
+            opmul_sparse_kernel<T, w, TAG, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
         break;
         switch (mbw) {
             FR_SPARSE(1) FR_SPARSE(2) FR_SPARSE(3) FR_SPARSE(4)

@@ -169,7 +169,7 @@ def test_every_product_variant_gives_identical_bits(kind, p, prec):
     M.rhs(ptr(u), ptr(r0))
     torch.cuda.synchronize()
     n = 0
-    stages = {"fp32": (0, 1, 2, 3, 4, 5), "fp64": (0, 3, 5)}.get(prec, (0, 1))
+    stages = {"fp32": (0, 1, 2, 3, 4, 5, 6), "fp64": (0, 3, 5, 6)}.get(prec, (0, 1))
     for stage in stages:
         for cap in (1, 2, 3, 4, 8):
             ok = True
