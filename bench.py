@@ -169,8 +169,10 @@ def kernel_model(mesh, system):
     Operator products C = A B: the paper's dense-operator count 2 M K n flops
     ("flops") and 4 (K + M) n bytes over the n = fields x elements real
     columns; the structural nonzeros' 2 nnz(A) n is kept beside it
-    ("nnz_flops").  Point-wise kernels: the values they must read and write
-    once (states, gradients, fluxes, geometry)."""
+    ("nnz_flops").  The divergence product also carries the last step's
+    bytes (its store applies -R~/J and the register update).  Point-wise
+    kernels: the values they must read and write once (states, gradients,
+    fluxes, geometry)."""
     ns = system == "ns"
     out = {}
     s = 4
@@ -193,7 +195,11 @@ def kernel_model(mesh, system):
         ng = (9, 15, 21)[t]
         pt = (5 + (15 + 15 if ns else 0) + 15) * nu * E * s + ng * E * s
         out[f"upts_{name}"] = {"flops": 0.0, "bytes": float(pt)}
-        out[f"negdivconf_{name}"] = {"flops": 0.0, "bytes": float((5 + 5 + 5) * nu * E * s + ng * E * s)}
+        neg = (5 + 5 + 5) * nu * E * s + ng * E * s
+        out[f"negdivconf_{name}"] = {"flops": 0.0, "bytes": float(neg)}
+        # the divergence product applies -R~/J and the register update in
+        # its store: R~ is neither written nor read back
+        out[f"div_{name}"]["bytes"] += neg - 2 * 5 * nu * E * s
     npairs //= 2
     # with the LDG beta = 1/2 (the default) only side L's gradient enters the
     # common viscous flux

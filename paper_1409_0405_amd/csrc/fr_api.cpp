@@ -622,15 +622,19 @@ struct StageOut {
 };
 
 // Operator product through the kernel of the mesh's precision.
+// With ep the product's output goes through the last pipeline step instead
+// of into C (FP32 and FP64 products only).
 template <typename T>
 hipError_t opmul(fr_mesh m, int tag, const frd::Op<T> &A, const frd::OpSplit &S, const T *B1,
                  int64_t ldb1, int K1, const T *B2, int64_t ldb2, int K2, T *C, int64_t ldc,
-                 int64_t ncols, hipStream_t s) {
+                 int64_t ncols, hipStream_t s, const frd::NegArgs<T> *ep = nullptr) {
     if constexpr (std::is_same<T, float>::value) {
-        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16)
+        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
+            if (ep) return hipErrorInvalidValue;
             return frd::launch_opmul_split(tag, S, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s);
+        }
     }
-    return frd::launch_opmul<T>(tag, A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s);
+    return frd::launch_opmul<T>(tag, A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s, ep);
 }
 
 template <typename T>
@@ -725,8 +729,6 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
         const int64_t w5 = 5 * D.ld;
-        FR_LAUNCH(m, prof_op(t, frd::OP_DIV), s,
-                  opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         frd::NegArgs<T> na{D.Rt, so[t].out, so[t].acc, so[t].base, so[t].a, so[t].b,
                            D.jinv, D.ld, D.nelem, D.nu,
                            so[t].per_elem_dt ? D.dte : nullptr};
@@ -739,6 +741,19 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
             na.clift = cl->lift[t];
             na.goff = t ? d.t[0].nelem : 0;
         }
+        // -R~/J and the register update ride in the divergence product's
+        // store (R~ never reaches memory) unless a split form, the closure
+        // or FR_SEPARATE_UPDATE asks for the separate kernel
+        const bool split = m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16;
+        if (!split && !na.cy && !(m->flags & FR_SEPARATE_UPDATE)) {
+            na.fuse = true;
+            FR_LAUNCH(m, prof_op(t, frd::OP_DIV), s,
+                      opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5,
+                               w5, s, &na));
+            continue;
+        }
+        FR_LAUNCH(m, prof_op(t, frd::OP_DIV), s,
+                  opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5, w5, s));
         FR_LAUNCH(m, prof_neg(t), s, frd::launch_negdivconf<T>(t, na, s));
     }
     return FR_OK;

@@ -50,10 +50,15 @@ inline void row_groups(int M, int cap, int &nmg, int &mbw) {
 // ldb1, ldb2, ldc (elements); ncols a multiple of 64.  tag = 4 * element type +
 // operator (0 interpolation, 1 gradient, 2 gradient interpolation, 3
 // divergence), 0..11, names the kernel instantiation.
+// With ep (fuse set; divergence only) the product's output goes through the
+// last pipeline step (negdivconf_kernel's update) instead of into C.
 enum { OP_INTERP = 0, OP_GRAD = 1, OP_GRADINTERP = 2, OP_DIV = 3 };
 template <typename T>
+struct NegArgs;
+template <typename T>
 hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
-                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s);
+                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s,
+                        const NegArgs<T> *ep = nullptr);
 
 // Split-precision operator for the 16-bit MFMA product kernel.  BF16
 // (format 1): A = h + m + l, three parts; FP16 (format 2): A = h + l / 2^11,
@@ -163,6 +168,8 @@ struct NegArgs {
     bool err_set = false;
     const float *clift = nullptr;   // [nu][4]
     int64_t goff = 0;
+    // set: applied in the divergence product's store (Rt unused)
+    bool fuse = false;
 };
 template <typename T>
 hipError_t launch_negdivconf(int etype, const NegArgs<T> &a, hipStream_t s);

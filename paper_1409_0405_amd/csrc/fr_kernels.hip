@@ -73,6 +73,88 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 inline unsigned xcd_grid(int64_t nblocks) { return unsigned((nblocks + 7) / 8 * 8); }
 
+// The last pipeline step at one (solution point i, field v, element e), with
+// o = (5 i + v) ld + e: k = -r / J (plus the learned closure's lifted
+// correction), times the element's step size, into the error, accumulator
+// and output registers (frd::NegArgs).  negdivconf_kernel and the fused
+// store of the divergence products both call it, so the two give the same
+// bits.
+template <typename T>
+__device__ __forceinline__ void neg_update(const NegArgs<T> &a, int i, int v, int64_t e, int64_t o,
+                                           T r) {
+    const T Jinv = a.jinv[int64_t(i) * a.ld + e];
+    const T sc = a.dte ? a.dte[e] : T(1);
+    T k = -r * Jinv;
+    if (a.cy) {
+        const float *y = a.cy + (a.goff + e) + int64_t(v) * 4 * a.cys;
+        const float *l = a.clift + i * 4;
+        k += T(l[0] * y[0] + l[1] * y[a.cys] + l[2] * y[2 * a.cys] + l[3] * y[3 * a.cys]);
+    }
+    k *= sc;
+    if (a.err) a.err[o] = (a.err_set ? T(0) : a.err[o]) + a.c * k;
+    T accv = 0;
+    if (a.acc) {
+        accv = a.acc[o] + a.a * k;
+        a.acc[o] = accv;
+    }
+    if (a.out) a.out[o] = (a.base ? a.base[o] : accv) + a.b * k;
+}
+
+// Store of four consecutive columns of one output row.  For a divergence
+// product with ep.fuse set the row is solution point i and the columns are
+// (field v, elements e .. e + 3) of the [point][field][ld] layout (ldc = 5
+// ld, checked at launch): the values go through neg_update's arithmetic
+// instead of being stored, and the padding elements past nelem are skipped.
+// The register pointers are 4-element aligned (checked at entry).
+template <int TAG, typename T, typename V4>
+__device__ __forceinline__ void store_c(T *C, int64_t ldc, int row, int64_t col, const V4 &val,
+                                        const NegArgs<T> &ep) {
+    if constexpr (TAG % 4 == 3) {
+        if (ep.fuse) {
+            const int v = int(col / ep.ld);
+            const int64_t e0 = col - int64_t(v) * ep.ld;
+            const int64_t o0 = int64_t(row) * ldc + col;
+            if (e0 + 3 < ep.nelem && !ep.cy) {
+                // four whole elements: the same arithmetic as neg_update on
+                // 16-byte (FP32) / 32-byte (FP64) loads and stores
+                const V4 J = *reinterpret_cast<const V4 *>(ep.jinv + int64_t(row) * ep.ld + e0);
+                const V4 S = ep.dte ? *reinterpret_cast<const V4 *>(ep.dte + e0) : V4{1, 1, 1, 1};
+                V4 k;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    k[j] = -T(val[j]) * J[j];
+                    k[j] *= S[j];
+                }
+                if (ep.err) {
+                    V4 er = ep.err_set ? V4{0, 0, 0, 0} : *reinterpret_cast<const V4 *>(ep.err + o0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) er[j] = er[j] + ep.c * k[j];
+                    *reinterpret_cast<V4 *>(ep.err + o0) = er;
+                }
+                V4 accv = V4{0, 0, 0, 0};
+                if (ep.acc) {
+                    accv = *reinterpret_cast<const V4 *>(ep.acc + o0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) accv[j] = accv[j] + ep.a * k[j];
+                    *reinterpret_cast<V4 *>(ep.acc + o0) = accv;
+                }
+                if (ep.out) {
+                    V4 o = ep.base ? *reinterpret_cast<const V4 *>(ep.base + o0) : accv;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) o[j] = o[j] + ep.b * k[j];
+                    *reinterpret_cast<V4 *>(ep.out + o0) = o;
+                }
+                return;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (e0 + j < ep.nelem) neg_update(ep, row, v, e0 + j, o0 + j, T(val[j]));
+            return;
+        }
+    }
+    *reinterpret_cast<V4 *>(C + int64_t(row) * ldc + col) = val;
+}
+
 // ---------------------------------------------------------------------------
 // Operator product C = A [B1; B2] on the matrix cores.  TAG (4 * element type
 // + operator id) only names the instantiation, so that a profiler reports each
@@ -93,7 +175,7 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
                                                     int64_t ldb1, int K1,
                                                     const T *__restrict__ B2, int64_t ldb2,
                                                     int K2, T *__restrict__ C, int64_t ldc,
-                                                    int64_t npanels, int nmg) {
+                                                    int64_t npanels, int nmg, NegArgs<T> ep) {
     using v4 = typename Vec4<T>::type;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
@@ -151,10 +233,8 @@ __global__ __launch_bounds__(256) void opmul_kernel(Op<T> A, const T *__restrict
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * (mb0 + m) + acc_row<T>(krow, r);
-            if (row < A.M) {
-                v4 out = v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
-                *reinterpret_cast<v4 *>(C + int64_t(row) * ldc + col) = out;
-            }
+            if (row < A.M)
+                store_c<TAG>(C, ldc, row, col, v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]}, ep);
         }
     }
 }
@@ -177,7 +257,7 @@ __global__ __launch_bounds__(256) void opmul_sparse_kernel(Op<T> A, const T *__r
                                                            int64_t ldb1, int K1,
                                                            const T *__restrict__ B2, int64_t ldb2,
                                                            int K2, T *__restrict__ C, int64_t ldc,
-                                                           int64_t npanels, int nmg) {
+                                                           int64_t npanels, int nmg, NegArgs<T> ep) {
     using v4 = typename Vec4<T>::type;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t(xcd_block()) * blockDim.x + threadIdx.x) >> 6;
@@ -234,10 +314,8 @@ __global__ __launch_bounds__(256) void opmul_sparse_kernel(Op<T> A, const T *__r
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = A.rowmap[16 * (mb0 + m) + acc_row<T>(krow, r)];
-            if (row >= 0) {
-                v4 out = v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
-                *reinterpret_cast<v4 *>(C + int64_t(row) * ldc + col) = out;
-            }
+            if (row >= 0)
+                store_c<TAG>(C, ldc, row, col, v4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]}, ep);
         }
     }
 }
@@ -258,7 +336,7 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
                                                         const float *__restrict__ B2,
                                                         int64_t ldb2, int K2,
                                                         float *__restrict__ C, int64_t ldc,
-                                                        int64_t npanels) {
+                                                        int64_t npanels, NegArgs<float> ep) {
     constexpr int NV = 64 * KS;                 // 16-byte vectors per chunk
     const unsigned blk = xcd_block();
     if (blk >= npanels) return;                 // whole workgroup: padding of the grid
@@ -348,8 +426,7 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * (mb0 + m) + acc_row<float>(krow, r);
             if (row < A.M)
-                *reinterpret_cast<floatx4 *>(C + int64_t(row) * ldc + col) =
-                    floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+                store_c<TAG>(C, ldc, row, col, floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]}, ep);
         }
     }
 }
@@ -370,7 +447,7 @@ __global__ __launch_bounds__(256) void opmul_ldsa_kernel(Op<float> A, const floa
                                                          int64_t ldb1, int K1,
                                                          const float *__restrict__ B2, int64_t ldb2,
                                                          int K2, float *__restrict__ C, int64_t ldc,
-                                                         int64_t npanels, int nmg) {
+                                                         int64_t npanels, int nmg, NegArgs<float> ep) {
     extern __shared__ floatx4 As[];             // [MBW][Kb / 4][64]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int Kb = A.Kb, Kq = Kb / 4;
@@ -426,8 +503,7 @@ __global__ __launch_bounds__(256) void opmul_ldsa_kernel(Op<float> A, const floa
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * (mb0 + m) + acc_row<float>(krow, r);
             if (row < A.M)
-                *reinterpret_cast<floatx4 *>(C + int64_t(row) * ldc + col) =
-                    floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]};
+                store_c<TAG>(C, ldc, row, col, floatx4{acc[m][0][r], acc[m][1][r], acc[m][2][r], acc[m][3][r]}, ep);
         }
     }
 }
@@ -1119,25 +1195,10 @@ __global__ __launch_bounds__(256) void negdivconf_kernel(NegArgs<T> a) {
     const int i = blockIdx.y;
     if (e >= a.nelem) return;
     const int64_t ld = a.ld;
-    const T Jinv = a.jinv[int64_t(i) * ld + e];
-    const T sc = a.dte ? a.dte[e] : T(1);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         const int64_t o = (int64_t(i) * 5 + v) * ld + e;
-        T k = -a.Rt[o] * Jinv;
-        if (a.cy) {
-            const float *y = a.cy + (a.goff + e) + int64_t(v) * 4 * a.cys;
-            const float *l = a.clift + i * 4;
-            k += T(l[0] * y[0] + l[1] * y[a.cys] + l[2] * y[2 * a.cys] + l[3] * y[3 * a.cys]);
-        }
-        k *= sc;
-        if (a.err) a.err[o] = (a.err_set ? T(0) : a.err[o]) + a.c * k;
-        T accv = 0;
-        if (a.acc) {
-            accv = a.acc[o] + a.a * k;
-            a.acc[o] = accv;
-        }
-        if (a.out) a.out[o] = (a.base ? a.base[o] : accv) + a.b * k;
+        neg_update(a, i, v, e, o, a.Rt[o]);
     }
 }
 
@@ -1214,7 +1275,7 @@ __global__ void copy_kernel(T *dst, const T *src, int64_t n) {
 template <typename T, int TAG>
 hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
                             int64_t ldb2, int K2, T *C, int64_t ldc, int64_t npanels,
-                            hipStream_t s) {
+                            hipStream_t s, const NegArgs<T> &E) {
     const int nmg = A.nmg, mbw = A.mbw;
     if (A.Kb % ((A.stage == 2 || A.stage == 4) ? 8 : (A.stage == 1 || A.stage == 3) ? 4 : 2))
         return hipErrorInvalidValue;
@@ -1226,7 +1287,7 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
             const dim3 g{xcd_grid((npanels + 3) / 4 * nmg)}, b{256u};
 #define FR_LDSA(w)                                                                                   \
     case w:                                                                                          \
-        opmul_ldsa_kernel<w, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+        opmul_ldsa_kernel<w, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg, E); \
         break;
             switch (mbw) {
                 FR_LDSA(1) FR_LDSA(2) FR_LDSA(3) FR_LDSA(4) FR_LDSA(5) FR_LDSA(6) FR_LDSA(7) FR_LDSA(8)
@@ -1241,9 +1302,9 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
 #define FR_LDS(w)                                                                                  \
     case w:                                                                                        \
         if (A.stage == 2)                                                                          \
-            opmul_lds_kernel<w, TAG, 8><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
+            opmul_lds_kernel<w, TAG, 8><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, E); \
         else                                                                                       \
-            opmul_lds_kernel<w, TAG, 4><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
+            opmul_lds_kernel<w, TAG, 4><<<g, b, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, E); \
         break;
             switch (mbw) {
                 FR_LDS(1) FR_LDS(2) FR_LDS(3) FR_LDS(4) FR_LDS(5) FR_LDS(6) FR_LDS(7) FR_LDS(8)
@@ -1260,9 +1321,9 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
 #define FR_SPARSE(w)                                                                                       \
     case w:                                                                                                \
         if (A.stage == 6)                                                                                  \
-            opmul_sparse_kernel<T, w, TAG, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+            opmul_sparse_kernel<T, w, TAG, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg, E); \
         else                                                                                               \
-            opmul_sparse_kernel<T, w, TAG, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg); \
+            opmul_sparse_kernel<T, w, TAG, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, nmg, E); \
         break;
         switch (mbw) {
             FR_SPARSE(1) FR_SPARSE(2) FR_SPARSE(3) FR_SPARSE(4)
@@ -1275,10 +1336,10 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
     case w:                                                                                      \
         if (A.stage == 3)                                                                        \
             opmul_kernel<T, w, TAG, 4><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
-                                                              npanels, nmg);                     \
+                                                              npanels, nmg, E);                  \
         else                                                                                     \
             opmul_kernel<T, w, TAG, 2><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, \
-                                                              npanels, nmg);                     \
+                                                              npanels, nmg, E);                  \
         break;
     if (sizeof(T) == 4) {
         switch (mbw) {
@@ -1297,11 +1358,17 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
 
 template <typename T>
 hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int K1, const T *B2,
-                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s) {
+                        int64_t ldb2, int K2, T *C, int64_t ldc, int64_t ncols, hipStream_t s,
+                        const NegArgs<T> *ep) {
     if (ncols % 64 || K1 + K2 <= 0 || A.nmg * A.mbw * 16 < A.M) return hipErrorInvalidValue;
+    const NegArgs<T> E = ep ? *ep : NegArgs<T>{};
+    // the fused store addresses the divergence output layout [nu][5][ld]
+    if (E.fuse && (tag % 4 != 3 || E.ld % 64 || ldc != 5 * E.ld || ncols != ldc || A.M != E.nu ||
+                   E.nelem > E.ld || !E.jinv))
+        return hipErrorInvalidValue;
     const int64_t npanels = ncols / 64;
 #define FR_TAG(t) \
-    case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, s);
+    case t: return launch_opmul_tag<T, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, s, E);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
         FR_TAG(8) FR_TAG(9) FR_TAG(10) FR_TAG(11)
@@ -1440,7 +1507,7 @@ hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t s) {
 #define FR_INSTANTIATE(T)                                                                     \
     template hipError_t launch_opmul<T>(int, const Op<T> &, const T *, int64_t, int,          \
                                         const T *, int64_t, int, T *, int64_t, int64_t,       \
-                                        hipStream_t);                                         \
+                                        hipStream_t, const NegArgs<T> *);                     \
     template hipError_t launch_upts<T>(int, bool, const UptsArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_solution<T>(const PairArgs<T> &, hipStream_t);          \
     template hipError_t launch_common_flux<T>(bool, const PairArgs<T> &, hipStream_t);        \
