@@ -78,9 +78,10 @@ typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
 #define FR_VALIDATE_ONLY 0x1u  /* build host-side tables only; no device work */
 #define FR_CHECK_FINITE 0x2u   /* fr_rk_step ends with a finiteness check */
 /* Run -R~/J and the RK register update as a kernel of their own after the
- * divergence product.  By default (FP32 and FP64, no closure) they are
+ * divergence product.  By default (every precision, no closure) they are
  * applied in the divergence product's store, so R~ is never written; both
- * orders of work give the same bits. */
+ * orders of work give the same bits.  The autotuner times the divergence
+ * products the way the right-hand side runs them. */
 #define FR_SEPARATE_UPDATE 0x4u
 
 typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */

@@ -623,16 +623,14 @@ struct StageOut {
 
 // Operator product through the kernel of the mesh's precision.
 // With ep the product's output goes through the last pipeline step instead
-// of into C (FP32 and FP64 products only).
+// of into C.
 template <typename T>
 hipError_t opmul(fr_mesh m, int tag, const frd::Op<T> &A, const frd::OpSplit &S, const T *B1,
                  int64_t ldb1, int K1, const T *B2, int64_t ldb2, int K2, T *C, int64_t ldc,
                  int64_t ncols, hipStream_t s, const frd::NegArgs<T> *ep = nullptr) {
     if constexpr (std::is_same<T, float>::value) {
-        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
-            if (ep) return hipErrorInvalidValue;
-            return frd::launch_opmul_split(tag, S, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s);
-        }
+        if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16)
+            return frd::launch_opmul_split(tag, S, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s, ep);
     }
     return frd::launch_opmul<T>(tag, A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s, ep);
 }
@@ -742,10 +740,9 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
             na.goff = t ? d.t[0].nelem : 0;
         }
         // -R~/J and the register update ride in the divergence product's
-        // store (R~ never reaches memory) unless a split form, the closure
-        // or FR_SEPARATE_UPDATE asks for the separate kernel
-        const bool split = m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16;
-        if (!split && !na.cy && !(m->flags & FR_SEPARATE_UPDATE)) {
+        // store (R~ never reaches memory) unless the closure or
+        // FR_SEPARATE_UPDATE asks for the separate kernel
+        if (!na.cy && !(m->flags & FR_SEPARATE_UPDATE)) {
             na.fuse = true;
             FR_LAUNCH(m, prof_op(t, frd::OP_DIV), s,
                       opmul<T>(m, 4 * t + frd::OP_DIV, D.Adiv, D.Sdiv, D.Ft, w5, 3 * D.nu, D.Fn, w5, D.nf, D.Rt, w5,
@@ -1091,14 +1088,26 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                     op = fragment<T>(*c.A, c.M, c.K, f, cap, stage, &idx);
                     FR_HIP(m, upload_op(op, f, idx, mine));
                 }
+                // the divergence is timed with the fused store the right-hand
+                // side uses, writing -R~/J into the R~ buffer (no registers)
+                frd::NegArgs<T> na{};
+                na.out = D.Rt;
+                na.b = T(1);
+                na.jinv = D.jinv;
+                na.ld = D.ld;
+                na.nelem = D.nelem;
+                na.nu = D.nu;
+                na.fuse = true;
+                const frd::NegArgs<T> *ep =
+                    c.op == frd::OP_DIV && !(m->flags & FR_SEPARATE_UPDATE) ? &na : nullptr;
                 auto run = [&]() -> hipError_t {
                     if constexpr (std::is_same<T, float>::value) {
                         if (split)
                             return frd::launch_opmul_split(4 * t + c.op, sop, c.B1, c.l1, c.K1, c.B2, c.l2,
-                                                           c.K2, c.C, c.lc, c.ncols, s);
+                                                           c.K2, c.C, c.lc, c.ncols, s, ep);
                     }
                     return frd::launch_opmul<T>(4 * t + c.op, op, c.B1, c.l1, c.K1, c.B2, c.l2, c.K2,
-                                                c.C, c.lc, c.ncols, s);
+                                                c.C, c.lc, c.ncols, s, ep);
                 };
                 FR_HIP(m, run());
                 FR_HIP(m, hipEventRecord(e0, s));

@@ -79,7 +79,7 @@ struct OpSplit {
 // accumulation (six products for BF16, three for FP16).
 hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_t ldb1, int K1,
                               const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
-                              int64_t ncols, hipStream_t s);
+                              int64_t ncols, hipStream_t s, const NegArgs<float> *ep = nullptr);
 
 // Point-wise work at the solution points of one element type (ETYPE 0 tet,
 // 1 prism, 2 hexahedron): physical gradient Q from the reference gradient Qt

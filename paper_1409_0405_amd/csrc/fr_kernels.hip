@@ -545,14 +545,18 @@ hipError_t launch_opmul(int tag, const Op<T> &A, const T *B1, int64_t ldb1, int 
 
 hipError_t launch_opmul_split(int tag, const OpSplit &A, const float *B1, int64_t ldb1, int K1,
                               const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
-                              int64_t ncols, hipStream_t s) {
+                              int64_t ncols, hipStream_t s, const NegArgs<float> *ep) {
     if (ncols % 64 || K1 + K2 <= 0 || A.nmg * A.mbw * 16 < A.M || (A.Kb & 1))
+        return hipErrorInvalidValue;
+    const NegArgs<float> E = ep ? *ep : NegArgs<float>{};
+    if (E.fuse && (tag % 4 != 3 || E.ld % 64 || ldc != 5 * E.ld || ncols != ldc || A.M != E.nu ||
+                   E.nelem > E.ld || !E.jinv))
         return hipErrorInvalidValue;
     const int64_t np = ncols / 64;
 #define FR_TAG(t)                                                                            \
     case t:                                                                                  \
-        return A.format == 2 ? launch_split_tag<true, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s) \
-                             : launch_split_tag<false, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s);
+        return A.format == 2 ? launch_split_tag<true, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s, E) \
+                             : launch_split_tag<false, t>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, np, s, E);
     switch (tag) {
         FR_TAG(0) FR_TAG(1) FR_TAG(2) FR_TAG(3) FR_TAG(4) FR_TAG(5) FR_TAG(6) FR_TAG(7)
         FR_TAG(8) FR_TAG(9) FR_TAG(10) FR_TAG(11)

@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void opmul_split_kernel(OpSplit A, const float
                                                           const float *__restrict__ B2,
                                                           int64_t ldb2, int K2,
                                                           float *__restrict__ C, int64_t ldc,
-                                                          int64_t npanels, int nmg) {
+                                                          int64_t npanels, int nmg, NegArgs<float> ep) {
     constexpr int NP = F16 ? 2 : 3;       // parts per operand
     constexpr int NACC = F16 ? 2 : 1;
     const int lane = threadIdx.x & 63;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) void opmul_split_kernel(OpSplit A, const float
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
                     out[n] = NACC == 2 ? acc[0][m][n][r] + acc[NACC - 1][m][n][r] * is : acc[0][m][n][r];
-                *reinterpret_cast<floatx4 *>(C + int64_t(rw) * ldc + col) = out;
+                store_c<TAG>(C, ldc, rw, col, out, ep);
             }
         }
     }
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(512) void opmul_split_lds_kernel(OpSplit A, const f
                                                               const float *__restrict__ B2,
                                                               int64_t ldb2, int K2,
                                                               float *__restrict__ C, int64_t ldc,
-                                                              int64_t npanels) {
+                                                              int64_t npanels, NegArgs<float> ep) {
     constexpr int NP = F16 ? 2 : 3;
     constexpr int NACC = F16 ? 2 : 1;
     extern __shared__ uintx4 Bs[];              // [nmg][NP][4][64]
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(512) void opmul_split_lds_kernel(OpSplit A, const f
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
                     out[n] = NACC == 2 ? acc[0][m][n][r] + acc[NACC - 1][m][n][r] * is : acc[0][m][n][r];
-                *reinterpret_cast<floatx4 *>(C + int64_t(rw) * ldc + col) = out;
+                store_c<TAG>(C, ldc, rw, col, out, ep);
             }
         }
     }
@@ -886,14 +886,14 @@ hipError_t launch_opmul_tag(const Op<T> &A, const T *B1, int64_t ldb1, int K1, c
 template <bool F16, int TAG>
 hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int K1,
                             const float *B2, int64_t ldb2, int K2, float *C, int64_t ldc,
-                            int64_t npanels, hipStream_t s) {
+                            int64_t npanels, hipStream_t s, const NegArgs<float> &E) {
     if (A.stage == 1) {
         const size_t lds = size_t(A.nmg) * (F16 ? 2 : 3) * 4 * 64 * 16;
         if (A.nmg > 8 || lds > 65536) return hipErrorInvalidValue;
         const dim3 g{xcd_grid(npanels)}, b{unsigned(64 * A.nmg)};
 #define FR_SLDS(w)                                                                                       \
     case w:                                                                                              \
-        opmul_split_lds_kernel<w, F16, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels); \
+        opmul_split_lds_kernel<w, F16, TAG><<<g, b, lds, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, npanels, E); \
         break;
         switch (A.mbw) {
             FR_SLDS(1) FR_SLDS(2) FR_SLDS(3) FR_SLDS(4)
@@ -907,7 +907,7 @@ hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int
 #define FR_MBW(w)                                                                           \
     case w:                                                                                 \
         opmul_split_kernel<w, F16, TAG><<<grid, block, 0, s>>>(A, B1, ldb1, K1, B2, ldb2, K2, \
-                                                               C, ldc, npanels, A.nmg);      \
+                                                               C, ldc, npanels, A.nmg, E);   \
         break;
     switch (A.mbw) {
         FR_MBW(1) FR_MBW(2) FR_MBW(3) FR_MBW(4)
@@ -921,7 +921,7 @@ hipError_t launch_split_tag(const OpSplit &A, const float *B1, int64_t ldb1, int
 // tag: the FP32 and FP64 products, and the two split forms.
 #define FR_OPMUL_INSTANCE(T, t) template hipError_t launch_opmul_tag<T, t>(const Op<T> &, const T *, int64_t, int, const T *, int64_t, int, T *, int64_t, int64_t, hipStream_t, const NegArgs<T> &);
 #define FR_OPMUL_EXTERN(T, t) extern template hipError_t launch_opmul_tag<T, t>(const Op<T> &, const T *, int64_t, int, const T *, int64_t, int, T *, int64_t, int64_t, hipStream_t, const NegArgs<T> &);
-#define FR_SPLIT_INSTANCE(f, t) template hipError_t launch_split_tag<f, t>(const OpSplit &, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, int64_t, hipStream_t);
-#define FR_SPLIT_EXTERN(f, t) extern template hipError_t launch_split_tag<f, t>(const OpSplit &, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, int64_t, hipStream_t);
+#define FR_SPLIT_INSTANCE(f, t) template hipError_t launch_split_tag<f, t>(const OpSplit &, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, int64_t, hipStream_t, const NegArgs<float> &);
+#define FR_SPLIT_EXTERN(f, t) extern template hipError_t launch_split_tag<f, t>(const OpSplit &, const float *, int64_t, int, const float *, int64_t, int, float *, int64_t, int64_t, hipStream_t, const NegArgs<float> &);
 
 }  // namespace frd

@@ -8,8 +8,8 @@ result is bitwise the same:
 * fr_rhs, fixed RK45[2R+] and RK4 steps, and the adaptive RK45[2R+] with
   its error register;
 * a batch of problems with per-problem step sizes;
-* FP32 and FP64, on the mixed tet/prism box and the three-type box (element
-  counts ragged against the 64-column panels).
+* FP32, FP64 and the split BF16 / FP16 forms, on the mixed tet/prism box and
+  the three-type box (element counts ragged against the 64-column panels).
 """
 import math
 
@@ -55,8 +55,8 @@ def _run(M, U, ts, dt):
     return r, s, a, counts, state
 
 
-@pytest.mark.parametrize("kind", ["mixed", "hybrid"])
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("kind,prec", [("mixed", "fp32"), ("mixed", "fp64"), ("hybrid", "fp32"),
+                                       ("hybrid", "fp64"), ("mixed", "split_bf16"), ("hybrid", "split_fp16")])
 def test_fused_update_gives_the_bits_of_the_separate_kernel(kind, prec):
     from paper_1409_0405_amd import frlib
     p = 3
