@@ -1088,10 +1088,13 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                     op = fragment<T>(*c.A, c.M, c.K, f, cap, stage, &idx);
                     FR_HIP(m, upload_op(op, f, idx, mine));
                 }
-                // the divergence is timed with the fused store the right-hand
-                // side uses, writing -R~/J into the R~ buffer (no registers)
+                // the divergence is timed with the fused store the RK stages
+                // use: read, update and write an accumulator and write the
+                // output (both the R~ buffer here, unused when fused)
                 frd::NegArgs<T> na{};
                 na.out = D.Rt;
+                na.acc = D.Rt;
+                na.a = T(0);
                 na.b = T(1);
                 na.jinv = D.jinv;
                 na.ld = D.ld;
