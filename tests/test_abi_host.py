@@ -24,6 +24,23 @@ def test_header_and_binding_agree():
     assert _declared() == sorted(frlib.EXPORTED)
 
 
+def test_header_constants_match_binding():
+    """Every #define FR_* and enum constant of the header has the binding's
+    value (flags, element types, boundary kinds, precisions, schemes)."""
+    src = open(os.path.join(ROOT, "include", "fr.h")).read()
+    consts = {k: int(v, 0) for k, v in re.findall(r"^#define\s+(FR_\w+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", src, re.M)}
+    consts.update({k: int(v) for k, v in re.findall(r"\b(FR_[A-Z0-9_]+)\s*=\s*(\d+)", src)})
+    assert consts["FR_SEPARATE_UPDATE"] == 0x4
+    checked = 0
+    for k, v in consts.items():
+        if hasattr(frlib, k):
+            assert getattr(frlib, k) == v, k
+            checked += 1
+    assert checked >= 12
+    assert consts["FR_NTYPES"] == frlib.NTYPES == len(frlib.TYPE_NAMES)
+    assert consts["FR_PROF_NCLASS"] == len(frlib.PROF_CLASSES)
+
+
 def test_library_exports_declared_symbols():
     L = frlib.lib()
     for name in _declared():
