@@ -39,6 +39,7 @@ def test_header_constants_match_binding():
     assert checked >= 12
     assert consts["FR_NTYPES"] == frlib.NTYPES == len(frlib.TYPE_NAMES)
     assert consts["FR_PROF_NCLASS"] == len(frlib.PROF_CLASSES)
+    assert (consts["FR_MLP_NPARAM"], consts["FR_MLP_NSTATS"]) == (frlib.MLP_NPARAM, frlib.MLP_NSTATS)
 
 
 def test_library_exports_declared_symbols():
