@@ -413,6 +413,47 @@ def batch_form(steps, warmup, cfl=0.2):
     return out
 
 
+def graph_form(arrays, p, steps, warmup, mach, mu, pr, dt):
+    """The headline mesh as a one-problem batch (autotuned at creation), whose
+    RK45[2R+] step the library captures once as a HIP graph: the per-step
+    and per-stage time of graph replay against the same steps launched
+    eagerly."""
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import frlib, inputs
+    B = frlib.Batch([(arrays, p)], system="ns", precision="fp32", mu=mu, prandtl=pr)
+    dof = 0
+    for t in (0, 1):
+        q = B.query(0, t)
+        x = B.upts_coords(0, t)
+        U = inputs.taylor_green(x[:, 0], x[:, 1], x[:, 2], mach=mach)
+        dev = B.state_tensor(0, t)
+        dev[:, :, :q["nelem"]] = torch.as_tensor(np.transpose(U, (1, 0, 2)), dtype=torch.float32)
+        dev[:, :, q["nelem"]:] = dev[:, :, :1]
+        B.set_solution(0, t, dev.data_ptr())
+        torch.cuda.synchronize()
+        dof += q["nupts"] * q["nelem"] * 5
+    B.set_dt([dt])
+    out = {"n_dof": dof}
+    for graph in (True, False):
+        B.set_graph(graph)
+        B.rk_step(frlib.FR_RK45_2RP, max(warmup, 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.rk_step(frlib.FR_RK45_2RP, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["graph" if graph else "eager"] = {"ms_per_step": 1e3 * el / steps, "ms_per_stage": 1e3 * el / steps / 5,
+                                              "value": 5.0 * dof * steps / el / 1e9}
+    x = B.state_tensor(0, 1)
+    B.get_solution(0, 1, x.data_ptr())
+    torch.cuda.synchronize()
+    out["finite"] = bool(torch.isfinite(x).all().item())
+    out["unit"] = "GDOF/s per RHS"
+    B.close()
+    return out
+
+
 def roofline_of(model, avg_s, k, key="flops"):
     """Roofline entry of kernel class k from its algorithmic model (flops of
     the given key: the paper's dense count, or the structural nonzeros) and
@@ -794,6 +835,9 @@ def main():
         forms = forms or {}
         forms["batch_512_euler"] = bf
         print(f"batch: {bf}", file=sys.stderr, flush=True)
+        gf = graph_form(arrays, p, args.steps, args.warmup, mach, mu, pr, dt)
+        forms["rk_graph_headline"] = gf
+        print(f"rk graph: {gf}", file=sys.stderr, flush=True)
 
     if not args.no_hex:
         mesh.close()
