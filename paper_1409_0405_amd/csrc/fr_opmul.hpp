@@ -390,15 +390,18 @@ __global__ __launch_bounds__(512) void opmul_lds_kernel(Op<float> A, const float
     for (int c = 0; c < nchunk; ++c) {
         const bool more = c + 1 < nchunk;
         if (more) {
+            __builtin_amdgcn_s_setprio(2);
             gload(c + 1);
             aload(c + 1, an);
+            __builtin_amdgcn_s_setprio(1);
         }
         const floatx4 *Bc = Bs[c & 1];
         // Kb is a multiple of KS (the fragment is zero padded): no tail test.
-        // The wave's issue priority is raised over its matrix instructions,
-        // so that the SIMD keeps feeding the matrix core while the other
-        // wavefronts' loads wait (measured: 3 % on this kernel; the same in
-        // the direct and step-list kernels slows them)
+        // Issue priority: highest while a wave sends out the next chunk's
+        // loads, raised over its matrix instructions, normal otherwise, so
+        // the loads leave early and the SIMD keeps feeding the matrix core
+        // (measured: 4 % on this kernel; the same in the direct and
+        // step-list kernels slows them)
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
