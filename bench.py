@@ -45,82 +45,82 @@ RIDGE = PEAK_FP32_MFMA / PEAK_HBM
 MEASURED_TRAFFIC = {
     ('common_flux', 0, 0): 1966.1e6,
     ('common_solution', 0, 0): 795.8e6,
-    ('div_pri', 5, 0): 1067.4e6,
+    ('div_pri', 5, 0): 1067.5e6,
     ('div_tet', 3, 0): 926.3e6,
     ('grad_pri', 1, 0): 897.2e6,
     ('grad_pri', 1, 3): 897.3e6,
-    ('grad_pri', 1, 4): 897.5e6,
-    ('grad_pri', 1, 5): 902.0e6,
-    ('grad_pri', 1, 6): 906.1e6,
+    ('grad_pri', 1, 4): 897.6e6,
+    ('grad_pri', 1, 5): 903.0e6,
+    ('grad_pri', 1, 6): 906.4e6,
     ('grad_pri', 2, 0): 897.4e6,
-    ('grad_pri', 2, 1): 899.6e6,
-    ('grad_pri', 2, 2): 902.0e6,
-    ('grad_pri', 2, 3): 897.5e6,
-    ('grad_pri', 2, 4): 898.2e6,
-    ('grad_pri', 2, 5): 915.9e6,
-    ('grad_pri', 2, 6): 901.6e6,
+    ('grad_pri', 2, 1): 903.8e6,
+    ('grad_pri', 2, 2): 901.8e6,
+    ('grad_pri', 2, 3): 897.6e6,
+    ('grad_pri', 2, 4): 898.3e6,
+    ('grad_pri', 2, 5): 913.5e6,
+    ('grad_pri', 2, 6): 900.4e6,
     ('grad_pri', 3, 0): 898.6e6,
-    ('grad_pri', 3, 1): 899.3e6,
+    ('grad_pri', 3, 1): 899.4e6,
     ('grad_pri', 3, 2): 901.3e6,
-    ('grad_pri', 3, 3): 903.9e6,
-    ('grad_pri', 3, 4): 900.9e6,
-    ('grad_pri', 3, 5): 934.3e6,
-    ('grad_pri', 3, 6): 912.9e6,
-    ('grad_pri', 4, 0): 899.1e6,
-    ('grad_pri', 4, 1): 900.4e6,
-    ('grad_pri', 4, 2): 905.4e6,
+    ('grad_pri', 3, 3): 903.3e6,
+    ('grad_pri', 3, 4): 901.0e6,
+    ('grad_pri', 3, 5): 938.0e6,
+    ('grad_pri', 3, 6): 913.1e6,
+    ('grad_pri', 4, 0): 898.8e6,
+    ('grad_pri', 4, 1): 903.7e6,
+    ('grad_pri', 4, 2): 906.4e6,
     ('grad_pri', 4, 3): 898.2e6,
-    ('grad_pri', 4, 4): 906.1e6,
-    ('grad_pri', 4, 5): 903.2e6,
-    ('grad_pri', 4, 6): 910.6e6,
-    ('grad_pri', 5, 0): 903.3e6,
-    ('grad_pri', 5, 1): 899.7e6,
-    ('grad_pri', 5, 2): 905.4e6,
-    ('grad_pri', 5, 3): 908.7e6,
+    ('grad_pri', 4, 4): 906.2e6,
+    ('grad_pri', 4, 5): 903.6e6,
+    ('grad_pri', 4, 6): 910.0e6,
+    ('grad_pri', 5, 0): 903.8e6,
+    ('grad_pri', 5, 1): 900.0e6,
+    ('grad_pri', 5, 2): 908.6e6,
+    ('grad_pri', 5, 3): 909.1e6,
     ('grad_pri', 5, 4): 908.2e6,
-    ('grad_pri', 8, 0): 908.2e6,
-    ('grad_pri', 8, 1): 903.6e6,
-    ('grad_pri', 8, 2): 2118.6e6,
+    ('grad_pri', 8, 0): 907.6e6,
+    ('grad_pri', 8, 1): 903.4e6,
+    ('grad_pri', 8, 2): 2097.9e6,
     ('grad_pri', 8, 3): 903.0e6,
     ('grad_tet', 7, 0): 788.0e6,
-    ('gradinterp_pri', 1, 0): 1194.6e6,
-    ('gradinterp_pri', 1, 1): 1194.6e6,
+    ('gradinterp_pri', 1, 0): 1194.7e6,
+    ('gradinterp_pri', 1, 1): 1194.7e6,
     ('gradinterp_pri', 1, 2): 1194.7e6,
     ('gradinterp_pri', 1, 3): 1194.8e6,
     ('gradinterp_pri', 1, 4): 1194.8e6,
-    ('gradinterp_pri', 1, 5): 1201.9e6,
+    ('gradinterp_pri', 1, 5): 1200.9e6,
     ('gradinterp_pri', 1, 6): 1196.3e6,
     ('gradinterp_pri', 2, 0): 1194.7e6,
-    ('gradinterp_pri', 2, 1): 1194.8e6,
-    ('gradinterp_pri', 2, 2): 1194.9e6,
+    ('gradinterp_pri', 2, 1): 1195.0e6,
+    ('gradinterp_pri', 2, 2): 1195.0e6,
     ('gradinterp_pri', 2, 3): 1194.8e6,
     ('gradinterp_pri', 2, 4): 1194.9e6,
-    ('gradinterp_pri', 2, 5): 1205.0e6,
-    ('gradinterp_pri', 2, 6): 1200.8e6,
+    ('gradinterp_pri', 2, 5): 1206.9e6,
+    ('gradinterp_pri', 2, 6): 1201.0e6,
     ('gradinterp_pri', 3, 0): 1194.9e6,
-    ('gradinterp_pri', 3, 1): 1195.0e6,
-    ('gradinterp_pri', 3, 2): 1195.0e6,
+    ('gradinterp_pri', 3, 1): 1195.1e6,
+    ('gradinterp_pri', 3, 2): 1195.1e6,
     ('gradinterp_pri', 3, 3): 1195.0e6,
     ('gradinterp_pri', 3, 4): 1195.6e6,
-    ('gradinterp_pri', 3, 5): 1199.6e6,
-    ('gradinterp_pri', 3, 6): 1197.6e6,
+    ('gradinterp_pri', 3, 5): 1199.4e6,
+    ('gradinterp_pri', 3, 6): 1197.4e6,
     ('gradinterp_pri', 4, 0): 1194.9e6,
-    ('gradinterp_pri', 4, 1): 1195.0e6,
+    ('gradinterp_pri', 4, 1): 1195.2e6,
     ('gradinterp_pri', 4, 2): 1195.1e6,
     ('gradinterp_pri', 4, 3): 1194.9e6,
     ('gradinterp_pri', 4, 4): 1195.4e6,
-    ('gradinterp_pri', 4, 5): 1198.6e6,
-    ('gradinterp_pri', 4, 6): 1198.9e6,
+    ('gradinterp_pri', 4, 5): 1198.0e6,
+    ('gradinterp_pri', 4, 6): 1198.3e6,
     ('gradinterp_pri', 7, 0): 1195.5e6,
-    ('gradinterp_pri', 7, 1): 1195.3e6,
-    ('gradinterp_pri', 7, 2): 2028.3e6,
+    ('gradinterp_pri', 7, 1): 1195.5e6,
+    ('gradinterp_pri', 7, 2): 1996.6e6,
     ('gradinterp_pri', 7, 3): 1197.1e6,
-    ('gradinterp_pri', 7, 4): 1196.8e6,
+    ('gradinterp_pri', 7, 4): 1196.7e6,
     ('gradinterp_tet', 4, 0): 1120.8e6,
-    ('interp_pri', 7, 0): 399.0e6,
+    ('interp_pri', 7, 0): 399.1e6,
     ('interp_tet', 4, 0): 373.8e6,
-    ('upts_pri', 0, 0): 1811.2e6,
-    ('upts_tet', 0, 0): 1569.9e6,
+    ('upts_pri', 0, 0): 1811.1e6,
+    ('upts_tet', 0, 0): 1570.8e6,
 }
 
 
