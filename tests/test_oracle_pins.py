@@ -307,12 +307,45 @@ def test_rk45_order_conditions():
              (b @ A @ A @ c, 1 / 24)]
     for got, want in conds:
         assert abs(got - want) < 1e-14
-    for got, want in conds[:4]:
-        pass
     for got, want in [(bh.sum(), 1), (bh @ c, 1 / 2), (bh @ c ** 2, 1 / 3), (bh @ A @ c, 1 / 6)]:
         assert abs(got - want) < 1e-14
     # it is genuinely an embedded pair, not a copy
     assert np.abs(b - bh).max() > 1e-3
+
+
+def test_controller_factors_by_hand():
+    """The PI step-size factors of the adaptive RK45[2R+] (k = 4, safety 0.9,
+    factor clamped to [0.2, 5], at most 1 after a rejection), worked out by
+    hand on error values whose powers are exact:
+    * accepted, err = 1e-2, err_prev = 1e-1:
+      0.9 (1e-2)^(-0.7/4) (1e-1)^(0.4/4) = 0.9 10^(0.35 - 0.1) = 0.9 10^0.25;
+    * accepted, err = err_prev = 1: 0.9;
+    * accepted, err = 1e-8, err_prev = 1e-4: 0.9 10^(1.4 - 0.4) = 9 -> 5;
+    * accepted, err = 0: the maximum factor 5;
+    * accepted, err = 1, err_prev = 1e-12 (below any floor): 0.9 10^-1.2 =
+      0.0568 -> 0.2;
+    * rejected, err = 16: 0.9 16^(-1/4) = 0.45;
+    * rejected, err = 1e4: 0.9 10^-1 = 0.09 -> 0.2;
+    * rejected, err = 1 + 1e-12: 0.9 (1 + 1e-12)^(-1/4) < 1, ~0.9."""
+    cases = [((1e-2, 1e-1, True), 0.9 * 10 ** 0.25), ((1.0, 1.0, True), 0.9),
+             ((1e-8, 1e-4, True), 5.0), ((0.0, 0.5, True), 5.0), ((1.0, 1e-12, True), 0.2),
+             ((16.0, 1.0, False), 0.45), ((1e4, 1.0, False), 0.2), ((1.0 + 1e-12, 1.0, False), 0.9)]
+    for (err, prev, acc), want in cases:
+        got = rk.controller(err, prev, acc)
+        assert abs(got - want) < 1e-12, (err, prev, acc, got, want)
+
+
+def test_adaptive_err_prev_floor():
+    """After an accepted step the controller's memory is max(err, 1e-4):
+    y' = 0 has zero embedded error on every step, so each accepted step
+    leaves err_prev = 1e-4 and grows dt by the maximum factor 5."""
+    U = {"x": np.ones((2, 3, 5))}
+    out = rk.rk45_adaptive(lambda V: {n: np.zeros_like(V[n]) for n in V}, U, 0.0, 10.0, 0.01, 1e-6, 1e-6)
+    _, t, dt, err_prev, n_acc, n_rej, errs = out
+    assert t == 10.0 and n_rej == 0 and err_prev == 1e-4 and max(errs) == 0.0
+    # steps 0.01, 0.05, 0.25, 1.25, 6.25 (t = 7.81), then the last step is cut
+    # to 10 - 7.81 and the next dt is five times that
+    assert n_acc == 6 and abs(dt - 5.0 * (10.0 - (0.01 + 0.05 + 0.25 + 1.25 + 6.25))) < 1e-12
 
 
 @pytest.mark.parametrize("stepper,order", [(rk.rk4_step, 4), (rk.rk45_step, 4),
