@@ -1165,6 +1165,10 @@ struct fr_batch_s {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // register pointers (group, type, register) the graph was captured with:
+    // an RK4 step swaps registers, after which the graph would advance a
+    // stale buffer, so a mismatch re-captures it
+    std::vector<const void *> graph_regs;
     bool use_graph = true;
     std::string err;
     ~fr_batch_s() {
@@ -1726,6 +1730,24 @@ fr_status fr_batch_rk_step(fr_batch b, int32_t scheme, int32_t n_steps, void *st
     };
     // RK4 swaps its registers every step and cannot be replayed as one graph
     if (!b->use_graph || scheme != FR_RK45_2RP) return step_all(s, n_steps);
+    std::vector<const void *> regs;
+    for (int g = 0; g < 4; ++g) {
+        fr_mesh m = b->group[g].get();
+        if (!m) continue;
+        for (int t = 0; t < frh::NTYPE; ++t)
+            for (int r = 0; r < 3; ++r)
+                regs.push_back(m->precision != FR_FP64 ? static_cast<const void *>(dev_of<float>(m).t[t].reg[r])
+                                                       : static_cast<const void *>(dev_of<double>(m).t[t].reg[r]));
+    }
+    if (b->exec && regs != b->graph_regs) {
+        // the captured launches still use the previous register order: wait
+        // for its replays on the batch stream, then capture again
+        FR_BHIP(b, hipStreamSynchronize(b->stream));
+        FR_BHIP(b, hipGraphExecDestroy(b->exec));
+        FR_BHIP(b, hipGraphDestroy(b->graph));
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
     if (!b->exec) {
         FR_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         fr_status r = step_all(b->stream, 1);
@@ -1738,6 +1760,7 @@ fr_status fr_batch_rk_step(fr_batch b, int32_t scheme, int32_t n_steps, void *st
         if (e != hipSuccess) return bfail(b, FR_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
         b->graph = gph;
         FR_BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_regs = regs;
     }
     FR_BHIP(b, hipEventRecord(b->ev_in, s));
     FR_BHIP(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));

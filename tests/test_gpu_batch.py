@@ -124,6 +124,34 @@ def test_graph_replays_match_eager():
                 assert np.array_equal(got, ref[s][i][t]), (s, i, t)
 
 
+
+def test_graph_recaptured_after_rk4_swaps_registers():
+    """An RK4 step swaps the state registers; an RK45[2R+] step replayed from
+    the graph captured before it must advance the new state register.  The
+    sequence RK45 (graph), RK4 (odd count), RK45 (graph) is compared bit for
+    bit with the same sequence stepped eagerly."""
+    from paper_1409_0405_amd import frlib
+    probs = _problems(n=4, seed=12)
+    seq = [(frlib.FR_RK45_2RP, 2), (frlib.FR_RK4, 1), (frlib.FR_RK45_2RP, 2), (frlib.FR_RK4, 3),
+           (frlib.FR_RK45_2RP, 1)]
+    out = {}
+    for use_graph in (False, True):
+        B, _ = _batch(probs, "fp32")
+        B.set_graph(use_graph)
+        snaps = []
+        for scheme, n in seq:
+            B.rk_step(scheme, n)
+            torch.cuda.synchronize()
+            snaps.append([[_get(B, i, t, B.query(i, t)["nelem"]) for t in (0, 1)] for i in range(len(probs))])
+        B.close()
+        out[use_graph] = snaps
+    for k in range(len(seq)):
+        for i in range(len(probs)):
+            for t in (0, 1):
+                assert np.array_equal(out[True][k][i][t], out[False][k][i][t]), (k, i, t)
+    # the state moved on every call
+    assert not np.array_equal(out[True][0][0][0], out[True][2][0][0])
+
 def test_autotune_keeps_results_bitwise():
     from paper_1409_0405_amd import frlib
     arrays = inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=2)

@@ -409,4 +409,44 @@ def test_freestream_and_conservation_fp32(kind):
     Rg = _gpu_rhs(M, O, U)
     fscale = 5.0   # |flux| ~ p + rho u^2 ~ 1 for inputs.uniform
     worst = max(np.abs(Rg[n]).max() for n in Rg)
+    print(f"  freestream max |R| {worst:.2e}", flush=True)
     assert worst < 1e-4 * fscale, worst
+    # conservation: the FP64 sum of w J R(U) over the periodic mesh is zero
+    # up to the FP32 rounding of the summed terms, for a state that is not
+    # uniform (scale: the same sum over |R|, from the oracle)
+    prm = fr.Params(system="ns", mu=0.01)
+    V = _round32(_state(O, inputs.taylor_green, 7, mach=0.3))
+    Ro = fr.rhs(O, V, prm)
+    for n in O.types:
+        t = NAMES.index(n)
+        M.set_solution(t, _lib().to_device_state(M, t, np.transpose(V[n], (1, 2, 0))).data_ptr())
+    torch.cuda.synchronize()
+    ir = M.reduce(_lib().FR_RED_INT_R)
+    scale = reduce.integral(O, {n: np.abs(Ro[n]) for n in Ro})
+    print(f"  integral R / integral |R| {np.abs(ir) / scale}", flush=True)
+    assert (np.abs(ir) <= 1e-5 * scale).all(), np.abs(ir) / scale
+
+
+def test_nonfinite_state_is_reported():
+    """FR_CHECK_FINITE: a NaN written into one state value through
+    fr_set_solution makes fr_rk_step return FR_ERR_NONFINITE (the check is a
+    device-side FP64 count of non-finite values after the steps); the same
+    mesh with a finite state steps without error."""
+    frlib = _lib()
+    arrays = _mesh("mixed", seed=8)
+    p = 2
+    O = om.build_mesh(arrays, p)
+    U = _round32(_state(O, inputs.taylor_green, 8, mach=0.3))
+    M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.02, check_finite=True)
+    for n in O.types:
+        t = NAMES.index(n)
+        M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U[n], (1, 2, 0))).data_ptr())
+    M.rk_step(frlib.FR_RK45_2RP, 1e-4, 2)
+    torch.cuda.synchronize()
+    bad = np.transpose(U["pri"], (1, 2, 0)).copy()
+    bad[3, 4, 17] = np.nan                      # energy at solution point 3 of prism 17
+    M.set_solution(1, frlib.to_device_state(M, 1, bad).data_ptr())
+    with pytest.raises(frlib.FrError) as ei:
+        M.rk_step(frlib.FR_RK45_2RP, 1e-4, 1)
+    assert ei.value.status == frlib.FR_ERR_NONFINITE, ei.value
+    print(f"  {ei.value}", flush=True)

@@ -298,19 +298,3 @@ def test_hex_taylor_green_initial_dissipation():
     rate = reduce.kinetic_energy_rate(M, U, R)
     assert abs(-rate / (0.75 * mu) - 1.0) < 0.03, -rate / (0.75 * mu)
 
-
-@pytest.mark.slow
-def test_taylor_green_initial_dissipation_converges():
-    """The same rate on boxes of 8, 12 and 16 cells per side (p = 4,
-    mu = 1/100): the relative error of -dE_k/dt against 3/4 mu falls at
-    least at order p (measured ~4.6) and is below 1e-3 on the finest box."""
-    mu = 1.0 / 100.0
-    errs = []
-    for n in (8, 12, 16):
-        M = _mixed(4, nxy=n, n_pri_layers=n // 2, n_tet_layers=n // 2, jitter=0.05)
-        U = fr.initial_state(M, inputs.taylor_green)
-        R = fr.rhs(M, U, fr.Params(system="ns", mu=mu))
-        errs.append(abs(-reduce.kinetic_energy_rate(M, U, R) / (0.75 * mu) - 1.0))
-    order = np.log(errs[1] / errs[2]) / np.log(16 / 12)
-    print("relative errors", errs, "observed order", order)
-    assert errs[2] < 1e-3 and errs[0] > errs[1] > errs[2] and order >= 4, (errs, order)
