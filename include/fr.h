@@ -83,6 +83,12 @@ typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
  * orders of work give the same bits.  The autotuner times the divergence
  * products the way the right-hand side runs them. */
 #define FR_SEPARATE_UPDATE 0x4u
+/* Navier-Stokes tets and prisms in FP32 / FP64: run the corrected gradient
+ * product, the solution-point work (physical gradient, transformed flux) and
+ * the gradient interpolation as three kernels that pass the reference and
+ * physical gradients through memory.  By default one kernel does all three
+ * per tile of elements with those gradients in LDS; both give the same bits. */
+#define FR_SEPARATE_GRADIENT 0x8u
 
 typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
 
@@ -144,6 +150,16 @@ typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
  *            with xyz (and the images), neighbours must share face nodes.
  *            The metric terms are then stored per solution point (9 + 1
  *            values).
+ * p_ref      reference pressure taken out of the pressure term of the
+ *            momentum flux, in the volume flux and in the interface and
+ *            boundary fluxes alike (0: the plain flux).  The flux of a
+ *            uniform state has zero discrete divergence on a mesh that
+ *            preserves such a state (every straight-sided mesh; curved ones
+ *            at the orders where the metric terms are interpolated exactly),
+ *            so the residual is unchanged in exact arithmetic, while single
+ *            precision no longer rounds the large constant part of the
+ *            pressure gradient at low Mach number.  A batch takes it from its
+ *            first description (all must agree).
  */
 typedef struct {
     int32_t order;
@@ -168,6 +184,7 @@ typedef struct {
     double t_wall;
     double farfield[5];
     const double *tet_q, *pri_q, *hex_q;
+    double p_ref;
 } fr_mesh_desc;
 
 /* Build operators (FP64 on the host), geometry and the interface pairing,
@@ -273,8 +290,10 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * 11 common interface flux, 12 + etype negdivconf with the Runge-Kutta
  * update, 14 closure inputs (moments and neighbour gathering), 15 closure
  * network forward; hexahedra: 16 + op the products, 20 the solution-point
- * kernel, 21 negdivconf; 22 boundary states, 23 boundary flux. */
-#define FR_PROF_NCLASS 24
+ * kernel, 21 negdivconf; 22 boundary states, 23 boundary flux; 24 + etype
+ * the fused gradient stage of tets and prisms (corrected gradient, point-wise
+ * work and gradient interpolation in one kernel). */
+#define FR_PROF_NCLASS 26
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 

@@ -45,6 +45,8 @@ struct DevType {
     int nu = 0, nf = 0;
     int64_t nelem = 0, ld = 0;
     frd::Op<T> Aint, Agint, Agrad, Adiv;          // Agint: M0 for the gradients
+    frd::Op<T> Fgrad, Fgint;                      // fused gradient stage (step lists, one row block per group)
+    bool fuse_grad = true;                        // use it (the autotuner times both forms)
     frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
     T *jinv = nullptr;        // [nu][ld] 1 / J at the solution points (host FP64, rounded)
@@ -108,6 +110,7 @@ struct fr_mesh_s {
     uint32_t flags = 0;
     double gamma = 1.4, mu = 0, prandtl = 0.72, beta = 0.5, tau = 0.1;
     double t_wall = 1.0, farfield[5] = {1.0, 0.0, 0.0, 0.0, 1.0 / 1.4};
+    double pref = 0;          // reference pressure left out of the momentum flux
     frh::MeshHost host;
     hipStream_t create_stream = nullptr;
     bool device = false;
@@ -143,11 +146,13 @@ fr_status fail(fr_mesh m, fr_status st, const std::string &msg) {
 // tets and prisms, 8/9 solution-point kernel (tet/prism), 10 common solution,
 // 11 common flux, 12/13 negdivconf (tet/prism), 14/15 closure, 16..19
 // hexahedron products (16 + op), 20 hexahedron solution-point kernel, 21
-// hexahedron negdivconf, 22 / 23 boundary states / boundary flux.
+// hexahedron negdivconf, 22 / 23 boundary states / boundary flux, 24 / 25
+// fused gradient stage (tet / prism).
 constexpr int PROF_NCLASS = FR_PROF_NCLASS;
 constexpr int prof_op(int t, int op) { return t < 2 ? 4 * t + op : 16 + op; }
 constexpr int prof_upts(int t) { return t < 2 ? 8 + t : 20; }
 constexpr int prof_neg(int t) { return t < 2 ? 12 + t : 21; }
+constexpr int prof_gradflux(int t) { return 24 + t; }
 constexpr size_t PROF_NONE = size_t(-1);
 
 size_t prof_begin(fr_mesh m, hipStream_t s) {
@@ -215,12 +220,12 @@ std::vector<int> cluster_rows(const std::vector<double> &A, int M, int K, int gs
 
 template <typename T>
 frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T> &f, int cap = 0,
-                    int stage = 0, std::vector<int32_t> *idx = nullptr) {
+                    int stage = 0, std::vector<int32_t> *idx = nullptr, bool cluster = true) {
     frd::Op<T> op;
     op.M = M;
     op.stage = stage;
     // stages 5 and 6 (step lists): rows permuted into clustered groups
-    // (perm[r'] = source row)
+    // (perm[r'] = source row), unless the caller has ordered them
     const bool steps = stage == 5 || stage == 6;
     std::vector<int> perm;
     std::vector<double> Aperm;
@@ -232,7 +237,12 @@ frd::Op<T> fragment(const std::vector<double> &A_in, int M, int K, std::vector<T
     frd::row_groups(M, cap ? cap : (sizeof(T) == 4 ? 8 : 4), op.nmg, op.mbw);
     const int Mb = op.nmg * op.mbw;
     if (steps) {
-        perm = cluster_rows(A_in, M, K, 16 * op.mbw);
+        if (cluster) {
+            perm = cluster_rows(A_in, M, K, 16 * op.mbw);
+        } else {
+            perm.resize(M);
+            for (int r = 0; r < M; ++r) perm[r] = r;
+        }
         Aperm.resize(size_t(M) * K);
         for (int r = 0; r < M; ++r)
             std::copy(A_in.begin() + size_t(perm[r]) * K, A_in.begin() + size_t(perm[r] + 1) * K,
@@ -460,6 +470,14 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         FR_TRY(dev_upload(m, d, p, f, s));
         D.Adiv.frag = p;
         D.Agint = D.Aint;
+        if (ns && t < 2 && (m->precision == FR_FP32 || m->precision == FR_FP64)) {
+            // the fused gradient stage walks the step lists of one row block
+            std::vector<int32_t> idx;
+            D.Fgrad = fragment<T>(grad, 3 * nu, nu + nf, f, 1, 6, &idx);
+            FR_HIP(m, upload_op(D.Fgrad, f, idx, d.allocs));
+            D.Fgint = fragment<T>(R.M0, nf, nu, f, 1, 6, &idx);
+            FR_HIP(m, upload_op(D.Fgint, f, idx, d.allocs));
+        }
         if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
             const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
             std::vector<uint16_t> parts[3];
@@ -635,6 +653,42 @@ hipError_t opmul(fr_mesh m, int tag, const frd::Op<T> &A, const frd::OpSplit &S,
     return frd::launch_opmul<T>(tag, A, B1, ldb1, K1, B2, ldb2, K2, C, ldc, ncols, s, ep);
 }
 
+// Arguments of the fused gradient stage of one element type on state U.
+template <typename T>
+frd::GradFluxArgs<T> gradflux_args(fr_mesh m, const DevType<T> &D, const T *U) {
+    frd::GradFluxArgs<T> ga;
+    ga.U = U;
+    ga.Cf = D.Cf;
+    ga.Ft = D.Ft;
+    ga.Qf = D.Qf;
+    ga.geom = D.geom;
+    ga.xi = D.xi;
+    ga.padj = D.padj;
+    ga.pjinv = D.padj ? D.jinv : nullptr;
+    ga.ld = D.ld;
+    ga.nelem = D.nelem;
+    ga.nu = D.nu;
+    ga.nf = D.nf;
+    ga.gamma = T(m->gamma);
+    ga.mu = T(m->mu);
+    ga.prandtl = T(m->prandtl);
+    ga.pref = T(m->pref);
+    ga.G = D.Fgrad;
+    ga.M = D.Fgint;
+    return ga;
+}
+
+// Solution-point kernel arguments of one element type on state U.
+template <typename T>
+frd::UptsArgs<T> upts_args(fr_mesh m, const DevType<T> &D, const T *U) {
+    frd::UptsArgs<T> ua{U, D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu,
+                        T(m->gamma), T(m->mu), T(m->prandtl)};
+    ua.padj = D.padj;
+    ua.pjinv = D.jinv;
+    ua.pref = T(m->pref);
+    return ua;
+}
+
 template <typename T>
 fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T> so[frh::NTYPE],
                        hipStream_t s) {
@@ -665,6 +719,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     pa.prandtl = pr;
     pa.beta = T(m->beta);
     pa.tau = T(m->tau);
+    pa.pref = T(m->pref);
     frd::BndArgs<T> ba{};
     ba.side = d.bside;
     ba.geo = d.bgeo;
@@ -683,12 +738,23 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     ba.tau = T(m->tau);
     ba.t_wall = T(m->t_wall);
     for (int k = 0; k < 5; ++k) ba.free[k] = T(m->farfield[k]);
+    ba.pref = T(m->pref);
+    // Navier-Stokes tets and prisms: corrected gradient, point-wise work and
+    // gradient interpolation in one kernel (FR_SEPARATE_GRADIENT: three)
+    bool fused[frh::NTYPE] = {false, false, false};
+    for (int t = 0; t < frh::NTYPE; ++t)
+        fused[t] = ns && d.t[t].nelem && d.t[t].Fgrad.frag && d.t[t].fuse_grad && !(m->flags & FR_SEPARATE_GRADIENT);
     if (ns) {
         FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
         if (d.nb) FR_LAUNCH(m, 22, s, frd::launch_boundary_solution<T>(ba, s));
         for (int t = 0; t < frh::NTYPE; ++t) {
             DevType<T> &D = d.t[t];
             if (!D.nelem) continue;
+            if (fused[t]) {
+                const frd::GradFluxArgs<T> ga = gradflux_args<T>(m, D, U[t]);
+                FR_LAUNCH(m, prof_gradflux(t), s, frd::launch_gradflux<T>(t, ga, s));
+                continue;
+            }
             const int64_t w5 = 5 * D.ld;
             FR_LAUNCH(m, prof_op(t, frd::OP_GRAD), s,
                       opmul<T>(m, 4 * t + frd::OP_GRAD, D.Agrad, D.Sgrad, U[t], w5, D.nu, D.Cf, w5, D.nf, D.Qt, w5, w5, s));
@@ -697,9 +763,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
-        frd::UptsArgs<T> ua{U[t], D.Qt, D.Q, D.Ft, D.geom, D.xi, D.ld, D.nelem, D.nu, gamma, mu, pr};
-        ua.padj = D.padj;
-        ua.pjinv = D.jinv;
+        if (fused[t]) continue;
+        const frd::UptsArgs<T> ua = upts_args<T>(m, D, U[t]);
         FR_LAUNCH(m, prof_upts(t), s, frd::launch_upts<T>(t, ns, ua, s));
         if (ns) {
             const int64_t w15 = 15 * D.ld;
@@ -1141,6 +1206,34 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                       std::to_string(best_cap) + " stage " + std::to_string(best_stage) + " " +
                       std::to_string(best / 3 * 1e3) + " us; ";
         }
+        // the gradient stage (Navier-Stokes tets and prisms): the fused kernel
+        // against the three separate kernels with the variants just chosen
+        if (ns && D.Fgrad.frag && !(m->flags & FR_SEPARATE_GRADIENT)) {
+            const T *U = D.reg[0];
+            auto fused = [&]() -> hipError_t { return frd::launch_gradflux<T>(t, gradflux_args<T>(m, D, U), s); };
+            auto separate = [&]() -> hipError_t {
+                hipError_t e = opmul<T>(m, 4 * t + frd::OP_GRAD, D.Agrad, D.Sgrad, U, w5, nu, D.Cf, w5, nf, D.Qt,
+                                        w5, w5, s);
+                if (e == hipSuccess) e = frd::launch_upts<T>(t, true, upts_args<T>(m, D, U), s);
+                if (e == hipSuccess)
+                    e = opmul<T>(m, 4 * t + frd::OP_GRADINTERP, D.Agint, D.Sgint, D.Q, w15, nu, nullptr, 0, 0,
+                                 D.Qf, w15, w15, s);
+                return e;
+            };
+            float ms[2] = {0, 0};
+            for (int form = 0; form < 2; ++form) {
+                FR_HIP(m, form ? separate() : fused());
+                FR_HIP(m, hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) FR_HIP(m, form ? separate() : fused());
+                FR_HIP(m, hipEventRecord(e1, s));
+                FR_HIP(m, hipEventSynchronize(e1));
+                FR_HIP(m, hipEventElapsedTime(&ms[form], e0, e1));
+            }
+            D.fuse_grad = ms[0] <= ms[1];
+            static const char *const sn[frh::NTYPE] = {"tet", "pri", "hex"};
+            report += sn[t] + std::string(" gradient stage fused ") + std::to_string(ms[0] / 3 * 1e3) +
+                      " us, separate " + std::to_string(ms[1] / 3 * 1e3) + " us; ";
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1249,7 +1342,7 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
         desc->n_tets + desc->n_prisms + desc->n_hex == 0)
         return fail(nullptr, FR_ERR_INVALID_ARG, "empty or inconsistent mesh arrays");
     if (!(desc->gamma > 1) || desc->mu < 0 ||
-        (desc->system == FR_NAVIER_STOKES && !(desc->prandtl > 0)))
+        (desc->system == FR_NAVIER_STOKES && !(desc->prandtl > 0)) || !std::isfinite(desc->p_ref))
         return fail(nullptr, FR_ERR_INVALID_ARG, "invalid physical constants");
     if (desc->n_bfaces < 0 || (desc->n_bfaces && !desc->bfaces))
         return fail(nullptr, FR_ERR_INVALID_ARG, "inconsistent boundary face list");
@@ -1272,6 +1365,7 @@ fr_status fr_mesh_create(const fr_mesh_desc *desc, void *stream, fr_mesh *out) {
     m->tau = desc->ldg_tau;
     m->t_wall = desc->t_wall;
     for (int k = 0; k < 5; ++k) m->farfield[k] = desc->farfield[k];
+    m->pref = desc->p_ref;
     std::string err;
     try {
         if (!build_host(*desc, m->host, err)) return fail(nullptr, FR_ERR_BAD_MESH, err);
@@ -1535,7 +1629,7 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
         for (int k = 0; k < 5; ++k) same_bc = same_bc && d.farfield[k] == d0.farfield[k];
         if (d.system != d0.system || d.precision != d0.precision || d.gamma != d0.gamma ||
             d.mu != d0.mu || d.prandtl != d0.prandtl || d.ldg_beta != d0.ldg_beta ||
-            d.ldg_tau != d0.ldg_tau || !same_bc)
+            d.ldg_tau != d0.ldg_tau || d.p_ref != d0.p_ref || !std::isfinite(d.p_ref) || !same_bc)
             return bfail(nullptr, FR_ERR_INVALID_ARG,
                          "problem " + std::to_string(i) + ": system, precision and constants must match");
         if (d.order < 1 || d.order > 4)
@@ -1586,6 +1680,7 @@ fr_status fr_batch_create(int32_t n, const fr_mesh_desc *descs, void *stream, fr
         m->tau = d0.ldg_tau;
         m->t_wall = d0.t_wall;
         for (int k = 0; k < 5; ++k) m->farfield[k] = d0.farfield[k];
+        m->pref = d0.p_ref;
         std::vector<std::array<int64_t, frh::NTYPE>> off;
         std::string err;
         if (!frh::merge_meshes(parts[g], m->host, off, err)) return bfail(nullptr, FR_ERR_BAD_MESH, err);

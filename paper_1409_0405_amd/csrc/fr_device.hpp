@@ -98,9 +98,37 @@ struct UptsArgs {
     // curved elements: adjugate [9][nu][ld] (entry 3k + j = J dxi_k/dx_j)
     // and 1 / J [nu][ld] per point, used instead of geom when padj is set
     const T *padj = nullptr, *pjinv = nullptr;
+    T pref = 0;        // reference pressure left out of the momentum flux
 };
 template <typename T>
 hipError_t launch_upts(int etype, bool ns, const UptsArgs<T> &a, hipStream_t s);
+
+// Fused gradient stage of one element type (Navier-Stokes; tets and prisms):
+// per tile of elements (all five fields), the corrected gradient product
+// Qt = [G_k | L_k] [U; Cf], the point-wise work (Q = adj^T Qt / J, Ft) and the
+// gradient interpolation Qf = M0 Q, with Qt and Q held in LDS.  Gives the
+// bits of the separate kernels (same operator fragments, same K order, same
+// point-wise arithmetic).
+template <typename T>
+struct GradFluxArgs {
+    const T *U;          // [nu][5][ld]
+    const T *Cf;         // [nf][5][ld] jump to the common solution
+    T *Ft;               // [3 nu][5][ld] transformed flux, row k nu + i
+    T *Qf;               // [nf][15][ld] physical gradient at the flux points
+    const T *geom;       // [ng][ld] Jacobian coefficients (straight elements)
+    const T *xi;         // [nu][3]
+    const T *padj = nullptr, *pjinv = nullptr;   // curved: [9][nu][ld], [nu][ld]
+    int64_t ld = 0, nelem = 0;
+    int nu = 0, nf = 0;
+    T gamma = 0, mu = 0, prandtl = 0, pref = 0;
+    Op<T> G;             // [G_k | L_k], 3 nu x (nu + nf): step lists, one row block per group (stage 6)
+    Op<T> M;             // M0, nf x nu: step lists, one row block per group (stage 6)
+};
+// LDS bytes of one workgroup of the fused kernel (0: shape not supported).
+template <typename T>
+size_t gradflux_lds(int etype, const GradFluxArgs<T> &a);
+template <typename T>
+hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s);
 
 // Interface work on the paired flux points.
 template <typename T>
@@ -114,6 +142,7 @@ struct PairArgs {
     T *Fn[NTYPE];                    // [nf][5][ld]
     int64_t ld[NTYPE];
     T gamma, mu, prandtl, beta, tau;
+    T pref = 0;                      // reference pressure left out of the momentum flux
 };
 template <typename T>
 hipError_t launch_common_solution(const PairArgs<T> &a, hipStream_t s);
@@ -138,6 +167,7 @@ struct BndArgs {
     T gamma, mu, prandtl, tau;
     T t_wall;                        // wall temperature p / rho
     T free[5];                       // free stream rho, u, v, w, p
+    T pref = 0;                      // reference pressure left out of the momentum flux
 };
 // Cf = Ub - U_f at each boundary point (NS).
 template <typename T>

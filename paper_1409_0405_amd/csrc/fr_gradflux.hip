@@ -1,0 +1,303 @@
+// Fused gradient stage of the Navier-Stokes right-hand side (gfx950).
+//
+// Paper, Section 2.1: an FR step is operator products C <- A B with the
+// element state as B, separated by point-wise work.  Between the common
+// solution and the common flux the separate kernels pass three arrays
+// through memory: the reference gradient Qt (corrected gradient product),
+// the physical gradient Q and the transformed flux Ft (point-wise kernel),
+// and Q again (gradient interpolation).  Here one workgroup takes a tile of
+// NE elements with all five fields and keeps Qt and Q in LDS:
+//   1. B = [U; Cf] of the tile -> LDS;
+//   2. Qt = [G_k | L_k] B on the matrix cores -> LDS;
+//   3. per (solution point, element): Q = adj^T Qt / J (in place), and
+//      Ft = adj (F_inv(U) - F_vis(U, Q)) -> memory;
+//   4. Qf = M0 Q on the matrix cores -> memory.
+// Only U and Cf are read and only Ft and Qf are written.  The operator
+// fragments are those of the step-list products (one row block per group),
+// walked in the same K order, and the point-wise arithmetic is the shared
+// upts_point, so every value has the bits of the separate kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fr_device.hpp"
+#include "fr_opmul.hpp"
+#include "fr_pointwise.hpp"
+
+namespace frd {
+namespace {
+
+template <int ET>
+constexpr int n_geom_coeffs() { return ET == 0 ? 9 : 15; }
+
+// Entry i of a step list through the scalar data cache: the lists are
+// read-only and the index is uniform in the wavefront, and a constant-space
+// load lets the compiler use a scalar load, which the vector-memory counter
+// (the operator fragments in flight) does not wait for.
+__device__ __forceinline__ int sload(const int32_t *p, int i) {
+    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
+
+// acc[n] += A_g B[:, 16 n .. 16 n + 15] for row block g of a step-list
+// operator (one row block per group), B in LDS: brow(kb) points at row
+// 4 kb + krow, column lane % 16 of B.  The list is walked in chunks of four
+// steps (lists are padded to a multiple of four): while the 4 NB matrix
+// instructions of one chunk issue, the operator fragments (memory) and the
+// B values (LDS) of the next chunk are already on their way, so a wave waits
+// for neither.  The K order is the list order, as in the step-list product
+// kernel.
+template <typename T, int NB, typename V4, typename RowFn>
+__device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, RowFn brow, V4 (&acc)[NB]) {
+    const int s0 = sload(A.koff, g), ns = sload(A.koff, g + 1) - s0;   // a multiple of 4, >= 4
+    const int32_t *kl = A.klist + s0;
+    const T *Af = A.frag + size_t(s0) * 64 + lane;
+    T a0[4], b0[4][NB];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        a0[d] = Af[size_t(d) * 64];
+        const T *br = brow(sload(kl, d));
+#pragma unroll
+        for (int n = 0; n < NB; ++n) b0[d][n] = br[16 * n];
+    }
+    for (int st = 0; st < ns; st += 4) {
+        // the next chunk (the last chunk loads itself again: in bounds, unused)
+        const int nx = min(st + 4, ns - 4);
+        T a1[4], b1[4][NB];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            a1[d] = Af[size_t(nx + d) * 64];
+            const T *br = brow(sload(kl, nx + d));
+#pragma unroll
+            for (int n = 0; n < NB; ++n) b1[d][n] = br[16 * n];
+        }
+        // keep the scheduler from sinking the loads above next to their use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[n] = mfma16(a0[d], b0[d][n], acc[n]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            a0[d] = a1[d];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) b0[d][n] = b1[d][n];
+        }
+    }
+}
+
+// Tile of NE elements with all five fields: row r of a tile in LDS holds W5
+// columns, (field v, element e) at v NE + e and zeros up to W5; column block
+// n of the matrix instructions is columns 16 n .. 16 n + 15.
+template <int NE>
+struct TileShape {
+    static constexpr int W5 = (5 * NE + 15) / 16 * 16;
+    static constexpr int NB = W5 / 16;
+};
+
+// Elements per tile: 16 in FP32 (column block n = field n), 4 in FP64 (whose
+// LDS footprint per value is twice as large).
+template <typename T>
+constexpr int tile_elems() { return sizeof(T) == 4 ? 16 : 4; }
+
+// One workgroup of NW wavefronts per tile.  MG: row blocks of the gradient
+// operator per wavefront (>= nmg / NW); their accumulators stay in registers
+// until every wavefront has finished reading B, so that Qt takes B's place in
+// LDS and a tile needs max(B, Qt) of it.
+template <typename T, int ET, int NE, int NW, int MG>
+__global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
+    using v4 = typename Vec4<T>::type;
+    constexpr int W5 = TileShape<NE>::W5, NB = TileShape<NE>::NB;
+    constexpr int NG = n_geom_coeffs<ET>();
+    constexpr int VPR = NE * int(sizeof(T)) / 16;       // 16-byte vectors per (row, field)
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int Kp = 4 * a.G.Kb;
+    const int nu = a.nu;
+    // one region: B = [U; Cf] ([Kp][W5]) for the gradient product, then Qt
+    // and, in place, Q ([3 nu][W5], row k nu + i)
+    T *Bs = reinterpret_cast<T *>(lds_raw);
+    T *QT = Bs;
+    T *Gs = Bs + size_t(max(Kp, 3 * nu)) * W5;           // [NG][NE] Jacobian coefficients
+    T *Xs = Gs + NG * NE;                                // [nu][3] reference coordinates
+
+    const int64_t e0 = int64_t(xcd_block()) * NE;
+    if (e0 >= a.nelem) return;                           // whole workgroup: padding of the grid
+    // the wavefront index is uniform in the wavefront: say so, so that the
+    // step lists are read through scalar loads and the loops branch on
+    // scalars
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int krow = lane >> 4, c16 = lane & 15;
+    const int64_t ld = a.ld;
+
+    // 1. B rows: U (k < nu), Cf (nu <= k < nu + nf), zero up to Kp
+    {
+        const int nvec = Kp * 5 * VPR;
+        for (int idx = tid; idx < nvec; idx += 64 * NW) {
+            const int q = idx % VPR, kv = idx / VPR;
+            const int v = kv % 5, k = kv / 5;
+            floatx4 val = {0, 0, 0, 0};
+            if (k < nu)
+                val = *reinterpret_cast<const floatx4 *>(a.U + (int64_t(k) * 5 + v) * ld + e0 + q * (16 / sizeof(T)));
+            else if (k < nu + a.nf)
+                val = *reinterpret_cast<const floatx4 *>(a.Cf + (int64_t(k - nu) * 5 + v) * ld + e0 +
+                                                         q * (16 / sizeof(T)));
+            *reinterpret_cast<floatx4 *>(Bs + k * W5 + v * NE + q * (16 / sizeof(T))) = val;
+        }
+        if constexpr (W5 > 5 * NE) {
+            constexpr int PADC = W5 - 5 * NE;
+            for (int idx = tid; idx < Kp * PADC; idx += 64 * NW)
+                Bs[(idx / PADC) * W5 + 5 * NE + idx % PADC] = T(0);
+        }
+        if (!a.padj)
+            for (int idx = tid; idx < NG * NE; idx += 64 * NW)
+                Gs[idx] = a.geom[int64_t(idx / NE) * ld + e0 + idx % NE];
+        for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
+    }
+    __syncthreads();
+
+    // 2. Qt = [G_k | L_k] B: wavefront w takes row blocks w, w + NW, ..., each
+    // against every column block
+    v4 acc[MG][NB];
+#pragma unroll
+    for (int m = 0; m < MG; ++m) {
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = v4{0, 0, 0, 0};
+        const int g = w + m * NW;
+        if (g < a.G.nmg)
+            step_products<T, NB>(a.G, g, lane, [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; }, acc[m]);
+    }
+    __syncthreads();                                     // every wavefront is done with B
+#pragma unroll
+    for (int m = 0; m < MG; ++m) {
+        const int g = w + m * NW;
+        if (g >= a.G.nmg) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = a.G.rowmap[16 * g + acc_row<T>(krow, r)];
+            if (row >= 0) {
+#pragma unroll
+                for (int n = 0; n < NB; ++n) QT[row * W5 + 16 * n + c16] = acc[m][n][r];
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. point-wise: one (solution point, element) per thread; Q replaces Qt
+    // in place, Ft goes to memory
+    for (int it = tid; it < nu * NE; it += 64 * NW) {
+        const int i = it / NE, e = it - i * NE;
+        const int64_t eg = e0 + e;
+        if (eg >= a.nelem) continue;
+        T adj[3][3], Jinv;
+        if (a.padj) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * nu + i) * ld + eg];
+            Jinv = a.pjinv[int64_t(i) * ld + eg];
+        } else {
+            Jinv = T(1) / metric<T, ET>(Gs, NE, e, Xs + 3 * i, adj);
+        }
+        // U again from memory (B's place in LDS holds Qt now; the tile was
+        // just read, so these loads are served by L2)
+        T u[5], qt[3][5], q[3][5], Ft[3][5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u[v] = a.U[(int64_t(i) * 5 + v) * ld + eg];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qt[k][v] = QT[(k * nu + i) * W5 + v * NE + e];
+        upts_point<T, true>(u, qt, adj, Jinv, a.gamma, a.mu, a.prandtl, a.pref, q, Ft);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) QT[(j * nu + i) * W5 + v * NE + e] = q[j][v];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a.Ft[((int64_t(k) * nu + i) * 5 + v) * ld + eg] = Ft[k][v];
+    }
+    __syncthreads();
+
+    // 4. Qf = M0 Q for each gradient direction j: work items (row block, j)
+    for (int it = w; it < a.M.nmg * 3; it += NW) {
+        const int g = it / 3, j = it - 3 * g;
+        const T *Qj = QT + size_t(j) * nu * W5 + c16;
+        v4 acc2[NB];
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc2[n] = v4{0, 0, 0, 0};
+        // rows of B past K are clamped to a real row (times zero columns of A)
+        step_products<T, NB>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; }, acc2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = a.M.rowmap[16 * g + acc_row<T>(krow, r)];
+            if (f < 0) continue;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int flat = 16 * n + c16, v = flat / NE, e = flat - v * NE;
+                if (v < 5 && e0 + e < a.nelem) a.Qf[(int64_t(f) * 15 + j * 5 + v) * ld + e0 + e] = acc2[n][r];
+            }
+        }
+    }
+}
+
+constexpr size_t GRADFLUX_LDS_MAX = 160 * 1024;
+
+template <typename T, int ET, int NE, int NW, int MG>
+hipError_t launch_gf_mg(const GradFluxArgs<T> &a, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(gradflux_kernel<T, ET, NE, NW, MG>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(GRADFLUX_LDS_MAX));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t ntiles = (a.nelem + NE - 1) / NE;
+    gradflux_kernel<T, ET, NE, NW, MG><<<xcd_grid(ntiles), 64 * NW, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, int ET, int NE, int NW>
+hipError_t launch_gf(const GradFluxArgs<T> &a, size_t lds, hipStream_t s) {
+    const int mg = (a.G.nmg + NW - 1) / NW;
+    if (mg <= 1) return launch_gf_mg<T, ET, NE, NW, 1>(a, lds, s);
+    if (mg <= 2) return launch_gf_mg<T, ET, NE, NW, 2>(a, lds, s);
+    if (mg <= 4) return launch_gf_mg<T, ET, NE, NW, 4>(a, lds, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <typename T>
+size_t gradflux_lds(int etype, const GradFluxArgs<T> &a) {
+    if (etype != 0 && etype != 1) return 0;
+    constexpr int NE = tile_elems<T>();
+    constexpr int W5 = TileShape<NE>::W5;
+    const int ng = etype == 0 ? 9 : 15;
+    const size_t n = size_t(std::max(4 * a.G.Kb, 3 * a.nu)) * W5 + size_t(ng) * NE + size_t(3 * a.nu);
+    const size_t bytes = n * sizeof(T);
+    return bytes <= GRADFLUX_LDS_MAX ? bytes : 0;
+}
+
+template <typename T>
+hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s) {
+    const size_t lds = gradflux_lds<T>(etype, a);
+    // operator layout: step lists (4 steps in flight), one row block per group
+    if (!lds || a.G.stage != 6 || a.M.stage != 6 || a.G.mbw != 1 || a.M.mbw != 1 || !a.G.klist ||
+        !a.G.koff || !a.G.rowmap || !a.M.klist || !a.M.koff || !a.M.rowmap || a.G.M != 3 * a.nu ||
+        a.M.M != a.nf || 4 * a.G.Kb < a.nu + a.nf || 4 * a.M.Kb < a.nu || a.ld % 64 || a.nelem > a.ld ||
+        (reinterpret_cast<uintptr_t>(a.U) | reinterpret_cast<uintptr_t>(a.Cf)) % 16)
+        return hipErrorInvalidValue;
+    if (!a.nelem) return hipSuccess;
+    constexpr int NE = tile_elems<T>();
+    // eight wavefronts per workgroup (FP32), four in FP64
+    if (etype == 0) return launch_gf<T, 0, NE, sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+    return launch_gf<T, 1, NE, sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+}
+
+template size_t gradflux_lds<float>(int, const GradFluxArgs<float> &);
+template size_t gradflux_lds<double>(int, const GradFluxArgs<double> &);
+template hipError_t launch_gradflux<float>(int, const GradFluxArgs<float> &, hipStream_t);
+template hipError_t launch_gradflux<double>(int, const GradFluxArgs<double> &, hipStream_t);
+
+}  // namespace frd

@@ -26,7 +26,7 @@ FR_FP32, FR_FP64, FR_SPLIT_BF16, FR_SPLIT_FP16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FR_FP32, "fp64": FR_FP64, "split_bf16": FR_SPLIT_BF16,
               "split_fp16": FR_SPLIT_FP16}
 FR_RK4, FR_RK45_2RP, FR_FWD_EULER = 0, 1, 2
-FR_VALIDATE_ONLY, FR_CHECK_FINITE, FR_SEPARATE_UPDATE = 0x1, 0x2, 0x4
+FR_VALIDATE_ONLY, FR_CHECK_FINITE, FR_SEPARATE_UPDATE, FR_SEPARATE_GRADIENT = 0x1, 0x2, 0x4, 0x8
 FR_BC_WALL, FR_BC_FARFIELD = 1, 2
 FR_RED_INT_U, FR_RED_INT_R, FR_RED_NORM2_R, FR_RED_KE = 1, 2, 3, 4
 
@@ -48,7 +48,7 @@ PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "upts_tet", "upts_pri", "common_solution", "common_flux",
                 "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward",
                 "interp_hex", "grad_hex", "gradinterp_hex", "div_hex", "upts_hex", "negdivconf_hex",
-                "boundary_solution", "boundary_flux")
+                "boundary_solution", "boundary_flux", "gradflux_tet", "gradflux_pri")
 
 
 class FrError(RuntimeError):
@@ -75,6 +75,7 @@ class fr_mesh_desc(ctypes.Structure):
         ("t_wall", ctypes.c_double), ("farfield", ctypes.c_double * 5),
         ("tet_q", ctypes.POINTER(ctypes.c_double)), ("pri_q", ctypes.POINTER(ctypes.c_double)),
         ("hex_q", ctypes.POINTER(ctypes.c_double)),
+        ("p_ref", ctypes.c_double),
     ]
 
 
@@ -166,17 +167,22 @@ def _type_ptrs(ptrs):
 
 def make_desc(keep, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4, mu=0.0,
               prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False, check_finite=False,
-              t_wall=1.0, farfield=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4), separate_update=False):
+              t_wall=1.0, farfield=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4), separate_update=False,
+              separate_gradient=False, p_ref=0.0):
     """fr_mesh_desc for the generator's mesh arrays; the numpy arrays it points
     into are appended to ``keep`` (they must outlive the create call).
     separate_update: FR_SEPARATE_UPDATE (-R~/J and the RK update as a kernel
-    of their own instead of in the divergence product's store)."""
+    of their own instead of in the divergence product's store);
+    separate_gradient: FR_SEPARATE_GRADIENT (the gradient stage as three
+    kernels); p_ref: reference pressure left out of the momentum flux."""
     d = fr_mesh_desc()
     d.order = order
     d.system = {"euler": FR_EULER, "ns": FR_NAVIER_STOKES}[system]
     d.precision = PRECISIONS[precision]
     d.flags = ((FR_VALIDATE_ONLY if validate_only else 0) | (FR_CHECK_FINITE if check_finite else 0)
-               | (FR_SEPARATE_UPDATE if separate_update else 0))
+               | (FR_SEPARATE_UPDATE if separate_update else 0)
+               | (FR_SEPARATE_GRADIENT if separate_gradient else 0))
+    d.p_ref = float(p_ref)
     d.gamma, d.mu, d.prandtl, d.ldg_beta, d.ldg_tau = gamma, mu, prandtl, ldg_beta, ldg_tau
     xyz = np.ascontiguousarray(mesh_arrays["xyz"], dtype=np.float64)
     tv = np.ascontiguousarray(mesh_arrays["tet_v"], dtype=np.int64)
@@ -221,10 +227,11 @@ class Mesh:
     def __init__(self, mesh_arrays, order, system="euler", precision="fp32", gamma=1.4,
                  mu=0.0, prandtl=0.71, ldg_beta=0.5, ldg_tau=0.1, validate_only=False,
                  check_finite=False, stream=0, t_wall=1.0, farfield=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4),
-                 separate_update=False):
+                 separate_update=False, separate_gradient=False, p_ref=0.0):
         self._keep = []
         d = make_desc(self._keep, mesh_arrays, order, system, precision, gamma, mu, prandtl,
-                      ldg_beta, ldg_tau, validate_only, check_finite, t_wall, farfield, separate_update)
+                      ldg_beta, ldg_tau, validate_only, check_finite, t_wall, farfield, separate_update,
+                      separate_gradient, p_ref)
         h = ctypes.c_void_p()
         _check(lib().fr_mesh_create(ctypes.byref(d), ctypes.c_void_p(stream), ctypes.byref(h)))
         self.h = h

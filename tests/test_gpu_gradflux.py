@@ -1,0 +1,144 @@
+"""The gradient stage of the Navier-Stokes residual (corrected gradient
+product, solution-point work, gradient interpolation) runs for tets and
+prisms as one kernel per tile of elements with the reference and physical
+gradients in LDS.  With FR_SEPARATE_GRADIENT it runs as three kernels that
+pass those gradients through memory.  Both walk the same operator fragments
+in the same order and share the point-wise arithmetic, so every result is
+bitwise the same: the residual, the interface intermediates (state, gradient
+and common flux at the flux points) and RK45[2R+] steps, in FP32 and FP64,
+on straight, curved and wall-bounded meshes.
+
+The reference pressure p_ref left out of the momentum flux changes no
+residual beyond rounding (the discrete divergence of a uniform flux vanishes
+on these meshes): FP64 against the oracle to 1e-11 with and without it."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fr, mesh as om
+from paper_1409_0405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ("tet", "pri", "hex")
+P0 = 1.0 / (1.4 * 0.09)      # Taylor-Green reference pressure at Mach 0.3
+
+
+def _arrays(kind):
+    if kind == "hybrid":
+        return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2)
+    if kind == "curvedwall":
+        return inputs.curve(inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2,
+                                              y_bc="wall"), 0.03)
+    if kind == "wallbox":
+        return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2, y_bc="wall")
+    if kind == "big":
+        # 8 x 8 x (4 + 4): 512 prisms and 1,536 tets, many tiles of both types
+        return inputs.small_mixed_box(nxy=8, n_pri_layers=4, n_tet_layers=4, jitter=0.1, seed=2)
+    # 4 x 4 x (3 + 3): 96 prisms and 288 tets, ragged against the tiles
+    return inputs.small_mixed_box(nxy=4, n_pri_layers=3, n_tet_layers=3, jitter=0.1, seed=2)
+
+
+def _state(O, seed, mach=0.3):
+    U = fr.initial_state(O, inputs.taylor_green, mach=mach)
+    for n in U:
+        U[n] = U[n] * inputs.random_perturbation(U[n].shape, seed, 0.01)
+    return U
+
+
+def _run(M, O, U, dt):
+    """fr_rhs of U with its interface intermediates, then 3 RK45[2R+] steps
+    from U; every result as a device tensor."""
+    from paper_1409_0405_amd import frlib
+    ts = [NAMES.index(n) for n in O.types]
+    ptr = lambda d: [d[t].data_ptr() if t in d else 0 for t in range(3)]
+    u = {t: frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))) for t in ts}
+    r = {t: frlib.state_tensor(M, t) for t in ts}
+    M.profile(True)
+    M.rhs(ptr(u), ptr(r))
+    prof = M.profile_read()
+    M.profile(False)
+    inter = {}
+    for t in ts:
+        q = M.query(t)
+        for which, nv in ((0, 5), (1, 5), (2, 15)):
+            buf = torch.zeros((q["nfpts"], nv, q["ld"]), dtype=r[t].dtype, device="cuda")
+            M.intermediate(t, which, buf.data_ptr())
+            inter[(t, which)] = buf
+    for t in ts:
+        M.set_solution(t, u[t].data_ptr())
+    M.rk_step(frlib.FR_RK45_2RP, dt, 3)
+    s = {t: frlib.state_tensor(M, t) for t in ts}
+    for t in ts:
+        M.get_solution(t, s[t].data_ptr())
+    torch.cuda.synchronize()
+    return r, inter, s, prof
+
+
+CASES = [("mixed", 1, "fp32"), ("mixed", 2, "fp32"), ("mixed", 3, "fp32"), ("mixed", 4, "fp32"),
+         ("mixed", 2, "fp64"), ("mixed", 4, "fp64"), ("big", 4, "fp32"), ("hybrid", 3, "fp32"),
+         ("hybrid", 3, "fp64"), ("curvedwall", 3, "fp32"), ("wallbox", 2, "fp64")]
+
+
+@pytest.mark.parametrize("kind,p,prec", CASES, ids=[f"{k}-p{p}-{q}" for k, p, q in CASES])
+def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, prec):
+    from paper_1409_0405_amd import frlib
+    arrays = _arrays(kind)
+    O = om.build_mesh(arrays, p)
+    U = _state(O, 4)
+    kw = {"t_wall": P0} if kind in ("curvedwall", "wallbox") else {}
+    out = []
+    for separate in (False, True):
+        print(f"{kind} p{p} {prec} separate_gradient={separate}", flush=True)
+        M = frlib.Mesh(arrays, p, system="ns", precision=prec, mu=0.02, separate_gradient=separate, **kw)
+        out.append(_run(M, O, U, 2e-3))
+        M.close()
+    (r0, i0, s0, p0), (r1, i1, s1, p1) = out
+    ts = sorted(r0)
+    # the fused kernel ran for the tets and prisms present, and only there
+    for t, n in ((0, "gradflux_tet"), (1, "gradflux_pri")):
+        assert p0[n][1] == (1 if t in ts else 0) and p1[n][1] == 0, (n, p0[n], p1[n])
+        g = ("grad_tet", "grad_pri")[t]
+        assert p0[g][1] == 0 and p1[g][1] == (1 if t in ts else 0), (g, p0[g], p1[g])
+    for t in ts:
+        assert torch.equal(r0[t], r1[t]), ("rhs", NAMES[t])
+        for which in (0, 1, 2):
+            ne = O.types[NAMES[t]].nelem
+            assert torch.equal(i0[(t, which)][:, :, :ne], i1[(t, which)][:, :, :ne]), ("intermediate", which, NAMES[t])
+        assert torch.equal(s0[t], s1[t]), ("rk45 steps", NAMES[t])
+    assert max(float(r0[t].abs().max()) for t in ts) > 1e-3
+
+
+@pytest.mark.parametrize("kind,system", [("mixed", "ns"), ("hybrid", "ns"), ("mixed", "euler"),
+                                         ("wallbox", "ns")])
+def test_reference_pressure_keeps_the_residual_fp64(kind, system):
+    """p_ref = the Taylor-Green reference pressure: FP64 residual against the
+    oracle's plain residual to 1e-11 per field, as without it."""
+    from paper_1409_0405_amd import frlib
+    p = 3
+    arrays = _arrays(kind)
+    O = om.build_mesh(arrays, p)
+    kw = {"t_wall": P0} if kind == "wallbox" else {}
+    prm = fr.Params(system=system, mu=0.02, **kw)
+    U = _state(O, 6)
+    Ro = fr.rhs(O, U, prm)
+    ts = [NAMES.index(n) for n in O.types]
+    for pref in (0.0, P0):
+        M = frlib.Mesh(arrays, p, system=system, precision="fp64", mu=0.02, p_ref=pref, **kw)
+        u = {t: frlib.to_device_state(M, t, np.transpose(U[NAMES[t]], (1, 2, 0))) for t in ts}
+        r = {t: frlib.state_tensor(M, t) for t in ts}
+        M.rhs([u[t].data_ptr() if t in u else 0 for t in range(3)], [r[t].data_ptr() if t in r else 0 for t in range(3)])
+        torch.cuda.synchronize()
+        num = np.zeros(5)
+        den = np.zeros(5)
+        for t in ts:
+            n = NAMES[t]
+            g = np.transpose(r[t][:, :, :O.types[n].nelem].cpu().numpy(), (2, 0, 1))
+            num += ((g - Ro[n]) ** 2).sum(axis=(0, 1))
+            den += (Ro[n] ** 2).sum(axis=(0, 1))
+        err = np.sqrt(num / den)
+        print(f"  {kind} {system} p_ref={pref:.3f}: field errors {err}", flush=True)
+        assert (err < 1e-11).all(), (pref, err)
+        M.close()
