@@ -5,8 +5,17 @@ Sizes span several MFMA tiles and a ragged element tail (element counts not
 multiples of 64).  Tolerances (relative L2 per conserved field):
 * FP64 build of the kernels:  1e-11 (operators built by two independent
   routes agree to ~2e-13; the residual amplifies that by ~p^2/h);
-* FP32 build: stated per case, derived from the single-precision unit
-  roundoff times the cancellation factor of the case (see _fp32_tol).
+* FP32 build, with the case's pressure scale as the reference pressure left
+  out of the momentum flux (exact on these meshes; not on the curved mesh at
+  p = 2, whose metric terms are not interpolated exactly there):
+  - 1e-5 per field on the cases where single precision reaches it
+    (FP32_1E5);
+  - elsewhere the residual is a difference of flux terms 10^2 - 10^3 times
+    larger than itself, and single-precision rounding of those terms gives
+    1.0 - 1.5e-5 (measured); there the test asserts the bound derived from
+    the unit roundoff and that cancellation factor (see _fp32_tol) and 2e-5,
+    and the state after 20 RK45[2R+] steps against the oracle's stepper is
+    held to 1e-5 per field (test_fp32_state_after_rk45_steps).
 """
 import math
 
@@ -63,6 +72,27 @@ def _field_errors(Rg, Ro):
     num = sum(((Rg[n] - Ro[n]) ** 2).sum(axis=(0, 1)) for n in Ro)
     den = sum((Ro[n] ** 2).sum(axis=(0, 1)) for n in Ro)
     return np.sqrt(num / den)
+
+
+def _state_errors(G, Uo):
+    """Relative L2 error of a state: density, momentum (as a vector field:
+    |dm| / |m|, since the Taylor-Green w-momentum starts at exactly zero and
+    a per-component ratio of it is meaningless) and energy; the three
+    momentum components are also returned per component for the record."""
+    num = sum(((G[n] - Uo[n]) ** 2).sum(axis=(0, 1)) for n in Uo)
+    den = sum((Uo[n] ** 2).sum(axis=(0, 1)) for n in Uo)
+    vec = np.array([num[0] / den[0], num[1:4].sum() / den[1:4].sum(), num[4] / den[4]])
+    return np.sqrt(vec), np.sqrt(num[1:4] / den[1:4])
+
+
+def _pref(case):
+    """Reference pressure of a case: the pressure scale of its initial state
+    (free-stream pressure of the vortex, p0 = 1 / (gamma Ma^2) of the
+    Taylor-Green state); none on the curved mesh below p = 3."""
+    kind, p, system, ic, kw, mu = case
+    if kind.startswith("curved") and p < 3:
+        return 0.0
+    return 1.0 if ic is inputs.isentropic_vortex else 1.0 / (1.4 * kw["mach"] ** 2)
 
 
 def _fp32_tol(O, U, prm):
@@ -168,21 +198,81 @@ def test_rhs_fp64_parity(case):
     assert (err < 1e-11).all(), err
 
 
-@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
-def test_rhs_fp32_parity(case):
+# cases whose FP32 residual is within 1e-5 of the oracle's in every field
+# (measured 5.1e-6 .. 8.3e-6)
+FP32_1E5 = ("prisms-p1-euler", "hex-p2-euler", "hex-p4-ns", "farbox-p2-ns")
+FP32_CASES = [c for c in CASES if _ids(c) in FP32_1E5]
+FP32_KAPPA = [c for c in CASES if _ids(c) not in FP32_1E5]
+
+
+def _fp32_case_errors(case):
     kind, p, system, ic, kw, mu = case
-    print(f"case {_ids(case)} fp32", flush=True)
     arrays = _mesh(kind)
     O = om.build_mesh(arrays, p)
     prm = fr.Params(system=system, mu=mu, **BC.get(kind, {}))
     U = _round32(_state(O, ic, 3, **kw))
     Ro = fr.rhs(O, U, prm)
-    M = _lib().Mesh(arrays, p, system=system, precision="fp32", mu=mu, **BC.get(kind, {}))
-    Rg = _gpu_rhs(M, O, U)
-    err = _field_errors(Rg, Ro)
-    tol = _fp32_tol(O, U, prm)
-    print("  field errors", err, "tol", tol, flush=True)
-    assert (err < tol).all(), (err, tol)
+    M = _lib().Mesh(arrays, p, system=system, precision="fp32", mu=mu, p_ref=_pref(case), **BC.get(kind, {}))
+    err = _field_errors(_gpu_rhs(M, O, U), Ro)
+    M.close()
+    return err, _fp32_tol(O, U, prm)
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[_ids(c) for c in FP32_CASES])
+def test_rhs_fp32_parity(case):
+    print(f"case {_ids(case)} fp32", flush=True)
+    err, _ = _fp32_case_errors(case)
+    print("  field errors", err, flush=True)
+    assert (err < 1e-5).all(), err
+
+
+@pytest.mark.parametrize("case", FP32_KAPPA, ids=[_ids(c) for c in FP32_KAPPA])
+def test_rhs_fp32_parity_cancellation_limited(case):
+    """The FP32 residual where the cancellation of its flux terms keeps it
+    above 1e-5: within the single-precision bound of the case and 2e-5
+    (5e-5 on the curved mesh at p = 2, which runs without the reference
+    pressure: measured 2.9e-5)."""
+    print(f"case {_ids(case)} fp32 (cancellation-limited)", flush=True)
+    err, tol = _fp32_case_errors(case)
+    cap = 2e-5 if _pref(case) > 0 else 5e-5
+    print("  field errors", err, "kappa bound", tol, flush=True)
+    assert (err < tol).all() and (err < cap).all(), (err, tol)
+
+
+@pytest.mark.parametrize("kind,p,system,mach,noise,mu", [
+    ("mixed", 4, "ns", 0.3, 0.01, 0.02), ("mixed", 4, "euler", 0.1, 0.01, 0.0), ("hybrid", 3, "ns", 0.3, 0.01, 0.02),
+    ("mixed", 4, "ns", 0.1, 0.0, 1.0 / 1600)])
+def test_fp32_state_after_rk45_steps(kind, p, system, mach, noise, mu):
+    """What the solver delivers where the FP32 residual is cancellation-
+    limited: 20 RK45[2R+] steps (CFL 0.3) of the FP32 library against the
+    oracle's stepper on the same box, density, momentum and energy within
+    1e-5.  The last case is the headline state itself (Taylor-Green at Mach
+    0.1, Re 1600, no noise, p = 4)."""
+    frlib = _lib()
+    print(f"fp32 rk45 state {kind} p{p} {system} Ma {mach} noise {noise}", flush=True)
+    arrays = _mesh(kind, seed=1)
+    O = om.build_mesh(arrays, p)
+    prm = fr.Params(system=system, mu=mu)
+    U0 = _round32(_state(O, inputs.taylor_green, 5, noise=noise, mach=mach))
+    nsteps = 20
+    dt = 0.3 * (2 * math.pi / 6) / ((1 + 1 / mach) * (2 * p + 1))
+    Uo = rk.run(rk.rk45_step, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
+    M = frlib.Mesh(arrays, p, system=system, precision="fp32", mu=mu, p_ref=1.0 / (1.4 * mach ** 2),
+                   check_finite=True)
+    for n in O.types:
+        t = NAMES.index(n)
+        M.set_solution(t, frlib.to_device_state(M, t, np.transpose(U0[n], (1, 2, 0))).data_ptr())
+    M.rk_step(frlib.FR_RK45_2RP, dt, nsteps)
+    G = {}
+    for n in O.types:
+        t = NAMES.index(n)
+        out = frlib.state_tensor(M, t)
+        M.get_solution(t, out.data_ptr())
+        torch.cuda.synchronize()
+        G[n] = np.transpose(out[:, :, :O.types[n].nelem].cpu().numpy().astype(np.float64), (2, 0, 1))
+    err, comp = _state_errors(G, Uo)
+    print(f"  state errors (rho, momentum, E) {err}; momentum components {comp}", flush=True)
+    assert (err < 1e-5).all(), err
 
 
 @pytest.mark.parametrize("kind,p,system", [("mixed", 2, "ns"), ("mixed", 4, "ns"), ("mixed", 3, "euler"),
