@@ -87,7 +87,8 @@ typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
  * product, the solution-point work (physical gradient, transformed flux) and
  * the gradient interpolation as three kernels that pass the reference and
  * physical gradients through memory.  By default one kernel does all three
- * per tile of elements with those gradients in LDS; both give the same bits. */
+ * per tile of elements with those gradients in LDS (fr_autotune keeps
+ * whichever form is fastest per element type); all give the same bits. */
 #define FR_SEPARATE_GRADIENT 0x8u
 
 typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
@@ -316,8 +317,12 @@ fr_status fr_autotune(fr_mesh mesh, void *stream);
  * blocks per wavefront), 6 = the same with 4 instead of 2 K steps of loads
  * in flight.  The split forms have stage 0 (each wavefront splits
  * its B panel) and 1 (the panel's row groups, at most 8 and 64 KiB of parts,
- * share the split B in LDS).  Results are bitwise the same for every variant
- * (for finite states).  Synchronous
+ * share the split B in LDS).  op 4 selects the form of the Navier-Stokes
+ * gradient stage of tets and prisms (cap ignored): stage 0 the three
+ * separate kernels, 1 one fused kernel per tile of elements, 2 (FP32) the
+ * fused kernel streaming runs of tiles with the next tile's input loaded
+ * into LDS during the current one.  Results are bitwise the same for every
+ * variant (for finite states).  Synchronous
  * (uploads the operator); FR_ERR_UNSUPPORTED for a combination the form
  * does not have. */
 fr_status fr_set_blocking(fr_mesh mesh, int32_t etype, int32_t op, int32_t cap, int32_t stage);

@@ -46,7 +46,9 @@ struct DevType {
     int64_t nelem = 0, ld = 0;
     frd::Op<T> Aint, Agint, Agrad, Adiv;          // Agint: M0 for the gradients
     frd::Op<T> Fgrad, Fgint;                      // fused gradient stage (step lists, one row block per group)
-    bool fuse_grad = true;                        // use it (the autotuner times both forms)
+    // gradient stage form: 0 three kernels, 1 fused per tile, 2 fused and
+    // streaming (FP32); the autotuner keeps the fastest
+    int grad_form = 1;
     frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
     T *jinv = nullptr;        // [nu][ld] 1 / J at the solution points (host FP64, rounded)
@@ -743,7 +745,8 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
     // gradient interpolation in one kernel (FR_SEPARATE_GRADIENT: three)
     bool fused[frh::NTYPE] = {false, false, false};
     for (int t = 0; t < frh::NTYPE; ++t)
-        fused[t] = ns && d.t[t].nelem && d.t[t].Fgrad.frag && d.t[t].fuse_grad && !(m->flags & FR_SEPARATE_GRADIENT);
+        fused[t] = ns && d.t[t].nelem && d.t[t].Fgrad.frag && d.t[t].grad_form > 0 &&
+                   !(m->flags & FR_SEPARATE_GRADIENT);
     if (ns) {
         FR_LAUNCH(m, 10, s, frd::launch_common_solution<T>(pa, s));
         if (d.nb) FR_LAUNCH(m, 22, s, frd::launch_boundary_solution<T>(ba, s));
@@ -752,7 +755,7 @@ fr_status rhs_pipeline(fr_mesh m, const T *const U[frh::NTYPE], const StageOut<T
             if (!D.nelem) continue;
             if (fused[t]) {
                 const frd::GradFluxArgs<T> ga = gradflux_args<T>(m, D, U[t]);
-                FR_LAUNCH(m, prof_gradflux(t), s, frd::launch_gradflux<T>(t, ga, s));
+                FR_LAUNCH(m, prof_gradflux(t), s, frd::launch_gradflux<T>(t, ga, s, D.grad_form == 2));
                 continue;
             }
             const int64_t w5 = 5 * D.ld;
@@ -1210,8 +1213,8 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
         // against the three separate kernels with the variants just chosen
         if (ns && D.Fgrad.frag && !(m->flags & FR_SEPARATE_GRADIENT)) {
             const T *U = D.reg[0];
-            auto fused = [&]() -> hipError_t { return frd::launch_gradflux<T>(t, gradflux_args<T>(m, D, U), s); };
-            auto separate = [&]() -> hipError_t {
+            auto run = [&](int form) -> hipError_t {
+                if (form > 0) return frd::launch_gradflux<T>(t, gradflux_args<T>(m, D, U), s, form == 2);
                 hipError_t e = opmul<T>(m, 4 * t + frd::OP_GRAD, D.Agrad, D.Sgrad, U, w5, nu, D.Cf, w5, nf, D.Qt,
                                         w5, w5, s);
                 if (e == hipSuccess) e = frd::launch_upts<T>(t, true, upts_args<T>(m, D, U), s);
@@ -1220,19 +1223,25 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                                  D.Qf, w15, w15, s);
                 return e;
             };
-            float ms[2] = {0, 0};
-            for (int form = 0; form < 2; ++form) {
-                FR_HIP(m, form ? separate() : fused());
+            const int nform = sizeof(T) == 4 ? 3 : 2;
+            float ms[3] = {0, 0, 0};
+            for (int form = 0; form < nform; ++form) {
+                FR_HIP(m, run(form));
                 FR_HIP(m, hipEventRecord(e0, s));
-                for (int r = 0; r < 3; ++r) FR_HIP(m, form ? separate() : fused());
+                for (int r = 0; r < 3; ++r) FR_HIP(m, run(form));
                 FR_HIP(m, hipEventRecord(e1, s));
                 FR_HIP(m, hipEventSynchronize(e1));
                 FR_HIP(m, hipEventElapsedTime(&ms[form], e0, e1));
             }
-            D.fuse_grad = ms[0] <= ms[1];
+            int best = 0;
+            for (int form = 1; form < nform; ++form)
+                if (ms[form] < ms[best]) best = form;
+            D.grad_form = best;
             static const char *const sn[frh::NTYPE] = {"tet", "pri", "hex"};
-            report += sn[t] + std::string(" gradient stage fused ") + std::to_string(ms[0] / 3 * 1e3) +
-                      " us, separate " + std::to_string(ms[1] / 3 * 1e3) + " us; ";
+            report += sn[t] + std::string(" gradient stage: separate ") + std::to_string(ms[0] / 3 * 1e3) +
+                      " us, fused " + std::to_string(ms[1] / 3 * 1e3) + " us" +
+                      (nform > 2 ? ", streaming " + std::to_string(ms[2] / 3 * 1e3) + " us" : std::string()) +
+                      ", form " + std::to_string(best) + "; ";
         }
     }
     (void)hipEventDestroy(e0);
@@ -1602,8 +1611,23 @@ extern "C" {
 
 fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int32_t stage) {
     if (fr_status st = check_mesh(m, etype, true)) return st;
+    if (op == 4) {
+        // the gradient stage's form (stage 0 separate, 1 fused, 2 streaming)
+        if (stage < 0 || stage > 2) return fail(m, FR_ERR_INVALID_ARG, "gradient stage form 0..2");
+        if (!m->host.t[etype].nelem) return FR_OK;
+        const bool have = m->precision == FR_FP64 ? dev_of<double>(m).t[etype].Fgrad.frag != nullptr
+                                                  : dev_of<float>(m).t[etype].Fgrad.frag != nullptr;
+        if (stage > 0 && !have) return fail(m, FR_ERR_UNSUPPORTED, "no fused gradient stage for this type or form");
+        if (stage == 2 && m->precision != FR_FP32)
+            return fail(m, FR_ERR_UNSUPPORTED, "the streaming gradient stage is FP32 only");
+        if (m->precision == FR_FP64)
+            dev_of<double>(m).t[etype].grad_form = stage;
+        else
+            dev_of<float>(m).t[etype].grad_form = stage;
+        return FR_OK;
+    }
     if (op < 0 || op > 3 || cap < 1 || stage < 0 || stage > 6)
-        return fail(m, FR_ERR_INVALID_ARG, "operator 0..3, cap >= 1, stage 0..6");
+        return fail(m, FR_ERR_INVALID_ARG, "operator 0..4, cap >= 1, stage 0..6");
     if (!m->host.t[etype].nelem) return FR_OK;
     return m->precision != FR_FP64 ? set_blocking_impl<float>(m, etype, op, cap, stage)
                                    : set_blocking_impl<double>(m, etype, op, cap, stage);

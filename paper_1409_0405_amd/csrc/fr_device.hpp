@@ -127,8 +127,10 @@ struct GradFluxArgs {
 // LDS bytes of one workgroup of the fused kernel (0: shape not supported).
 template <typename T>
 size_t gradflux_lds(int etype, const GradFluxArgs<T> &a);
+// stream: the streaming form (FP32 only), a workgroup per run of tiles with
+// the next tile's input loaded straight into LDS while one is computed.
 template <typename T>
-hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s);
+hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, bool stream = false);
 
 // Interface work on the paired flux points.
 template <typename T>

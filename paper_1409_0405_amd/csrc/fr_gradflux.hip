@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fr_device.hpp"
 #include "fr_opmul.hpp"
@@ -243,6 +244,141 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
 
 constexpr size_t GRADFLUX_LDS_MAX = 160 * 1024;
 
+// Streaming form (FP32): a workgroup takes a contiguous run of tiles and,
+// while it works on one, the next tile's B = [U; Cf] and Jacobian
+// coefficients travel straight from memory into a second LDS buffer
+// (global_load_lds: no registers, no wait until the tile starts), so the
+// matrix cores do not sit idle on the loads.  LDS: Qt / Q [3 nu][80], B
+// [Kp][80], two geometry buffers, reference coordinates.  Same arithmetic,
+// same bits as gradflux_kernel.
+template <int ET, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ET == 0 ? 4 : 2))) void gradflux_stream_kernel(GradFluxArgs<float> a, int tiles_per_wg) {
+    using v4 = floatx4;
+    constexpr int NE = 16, W5 = 80, NB = 5;
+    constexpr int NG = n_geom_coeffs<ET>();
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int Kp = 4 * a.G.Kb;
+    const int nu = a.nu, nf = a.nf;
+    float *QT = reinterpret_cast<float *>(lds_raw);      // [3 nu][W5]
+    float *Bs = QT + size_t(3 * nu) * W5;                // [Kp][W5]
+    float *Gs = Bs + size_t(Kp) * W5;                    // [2][NG][NE]
+    float *Xs = Gs + 2 * NG * NE;                        // [nu][3]
+
+    const int64_t ntiles = (a.nelem + NE - 1) / NE;
+    const int64_t t_begin = int64_t(xcd_block()) * tiles_per_wg;
+    const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
+    if (t_begin >= t_end) return;                        // whole workgroup
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int krow = lane >> 4, c16 = lane & 15;
+    const int64_t ld = a.ld;
+
+    // rows of B past K stay zero (the direct loads skip them)
+    for (int idx = tid; idx < (Kp - nu - nf) * W5; idx += 64 * NW) Bs[(nu + nf) * W5 + idx] = 0.0f;
+    for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
+
+    // B and the coefficients of tile `tile` into LDS: chunk c (16 bytes) of
+    // B is row k, field v, elements 4 q .. 4 q + 3 with c = 4 (5 k + v) + q;
+    // lane l of a wavefront instruction writes chunk base + l
+    auto issue = [&](int64_t tile, float *gdst) {
+        const int64_t e0 = tile * NE;
+        const int nchunk = (nu + nf) * 5 * 4;
+        for (int base = w * 64; base < nchunk; base += NW * 64) {
+            const int c = base + lane, q = c & 3, kv = c >> 2, v = kv % 5, k = kv / 5;
+            if (c < nchunk) {
+                const float *src = k < nu ? a.U + (int64_t(k) * 5 + v) * ld + e0 + 4 * q
+                                          : a.Cf + (int64_t(k - nu) * 5 + v) * ld + e0 + 4 * q;
+                __builtin_amdgcn_global_load_lds(src, Bs + size_t(base) * 4, 16, 0, 0);
+            }
+        }
+        if (!a.padj && w == NW - 1) {
+            // NG rows of 16 coefficients: 4 NG chunks, one instruction
+            const int c = lane, g = c >> 2, q = c & 3;
+            if (c < 4 * NG) __builtin_amdgcn_global_load_lds(a.geom + int64_t(g) * ld + e0 + 4 * q, gdst, 16, 0, 0);
+        }
+    };
+    issue(t_begin, Gs);
+    int buf = 0;
+    for (int64_t tile = t_begin; tile < t_end; ++tile, buf ^= 1) {
+        const int64_t e0 = tile * NE;
+        float *G = Gs + buf * NG * NE;
+        __builtin_amdgcn_s_waitcnt(0);                   // this wavefront's direct loads (and stores) are done
+        __syncthreads();                                 // everyone's: B and G of this tile are in LDS
+
+        // 1. Qt = [G_k | L_k] B -> LDS
+        for (int g = w; g < a.G.nmg; g += NW) {
+            v4 acc[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[n] = v4{0, 0, 0, 0};
+            step_products<float, NB>(a.G, g, lane, [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; }, acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = a.G.rowmap[16 * g + acc_row<float>(krow, r)];
+                if (row >= 0) {
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) QT[row * W5 + 16 * n + c16] = acc[n][r];
+                }
+            }
+        }
+        __syncthreads();                                 // B is free, Qt complete
+        if (tile + 1 < t_end) issue(tile + 1, Gs + (buf ^ 1) * NG * NE);
+
+        // 2. point-wise: Q replaces Qt in place, Ft to memory
+        for (int it = tid; it < nu * NE; it += 64 * NW) {
+            const int i = it / NE, e = it - i * NE;
+            const int64_t eg = e0 + e;
+            if (eg >= a.nelem) continue;
+            float adj[3][3], Jinv;
+            if (a.padj) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * nu + i) * ld + eg];
+                Jinv = a.pjinv[int64_t(i) * ld + eg];
+            } else {
+                Jinv = 1.0f / metric<float, ET>(G, NE, e, Xs + 3 * i, adj);
+            }
+            float u[5], qt[3][5], q[3][5], Ft[3][5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[v] = a.U[(int64_t(i) * 5 + v) * ld + eg];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qt[k][v] = QT[(k * nu + i) * W5 + v * NE + e];
+            upts_point<float, true>(u, qt, adj, Jinv, a.gamma, a.mu, a.prandtl, a.pref, q, Ft);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) QT[(j * nu + i) * W5 + v * NE + e] = q[j][v];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) a.Ft[((int64_t(k) * nu + i) * 5 + v) * ld + eg] = Ft[k][v];
+        }
+        __syncthreads();
+
+        // 3. Qf = M0 Q
+        for (int it = w; it < a.M.nmg * 3; it += NW) {
+            const int g = it / 3, j = it - 3 * g;
+            const float *Qj = QT + size_t(j) * nu * W5 + c16;
+            v4 acc2[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc2[n] = v4{0, 0, 0, 0};
+            step_products<float, NB>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; },
+                                     acc2);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = a.M.rowmap[16 * g + acc_row<float>(krow, r)];
+                if (f < 0 || e0 + c16 >= a.nelem) continue;
+#pragma unroll
+                for (int n = 0; n < NB; ++n) a.Qf[(int64_t(f) * 15 + j * 5 + n) * ld + e0 + c16] = acc2[n][r];
+            }
+        }
+        // the next iteration's barrier keeps Qt of the next tile from
+        // overwriting Q while it is read here
+    }
+}
+
+
 template <typename T, int ET, int NE, int NW, int MG>
 hipError_t launch_gf_mg(const GradFluxArgs<T> &a, size_t lds, hipStream_t s) {
     static bool attr_set = false;
@@ -266,6 +402,34 @@ hipError_t launch_gf(const GradFluxArgs<T> &a, size_t lds, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+size_t gradflux_stream_lds_bytes(int etype, const GradFluxArgs<float> &a) {
+    const int ng = etype == 0 ? 9 : 15;
+    return (size_t(3 * a.nu) * 80 + size_t(4 * a.G.Kb) * 80 + 2 * size_t(ng) * 16 + size_t(3 * a.nu)) * 4;
+}
+
+template <int ET, int NW>
+hipError_t launch_gf_stream(const GradFluxArgs<float> &a, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    static int ncu = 0;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(gradflux_stream_kernel<ET, NW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(GRADFLUX_LDS_MAX));
+        if (e != hipSuccess) return e;
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        attr_set = true;
+    }
+    // as many workgroups as fit at once (LDS-bound), each a contiguous run of tiles
+    const int per_cu = std::max(1, int(GRADFLUX_LDS_MAX / lds));
+    const int64_t ntiles = (a.nelem + 15) / 16;
+    int64_t nwg = std::min<int64_t>(ntiles, int64_t(ncu) * per_cu);
+    const int tiles_per_wg = int((ntiles + nwg - 1) / nwg);
+    nwg = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
+    gradflux_stream_kernel<ET, NW><<<xcd_grid(nwg), 64 * NW, lds, s>>>(a, tiles_per_wg);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename T>
@@ -280,8 +444,16 @@ size_t gradflux_lds(int etype, const GradFluxArgs<T> &a) {
 }
 
 template <typename T>
-hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s) {
-    const size_t lds = gradflux_lds<T>(etype, a);
+hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, bool stream) {
+    size_t lds = gradflux_lds<T>(etype, a);
+    if constexpr (std::is_same<T, float>::value) {
+        if (stream) {
+            lds = gradflux_stream_lds_bytes(etype, a);
+            if (lds > GRADFLUX_LDS_MAX) return hipErrorInvalidValue;
+        }
+    } else {
+        if (stream) return hipErrorInvalidValue;
+    }
     // operator layout: step lists (4 steps in flight), one row block per group
     if (!lds || a.G.stage != 6 || a.M.stage != 6 || a.G.mbw != 1 || a.M.mbw != 1 || !a.G.klist ||
         !a.G.koff || !a.G.rowmap || !a.M.klist || !a.M.koff || !a.M.rowmap || a.G.M != 3 * a.nu ||
@@ -289,6 +461,9 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s) {
         (reinterpret_cast<uintptr_t>(a.U) | reinterpret_cast<uintptr_t>(a.Cf)) % 16)
         return hipErrorInvalidValue;
     if (!a.nelem) return hipSuccess;
+    if constexpr (std::is_same<T, float>::value) {
+        if (stream) return etype == 0 ? launch_gf_stream<0, 8>(a, lds, s) : launch_gf_stream<1, 8>(a, lds, s);
+    }
     constexpr int NE = tile_elems<T>();
     // eight wavefronts per workgroup (FP32), four in FP64
     if (etype == 0) return launch_gf<T, 0, NE, sizeof(T) == 4 ? 8 : 4>(a, lds, s);
@@ -297,7 +472,7 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s) {
 
 template size_t gradflux_lds<float>(int, const GradFluxArgs<float> &);
 template size_t gradflux_lds<double>(int, const GradFluxArgs<double> &);
-template hipError_t launch_gradflux<float>(int, const GradFluxArgs<float> &, hipStream_t);
-template hipError_t launch_gradflux<double>(int, const GradFluxArgs<double> &, hipStream_t);
+template hipError_t launch_gradflux<float>(int, const GradFluxArgs<float> &, hipStream_t, bool);
+template hipError_t launch_gradflux<double>(int, const GradFluxArgs<double> &, hipStream_t, bool);
 
 }  // namespace frd

@@ -334,6 +334,11 @@ class Mesh:
     def set_blocking(self, etype, op, cap, stage=0):
         _check(lib().fr_set_blocking(self.h, int(etype), int(op), int(cap), int(stage)), self.h)
 
+    def set_gradient_form(self, etype, form):
+        """Navier-Stokes gradient stage of a tet / prism type: 0 separate
+        kernels, 1 fused per tile, 2 fused and streaming (FP32)."""
+        _check(lib().fr_set_blocking(self.h, int(etype), 4, 1, int(form)), self.h)
+
     def closure_targets(self, a_ptrs, b_ptrs, stats_ptr, out_ptr, stream=0):
         A = _type_ptrs(a_ptrs)
         B = _type_ptrs(b_ptrs)

@@ -111,6 +111,37 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
     assert max(float(r0[t].abs().max()) for t in ts) > 1e-3
 
 
+@pytest.mark.parametrize("kind,p", [("mixed", 4), ("big", 4), ("mixed", 2), ("curvedwall", 3), ("hybrid", 1)])
+def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
+    """FP32: the autotuner's three forms of the gradient stage (separate
+    kernels, fused per tile, fused and streaming) give the same residual and
+    flux-point gradient, whichever it picks; forced through fr_set_blocking's
+    gradient-stage switch."""
+    from paper_1409_0405_amd import frlib
+    arrays = _arrays(kind)
+    O = om.build_mesh(arrays, p)
+    U = _state(O, 9)
+    kw = {"t_wall": P0} if kind == "curvedwall" else {}
+    ts = [NAMES.index(n) for n in O.types]
+    outs = []
+    for form in (0, 1, 2):
+        M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.02, **kw)
+        for t in ts:
+            if t < 2:
+                M.set_gradient_form(t, form)
+        r, inter, s, prof = _run(M, O, U, 2e-3)
+        M.close()
+        n_fused = sum(prof[k][1] for k in ("gradflux_tet", "gradflux_pri"))
+        assert (n_fused > 0) == (form > 0), (form, prof)
+        outs.append((r, inter, s))
+    for form in (1, 2):
+        for t in ts:
+            assert torch.equal(outs[0][0][t], outs[form][0][t]), ("rhs", form, NAMES[t])
+            ne = O.types[NAMES[t]].nelem
+            assert torch.equal(outs[0][1][(t, 2)][:, :, :ne], outs[form][1][(t, 2)][:, :, :ne]), ("Qf", form)
+            assert torch.equal(outs[0][2][t], outs[form][2][t]), ("rk45", form, NAMES[t])
+
+
 @pytest.mark.parametrize("kind,system", [("mixed", "ns"), ("hybrid", "ns"), ("mixed", "euler"),
                                          ("wallbox", "ns")])
 def test_reference_pressure_keeps_the_residual_fp64(kind, system):
