@@ -39,12 +39,19 @@ RIDGE = PEAK_FP32_MFMA / PEAK_HBM
 # HBM bytes per launch measured with rocprofv3 --pmc on this workload
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors read off the state
 # copies of known size), keyed (kernel class, 16-row blocks per wavefront,
-# stage) for the products and (class, 0, 0) for the point-wise kernels;
-# profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md.  A variant not listed here
-# reports traffic null.
+# stage) for the products and (class, 0, 0) for the point-wise kernels and the
+# fused gradient stage; the file below holds the commands and counts.  A
+# variant not listed reports traffic null.
+TRAFFIC_SOURCE = "profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md"
 MEASURED_TRAFFIC = {
-    ('common_flux', 0, 0): 1966.1e6,
-    ('common_solution', 0, 0): 795.8e6,
+    ('gradflux_tet', 0, 0): 1634.8e6,
+    ('gradflux_pri', 0, 0): 1852.5e6,
+    ('interp_tet', 2, 1): 373.8e6,
+    ('interp_pri', 2, 1): 398.8e6,
+    ('div_tet', 1, 3): 995.2e6,
+    ('div_pri', 1, 6): 1262.8e6,
+    ('common_flux', 0, 0): 1966.5e6,
+    ('common_solution', 0, 0): 795.9e6,
     ('div_pri', 5, 0): 1067.5e6,
     ('div_tet', 3, 0): 926.3e6,
     ('grad_pri', 1, 0): 897.2e6,
@@ -125,6 +132,7 @@ MEASURED_TRAFFIC = {
 
 
 PRODUCT_OPS = {"interp": 0, "grad": 1, "gradinterp": 2, "div": 3}
+ACC_STEPS = 100            # RK45[2R+] steps of the precision forms' accuracy table
 TYPE_SHORT = ("tet", "pri", "hex")
 
 
@@ -199,6 +207,13 @@ def kernel_model(mesh, system):
             out[f"{op}_{name}"] = {"flops": 2.0 * M * K * n, "nnz_flops": 2.0 * nnz[op] * n,
                                    "bytes": s * (K + M) * n}
         ng = (9, 15, 21)[t]
+        if ns and t < 2:
+            # fused gradient stage: reads U and the jump Cf, writes Ft and Qf
+            g, gi = ops["grad"], ops["gradinterp"]
+            out[f"gradflux_{name}"] = {
+                "flops": 2.0 * (g[0] * g[1] * g[2] + gi[0] * gi[1] * gi[2]),
+                "nnz_flops": 2.0 * (nnz["grad"] * g[2] + nnz["gradinterp"] * gi[2]),
+                "bytes": float(s * (5 * nu + 5 * nf + 15 * nu + 15 * nf) * E + s * ng * E)}
         pt = (5 + (15 + 15 if ns else 0) + 15) * nu * E * s + ng * E * s
         out[f"upts_{name}"] = {"flops": 0.0, "bytes": float(pt)}
         neg = (5 + 5 + 5) * nu * E * s + ng * E * s
@@ -231,33 +246,75 @@ def boundary_points(arrays, p):
     return n
 
 
-def cpu_baseline(target_seconds):
-    """The FP64 oracle on a bounded sample of the same workload (same mesh
-    structure, order and physics, fewer elements)."""
-    import numpy as np
+def _oracle_sample():
+    """The bounded sample of the headline workload the oracle evaluates: the
+    same mesh structure, order, physics and state on fewer elements."""
     from oracle import fr, mesh as om
     from paper_1409_0405_amd import inputs
     arrays = inputs.tgv_mixed_box(nxy=6, n_pri_layers=10, n_tet_layers=6, jitter=0.10, seed=0)
     O = om.build_mesh(arrays, 4)
     U = fr.initial_state(O, inputs.taylor_green, mach=0.1)
     prm = fr.Params(system="ns", mu=1.0 / 1600.0, prandtl=0.71)
-    dof = sum(tg.nelem * tg.ref.nupts * 5 for tg in O.types.values())
+    return O, U, prm
+
+
+def _oracle_worker(args):
+    """One host core: oracle right-hand sides on the sample for about
+    `seconds` (NumPy thread pools limited to one thread); returns (count,
+    seconds, DOF per RHS)."""
+    seconds, start_at = args
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):      # one core: BLAS / OpenMP pools pinned to one thread
-        fr.rhs(O, U, prm)       # first call outside the timing
+    from oracle import fr
+    O, U, prm = _oracle_sample()
+    dof = sum(tg.nelem * tg.ref.nupts * 5 for tg in O.types.values())
+    with threadpool_limits(limits=1):
+        fr.rhs(O, U, prm)                                # first call outside the timing
+        while time.time() < start_at:                    # every worker starts together
+            time.sleep(0.01)
         n, t0 = 0, time.perf_counter()
         while True:
             fr.rhs(O, U, prm)
             n += 1
             el = time.perf_counter() - t0
-            if el > target_seconds:
+            if el > seconds:
                 break
-    nt = O.types["tet"].nelem
-    npri = O.types["pri"].nelem
-    return {"value": dof * n / el / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} NS p=4 RHS evaluations of the FP64 NumPy oracle on a "
-                      f"{npri}-prism / {nt}-tet periodic TGV box of the same structure "
-                      f"({dof} DOF, {el:.1f} s; NumPy with its thread pools limited to one thread)"}
+    return n, el, dof
+
+
+def host_cores():
+    """Host cores this process may use: the affinity set, capped by the
+    thread count the environment grants (OMP_NUM_THREADS) when it is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(n, int(env))) if env and env.isdigit() else n
+
+
+def cpu_baseline(target_seconds):
+    """The FP64 oracle on a bounded sample of the same workload (same mesh
+    structure, order and physics, fewer elements): on one core, and on every
+    host core at once, one worker process per core evaluating the sample's
+    right-hand side, which splits the work over the cores by elements as the
+    paper's OpenMP backend splits the columns of B (the sample's periodic
+    RHS is not cut into slices: each core evaluates a whole sample, and the
+    throughput is the sum).  nproc and the BLAS thread count are reported."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_info
+    n1, el1, dof = _oracle_worker((target_seconds, 0.0))
+    cores = host_cores()
+    ctx = mp.get_context("spawn")                       # the parent holds a GPU context: no fork
+    start_at = time.time() + 5.0 + 0.02 * cores
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(target_seconds, start_at)] * cores)
+    rate_all = sum(n * d / el for n, el, d in res)
+    blas = [{"api": x.get("internal_api"), "threads": x.get("num_threads")} for x in threadpool_info()]
+    from oracle import mesh as om  # noqa: F401  (the workers imported it too)
+    return {"value": rate_all / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "one_core": {"value": dof * n1 / el1 / 1e9, "unit": "GDOF/s", "cores": 1},
+            "nproc": os.cpu_count(), "blas_threads_per_worker": 1, "blas_pools_parent": blas,
+            "sample": f"NS p=4 RHS evaluations of the FP64 NumPy oracle on a 720-prism / 1,296-tet periodic TGV "
+                      f"box of the headline's structure ({dof} DOF), about {target_seconds:.0f} s per worker: "
+                      f"{n1} on one core; {sum(r[0] for r in res)} over {cores} worker processes at once "
+                      f"(NumPy pools limited to one thread each)"}
 
 
 def measured_peaks():
@@ -475,7 +532,16 @@ def structural(model, avg_s, k):
     return {x: r[x] for x in ("bound", "achieved", "unit", "frac")}
 
 
+def walks_nonzeros(k, variant):
+    """Whether kernel class k walks only its operators' structural nonzeros
+    (step-list products, stages 5 and 6, and the fused gradient stage): such
+    a kernel is priced on its structural work, since the paper's dense count
+    would credit it with work it skips (a fraction above 1 of the roof)."""
+    return k.startswith("gradflux_") or bool(variant and variant[1] in (5, 6))
+
+
 def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=0.3, p=4, **mesh_kw):
+    mesh_kw.setdefault("p_ref", 1.0 / (1.4 * mach * mach))
     """Another mesh of the same physics (NS Taylor-Green, p = 4, FP32,
     autotuned): RK45[2R+] steps timed like the main workload, then a
     per-kernel profile and the dominant kernel's roofline.  mesh_kw: boundary
@@ -537,12 +603,16 @@ def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=
         avg = ms / cnt * 1e-3
         kern[k] = {"share": ms / tot, "avg_us": avg * 1e6}
         if k in model:
-            kern[k].update(roofline_of(model, avg, k))
+            key = "nnz_flops" if walks_nonzeros(k, variant_of(m, k, report)) else "flops"
+            kern[k].update(roofline_of(model, avg, k, key), priced_on="structural" if key == "nnz_flops" else "dense")
             if "nnz_flops" in model[k]:
+                kern[k]["dense_frac"] = roofline_of(model, avg, k)["frac"]
                 kern[k]["structural_frac"] = structural(model, avg, k)["frac"]
     ms, k, cnt = rows[0]
-    out["roofline"] = dict(roofline_of(model, ms / cnt * 1e-3, k), kernel=k, avg_launch_us=1e3 * ms / cnt,
-                           share_of_step=ms / tot, structural=structural(model, ms / cnt * 1e-3, k))
+    key = "nnz_flops" if walks_nonzeros(k, variant_of(m, k, report)) else "flops"
+    out["roofline"] = dict(roofline_of(model, ms / cnt * 1e-3, k, key), kernel=k, avg_launch_us=1e3 * ms / cnt,
+                           share_of_step=ms / tot, priced_on="structural" if key == "nnz_flops" else "dense",
+                           structural=structural(model, ms / cnt * 1e-3, k))
     out["kernels"] = kern
     m.close()
     del m
@@ -586,6 +656,8 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     mu, mach, pr, p = 1.0 / 1600.0, 0.1, 0.71, 4
     L = 2 * math.pi
+    # reference pressure left out of the momentum flux: the Taylor-Green p0
+    p_ref = 1.0 / (1.4 * mach * mach)
 
     def hex_form():
         hx = workload_form("hex", inputs.hex_box(50, jitter=0.10, seed=0), L / 50, args.steps, args.warmup,
@@ -619,7 +691,7 @@ def main():
 
     def make_mesh(precision):
         m = frlib.Mesh(arrays, p, system="ns", precision=precision, mu=mu, prandtl=pr,
-                       stream=stream)
+                       stream=stream, p_ref=p_ref)
         if not args.no_autotune and precision != "fp64":
             tuned[precision] = m.autotune(stream)
             print(f"autotune {precision}: {tuned[precision]}", file=sys.stderr, flush=True)
@@ -678,18 +750,21 @@ def main():
             out.append(x.double())
         return out
 
+    nel = [qs[t]["nelem"] for t in (0, 1)]
+
     def rel_err_pair(A, B):
-        """Per-field relative L2 of A against B over both types (momentum
-        components normalised by the momentum magnitude)."""
+        """Relative L2 of A against B over both types: per field, and for
+        density, momentum (as a vector field) and energy."""
         num = np.zeros(5)
         den = np.zeros(5)
         for t in (0, 1):
-            ne = mesh.query(t)["nelem"]
+            ne = nel[t]
             d = A[t][:, :, :ne] - B[t][:, :, :ne]
             num += (d ** 2).sum(dim=(0, 2)).cpu().numpy()
             den += (B[t][:, :, :ne] ** 2).sum(dim=(0, 2)).cpu().numpy()
-        den[1:4] = den[1:4].sum()
-        return [float(x) for x in np.sqrt(num / den)]
+        vec = [num[0] / den[0], num[1:4].sum() / den[1:4].sum(), num[4] / den[4]]
+        return {"per_field": [float(x) for x in np.sqrt(num / den)],
+                "rho_momentum_energy": [float(np.sqrt(x)) for x in vec]}
 
     def rhs_of(m):
         u = [frlib.to_device_state(m, t, host_state[t]) for t in (0, 1)]
@@ -749,8 +824,11 @@ def main():
         times_r.append(e0.elapsed_time(e1))
     rhs_med = float(np.median(times_r))
     del u_r, r_r
-    f_alg = sum(v["flops"] for v in kernel_model(mesh, "ns").values())
-    f_nnz = sum(v.get("nnz_flops", 0.0) for v in kernel_model(mesh, "ns").values())
+    # the operator products once each (the fused gradient stage's entry
+    # repeats the corrected-gradient and gradient-interpolation products)
+    prods = {k: v for k, v in kernel_model(mesh, "ns").items() if not k.startswith("gradflux_")}
+    f_alg = sum(v["flops"] for v in prods.values())
+    f_nnz = sum(v.get("nnz_flops", 0.0) for v in prods.values())
     print(f"fr_rhs median {rhs_med:.3f} ms", file=sys.stderr, flush=True)
     roof = None
     if not args.no_profile:
@@ -772,23 +850,33 @@ def main():
                   f" structural  {mdl['bytes'] / avg / 1e9:7.0f} GB/s", file=sys.stderr, flush=True)
         ms, k, cnt = rows[0]
         avg = ms / cnt * 1e-3
-        roof = roofline_of(model, avg, k)
-        roof["structural"] = structural(model, avg, k)
         vt = variant_of(mesh, k, tuned.get("fp32", ""))
+        key = "nnz_flops" if walks_nonzeros(k, vt) else "flops"
+        # the dominant kernel on the work it does: the dense-operator count
+        # for dense products, the structural nonzeros for kernels that skip
+        # the zero fragments (both kept in the record)
+        roof = roofline_of(model, avg, k, key)
+        roof["priced_on"] = "structural" if key == "nnz_flops" else "dense"
+        roof["dense"] = {x: roofline_of(model, avg, k)[x] for x in ("bound", "achieved", "unit", "frac")}
+        roof["structural"] = structural(model, avg, k)
+        roof["hbm"] = {"achieved": model[k]["bytes"] / avg / 1e9, "unit": "GB/s",
+                       "frac": model[k]["bytes"] / avg / PEAK_HBM, "algorithmic_bytes": model[k]["bytes"]}
         if vt:
             roof["variant"] = {"rows_blocks_per_wave": vt[0], "stage": vt[1]}
         roof["traffic"] = MEASURED_TRAFFIC.get((k,) + (vt or (0, 0)))
+        roof["traffic_source"] = (f"{TRAFFIC_SOURCE}: {k}" + (f" (row blocks {vt[0]}, stage {vt[1]})" if vt else "")
+                                  if roof["traffic"] else None)
         roof["kernel"] = k
         roof["avg_launch_us"] = avg * 1e6
         roof["share_of_step"] = ms / tot
 
     forms = None
     if not args.no_forms:
-        # accuracy of each precision on this workload: RHS of the same FP32
-        # input against the FP64 build of the same kernels
-        # reference: the FP64 build of the same kernels (pinned to the oracle),
-        # RHS of the same FP32 input and the state after the same steps
-        nsteps_total = args.steps + max(args.warmup, 1)
+        # accuracy of each precision on this workload against the FP64 build
+        # of the same kernels (itself held to the oracle within 1e-11 on
+        # sampled elements of this mesh, tests/test_gpu_fullsize.py): the RHS
+        # of the same FP32 input, and the state after 100 RK45[2R+] steps
+        nsteps_total = ACC_STEPS
         ref64 = make_mesh("fp64")
         R64 = rhs_of(ref64)
         load(ref64)
@@ -800,13 +888,16 @@ def main():
         load(mesh)                     # the FP32 mesh, the same number of steps
         mesh.rk_step(frlib.FR_RK45_2RP, dt, nsteps_total, stream)
         fp32_state = state_of(mesh)
-        forms = {"fp32": {"value": value, "ms_per_step": ms_per_step,
+        forms = {"accuracy_steps": ACC_STEPS, "accuracy_reference": "FP64 build of the same kernels",
+                 "fp32": {"value": value, "ms_per_step": ms_per_step,
                           "rhs_rel_l2_vs_fp64": rel_err_pair(rhs_of(mesh), R64),
                           "state_rel_l2_vs_fp64": rel_err_pair(fp32_state, U64)}}
         del fp32_state
         for prec in ("split_bf16", "split_fp16"):
             m2 = make_mesh(prec)
             ms2, v2, d2, f2 = timed(m2, args.steps, args.warmup)
+            load(m2)
+            m2.rk_step(frlib.FR_RK45_2RP, dt, nsteps_total, stream)
             st = rel_err_pair(state_of(m2), U64)
             forms[prec] = {"value": v2, "ms_per_step": ms2, "speedup_vs_fp32": v2 / value,
                            "rhs_rel_l2_vs_fp64": rel_err_pair(rhs_of(m2), R64),
