@@ -270,6 +270,19 @@ fr_status fr_rk45_adaptive(fr_mesh mesh, double t_end, double state[3], double a
 #define FR_RED_KE 4
 fr_status fr_reduce(fr_mesh mesh, int32_t what, double *out_host, void *stream);
 
+/* fr_reduce for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same items, arguments, kernels and results (bitwise), but the partial
+ * sums and the results live in a device array of the library's own, one per
+ * GPU, held until the process ends: 512 x 8 + 8 doubles (32.8 KB), enough for
+ * any mesh (the reduction's grid is fixed).  The call allocates nothing.  The
+ * array's address on the current device is looked up on its first use there.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (other threads, other streams) race; calls on different GPUs do not.
+ * Synchronises the stream.  Errors: as fr_reduce, FR_ERR_DEVICE if the
+ * array's address cannot be found. */
+fr_status fr_reduce_noalloc(fr_mesh mesh, int32_t what, double *out_host, void *stream);
+
 /* Copy an interface intermediate of the last fr_rhs into a caller device
  * array of the mesh's scalar type, layout [n_fpts][nvar][ld]:
  *   which 0: state at flux points U_f (nvar 5)

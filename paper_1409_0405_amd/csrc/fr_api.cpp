@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -842,9 +843,14 @@ fr_status rhs_entry(fr_mesh m, const void *const u[FR_NTYPES], void *const r[FR_
     return rhs_pipeline<T>(m, U, so, s);
 }
 
+// partial / red_out: device memory for the per-block partial sums
+// [RED_BLOCKS][8] and the 8 results (the mesh's own buffers when null).
 template <typename T>
-fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
+fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s, double *partial = nullptr,
+                      double *red_out = nullptr) {
     Dev<T> &d = dev_of<T>(m);
+    if (!partial) partial = d.partial;
+    if (!red_out) red_out = d.red_out;
     int nq = (what == 4) ? 2 : (what == 5 ? 1 : 5);
     std::vector<double> tot(8, 0.0);
     const bool needR = what == 2 || what == 3 || what == 4;
@@ -858,11 +864,11 @@ fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s) {
     for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
-        frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, d.partial};
+        frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, partial};
         FR_HIP(m, frd::launch_reduce<T>(ra, s));
-        FR_HIP(m, frd::launch_reduce_final(d.partial, frd::RED_BLOCKS, d.red_out, s));
+        FR_HIP(m, frd::launch_reduce_final(partial, frd::RED_BLOCKS, red_out, s));
         double h[8];
-        FR_HIP(m, hipMemcpyAsync(h, d.red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        FR_HIP(m, hipMemcpyAsync(h, red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         FR_HIP(m, hipStreamSynchronize(s));
         for (int q = 0; q < 8; ++q) tot[q] += h[q];
     }
@@ -1491,6 +1497,60 @@ fr_status fr_rk45_adaptive(fr_mesh m, double t_end, double state[3], double atol
     hipStream_t s = static_cast<hipStream_t>(stream);
     return m->precision != FR_FP64 ? rk_adaptive_impl<float>(m, t_end, state, atol, rtol, max_attempts, counts, s)
                                    : rk_adaptive_impl<double>(m, t_end, state, atol, rtol, max_attempts, counts, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of fr_reduce_noalloc: the per-block partial sums of the
+// reduction ([RED_BLOCKS][8] doubles) and its 8 results.  The reduction's
+// grid is fixed (RED_BLOCKS blocks striding over the mesh), so this array is
+// large enough for every mesh.  Each GPU the library runs on holds its own
+// copy until the process ends; in host code the name stands for no device
+// address, so the address is looked up once per device (hipGetSymbolAddress)
+// and only that pointer is passed to kernels and copies.
+constexpr size_t NOALLOC_DOUBLES = size_t(frd::RED_BLOCKS) * 8 + 8;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// This device's copy of `scratch` (looked up on its first use, with the
+// device current); null with the HIP error in *err on failure.
+double *scratch_of_current_device(hipError_t *err) {
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_reduce_noalloc(fr_mesh m, int32_t what, double *out, void *stream) {
+    if (fr_status st = check_mesh(m, 0, true)) return st;
+    if (!out || what < 1 || what > 4) return fail(m, FR_ERR_INVALID_ARG, "bad reduction request");
+    hipError_t e = hipSuccess;
+    double *ptr = scratch_of_current_device(&e);
+    if (!ptr) return fail(m, FR_ERR_DEVICE, std::string("device scratch of fr_reduce_noalloc: ") + hipGetErrorString(e));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *partial = ptr, *res = ptr + size_t(frd::RED_BLOCKS) * 8;
+    return m->precision != FR_FP64 ? reduce_impl<float>(m, what, out, s, partial, res)
+                                   : reduce_impl<double>(m, what, out, s, partial, res);
 }
 
 fr_status fr_reduce(fr_mesh m, int32_t what, double *out, void *stream) {

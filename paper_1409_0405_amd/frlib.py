@@ -40,7 +40,7 @@ EXPORTED = ("fr_mesh_create", "fr_mesh_destroy", "fr_mesh_query", "fr_upts_coord
             "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_get_grad", "fr_mlp_adam",
             "fr_mlp_last_error", "fr_project", "fr_closure_moments", "fr_closure_features",
             "fr_closure_targets", "fr_set_blocking", "fr_rk45_adaptive",
-            "fr_closure_attach", "fr_last_error")
+            "fr_closure_attach", "fr_reduce_noalloc", "fr_last_error")
 MLP_NPARAM, MLP_NSTATS = 13204, 280
 
 PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
@@ -102,6 +102,7 @@ def lib():
         L.fr_rhs.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.fr_rk_step.argtypes = [vp, i32, dbl, i32, vp]
         L.fr_reduce.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
+        L.fr_reduce_noalloc.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
         L.fr_intermediate.argtypes = [vp, i32, i32, vp, vp]
         L.fr_profile.argtypes = [vp, i32]
         L.fr_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -305,6 +306,13 @@ class Mesh:
         _check(lib().fr_reduce(self.h, what, _ptr(out, ctypes.c_double), ctypes.c_void_p(stream)), self.h)
         return out[:2] if what == FR_RED_KE else out[:5]
 
+
+    def reduce_noalloc(self, what, stream=0):
+        """fr_reduce through fr_reduce_noalloc (device scratch of the
+        library's own; allocates nothing)."""
+        out = np.zeros(8)
+        _check(lib().fr_reduce_noalloc(self.h, int(what), _ptr(out, ctypes.c_double), ctypes.c_void_p(stream)), self.h)
+        return out[:2] if what == FR_RED_KE else out[:5]
     def profile(self, enable):
         _check(lib().fr_profile(self.h, 1 if enable else 0), self.h)
 
