@@ -288,7 +288,12 @@ fr_status fr_reduce_noalloc(fr_mesh mesh, int32_t what, double *out_host, void *
  *   which 0: state at flux points U_f (nvar 5)
  *         1: common normal flux, transformed (nvar 5)
  *         2: physical gradient at flux points (NS only; nvar 15, direction
- *            major: index j*5 + field). */
+ *            major: index j*5 + field).  The fused gradient stage (tets
+ *            and prisms, FP32 and FP64, unless FR_SEPARATE_GRADIENT) writes
+ *            it only on the faces whose gradient the common flux reads:
+ *            boundary faces, and the sides of an interface whose LDG weight
+ *            1/2 +- beta is not zero (with beta = 1/2 side L only); the
+ *            other points keep what they held before. */
 fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_dev,
                           void *stream);
 

@@ -47,6 +47,10 @@ struct DevType {
     int64_t nelem = 0, ld = 0;
     frd::Op<T> Aint, Agint, Agrad, Adiv;          // Agint: M0 for the gradients
     frd::Op<T> Fgrad, Fgint;                      // fused gradient stage (step lists, one row block per group)
+    // fused gradient stage: bit f of qmask[e] is set when an interface or
+    // boundary kernel reads the gradient on face f of element e (the other
+    // flux points are not written); fbit[j] = 1 << face of flux point j
+    uint8_t *qmask = nullptr, *fbit = nullptr;
     // gradient stage form: 0 three kernels, 1 fused per tile, 2 fused and
     // streaming (FP32); the autotuner keeps the fastest
     int grad_form = 1;
@@ -610,6 +614,42 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         }
         FR_TRY(dev_upload(m, d, d.bgeo, bg, s));
     }
+    if (ns) {
+        // faces whose flux-point gradient the common flux reads: a side with
+        // a nonzero LDG weight (computed as the interface kernel does, in T),
+        // and every boundary face
+        const bool readL = T(0.5) + T(m->beta) != T(0), readR = T(0.5) - T(m->beta) != T(0);
+        std::vector<uint8_t> qm[frh::NTYPE];
+        for (int t = 0; t < frh::NTYPE; ++t)
+            if (d.t[t].Fgrad.frag) qm[t].assign(size_t(d.t[t].ld), 0);
+        auto mark = [&](uint32_t side) {
+            const int t = frh::side_type(side);
+            if (qm[t].empty()) return;
+            const int face = m->host.t[t].ops.fface[frh::side_fpt(side)];
+            qm[t][size_t(frh::side_elem(side))] |= uint8_t(1u << face);
+        };
+        for (size_t i = 0; i < P.sideL.size(); ++i) {
+            if (readL) mark(P.sideL[i]);
+            if (readR) mark(P.sideR[i]);
+        }
+        for (uint32_t side : m->host.bnd.side) mark(side);
+        for (int t = 0; t < frh::NTYPE; ++t) {
+            if (qm[t].empty()) continue;
+            DevType<T> &D = d.t[t];
+            const std::vector<int> &ff = m->host.t[t].ops.fface;
+            std::vector<uint8_t> fb(ff.size());
+            for (size_t j = 0; j < ff.size(); ++j) fb[j] = uint8_t(1u << ff[j]);
+            void *q;
+            FR_HIP(m, hipMalloc(&q, qm[t].size()));
+            d.allocs.push_back(q);
+            D.qmask = static_cast<uint8_t *>(q);
+            FR_HIP(m, hipMemcpy(D.qmask, qm[t].data(), qm[t].size(), hipMemcpyHostToDevice));
+            FR_HIP(m, hipMalloc(&q, fb.size()));
+            d.allocs.push_back(q);
+            D.fbit = static_cast<uint8_t *>(q);
+            FR_HIP(m, hipMemcpy(D.fbit, fb.data(), fb.size(), hipMemcpyHostToDevice));
+        }
+    }
     {
         void *q;
         FR_HIP(m, hipMalloc(&q, frd::RED_BLOCKS * 8 * sizeof(double)));
@@ -678,6 +718,8 @@ frd::GradFluxArgs<T> gradflux_args(fr_mesh m, const DevType<T> &D, const T *U) {
     ga.pref = T(m->pref);
     ga.G = D.Fgrad;
     ga.M = D.Fgint;
+    ga.qmask = D.qmask;
+    ga.fbit = D.fbit;
     return ga;
 }
 

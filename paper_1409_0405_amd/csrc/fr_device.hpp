@@ -123,6 +123,11 @@ struct GradFluxArgs {
     T gamma = 0, mu = 0, prandtl = 0, pref = 0;
     Op<T> G;             // [G_k | L_k], 3 nu x (nu + nf): step lists, one row block per group (stage 6)
     Op<T> M;             // M0, nf x nu: step lists, one row block per group (stage 6)
+    // Qf is written at flux point j of element e only where
+    // qmask[e] & fbit[j] (the faces whose gradient an interface or boundary
+    // kernel reads); every point when qmask is null
+    const uint8_t *qmask = nullptr;   // [ld]
+    const uint8_t *fbit = nullptr;    // [nf] 1 << local face of flux point j
 };
 // LDS bytes of one workgroup of the fused kernel (0: shape not supported).
 template <typename T>

@@ -12,7 +12,9 @@
 //   3. per (solution point, element): Q = adj^T Qt / J (in place), and
 //      Ft = adj (F_inv(U) - F_vis(U, Q)) -> memory;
 //   4. Qf = M0 Q on the matrix cores -> memory.
-// Only U and Cf are read and only Ft and Qf are written.  The operator
+// Only U and Cf are read and only Ft and Qf are written, Qf only on the
+// faces whose gradient the interface and boundary kernels read (with the
+// usual LDG weights one side of each interface).  The operator
 // fragments are those of the step-list products (one row block per group),
 // walked in the same K order, and the point-wise arithmetic is the shared
 // upts_point, so every value has the bits of the separate kernels.
@@ -220,7 +222,10 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     }
     __syncthreads();
 
-    // 4. Qf = M0 Q for each gradient direction j: work items (row block, j)
+    // 4. Qf = M0 Q for each gradient direction j: work items (row block, j).
+    // Lane l stores element l % NE of the tile; only the faces of it whose
+    // gradient is read (qm) are written.
+    const unsigned qm = a.qmask ? unsigned(a.qmask[e0 + c16 % NE]) : 0xffu;
     for (int it = w; it < a.M.nmg * 3; it += NW) {
         const int g = it / 3, j = it - 3 * g;
         const T *Qj = QT + size_t(j) * nu * W5 + c16;
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = a.M.rowmap[16 * g + acc_row<T>(krow, r)];
-            if (f < 0) continue;
+            if (f < 0 || (a.qmask && !(qm & a.fbit[f]))) continue;
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 const int flat = 16 * n + c16, v = flat / NE, e = flat - v * NE;
@@ -356,7 +361,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ET == 0
         }
         __syncthreads();
 
-        // 3. Qf = M0 Q
+        // 3. Qf = M0 Q (the faces whose gradient is read, as above)
+        const unsigned qm = a.qmask ? unsigned(a.qmask[e0 + c16]) : 0xffu;
         for (int it = w; it < a.M.nmg * 3; it += NW) {
             const int g = it / 3, j = it - 3 * g;
             const float *Qj = QT + size_t(j) * nu * W5 + c16;
@@ -368,7 +374,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ET == 0
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int f = a.M.rowmap[16 * g + acc_row<float>(krow, r)];
-                if (f < 0 || e0 + c16 >= a.nelem) continue;
+                if (f < 0 || e0 + c16 >= a.nelem || (a.qmask && !(qm & a.fbit[f]))) continue;
 #pragma unroll
                 for (int n = 0; n < NB; ++n) a.Qf[(int64_t(f) * 15 + j * 5 + n) * ld + e0 + c16] = acc2[n][r];
             }

@@ -4,9 +4,11 @@ prisms as one kernel per tile of elements with the reference and physical
 gradients in LDS.  With FR_SEPARATE_GRADIENT it runs as three kernels that
 pass those gradients through memory.  Both walk the same operator fragments
 in the same order and share the point-wise arithmetic, so every result is
-bitwise the same: the residual, the interface intermediates (state, gradient
-and common flux at the flux points) and RK45[2R+] steps, in FP32 and FP64,
-on straight, curved and wall-bounded meshes.
+bitwise the same: the residual, the interface intermediates (state and
+common flux at the flux points, the gradient where the common flux reads it)
+and RK45[2R+] steps, in FP32 and FP64, on straight, curved and wall-bounded
+meshes.  The fused kernel writes the flux-point gradient only on the faces
+whose gradient is read; the others keep their initial zero.
 
 The reference pressure p_ref left out of the momentum flux changes no
 residual beyond rounding (the discrete divergence of a uniform flux vanishes
@@ -16,6 +18,7 @@ import math
 import numpy as np
 import pytest
 
+from gradient_points import read_points
 from oracle import fr, mesh as om
 from paper_1409_0405_amd import inputs
 
@@ -97,6 +100,7 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
         M.close()
     (r0, i0, s0, p0), (r1, i1, s1, p1) = out
     ts = sorted(r0)
+    rp = read_points(O)
     # the fused kernel ran for the tets and prisms present, and only there
     for t, n in ((0, "gradflux_tet"), (1, "gradflux_pri")):
         assert p0[n][1] == (1 if t in ts else 0) and p1[n][1] == 0, (n, p0[n], p1[n])
@@ -104,9 +108,21 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
         assert p0[g][1] == 0 and p1[g][1] == (1 if t in ts else 0), (g, p0[g], p1[g])
     for t in ts:
         assert torch.equal(r0[t], r1[t]), ("rhs", NAMES[t])
-        for which in (0, 1, 2):
-            ne = O.types[NAMES[t]].nelem
+        ne = O.types[NAMES[t]].nelem
+        for which in (0, 1):
             assert torch.equal(i0[(t, which)][:, :, :ne], i1[(t, which)][:, :, :ne]), ("intermediate", which, NAMES[t])
+        # the gradient at flux points: the same bits where the common flux
+        # reads it; the fused kernel (of a fresh mesh) leaves the other
+        # points at their initial zero, the separate kernels write them
+        if t < 2:
+            mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
+            q0, q1 = i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]
+            assert torch.equal(torch.where(mask, q0, 0), torch.where(mask, q1, 0)), ("Qf read", NAMES[t])
+            assert not torch.where(mask, 0, q0).any(), ("Qf written off the read faces", NAMES[t])
+            assert torch.where(mask, 0, q1).any()
+            print(f"  {NAMES[t]}: gradient written at {float(mask.float().mean()):.3f} of the flux points", flush=True)
+        else:
+            assert torch.equal(i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]), ("intermediate", 2, NAMES[t])
         assert torch.equal(s0[t], s1[t]), ("rk45 steps", NAMES[t])
     assert max(float(r0[t].abs().max()) for t in ts) > 1e-3
 
@@ -123,6 +139,7 @@ def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
     U = _state(O, 9)
     kw = {"t_wall": P0} if kind == "curvedwall" else {}
     ts = [NAMES.index(n) for n in O.types]
+    rp = read_points(O)
     outs = []
     for form in (0, 1, 2):
         M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.02, **kw)
@@ -138,7 +155,9 @@ def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
         for t in ts:
             assert torch.equal(outs[0][0][t], outs[form][0][t]), ("rhs", form, NAMES[t])
             ne = O.types[NAMES[t]].nelem
-            assert torch.equal(outs[0][1][(t, 2)][:, :, :ne], outs[form][1][(t, 2)][:, :, :ne]), ("Qf", form)
+            mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
+            assert torch.equal(torch.where(mask, outs[0][1][(t, 2)][:, :, :ne], 0),
+                               torch.where(mask, outs[form][1][(t, 2)][:, :, :ne], 0)), ("Qf", form)
             assert torch.equal(outs[0][2][t], outs[form][2][t]), ("rk45", form, NAMES[t])
 
 

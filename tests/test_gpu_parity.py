@@ -22,6 +22,7 @@ import math
 import numpy as np
 import pytest
 
+from gradient_points import read_points
 from oracle import fr, mesh as om, reduce, rk
 from paper_1409_0405_amd import inputs
 
@@ -300,6 +301,11 @@ def test_interface_intermediates_fp64(kind, p, system):
             torch.cuda.synchronize()
             g = np.transpose(buf[:, :, :q["nelem"]].cpu().numpy(), (2, 0, 1))
             o = want[key][n].reshape(g.shape)
+            if key == "Qf":
+                # the gradient is held where the common flux reads it (the
+                # fused gradient stage writes no other point)
+                rp = read_points(O)[n]
+                g, o = g[rp], o[rp]
             rel = np.abs(g - o).max() / np.abs(o).max()
             print(f"  {key} {n} max rel {rel:.2e}", flush=True)
             assert rel < 1e-11, (key, n, rel)
