@@ -49,7 +49,8 @@ struct DevType {
     frd::Op<T> Fgrad, Fgint;                      // fused gradient stage (step lists, one row block per group)
     // fused gradient stage: bit f of qmask[e] is set when an interface or
     // boundary kernel reads the gradient on face f of element e (the other
-    // flux points are not written); fbit[j] = 1 << face of flux point j
+    // flux points are not written); fbit[s] = 1 << face of the flux point in
+    // row slot s of Fgint (0 for padding slots)
     uint8_t *qmask = nullptr, *fbit = nullptr;
     // gradient stage form: 0 three kernels, 1 fused per tile, 2 fused and
     // streaming (FP32); the autotuner keeps the fastest
@@ -452,6 +453,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
     do {                          \
         if ((st = (x))) return st; \
     } while (0)
+    std::vector<int32_t> gint_rows[frh::NTYPE];   // row slot -> flux point of Fgint (-1: padding)
     for (int t = 0; t < frh::NTYPE; ++t) {
         const frh::TypeHost &H = m->host.t[t];
         DevType<T> &D = d.t[t];
@@ -484,6 +486,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             FR_HIP(m, upload_op(D.Fgrad, f, idx, d.allocs));
             D.Fgint = fragment<T>(R.M0, nf, nu, f, 1, 6, &idx);
             FR_HIP(m, upload_op(D.Fgint, f, idx, d.allocs));
+            gint_rows[t].assign(idx.end() - 16 * D.Fgint.nmg, idx.end());
         }
         if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
             const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;
@@ -637,8 +640,9 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             if (qm[t].empty()) continue;
             DevType<T> &D = d.t[t];
             const std::vector<int> &ff = m->host.t[t].ops.fface;
-            std::vector<uint8_t> fb(ff.size());
-            for (size_t j = 0; j < ff.size(); ++j) fb[j] = uint8_t(1u << ff[j]);
+            std::vector<uint8_t> fb(gint_rows[t].size(), 0);
+            for (size_t j = 0; j < fb.size(); ++j)
+                if (gint_rows[t][j] >= 0) fb[j] = uint8_t(1u << ff[size_t(gint_rows[t][j])]);
             void *q;
             FR_HIP(m, hipMalloc(&q, qm[t].size()));
             d.allocs.push_back(q);

@@ -123,11 +123,11 @@ struct GradFluxArgs {
     T gamma = 0, mu = 0, prandtl = 0, pref = 0;
     Op<T> G;             // [G_k | L_k], 3 nu x (nu + nf): step lists, one row block per group (stage 6)
     Op<T> M;             // M0, nf x nu: step lists, one row block per group (stage 6)
-    // Qf is written at flux point j of element e only where
-    // qmask[e] & fbit[j] (the faces whose gradient an interface or boundary
-    // kernel reads); every point when qmask is null
+    // Qf is written at the flux point of row slot s of M for element e only
+    // where qmask[e] & fbit[s] (the faces whose gradient an interface or
+    // boundary kernel reads); every point when qmask is null
     const uint8_t *qmask = nullptr;   // [ld]
-    const uint8_t *fbit = nullptr;    // [nf] 1 << local face of flux point j
+    const uint8_t *fbit = nullptr;    // [16 M.nmg] 1 << local face of the row's flux point
 };
 // LDS bytes of one workgroup of the fused kernel (0: shape not supported).
 template <typename T>

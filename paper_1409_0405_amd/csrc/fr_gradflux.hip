@@ -131,6 +131,7 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int krow = lane >> 4, c16 = lane & 15;
     const int64_t ld = a.ld;
+    for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
 
     // 1. B rows: U (k < nu), Cf (nu <= k < nu + nf), zero up to Kp
     {
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
             const int v = kv % 5, k = kv / 5;
             floatx4 val = {0, 0, 0, 0};
             if (k < nu)
-                val = *reinterpret_cast<const floatx4 *>(a.U + (int64_t(k) * 5 + v) * ld + e0 + q * (16 / sizeof(T)));
+                val = *reinterpret_cast<const floatx4 *>(a.U + (int64_t(k) * 5 + v) * ld + e0 +
+                                                         q * (16 / sizeof(T)));
             else if (k < nu + a.nf)
                 val = *reinterpret_cast<const floatx4 *>(a.Cf + (int64_t(k - nu) * 5 + v) * ld + e0 +
                                                          q * (16 / sizeof(T)));
@@ -154,13 +156,21 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
         if (!a.padj)
             for (int idx = tid; idx < NG * NE; idx += 64 * NW)
                 Gs[idx] = a.geom[int64_t(idx / NE) * ld + e0 + idx % NE];
-        for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
     }
     __syncthreads();
 
     // 2. Qt = [G_k | L_k] B: wavefront w takes row blocks w, w + NW, ..., each
     // against every column block
+    // (the Qt row of each accumulator is loaded before the products, so
+    // that its latency hides behind them)
     v4 acc[MG][NB];
+    int qrow[MG][4];
+#pragma unroll
+    for (int m = 0; m < MG; ++m) {
+        const int g = w + m * NW;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qrow[m][r] = g < a.G.nmg ? a.G.rowmap[16 * g + acc_row<T>(krow, r)] : -1;
+    }
 #pragma unroll
     for (int m = 0; m < MG; ++m) {
 #pragma unroll
@@ -172,11 +182,9 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     __syncthreads();                                     // every wavefront is done with B
 #pragma unroll
     for (int m = 0; m < MG; ++m) {
-        const int g = w + m * NW;
-        if (g >= a.G.nmg) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = a.G.rowmap[16 * g + acc_row<T>(krow, r)];
+            const int row = qrow[m][r];
             if (row >= 0) {
 #pragma unroll
                 for (int n = 0; n < NB; ++n) QT[row * W5 + 16 * n + c16] = acc[m][n][r];
@@ -186,48 +194,73 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     __syncthreads();
 
     // 3. point-wise: one (solution point, element) per thread; Q replaces Qt
-    // in place, Ft goes to memory
-    for (int it = tid; it < nu * NE; it += 64 * NW) {
-        const int i = it / NE, e = it - i * NE;
-        const int64_t eg = e0 + e;
-        if (eg >= a.nelem) continue;
-        T adj[3][3], Jinv;
-        if (a.padj) {
+    // in place, Ft goes to memory.  U comes again from memory (B's place in
+    // LDS holds Qt now; the tile was just read, so L2 serves it): a thread
+    // loads the states of its next PI points first, so that no load queues
+    // behind the Ft stores of the points before it (memory operations of a
+    // wavefront retire in order).
+    constexpr int PI = 2;
+    for (int base = 0; base < nu * NE; base += PI * 64 * NW) {
+        T uu[PI][5];
+#pragma unroll
+        for (int q = 0; q < PI; ++q) {
+            const int it = base + q * 64 * NW + tid;
+            const int i = it / NE, e = it - i * NE;
+            if (it < nu * NE && e0 + e < a.nelem) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) uu[q][v] = a.U[(int64_t(i) * 5 + v) * ld + e0 + e];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PI; ++q) {
+            const int it = base + q * 64 * NW + tid;
+            const int i = it / NE, e = it - i * NE;
+            const int64_t eg = e0 + e;
+            if (it >= nu * NE || eg >= a.nelem) continue;
+            T adj[3][3], Jinv;
+            if (a.padj) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * nu + i) * ld + eg];
+                Jinv = a.pjinv[int64_t(i) * ld + eg];
+            } else {
+                Jinv = T(1) / metric<T, ET>(Gs, NE, e, Xs + 3 * i, adj);
+            }
+            T qt[3][5], q3[3][5], Ft[3][5];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * nu + i) * ld + eg];
-            Jinv = a.pjinv[int64_t(i) * ld + eg];
-        } else {
-            Jinv = T(1) / metric<T, ET>(Gs, NE, e, Xs + 3 * i, adj);
+                for (int v = 0; v < 5; ++v) qt[k][v] = QT[(k * nu + i) * W5 + v * NE + e];
+            upts_point<T, true>(uu[q], qt, adj, Jinv, a.gamma, a.mu, a.prandtl, a.pref, q3, Ft);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) QT[(j * nu + i) * W5 + v * NE + e] = q3[j][v];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) a.Ft[((int64_t(k) * nu + i) * 5 + v) * ld + eg] = Ft[k][v];
         }
-        // U again from memory (B's place in LDS holds Qt now; the tile was
-        // just read, so these loads are served by L2)
-        T u[5], qt[3][5], q[3][5], Ft[3][5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) u[v] = a.U[(int64_t(i) * 5 + v) * ld + eg];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qt[k][v] = QT[(k * nu + i) * W5 + v * NE + e];
-        upts_point<T, true>(u, qt, adj, Jinv, a.gamma, a.mu, a.prandtl, a.pref, q, Ft);
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) QT[(j * nu + i) * W5 + v * NE + e] = q[j][v];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) a.Ft[((int64_t(k) * nu + i) * 5 + v) * ld + eg] = Ft[k][v];
     }
     __syncthreads();
 
     // 4. Qf = M0 Q for each gradient direction j: work items (row block, j).
-    // Lane l stores element l % NE of the tile; only the faces of it whose
-    // gradient is read (qm) are written.
+    // Lane l stores element l % NE of the tile, only on the faces of it
+    // whose gradient is read (qm); the flux point and face of each
+    // accumulator row are loaded before the products, behind which their
+    // latency hides.
     const unsigned qm = a.qmask ? unsigned(a.qmask[e0 + c16 % NE]) : 0xffu;
     for (int it = w; it < a.M.nmg * 3; it += NW) {
         const int g = it / 3, j = it - 3 * g;
+        int frow[4];
+        unsigned fb[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int slot = 16 * g + acc_row<T>(krow, r);
+            frow[r] = a.M.rowmap[slot];
+            fb[r] = a.qmask ? unsigned(a.fbit[slot]) : 1u;
+        }
         const T *Qj = QT + size_t(j) * nu * W5 + c16;
         v4 acc2[NB];
 #pragma unroll
@@ -236,8 +269,8 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
         step_products<T, NB>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; }, acc2);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int f = a.M.rowmap[16 * g + acc_row<T>(krow, r)];
-            if (f < 0 || (a.qmask && !(qm & a.fbit[f]))) continue;
+            const int f = frow[r];
+            if (f < 0 || !(qm & fb[r])) continue;
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 const int flat = 16 * n + c16, v = flat / NE, e = flat - v * NE;
@@ -373,8 +406,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ET == 0
                                      acc2);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int f = a.M.rowmap[16 * g + acc_row<float>(krow, r)];
-                if (f < 0 || e0 + c16 >= a.nelem || (a.qmask && !(qm & a.fbit[f]))) continue;
+                const int slot = 16 * g + acc_row<float>(krow, r), f = a.M.rowmap[slot];
+                if (f < 0 || e0 + c16 >= a.nelem || (a.qmask && !(qm & a.fbit[slot]))) continue;
 #pragma unroll
                 for (int n = 0; n < NB; ++n) a.Qf[(int64_t(f) * 15 + j * 5 + n) * ld + e0 + c16] = acc2[n][r];
             }
