@@ -87,8 +87,10 @@ typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
  * product, the solution-point work (physical gradient, transformed flux) and
  * the gradient interpolation as three kernels that pass the reference and
  * physical gradients through memory.  By default one kernel does all three
- * per tile of elements with those gradients in LDS (fr_autotune keeps
- * whichever form is fastest per element type); all give the same bits. */
+ * per tile of elements with those gradients in LDS wherever the gradient
+ * operator has at least four 16-row blocks (tets from p = 3, prisms from
+ * p = 2), the three kernels below that; fr_autotune then keeps whichever
+ * form is fastest per element type.  All give the same bits. */
 #define FR_SEPARATE_GRADIENT 0x8u
 
 typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
@@ -289,7 +291,7 @@ fr_status fr_reduce_noalloc(fr_mesh mesh, int32_t what, double *out_host, void *
  *         1: common normal flux, transformed (nvar 5)
  *         2: physical gradient at flux points (NS only; nvar 15, direction
  *            major: index j*5 + field).  The fused gradient stage (tets
- *            and prisms, FP32 and FP64, unless FR_SEPARATE_GRADIENT) writes
+ *            and prisms, FP32 and FP64, where it runs) writes
  *            it only on the faces whose gradient the common flux reads:
  *            boundary faces, and the sides of an interface whose LDG weight
  *            1/2 +- beta is not zero (with beta = 1/2 side L only); the

@@ -53,7 +53,8 @@ struct DevType {
     // row slot s of Fgint (0 for padding slots)
     uint8_t *qmask = nullptr, *fbit = nullptr;
     // gradient stage form: 0 three kernels, 1 fused per tile, 2 fused and
-    // streaming (FP32); the autotuner keeps the fastest
+    // streaming (FP32); set from the operator's size at setup, the autotuner
+    // keeps the fastest
     int grad_form = 1;
     frd::OpSplit Sint, Sgint, Sgrad, Sdiv;        // split-precision forms only
     T *geom = nullptr, *xi = nullptr;
@@ -487,6 +488,11 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
             D.Fgint = fragment<T>(R.M0, nf, nu, f, 1, 6, &idx);
             FR_HIP(m, upload_op(D.Fgint, f, idx, d.allocs));
             gint_rows[t].assign(idx.end() - 16 * D.Fgint.nmg, idx.end());
+            // before autotuning: the fused stage where its gradient product
+            // has work for at least half of the workgroup's wavefronts
+            // (measured on the mixed Taylor-Green mesh: it loses for tets at
+            // p <= 2 and prisms at p = 1, wins above)
+            D.grad_form = D.Fgrad.nmg >= 4 ? 1 : 0;
         }
         if (m->precision == FR_SPLIT_BF16 || m->precision == FR_SPLIT_FP16) {
             const int fmt = m->precision == FR_SPLIT_FP16 ? 2 : 1;

@@ -328,9 +328,11 @@ def test_trained_closure_reduces_apriori_dissipation_error():
 def test_closure_trained_along_trajectory_runs_stably():
     """Trained on the order-1 run itself (inputs and order-1 residuals from
     U_1(t), targets against the filtered order-4 residual), the closure keeps
-    the order-1 Taylor-Green run finite over t in [0, 8] and is measured on the
-    kinetic-energy dissipation rate against the plain order-4 run (printed;
-    the gain is mesh dependent, see the design notes)."""
+    the order-1 Taylor-Green run finite over t in [0, 8], and on this machine
+    (8 x 8 x 22 cells) its kinetic-energy dissipation rate is closer to the
+    plain order-4 run's than the plain order-1 run's is (relative L2 over the
+    21 snapshots).  The gain is mesh dependent: on the 16 x 16 x 43 box the
+    same recipe ends slightly worse than plain order 1."""
     import math
     from paper_1409_0405_amd import closure as cl, frlib
     print("closure along the trajectory: generate", flush=True)
@@ -364,6 +366,7 @@ def test_closure_trained_along_trajectory_runs_stably():
     e = lambda r: float(np.sqrt(np.mean((r - rates4) ** 2) / np.mean(rates4 ** 2)))
     print(f"a-posteriori dissipation-rate error vs order 4: plain {e(plain):.3f}, closure {e(corr):.3f}",
           flush=True)
+    assert e(corr) < e(plain), (e(corr), e(plain))
 
 
 def test_closure_refuses_hexahedra():
