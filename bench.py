@@ -208,7 +208,7 @@ def kernel_model(mesh, system):
             out[f"{op}_{name}"] = {"flops": 2.0 * M * K * n, "nnz_flops": 2.0 * nnz[op] * n,
                                    "bytes": s * (K + M) * n}
         ng = (9, 15, 21)[t]
-        if ns and t < 2:
+        if ns:
             # fused gradient stage: reads U and the jump Cf, writes Ft and Qf
             g, gi = ops["grad"], ops["gradinterp"]
             out[f"gradflux_{name}"] = {

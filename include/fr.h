@@ -83,14 +83,15 @@ typedef enum { FR_RK4 = 0, FR_RK45_2RP = 1, FR_FWD_EULER = 2 } fr_scheme;
  * orders of work give the same bits.  The autotuner times the divergence
  * products the way the right-hand side runs them. */
 #define FR_SEPARATE_UPDATE 0x4u
-/* Navier-Stokes tets and prisms in FP32 / FP64: run the corrected gradient
+/* Navier-Stokes in FP32 / FP64: run the corrected gradient
  * product, the solution-point work (physical gradient, transformed flux) and
  * the gradient interpolation as three kernels that pass the reference and
  * physical gradients through memory.  By default one kernel does all three
  * per tile of elements with those gradients in LDS wherever the gradient
- * operator has at least four 16-row blocks (tets from p = 3, prisms from
- * p = 2), the three kernels below that; fr_autotune then keeps whichever
- * form is fastest per element type.  All give the same bits. */
+ * operator has at least four 16-row blocks (tets from p = 3, prisms and
+ * hexahedra from p = 2), the three kernels below that; fr_autotune then
+ * keeps whichever form is fastest per element type.  All give the same
+ * bits. */
 #define FR_SEPARATE_GRADIENT 0x8u
 
 typedef struct fr_mesh_s *fr_mesh;   /* opaque, library-owned */
@@ -290,8 +291,8 @@ fr_status fr_reduce_noalloc(fr_mesh mesh, int32_t what, double *out_host, void *
  *   which 0: state at flux points U_f (nvar 5)
  *         1: common normal flux, transformed (nvar 5)
  *         2: physical gradient at flux points (NS only; nvar 15, direction
- *            major: index j*5 + field).  The fused gradient stage (tets
- *            and prisms, FP32 and FP64, where it runs) writes
+ *            major: index j*5 + field).  The fused gradient stage (FP32
+ *            and FP64, where it runs) writes
  *            it only on the faces whose gradient the common flux reads:
  *            boundary faces, and the sides of an interface whose LDG weight
  *            1/2 +- beta is not zero (with beta = 1/2 side L only); the
@@ -312,9 +313,9 @@ fr_status fr_intermediate(fr_mesh mesh, int32_t etype, int32_t which, void *dst_
  * update, 14 closure inputs (moments and neighbour gathering), 15 closure
  * network forward; hexahedra: 16 + op the products, 20 the solution-point
  * kernel, 21 negdivconf; 22 boundary states, 23 boundary flux; 24 + etype
- * the fused gradient stage of tets and prisms (corrected gradient, point-wise
- * work and gradient interpolation in one kernel). */
-#define FR_PROF_NCLASS 26
+ * the fused gradient stage of tets, prisms and hexahedra (corrected
+ * gradient, point-wise work and gradient interpolation in one kernel). */
+#define FR_PROF_NCLASS 27
 fr_status fr_profile(fr_mesh mesh, int32_t enable);
 fr_status fr_profile_read(fr_mesh mesh, double *total_ms, int64_t *count);
 
@@ -338,10 +339,10 @@ fr_status fr_autotune(fr_mesh mesh, void *stream);
  * in flight.  The split forms have stage 0 (each wavefront splits
  * its B panel) and 1 (the panel's row groups, at most 8 and 64 KiB of parts,
  * share the split B in LDS).  op 4 selects the form of the Navier-Stokes
- * gradient stage of tets and prisms (cap ignored): stage 0 the three
- * separate kernels, 1 one fused kernel per tile of elements, 2 (FP32) the
- * fused kernel streaming runs of tiles with the next tile's input loaded
- * into LDS during the current one.  Results are bitwise the same for every
+ * gradient stage (FP32 and FP64; cap ignored): stage 0 the three separate
+ * kernels, 1 one fused kernel per tile of elements, 2 (FP32 tets and
+ * prisms) the fused kernel streaming runs of tiles with the next tile's
+ * input loaded into LDS during the current one.  Results are bitwise the same for every
  * variant (for finite states).  Synchronous
  * (uploads the operator); FR_ERR_UNSUPPORTED for a combination the form
  * does not have. */

@@ -480,7 +480,7 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
         FR_TRY(dev_upload(m, d, p, f, s));
         D.Adiv.frag = p;
         D.Agint = D.Aint;
-        if (ns && t < 2 && (m->precision == FR_FP32 || m->precision == FR_FP64)) {
+        if (ns && (m->precision == FR_FP32 || m->precision == FR_FP64)) {
             // the fused gradient stage walks the step lists of one row block
             std::vector<int32_t> idx;
             D.Fgrad = fragment<T>(grad, 3 * nu, nu + nf, f, 1, 6, &idx);
@@ -1267,7 +1267,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                       std::to_string(best_cap) + " stage " + std::to_string(best_stage) + " " +
                       std::to_string(best / 3 * 1e3) + " us; ";
         }
-        // the gradient stage (Navier-Stokes tets and prisms): the fused kernel
+        // the gradient stage (Navier-Stokes): the fused kernel
         // against the three separate kernels with the variants just chosen
         if (ns && D.Fgrad.frag && !(m->flags & FR_SEPARATE_GRADIENT)) {
             const T *U = D.reg[0];
@@ -1281,7 +1281,7 @@ fr_status autotune_impl(fr_mesh m, hipStream_t s, std::string &report) {
                                  D.Qf, w15, w15, s);
                 return e;
             };
-            const int nform = sizeof(T) == 4 ? 3 : 2;
+            const int nform = sizeof(T) == 4 && t < 2 ? 3 : 2;   // streaming: FP32 tets and prisms
             float ms[3] = {0, 0, 0};
             for (int form = 0; form < nform; ++form) {
                 FR_HIP(m, run(form));
@@ -1730,8 +1730,8 @@ fr_status fr_set_blocking(fr_mesh m, int32_t etype, int32_t op, int32_t cap, int
         const bool have = m->precision == FR_FP64 ? dev_of<double>(m).t[etype].Fgrad.frag != nullptr
                                                   : dev_of<float>(m).t[etype].Fgrad.frag != nullptr;
         if (stage > 0 && !have) return fail(m, FR_ERR_UNSUPPORTED, "no fused gradient stage for this type or form");
-        if (stage == 2 && m->precision != FR_FP32)
-            return fail(m, FR_ERR_UNSUPPORTED, "the streaming gradient stage is FP32 only");
+        if (stage == 2 && (m->precision != FR_FP32 || etype == 2))
+            return fail(m, FR_ERR_UNSUPPORTED, "the streaming gradient stage is FP32 tets and prisms only");
         if (m->precision == FR_FP64)
             dev_of<double>(m).t[etype].grad_form = stage;
         else

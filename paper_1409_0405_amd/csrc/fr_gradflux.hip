@@ -31,7 +31,7 @@ namespace frd {
 namespace {
 
 template <int ET>
-constexpr int n_geom_coeffs() { return ET == 0 ? 9 : 15; }
+constexpr int n_geom_coeffs() { return ET == 0 ? 9 : ET == 1 ? 15 : 21; }
 
 // Entry i of a step list through the scalar data cache: the lists are
 // read-only and the index is uniform in the wavefront, and a constant-space
@@ -99,8 +99,11 @@ struct TileShape {
 };
 
 // Elements per tile: 16 in FP32 (column block n = field n), 4 in FP64 (whose
-// LDS footprint per value is twice as large).
-template <typename T>
+// LDS footprint per value is twice as large).  FP32 hexahedra at p = 4 fill
+// 123 KB of LDS with it, one workgroup of 16 wavefronts per CU; tiles of 8
+// (two workgroups per CU) were measured 24 % slower: each operator fragment
+// then feeds 3 instead of 5 matrix instructions.
+template <typename T, int ET>
 constexpr int tile_elems() { return sizeof(T) == 4 ? 16 : 4; }
 
 // One workgroup of NW wavefronts per tile.  MG: row blocks of the gradient
@@ -471,15 +474,22 @@ hipError_t launch_gf_stream(const GradFluxArgs<float> &a, size_t lds, hipStream_
 
 }  // namespace
 
-template <typename T>
-size_t gradflux_lds(int etype, const GradFluxArgs<T> &a) {
-    if (etype != 0 && etype != 1) return 0;
-    constexpr int NE = tile_elems<T>();
+namespace {
+template <typename T, int ET>
+size_t gradflux_lds_t(const GradFluxArgs<T> &a) {
+    constexpr int NE = tile_elems<T, ET>();
     constexpr int W5 = TileShape<NE>::W5;
-    const int ng = etype == 0 ? 9 : 15;
-    const size_t n = size_t(std::max(4 * a.G.Kb, 3 * a.nu)) * W5 + size_t(ng) * NE + size_t(3 * a.nu);
+    const size_t n = size_t(std::max(4 * a.G.Kb, 3 * a.nu)) * W5 + size_t(n_geom_coeffs<ET>()) * NE +
+                     size_t(3 * a.nu);
     const size_t bytes = n * sizeof(T);
     return bytes <= GRADFLUX_LDS_MAX ? bytes : 0;
+}
+}  // namespace
+
+template <typename T>
+size_t gradflux_lds(int etype, const GradFluxArgs<T> &a) {
+    return etype == 0 ? gradflux_lds_t<T, 0>(a) : etype == 1 ? gradflux_lds_t<T, 1>(a)
+                                                : etype == 2 ? gradflux_lds_t<T, 2>(a) : 0;
 }
 
 template <typename T>
@@ -487,6 +497,7 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, b
     size_t lds = gradflux_lds<T>(etype, a);
     if constexpr (std::is_same<T, float>::value) {
         if (stream) {
+            if (etype > 1) return hipErrorInvalidValue;   // the streaming form covers tets and prisms
             lds = gradflux_stream_lds_bytes(etype, a);
             if (lds > GRADFLUX_LDS_MAX) return hipErrorInvalidValue;
         }
@@ -503,10 +514,12 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, b
     if constexpr (std::is_same<T, float>::value) {
         if (stream) return etype == 0 ? launch_gf_stream<0, 8>(a, lds, s) : launch_gf_stream<1, 8>(a, lds, s);
     }
-    constexpr int NE = tile_elems<T>();
-    // eight wavefronts per workgroup (FP32), four in FP64
-    if (etype == 0) return launch_gf<T, 0, NE, sizeof(T) == 4 ? 8 : 4>(a, lds, s);
-    return launch_gf<T, 1, NE, sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+    // eight wavefronts per workgroup for tets and prisms in FP32, four in
+    // FP64; hexahedra (24 row blocks of the gradient operator at p = 4) take
+    // sixteen in FP32 and eight in FP64, two row blocks per wavefront
+    if (etype == 0) return launch_gf<T, 0, tile_elems<T, 0>(), sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+    if (etype == 1) return launch_gf<T, 1, tile_elems<T, 1>(), sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+    return launch_gf<T, 2, tile_elems<T, 2>(), sizeof(T) == 4 ? 16 : 8>(a, lds, s);
 }
 
 template size_t gradflux_lds<float>(int, const GradFluxArgs<float> &);

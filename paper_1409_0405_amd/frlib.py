@@ -48,7 +48,7 @@ PROF_CLASSES = ("interp_tet", "grad_tet", "gradinterp_tet", "div_tet",
                 "upts_tet", "upts_pri", "common_solution", "common_flux",
                 "negdivconf_tet", "negdivconf_pri", "closure_inputs", "closure_forward",
                 "interp_hex", "grad_hex", "gradinterp_hex", "div_hex", "upts_hex", "negdivconf_hex",
-                "boundary_solution", "boundary_flux", "gradflux_tet", "gradflux_pri")
+                "boundary_solution", "boundary_flux", "gradflux_tet", "gradflux_pri", "gradflux_hex")
 
 
 class FrError(RuntimeError):
@@ -343,8 +343,9 @@ class Mesh:
         _check(lib().fr_set_blocking(self.h, int(etype), int(op), int(cap), int(stage)), self.h)
 
     def set_gradient_form(self, etype, form):
-        """Navier-Stokes gradient stage of a tet / prism type: 0 separate
-        kernels, 1 fused per tile, 2 fused and streaming (FP32)."""
+        """Navier-Stokes gradient stage of an element type: 0 separate
+        kernels, 1 fused per tile, 2 fused and streaming (FP32 tets and
+        prisms)."""
         _check(lib().fr_set_blocking(self.h, int(etype), 4, 1, int(form)), self.h)
 
     def closure_targets(self, a_ptrs, b_ptrs, stats_ptr, out_ptr, stream=0):

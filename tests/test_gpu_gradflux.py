@@ -1,6 +1,6 @@
 """The gradient stage of the Navier-Stokes residual (corrected gradient
-product, solution-point work, gradient interpolation) runs for tets and
-prisms as one kernel per tile of elements with the reference and physical
+product, solution-point work, gradient interpolation) runs for tets, prisms
+and hexahedra as one kernel per tile of elements with the reference and physical
 gradients in LDS.  With FR_SEPARATE_GRADIENT it runs as three kernels that
 pass those gradients through memory.  Both walk the same operator fragments
 in the same order and share the point-wise arithmetic, so every result is
@@ -37,6 +37,9 @@ def _arrays(kind):
                                               y_bc="wall"), 0.03)
     if kind == "wallbox":
         return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2, y_bc="wall")
+    if kind == "hexbox":
+        # 5 x 5 x 5 jittered hexahedra
+        return inputs.hex_box(5, jitter=0.1, seed=2)
     if kind == "big":
         # 8 x 8 x (4 + 4): 512 prisms and 1,536 tets, many tiles of both types
         return inputs.small_mixed_box(nxy=8, n_pri_layers=4, n_tet_layers=4, jitter=0.1, seed=2)
@@ -82,7 +85,8 @@ def _run(M, O, U, dt):
 
 CASES = [("mixed", 1, "fp32"), ("mixed", 2, "fp32"), ("mixed", 3, "fp32"), ("mixed", 4, "fp32"),
          ("mixed", 2, "fp64"), ("mixed", 4, "fp64"), ("big", 4, "fp32"), ("hybrid", 3, "fp32"),
-         ("hybrid", 3, "fp64"), ("curvedwall", 3, "fp32"), ("wallbox", 2, "fp64")]
+         ("hybrid", 3, "fp64"), ("hybrid", 4, "fp32"), ("curvedwall", 3, "fp32"), ("wallbox", 2, "fp64"),
+         ("hexbox", 4, "fp32"), ("hexbox", 2, "fp64"), ("hexbox", 1, "fp32")]
 
 
 @pytest.mark.parametrize("kind,p,prec", CASES, ids=[f"{k}-p{p}-{q}" for k, p, q in CASES])
@@ -100,17 +104,16 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
             # the fused form, also where the default (chosen by the operator's
             # size before autotuning) would be the separate kernels
             for n in O.types:
-                if NAMES.index(n) < 2:
-                    M.set_gradient_form(NAMES.index(n), 1)
+                M.set_gradient_form(NAMES.index(n), 1)
         out.append(_run(M, O, U, 2e-3))
         M.close()
     (r0, i0, s0, p0), (r1, i1, s1, p1) = out
     ts = sorted(r0)
     rp = read_points(O)
-    # the fused kernel ran for the tets and prisms present, and only there
-    for t, n in ((0, "gradflux_tet"), (1, "gradflux_pri")):
+    # the fused kernel ran for the types present, and only there
+    for t in range(3):
+        n, g = "gradflux_" + NAMES[t], "grad_" + NAMES[t]
         assert p0[n][1] == (1 if t in ts else 0) and p1[n][1] == 0, (n, p0[n], p1[n])
-        g = ("grad_tet", "grad_pri")[t]
         assert p0[g][1] == 0 and p1[g][1] == (1 if t in ts else 0), (g, p0[g], p1[g])
     for t in ts:
         assert torch.equal(r0[t], r1[t]), ("rhs", NAMES[t])
@@ -120,25 +123,23 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
         # the gradient at flux points: the same bits where the common flux
         # reads it; the fused kernel (of a fresh mesh) leaves the other
         # points at their initial zero, the separate kernels write them
-        if t < 2:
-            mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
-            q0, q1 = i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]
-            assert torch.equal(torch.where(mask, q0, 0), torch.where(mask, q1, 0)), ("Qf read", NAMES[t])
-            assert not torch.where(mask, 0, q0).any(), ("Qf written off the read faces", NAMES[t])
-            assert torch.where(mask, 0, q1).any()
-            print(f"  {NAMES[t]}: gradient written at {float(mask.float().mean()):.3f} of the flux points", flush=True)
-        else:
-            assert torch.equal(i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]), ("intermediate", 2, NAMES[t])
+        mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
+        q0, q1 = i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]
+        assert torch.equal(torch.where(mask, q0, 0), torch.where(mask, q1, 0)), ("Qf read", NAMES[t])
+        assert not torch.where(mask, 0, q0).any(), ("Qf written off the read faces", NAMES[t])
+        assert torch.where(mask, 0, q1).any()
+        print(f"  {NAMES[t]}: gradient written at {float(mask.float().mean()):.3f} of the flux points", flush=True)
         assert torch.equal(s0[t], s1[t]), ("rk45 steps", NAMES[t])
     assert max(float(r0[t].abs().max()) for t in ts) > 1e-3
 
 
-@pytest.mark.parametrize("kind,p", [("mixed", 4), ("big", 4), ("mixed", 2), ("curvedwall", 3), ("hybrid", 1)])
+@pytest.mark.parametrize("kind,p", [("mixed", 4), ("big", 4), ("mixed", 2), ("curvedwall", 3), ("hybrid", 1),
+                                    ("hexbox", 3)])
 def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
-    """FP32: the autotuner's three forms of the gradient stage (separate
-    kernels, fused per tile, fused and streaming) give the same residual and
-    flux-point gradient, whichever it picks; forced through fr_set_blocking's
-    gradient-stage switch."""
+    """FP32: the autotuner's forms of the gradient stage (separate kernels,
+    fused per tile, fused and streaming for tets and prisms) give the same
+    residual and flux-point gradient, whichever it picks; forced through
+    fr_set_blocking's gradient-stage switch."""
     from paper_1409_0405_amd import frlib
     arrays = _arrays(kind)
     O = om.build_mesh(arrays, p)
@@ -150,11 +151,12 @@ def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
     for form in (0, 1, 2):
         M = frlib.Mesh(arrays, p, system="ns", precision="fp32", mu=0.02, **kw)
         for t in ts:
-            if t < 2:
-                M.set_gradient_form(t, form)
+            # the streaming form covers tets and prisms; hexahedra take the
+            # fused one there
+            M.set_gradient_form(t, min(form, 1) if t == 2 else form)
         r, inter, s, prof = _run(M, O, U, 2e-3)
         M.close()
-        n_fused = sum(prof[k][1] for k in ("gradflux_tet", "gradflux_pri"))
+        n_fused = sum(prof[k][1] for k in ("gradflux_tet", "gradflux_pri", "gradflux_hex"))
         assert (n_fused > 0) == (form > 0), (form, prof)
         outs.append((r, inter, s))
     for form in (1, 2):
