@@ -43,31 +43,32 @@ __device__ __forceinline__ int sload(const int32_t *p, int i) {
 
 // acc[n] += A_g B[:, 16 n .. 16 n + 15] for row block g of a step-list
 // operator (one row block per group), B in LDS: brow(kb) points at row
-// 4 kb + krow, column lane % 16 of B.  The list is walked in chunks of four
-// steps (lists are padded to a multiple of four): while the 4 NB matrix
-// instructions of one chunk issue, the operator fragments (memory) and the
-// B values (LDS) of the next chunk are already on their way, so a wave waits
-// for neither.  The K order is the list order, as in the step-list product
-// kernel.
-template <typename T, int NB, typename V4, typename RowFn>
+// 4 kb + krow, column lane % 16 of B.  The list is walked in chunks of CH
+// steps (lists are padded to a multiple of four; CH is 4 or 2): while the
+// CH NB matrix instructions of one chunk issue, the operator fragments
+// (memory) and the B values (LDS) of the next chunk are already on their
+// way, so a wave waits for neither.  The K order is the list order, as in
+// the step-list product kernel.
+template <typename T, int NB, int CH = 4, typename V4, typename RowFn>
 __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, RowFn brow, V4 (&acc)[NB]) {
+    static_assert(CH == 2 || CH == 4, "chunks of 2 or 4 steps");
     const int s0 = sload(A.koff, g), ns = sload(A.koff, g + 1) - s0;   // a multiple of 4, >= 4
     const int32_t *kl = A.klist + s0;
     const T *Af = A.frag + size_t(s0) * 64 + lane;
-    T a0[4], b0[4][NB];
+    T a0[CH], b0[CH][NB];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
+    for (int d = 0; d < CH; ++d) {
         a0[d] = Af[size_t(d) * 64];
         const T *br = brow(sload(kl, d));
 #pragma unroll
         for (int n = 0; n < NB; ++n) b0[d][n] = br[16 * n];
     }
-    for (int st = 0; st < ns; st += 4) {
+    for (int st = 0; st < ns; st += CH) {
         // the next chunk (the last chunk loads itself again: in bounds, unused)
-        const int nx = min(st + 4, ns - 4);
-        T a1[4], b1[4][NB];
+        const int nx = min(st + CH, ns - CH);
+        T a1[CH], b1[CH][NB];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 0; d < CH; ++d) {
             a1[d] = Af[size_t(nx + d) * 64];
             const T *br = brow(sload(kl, nx + d));
 #pragma unroll
@@ -76,12 +77,12 @@ __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, R
         // keep the scheduler from sinking the loads above next to their use
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
+        for (int d = 0; d < CH; ++d)
 #pragma unroll
             for (int n = 0; n < NB; ++n) acc[n] = mfma16(a0[d], b0[d][n], acc[n]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 0; d < CH; ++d) {
             a0[d] = a1[d];
 #pragma unroll
             for (int n = 0; n < NB; ++n) b0[d][n] = b1[d][n];
@@ -104,7 +105,7 @@ struct TileShape {
 // (two workgroups per CU) were measured 24 % slower: each operator fragment
 // then feeds 3 instead of 5 matrix instructions.
 template <typename T, int ET>
-constexpr int tile_elems() { return sizeof(T) == 4 ? 16 : 4; }
+constexpr int tile_elems() { return sizeof(T) == 4 ? (ET == 0 ? 32 : 16) : 4; }
 
 // One workgroup of NW wavefronts per tile.  MG: row blocks of the gradient
 // operator per wavefront (>= nmg / NW); their accumulators stay in registers
@@ -116,6 +117,7 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     constexpr int W5 = TileShape<NE>::W5, NB = TileShape<NE>::NB;
     constexpr int NG = n_geom_coeffs<ET>();
     constexpr int VPR = NE * int(sizeof(T)) / 16;       // 16-byte vectors per (row, field)
+    constexpr int CH = NB > 5 ? 2 : 4;                   // step-list chunk: B values in flight fit registers
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int Kp = 4 * a.G.Kb;
     const int nu = a.nu;
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
         for (int n = 0; n < NB; ++n) acc[m][n] = v4{0, 0, 0, 0};
         const int g = w + m * NW;
         if (g < a.G.nmg)
-            step_products<T, NB>(a.G, g, lane, [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; }, acc[m]);
+            step_products<T, NB, CH>(a.G, g, lane, [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; }, acc[m]);
     }
     __syncthreads();                                     // every wavefront is done with B
 #pragma unroll
@@ -249,11 +251,15 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     __syncthreads();
 
     // 4. Qf = M0 Q for each gradient direction j: work items (row block, j).
-    // Lane l stores element l % NE of the tile, only on the faces of it
-    // whose gradient is read (qm); the flux point and face of each
-    // accumulator row are loaded before the products, behind which their
-    // latency hides.
-    const unsigned qm = a.qmask ? unsigned(a.qmask[e0 + c16 % NE]) : 0xffu;
+    // Column block n of lane l is element (16 n + l) % NE of the tile, stored
+    // only on the faces of it whose gradient is read (qm); the flux point
+    // and face of each accumulator row are loaded before the products,
+    // behind which their latency hides.
+    // (column blocks n and n + NE / 16 hold the same element)
+    constexpr int NQ = NE >= 16 ? NE / 16 : 1;
+    unsigned qm[NQ];
+#pragma unroll
+    for (int n = 0; n < NQ; ++n) qm[n] = a.qmask ? unsigned(a.qmask[e0 + (16 * n + c16) % NE]) : 0xffu;
     for (int it = w; it < a.M.nmg * 3; it += NW) {
         const int g = it / 3, j = it - 3 * g;
         int frow[4];
@@ -269,15 +275,17 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc2[n] = v4{0, 0, 0, 0};
         // rows of B past K are clamped to a real row (times zero columns of A)
-        step_products<T, NB>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; }, acc2);
+        step_products<T, NB, CH>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; },
+                                 acc2);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = frow[r];
-            if (f < 0 || !(qm & fb[r])) continue;
+            if (f < 0) continue;
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 const int flat = 16 * n + c16, v = flat / NE, e = flat - v * NE;
-                if (v < 5 && e0 + e < a.nelem) a.Qf[(int64_t(f) * 15 + j * 5 + v) * ld + e0 + e] = acc2[n][r];
+                if (v < 5 && e0 + e < a.nelem && (qm[n % NQ] & fb[r]))
+                    a.Qf[(int64_t(f) * 15 + j * 5 + v) * ld + e0 + e] = acc2[n][r];
             }
         }
     }
