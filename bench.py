@@ -44,10 +44,12 @@ RIDGE = PEAK_FP32_MFMA / PEAK_HBM
 # variant not listed reports traffic null.
 TRAFFIC_SOURCE = "profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md"
 MEASURED_TRAFFIC = {
-    ('gradflux_tet', 0, 0): 1199.3e6,
-    ('gradflux_pri', 0, 0): 1436.4e6,
+    ('gradflux_tet', 0, 0): 1267.2e6,
+    ('gradflux_pri', 0, 0): 1339.7e6,
     ('interp_tet', 2, 1): 373.8e6,
     ('interp_pri', 2, 1): 398.8e6,
+    ('interp_pri', 1, 1): 398.5e6,
+    ('interp_tet', 4, 0): 373.8e6,
     ('div_tet', 1, 3): 995.2e6,
     ('div_tet', 1, 1): 1037.2e6,
     ('div_pri', 1, 6): 1262.8e6,

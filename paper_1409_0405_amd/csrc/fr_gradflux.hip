@@ -99,13 +99,15 @@ struct TileShape {
     static constexpr int NB = W5 / 16;
 };
 
-// Elements per tile: 16 in FP32 (column block n = field n), 4 in FP64 (whose
-// LDS footprint per value is twice as large).  FP32 hexahedra at p = 4 fill
-// 123 KB of LDS with it, one workgroup of 16 wavefronts per CU; tiles of 8
-// (two workgroups per CU) were measured 24 % slower: each operator fragment
-// then feeds 3 instead of 5 matrix instructions.
+// Elements per tile.  The wider the tile, the more matrix instructions each
+// operator fragment feeds (NE / 16 x 5 in FP32), which the measurements
+// favour over more workgroups per CU: FP32 tets and prisms take 32 (at
+// p = 4: 69 KB of LDS, two workgroups per CU for tets; 147 KB, one
+// workgroup of 16 wavefronts for prisms), hexahedra 16 (123 KB; 32 would not
+// fit, 8 was 24 % slower), FP64 4 (its LDS footprint per value is twice as
+// large).
 template <typename T, int ET>
-constexpr int tile_elems() { return sizeof(T) == 4 ? (ET == 0 ? 32 : 16) : 4; }
+constexpr int tile_elems() { return sizeof(T) == 4 ? (ET == 2 ? 16 : 32) : 4; }
 
 // One workgroup of NW wavefronts per tile.  MG: row blocks of the gradient
 // operator per wavefront (>= nmg / NW); their accumulators stay in registers
@@ -522,11 +524,11 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, b
     if constexpr (std::is_same<T, float>::value) {
         if (stream) return etype == 0 ? launch_gf_stream<0, 8>(a, lds, s) : launch_gf_stream<1, 8>(a, lds, s);
     }
-    // eight wavefronts per workgroup for tets and prisms in FP32, four in
-    // FP64; hexahedra (24 row blocks of the gradient operator at p = 4) take
-    // sixteen in FP32 and eight in FP64, two row blocks per wavefront
+    // wavefronts per workgroup: tets 8 in FP32 (7 row blocks of the
+    // gradient operator at p = 4), prisms 16 (15 row blocks), hexahedra 16
+    // (24: two per wavefront); FP64 4, 4 and 8
     if (etype == 0) return launch_gf<T, 0, tile_elems<T, 0>(), sizeof(T) == 4 ? 8 : 4>(a, lds, s);
-    if (etype == 1) return launch_gf<T, 1, tile_elems<T, 1>(), sizeof(T) == 4 ? 8 : 4>(a, lds, s);
+    if (etype == 1) return launch_gf<T, 1, tile_elems<T, 1>(), sizeof(T) == 4 ? 16 : 4>(a, lds, s);
     return launch_gf<T, 2, tile_elems<T, 2>(), sizeof(T) == 4 ? 16 : 8>(a, lds, s);
 }
 
