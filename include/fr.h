@@ -277,8 +277,8 @@ fr_status fr_reduce(fr_mesh mesh, int32_t what, double *out_host, void *stream);
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same items, arguments, kernels and results (bitwise), but the partial
  * sums and the results live in a device array of the library's own, one per
- * GPU, held until the process ends: 512 x 8 + 8 doubles (32.8 KB), enough for
- * any mesh (the reduction's grid is fixed).  The call allocates nothing.  The
+ * GPU, held until the process ends: 3 x (512 x 8 + 8) doubles (98.5 KB),
+ * enough for any mesh (the reduction's grid is fixed per element type).  The call allocates nothing.  The
  * array's address on the current device is looked up on its first use there.
  * Every call on one GPU shares that array: calls that overlap on one GPU
  * (other threads, other streams) race; calls on different GPUs do not.

@@ -662,10 +662,10 @@ fr_status setup_device(fr_mesh m, hipStream_t s) {
     }
     {
         void *q;
-        FR_HIP(m, hipMalloc(&q, frd::RED_BLOCKS * 8 * sizeof(double)));
+        FR_HIP(m, hipMalloc(&q, size_t(frh::NTYPE) * frd::RED_BLOCKS * 8 * sizeof(double)));
         d.allocs.push_back(q);
         d.partial = static_cast<double *>(q);
-        FR_HIP(m, hipMalloc(&q, 2 * 8 * sizeof(double)));
+        FR_HIP(m, hipMalloc(&q, size_t(frh::NTYPE) * 8 * sizeof(double)));
         d.allocs.push_back(q);
         d.red_out = static_cast<double *>(q);
     }
@@ -896,7 +896,9 @@ fr_status rhs_entry(fr_mesh m, const void *const u[FR_NTYPES], void *const r[FR_
 }
 
 // partial / red_out: device memory for the per-block partial sums
-// [RED_BLOCKS][8] and the 8 results (the mesh's own buffers when null).
+// [NTYPE][RED_BLOCKS][8] and the [NTYPE][8] results (the mesh's own buffers
+// when null).  Every type's sums go to their own slots, so one copy and one
+// synchronisation bring them all back; the host adds them type by type.
 template <typename T>
 fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s, double *partial = nullptr,
                       double *red_out = nullptr) {
@@ -916,14 +918,17 @@ fr_status reduce_impl(fr_mesh m, int what, double *out, hipStream_t s, double *p
     for (int t = 0; t < frh::NTYPE; ++t) {
         DevType<T> &D = d.t[t];
         if (!D.nelem) continue;
-        frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, partial};
+        double *pt = partial + size_t(t) * frd::RED_BLOCKS * 8;
+        frd::RedArgs<T> ra{D.reg[0], needR ? D.R : nullptr, D.wJ, D.ld, D.nelem, D.nu, what, pt};
         FR_HIP(m, frd::launch_reduce<T>(ra, s));
-        FR_HIP(m, frd::launch_reduce_final(partial, frd::RED_BLOCKS, red_out, s));
-        double h[8];
-        FR_HIP(m, hipMemcpyAsync(h, red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-        FR_HIP(m, hipStreamSynchronize(s));
-        for (int q = 0; q < 8; ++q) tot[q] += h[q];
+        FR_HIP(m, frd::launch_reduce_final(pt, frd::RED_BLOCKS, red_out + 8 * t, s));
     }
+    double h[frh::NTYPE * 8];
+    FR_HIP(m, hipMemcpyAsync(h, red_out, sizeof(h), hipMemcpyDeviceToHost, s));
+    FR_HIP(m, hipStreamSynchronize(s));
+    for (int t = 0; t < frh::NTYPE; ++t)
+        if (d.t[t].nelem)
+            for (int q = 0; q < 8; ++q) tot[q] += h[8 * t + q];
     if (what == 4) {
         tot[0] /= m->host.volume;
         tot[1] /= m->host.volume;
@@ -1056,17 +1061,19 @@ fr_status rk_adaptive_impl(fr_mesh m, double t_end, double state[3], double atol
         for (int ty = 0; ty < frh::NTYPE; ++ty) {
             DevType<T> &D = d.t[ty];
             if (!D.nelem) continue;
-            frd::RedArgs<T> ra{D.reg[0], D.ereg, D.wJ, D.ld, D.nelem, D.nu, 6, d.partial};
+            double *pt = d.partial + size_t(ty) * frd::RED_BLOCKS * 8;
+            frd::RedArgs<T> ra{D.reg[0], D.ereg, D.wJ, D.ld, D.nelem, D.nu, 6, pt};
             ra.U0 = D.reg[2];
             ra.atol = atol;
             ra.rtol = rtol;
             FR_HIP(m, frd::launch_reduce<T>(ra, s));
-            FR_HIP(m, frd::launch_reduce_final(d.partial, frd::RED_BLOCKS, d.red_out, s));
-            double hsum[8];
-            FR_HIP(m, hipMemcpyAsync(hsum, d.red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-            FR_HIP(m, hipStreamSynchronize(s));
-            sum += hsum[0];
+            FR_HIP(m, frd::launch_reduce_final(pt, frd::RED_BLOCKS, d.red_out + 8 * ty, s));
         }
+        double hsum[frh::NTYPE * 8];
+        FR_HIP(m, hipMemcpyAsync(hsum, d.red_out, sizeof(hsum), hipMemcpyDeviceToHost, s));
+        FR_HIP(m, hipStreamSynchronize(s));
+        for (int ty = 0; ty < frh::NTYPE; ++ty)
+            if (d.t[ty].nelem) sum += hsum[8 * ty];
         const double err = std::sqrt(sum / double(ndof));
         if (!std::isfinite(err)) {
             for (int ty = 0; ty < frh::NTYPE; ++ty)
@@ -1556,13 +1563,13 @@ fr_status fr_rk45_adaptive(fr_mesh m, double t_end, double state[3], double atol
 namespace {
 
 // Device memory of fr_reduce_noalloc: the per-block partial sums of the
-// reduction ([RED_BLOCKS][8] doubles) and its 8 results.  The reduction's
-// grid is fixed (RED_BLOCKS blocks striding over the mesh), so this array is
-// large enough for every mesh.  Each GPU the library runs on holds its own
+// reduction ([NTYPE][RED_BLOCKS][8] doubles) and its [NTYPE][8] results.  The
+// reduction's grid is fixed (RED_BLOCKS blocks striding over each type's
+// elements), so this array is large enough for every mesh.  Each GPU the library runs on holds its own
 // copy until the process ends; in host code the name stands for no device
 // address, so the address is looked up once per device (hipGetSymbolAddress)
 // and only that pointer is passed to kernels and copies.
-constexpr size_t NOALLOC_DOUBLES = size_t(frd::RED_BLOCKS) * 8 + 8;
+constexpr size_t NOALLOC_DOUBLES = size_t(frh::NTYPE) * (size_t(frd::RED_BLOCKS) * 8 + 8);
 static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 constexpr int NOALLOC_MAX_DEVICES = 64;
@@ -1600,7 +1607,7 @@ fr_status fr_reduce_noalloc(fr_mesh m, int32_t what, double *out, void *stream) 
     double *ptr = scratch_of_current_device(&e);
     if (!ptr) return fail(m, FR_ERR_DEVICE, std::string("device scratch of fr_reduce_noalloc: ") + hipGetErrorString(e));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double *partial = ptr, *res = ptr + size_t(frd::RED_BLOCKS) * 8;
+    double *partial = ptr, *res = ptr + size_t(frh::NTYPE) * frd::RED_BLOCKS * 8;
     return m->precision != FR_FP64 ? reduce_impl<float>(m, what, out, s, partial, res)
                                    : reduce_impl<double>(m, what, out, s, partial, res);
 }
