@@ -37,6 +37,9 @@ def _arrays(kind):
                                               y_bc="wall"), 0.03)
     if kind == "wallbox":
         return inputs.hybrid_box(6, 4, 6, 3, 3, (2 * math.pi,) * 3, jitter=0.1, seed=2, y_bc="wall")
+    if kind == "tiny":
+        # 2 x 2 x (1 + 1): 8 prisms and 24 tets, fewer than one tile of each
+        return inputs.small_mixed_box(nxy=2, n_pri_layers=1, n_tet_layers=1, jitter=0.1, seed=2)
     if kind == "hexbox":
         # 5 x 5 x 5 jittered hexahedra
         return inputs.hex_box(5, jitter=0.1, seed=2)
@@ -86,7 +89,8 @@ def _run(M, O, U, dt):
 CASES = [("mixed", 1, "fp32"), ("mixed", 2, "fp32"), ("mixed", 3, "fp32"), ("mixed", 4, "fp32"),
          ("mixed", 2, "fp64"), ("mixed", 4, "fp64"), ("big", 4, "fp32"), ("hybrid", 3, "fp32"),
          ("hybrid", 3, "fp64"), ("hybrid", 4, "fp32"), ("curvedwall", 3, "fp32"), ("wallbox", 2, "fp64"),
-         ("hexbox", 4, "fp32"), ("hexbox", 2, "fp64"), ("hexbox", 1, "fp32")]
+         ("hexbox", 4, "fp32"), ("hexbox", 2, "fp64"), ("hexbox", 1, "fp32"), ("tiny", 4, "fp32"),
+         ("tiny", 3, "fp64")]
 
 
 @pytest.mark.parametrize("kind,p,prec", CASES, ids=[f"{k}-p{p}-{q}" for k, p, q in CASES])
