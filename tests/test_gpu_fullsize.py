@@ -145,8 +145,10 @@ def _full_state(M, frlib, seed, mach=MACH, noise=0.01):
 
 
 @pytest.mark.parametrize("workload,prec,mach,noise", [("mixed", "fp32", MACH, 0.01), ("mixed", "fp64", MACH, 0.01),
-                                                     ("hex", "fp32", MACH, 0.01), ("mixed", "fp32", 0.1, 0.0)],
-                         ids=["mixed-fp32", "mixed-fp64", "hex-fp32", "mixed-fp32-headline-state"])
+                                                     ("hex", "fp32", MACH, 0.01), ("mixed", "fp32", 0.1, 0.0),
+                                                     ("hybrid", "fp32", MACH, 0.01), ("hybrid", "fp64", MACH, 0.01)],
+                         ids=["mixed-fp32", "mixed-fp64", "hex-fp32", "mixed-fp32-headline-state", "hybrid-fp32",
+                              "hybrid-fp64"])
 def test_full_size_sampled_elements_match_oracle(workload, prec, mach, noise):
     """FP32 is held to the bound of single-precision rounding of the summed
     flux terms (16 unit roundoffs times the case's cancellation factor; 32
@@ -156,7 +158,12 @@ def test_full_size_sampled_elements_match_oracle(workload, prec, mach, noise):
     0.36 relative in density and energy, 7e-3 in momentum, which is ~17
     unit roundoffs of those terms."""
     from paper_1409_0405_amd import frlib
-    arrays = inputs.tgv_mixed_box() if workload == "mixed" else inputs.hex_box(50, jitter=0.10, seed=0)
+    L = 2 * math.pi
+    arrays = {"mixed": lambda: inputs.tgv_mixed_box(),
+              "hex": lambda: inputs.hex_box(50, jitter=0.10, seed=0),
+              # the 48^3-cell three-type box: 27,648 hexahedra, 110,592 prisms
+              # of two orientations, 165,888 tets
+              "hybrid": lambda: inputs.hybrid_box(48, 48, 48, 24, 24, (L, L, L), jitter=0.10, seed=0)}[workload]()
     print(f"full size {workload} {prec} Ma {mach} noise {noise}: building", flush=True)
     M = frlib.Mesh(arrays, 4, system="ns", precision=prec, mu=MU, prandtl=PR, p_ref=1.0 / (1.4 * mach * mach))
     if prec == "fp32":
@@ -175,7 +182,7 @@ def test_full_size_sampled_elements_match_oracle(workload, prec, mach, noise):
     counts = [len(arrays.get(f"{nm}_v", [])) for nm in NAMES]
     starts = np.cumsum([0] + counts)
     types = [t for t in range(3) if counts[t]]
-    sample = _interior_sample(arrays, nb, 6 if workload == "mixed" else 8, 3, types)
+    sample = _interior_sample(arrays, nb, {"mixed": 6, "hex": 8, "hybrid": 4}[workload], 3, types)
     prm = fr.Params(system="ns", mu=MU, prandtl=PR)
     num = np.zeros(5)
     den = np.zeros(5)
