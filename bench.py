@@ -373,6 +373,72 @@ def measured_peaks():
     return out
 
 
+def closure_at_size(stream, t_end=8.0, n_int=20, epochs=30, cfl=0.3, log=None):
+    """The learned closure judged a-posteriori at the headline's full size
+    (110,592 prisms + 196,608 tets, Taylor-Green, Re 1600, Ma 0.1): order 4
+    and order 1 advanced side by side to t_end from the Taylor-Green state
+    and its L2 projection, training pairs taken along the order-1 trajectory
+    at n_int + 1 snapshots (inputs from U_1(t), targets from the filtered
+    order-4 residual), the network trained on all of them, then order 1 run
+    again from the projection with and without the closure (BF16 weights).
+    Reported: the relative L2 over the snapshots of each run's kinetic-energy
+    dissipation rate against order 4's."""
+    import numpy as np
+    import torch
+    from paper_1409_0405_amd import closure as cl, frlib, inputs
+    t_start = time.time()
+    arrays = inputs.tgv_mixed_box()
+    kw = dict(system="ns", precision="fp32", mu=1.0 / 1600.0, prandtl=0.71, stream=stream, check_finite=True)
+    hi = frlib.Mesh(arrays, 4, **kw)
+    lo = frlib.Mesh(arrays, 1, **kw)
+    hi.autotune(stream)
+    lo.autotune(stream)
+    nel = {"tet": hi.query(0)["nelem"], "pri": hi.query(1)["nelem"]}
+    h_ref = math.pi / 54                           # the prism layers' spacing
+    dt4, dt1 = cl.dt_for(4, h_ref, cfl=cfl), cl.dt_for(1, h_ref, cfl=cfl)
+    sb4, sb1 = max(1, round(t_end / n_int / dt4)), max(1, round(t_end / n_int / dt1))
+    dt4, dt1 = t_end / n_int / sb4, t_end / n_int / sb1
+    if log:
+        log(f"closure at size: order 4 dt {dt4:.3e} x {sb4}, order 1 dt {dt1:.3e} x {sb1} per interval")
+    cl.load_tgv(hi, stream=stream)
+    cl.load_filtered(hi, lo, stream=stream)
+    X, Y, times, rates4, _ = cl.generate_along_trajectory(hi, lo, dt4, sb4, dt1, sb1, n_int + 1, stream, log=log)
+    nsamp = len(X)
+    stats = cl.stats_of(X, Y)
+    net, hist = cl.train(X, Y, stats, epochs=epochs, batch=8192, lr=2e-3, log=log)
+    del X, Y
+    torch.cuda.empty_cache()
+
+    def run(with_net):
+        cl.load_tgv(hi, stream=stream)
+        cl.load_filtered(hi, lo, stream=stream)
+        if with_net:
+            lo.closure_attach(net, stats.data_ptr(), bf16_weights=True)
+        try:
+            return cl.dissipation_history(lo, dt1, n_int + 1, sb1, stream, log=log)
+        except frlib.FrError as err:            # FR_CHECK_FINITE: the run went non-finite
+            if log:
+                log(f"order-1 run stopped: {err}")
+            return None
+        finally:
+            lo.closure_attach(None)
+    plain, corr = run(False), run(True)
+    e = lambda r: None if r is None else float(np.sqrt(np.mean((r - rates4) ** 2) / np.mean(rates4 ** 2)))
+    out = {"experiment": "closure_at_size", "elements": nel, "t_end": t_end, "snapshots": n_int + 1,
+           "samples": int(nsamp), "epochs": epochs, "cfl": cfl,
+           "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+           "times": [float(x) for x in times],
+           "order4_rates": [float(x) for x in rates4],
+           "order1_rates": None if plain is None else [float(x) for x in plain],
+           "closure_rates": None if corr is None else [float(x) for x in corr],
+           "aposteriori_rel_err_vs_order4": {"plain_order1": e(plain), "closure_bf16": e(corr)},
+           "finite": {"plain_order1": plain is not None, "closure_bf16": corr is not None},
+           "seconds": time.time() - t_start}
+    hi.close()
+    lo.close()
+    return out
+
+
 def closure_form(steps, warmup, arrays, mach, mu, pr, stream):
     """Cost of the learned closure in the order-1 residual on the full mixed
     mesh: RK45[2R+] steps of the order-1 NS solve without and with the network
@@ -639,6 +705,8 @@ def main():
     ap.add_argument("--no-hex", action="store_true", help="skip the hexahedral and three-type workloads")
     ap.add_argument("--workload", choices=("mixed", "hex", "hybrid", "curved_wall"), default="mixed",
                     help="hex / hybrid / curved_wall: run only that workload's form (for profiling) and print it")
+    ap.add_argument("--closure-at-size", action="store_true",
+                    help="train and judge the learned closure on the full headline mesh (about 15 minutes)")
     ap.add_argument("--variants", action="store_true",
                     help="time every variant of the prism corrected-gradient and gradient-"
                          "interpolation products on this workload (one JSON line) instead of the bench")
@@ -687,6 +755,10 @@ def main():
     if args.workload != "mixed":
         form = {"hex": hex_form, "hybrid": hybrid_form, "curved_wall": curved_wall_form}[args.workload]
         print(json.dumps({"form": args.workload, **form()}), flush=True)
+        return
+    if args.closure_at_size:
+        print(json.dumps(closure_at_size(stream, log=lambda msg: print(msg, file=sys.stderr, flush=True))),
+              flush=True)
         return
     arrays = inputs.tgv_mixed_box()
 

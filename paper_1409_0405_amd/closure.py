@@ -92,7 +92,7 @@ def generate(hi, lo, dt, n_snap, steps_between, stream=0):
     return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates), states
 
 
-def generate_along_trajectory(hi, lo, dt_hi, steps_hi, dt_lo, steps_lo, n_snap, stream=0):
+def generate_along_trajectory(hi, lo, dt_hi, steps_hi, dt_lo, steps_lo, n_snap, stream=0, log=None):
     """Like generate(), but the inputs and the order-1 residual come from the
     order-1 solution itself, advanced beside the order-q run from the
     filtered initial state (both meshes hold their initial states): targets
@@ -123,6 +123,8 @@ def generate_along_trajectory(hi, lo, dt_hi, steps_hi, dt_lo, steps_lo, n_snap, 
         times.append(t_now)
         rates.append(-hi.reduce(frlib.FR_RED_KE, stream)[1])
         states.append([x.clone() for x in u1])
+        if log:
+            log(f"snapshot {k + 1}/{n_snap}: t = {t_now:.3f}, order-{hi.order} dissipation rate {rates[-1]:.4e}")
     return X.reshape(-1, 120), Y.reshape(-1, 20), np.array(times), np.array(rates), states
 
 
@@ -181,13 +183,15 @@ def train(X, Y, stats, epochs=20, batch=8192, lr=2e-3, seed=0, log=None):
     return net, hist
 
 
-def dissipation_history(mesh, dt, n_snap, steps_between, stream=0):
+def dissipation_history(mesh, dt, n_snap, steps_between, stream=0, log=None):
     """-dE_k/dt of the mesh's current solution at n_snap times."""
     out = []
     for k in range(n_snap):
         if k:
             mesh.rk_step(frlib.FR_RK45_2RP, dt, steps_between, stream)
         out.append(-mesh.reduce(frlib.FR_RED_KE, stream)[1])
+        if log:
+            log(f"snapshot {k + 1}/{n_snap}: dissipation rate {out[-1]:.4e}")
     return np.array(out)
 
 
