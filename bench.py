@@ -50,6 +50,7 @@ MEASURED_TRAFFIC = {
     ('interp_pri', 2, 1): 398.8e6,
     ('interp_pri', 1, 1): 398.5e6,
     ('interp_tet', 4, 0): 373.8e6,
+    ('interp_tet', 2, 0): 373.7e6,
     ('div_tet', 1, 3): 995.2e6,
     ('div_tet', 1, 1): 1037.2e6,
     ('div_pri', 1, 6): 1262.8e6,
@@ -906,6 +907,7 @@ def main():
     f_nnz = sum(v.get("nnz_flops", 0.0) for v in prods.values())
     print(f"fr_rhs median {rhs_med:.3f} ms", file=sys.stderr, flush=True)
     roof = None
+    rhs_traffic = None
     if not args.no_profile:
         nprof = max(3, min(args.steps, 10))
         load(mesh)
@@ -923,6 +925,12 @@ def main():
             print(f"  {k:16s} {ms / nprof:8.3f} ms/step {100 * ms / tot:5.1f}%  avg {avg * 1e6:8.1f} us"
                   f"  {mdl['flops'] / avg / 1e12:7.1f} TFLOP/s dense  {mdl.get('nnz_flops', 0) / avg / 1e12:6.1f}"
                   f" structural  {mdl['bytes'] / avg / 1e9:7.0f} GB/s", file=sys.stderr, flush=True)
+        # the HBM bytes one RHS moves, from the measured per-launch traffic of
+        # each kernel variant the timed steps ran (null if one is not in the
+        # table)
+        per_rhs = [MEASURED_TRAFFIC.get((kk,) + (variant_of(mesh, kk, tuned.get("fp32", "")) or (0, 0)))
+                   for _, kk, cc in rows]
+        rhs_traffic = float(sum(per_rhs)) if all(x is not None for x in per_rhs) else None
         ms, k, cnt = rows[0]
         avg = ms / cnt * 1e-3
         vt = variant_of(mesh, k, tuned.get("fp32", ""))
@@ -1038,6 +1046,12 @@ def main():
     t_rhs = ms_per_step / 5 * 1e-3
     hbm = {"algorithmic_bytes_per_rhs": b_alg, "achieved_GBps": b_alg / t_rhs / 1e9,
            "frac_of_8TBps": b_alg / t_rhs / PEAK_HBM}
+    if rhs_traffic:
+        # the bytes the kernels actually move (rocprofv3 counters, per launch)
+        hbm["measured_traffic_per_rhs"] = rhs_traffic
+        hbm["measured_traffic_GBps"] = rhs_traffic / t_rhs / 1e9
+        hbm["measured_traffic_frac_of_8TBps"] = rhs_traffic / t_rhs / PEAK_HBM
+        hbm["traffic_source"] = TRAFFIC_SOURCE
     # whole right-hand side against both roofs: T_roof = max(B_alg / 8 TB/s,
     # F_alg / 157.3 TFLOP/s) with F_alg the dense operator products, over the
     # measured time of one RHS (RK45 step / 5, and the back-to-back fr_rhs median)
