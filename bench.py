@@ -611,11 +611,11 @@ def walks_nonzeros(k, variant):
 
 
 def workload_form(name, arrays, h_ref, steps, warmup, mach, mu, pr, stream, cfl=0.3, p=4, **mesh_kw):
-    mesh_kw.setdefault("p_ref", 1.0 / (1.4 * mach * mach))
     """Another mesh of the same physics (NS Taylor-Green, p = 4, FP32,
     autotuned): RK45[2R+] steps timed like the main workload, then a
     per-kernel profile and the dominant kernel's roofline.  mesh_kw: boundary
     data (t_wall, farfield) of bounded meshes."""
+    mesh_kw.setdefault("p_ref", 1.0 / (1.4 * mach * mach))
     import numpy as np
     import torch
     from paper_1409_0405_amd import frlib, inputs
