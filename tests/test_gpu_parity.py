@@ -316,10 +316,11 @@ def _vortex_dt(n, p):
     return 0.2 * (1.0 / n) / (lam * (2 * p + 1))
 
 
-@pytest.mark.parametrize("scheme", ["rk4", "rk45"])
+@pytest.mark.parametrize("scheme", ["rk4", "rk45", "euler"])
 def test_rk_steps_fp64_vortex(scheme):
     """The small Euler workload: 1,296 jittered tets, p = 2, isentropic vortex,
-    10 steps at CFL 0.2 (RK4 as stated for it, and RK45[2R+])."""
+    10 steps at CFL 0.2 (RK4 as stated for it, RK45[2R+], and forward Euler,
+    the test stepper)."""
     frlib = _lib()
     print(f"rk {scheme}", flush=True)
     arrays = inputs.vortex_tet_cube(n=6, jitter=0.05, seed=0)
@@ -328,12 +329,12 @@ def test_rk_steps_fp64_vortex(scheme):
     O = om.build_mesh(arrays, p)
     prm = fr.Params(system="euler")
     U0 = fr.initial_state(O, inputs.isentropic_vortex)
-    stepper = rk.rk4_step if scheme == "rk4" else rk.rk45_step
+    stepper = {"rk4": rk.rk4_step, "rk45": rk.rk45_step, "euler": rk.euler_step}[scheme]
     Uo = rk.run(stepper, lambda V: fr.rhs(O, V, prm), U0, dt, nsteps)
     M = frlib.Mesh(arrays, p, system="euler", precision="fp64", check_finite=True)
     u = frlib.to_device_state(M, 0, np.transpose(U0["tet"], (1, 2, 0)))
     M.set_solution(0, u.data_ptr())
-    M.rk_step(frlib.FR_RK4 if scheme == "rk4" else frlib.FR_RK45_2RP, dt, nsteps)
+    M.rk_step({"rk4": frlib.FR_RK4, "rk45": frlib.FR_RK45_2RP, "euler": frlib.FR_FWD_EULER}[scheme], dt, nsteps)
     out = frlib.state_tensor(M, 0)
     M.get_solution(0, out.data_ptr())
     torch.cuda.synchronize()
