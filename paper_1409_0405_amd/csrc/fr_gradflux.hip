@@ -41,6 +41,15 @@ __device__ __forceinline__ int sload(const int32_t *p, int i) {
     return ((const __attribute__((address_space(4))) int32_t *)p)[i];
 }
 
+// 16 (4) bytes from memory straight into LDS (global_load_lds): lane l of
+// the wavefront writes dst + 16 l (dst + 4 l), dst uniform in the wavefront.
+__device__ __forceinline__ void load_lds16(const void *src, void *dst) {
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+__device__ __forceinline__ void load_lds4(const void *src, void *dst) {
+    __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+}
+
 // acc[n] += A_g B[:, 16 n .. 16 n + 15] for row block g of a step-list
 // operator (one row block per group), B in LDS: brow(kb) points at row
 // 4 kb + krow, column lane % 16 of B.  The list is walked in chunks of CH
@@ -138,10 +147,39 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int krow = lane >> 4, c16 = lane & 15;
     const int64_t ld = a.ld;
-    for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
 
     // 1. B rows: U (k < nu), Cf (nu <= k < nu + nf), zero up to Kp
-    {
+    if constexpr (sizeof(T) == 4 && W5 == 5 * NE) {
+        // straight from memory into LDS (global_load_lds: no registers, and
+        // every load of the tile in flight before the one wait): chunk c
+        // (16 bytes) of B is row k, field v, elements 4 q .. 4 q + 3 with
+        // c = VPR (5 k + v) + q, and lane l of a wavefront instruction
+        // writes chunk base + l; the coefficients likewise, the reference
+        // coordinates value by value
+        const int nchunk = (nu + a.nf) * 5 * VPR;
+        for (int base = w * 64; base < nchunk; base += NW * 64) {
+            const int c = base + lane;
+            if (c < nchunk) {
+                const int q = c % VPR, kv = c / VPR, v = kv % 5, k = kv / 5;
+                const T *src = k < nu ? a.U + (int64_t(k) * 5 + v) * ld + e0 + 4 * q
+                                      : a.Cf + (int64_t(k - nu) * 5 + v) * ld + e0 + 4 * q;
+                load_lds16(src, Bs + size_t(base) * 4);
+            }
+        }
+        if (!a.padj)
+            for (int base = w * 64; base < NG * VPR; base += NW * 64) {
+                const int c = base + lane;
+                if (c < NG * VPR)
+                    load_lds16(a.geom + int64_t(c / VPR) * ld + e0 + 4 * (c % VPR), Gs + size_t(base) * 4);
+            }
+        for (int base = w * 64; base < 3 * nu; base += NW * 64) {
+            const int c = base + lane;
+            if (c < 3 * nu) load_lds4(a.xi + c, Xs + base);
+        }
+        for (int idx = (nu + a.nf) * W5 + tid; idx < Kp * W5; idx += 64 * NW) Bs[idx] = T(0);
+        __builtin_amdgcn_s_waitcnt(0);                   // this wavefront's direct loads are in LDS
+    } else {
+        for (int idx = tid; idx < 3 * nu; idx += 64 * NW) Xs[idx] = a.xi[idx];
         const int nvec = Kp * 5 * VPR;
         for (int idx = tid; idx < nvec; idx += 64 * NW) {
             const int q = idx % VPR, kv = idx / VPR;
