@@ -264,11 +264,19 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
             if (it >= nu * NE || eg >= a.nelem) continue;
             T adj[3][3], Jinv;
             if (a.padj) {
+                // (the metric is waited for inside this branch: left in
+                // flight, it would make the straight elements wait at the
+                // join, and with it for the previous point's Ft stores)
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
                     for (int j = 0; j < 3; ++j) adj[k][j] = a.padj[(int64_t(3 * k + j) * nu + i) * ld + eg];
                 Jinv = a.pjinv[int64_t(i) * ld + eg];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) adj[k][j] = opaque(adj[k][j]);
+                Jinv = opaque(Jinv);
             } else {
                 Jinv = T(1) / metric<T, ET>(Gs, NE, e, Xs + 3 * i, adj);
             }
