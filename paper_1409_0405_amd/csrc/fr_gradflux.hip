@@ -99,6 +99,49 @@ __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, R
     }
 }
 
+// acc[j][i] += A_g Q_j[:, column block NH i + h] for row block g of a
+// step-list operator and all three gradient directions j: one operator
+// fragment feeds 3 NBI matrix instructions.  q points at row 0, column
+// 16 h + lane % 16 of Q_0 in LDS, Q_j is jstride values further on; rows
+// past the last solution point are clamped to it (times zero columns of A).
+// The fragments (memory) travel 4 steps ahead of their use, the Q values
+// (LDS) one step; the K order is the list order, as in step_products.
+template <typename T, int NBI, int NH, int W5, typename V4>
+__device__ __forceinline__ void interp3_products(const Op<T> &A, int g, int lane, int krow, const T *q,
+                                                 int jstride, int nu, V4 (&acc)[3][NBI]) {
+    const int s0 = sload(A.koff, g), ns = sload(A.koff, g + 1) - s0;   // a multiple of 4, >= 4
+    const int32_t *kl = A.klist + s0;
+    const T *Af = A.frag + size_t(s0) * 64 + lane;
+    auto qload = [&](int s, T (&b)[3][NBI]) {
+        const T *br = q + min(4 * sload(kl, s) + krow, nu - 1) * W5;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < NBI; ++i) b[j][i] = br[j * jstride + 16 * NH * i];
+    };
+    T a[4], b0[3][NBI], b1[3][NBI];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) a[d] = Af[size_t(d) * 64];
+    qload(0, b0);
+    for (int st = 0; st < ns; st += 4) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            qload(min(st + d + 1, ns - 1), b1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int i = 0; i < NBI; ++i) acc[j][i] = mfma16(a[d], b0[j][i], acc[j][i]);
+            __builtin_amdgcn_sched_barrier(0);
+            a[d] = Af[size_t(min(st + d + 4, ns - 1)) * 64];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int i = 0; i < NBI; ++i) b0[j][i] = b1[j][i];
+        }
+    }
+}
+
 // Tile of NE elements with all five fields: row r of a tile in LDS holds W5
 // columns, (field v, element e) at v NE + e and zeros up to W5; column block
 // n of the matrix instructions is columns 16 n .. 16 n + 15.
@@ -308,6 +351,45 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     unsigned qm[NQ];
 #pragma unroll
     for (int n = 0; n < NQ; ++n) qm[n] = a.qmask ? unsigned(a.qmask[e0 + (16 * n + c16) % NE]) : 0xffu;
+    if constexpr (sizeof(T) == 4) {
+        // work items (row block, column half): the three directions together,
+        // so each operator fragment is loaded once for 15 matrix
+        // instructions and every wavefront takes at most one item at p = 4
+        constexpr int NH = NB % 5 == 0 ? NB / 5 : 1, NBI = NB / NH;
+        for (int it = w; it < a.M.nmg * NH; it += NW) {
+            const int g = it / NH, h = it - NH * g;
+            int frow[4];
+            unsigned fb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int slot = 16 * g + acc_row<T>(krow, r);
+                frow[r] = a.M.rowmap[slot];
+                fb[r] = a.qmask ? unsigned(a.fbit[slot]) : 1u;
+            }
+            v4 acc3[3][NBI];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int i = 0; i < NBI; ++i) acc3[j][i] = v4{0, 0, 0, 0};
+            interp3_products<T, NBI, NH, W5>(a.M, g, lane, krow, QT + 16 * h + c16, nu * W5, nu, acc3);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = frow[r];
+                if (f < 0) continue;
+#pragma unroll
+                for (int i = 0; i < NBI; ++i) {
+                    const int n = NH * i + h;
+                    const int flat = 16 * n + c16, v = flat / NE, e = flat - v * NE;
+                    if (v < 5 && e0 + e < a.nelem && (qm[n % NQ] & fb[r])) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            a.Qf[(int64_t(f) * 15 + j * 5 + v) * ld + e0 + e] = acc3[j][i][r];
+                    }
+                }
+            }
+        }
+        return;
+    }
     for (int it = w; it < a.M.nmg * 3; it += NW) {
         const int g = it / 3, j = it - 3 * g;
         int frow[4];
