@@ -99,6 +99,39 @@ __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, R
     }
 }
 
+// acc[n] += A_g B[:, 16 n .. 16 n + 15] like step_products, with the
+// operator fragments (memory) 4 steps ahead of their use and the B values
+// (LDS) one step ahead.
+template <typename T, int NB, typename V4, typename RowFn>
+__device__ __forceinline__ void step_products_deep(const Op<T> &A, int g, int lane, RowFn brow, V4 (&acc)[NB]) {
+    const int s0 = sload(A.koff, g), ns = sload(A.koff, g + 1) - s0;   // a multiple of 4, >= 4
+    const int32_t *kl = A.klist + s0;
+    const T *Af = A.frag + size_t(s0) * 64 + lane;
+    T a[4], b0[NB], b1[NB];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) a[d] = Af[size_t(d) * 64];
+    {
+        const T *br = brow(sload(kl, 0));
+#pragma unroll
+        for (int n = 0; n < NB; ++n) b0[n] = br[16 * n];
+    }
+    for (int st = 0; st < ns; st += 4) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const T *br = brow(sload(kl, min(st + d + 1, ns - 1)));
+#pragma unroll
+            for (int n = 0; n < NB; ++n) b1[n] = br[16 * n];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[n] = mfma16(a[d], b0[n], acc[n]);
+            __builtin_amdgcn_sched_barrier(0);
+            a[d] = Af[size_t(min(st + d + 4, ns - 1)) * 64];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) b0[n] = b1[n];
+        }
+    }
+}
+
 // acc[j][i] += A_g Q_j[:, column block NH i + h] for row block g of a
 // step-list operator and all three gradient directions j: one operator
 // fragment feeds 3 NBI matrix instructions.  q points at row 0, column
@@ -264,8 +297,13 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc[m][n] = v4{0, 0, 0, 0};
         const int g = w + m * NW;
-        if (g < a.G.nmg)
-            step_products<T, NB, CH>(a.G, g, lane, [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; }, acc[m]);
+        if (g < a.G.nmg) {
+            auto brow = [&](int kb) { return Bs + (4 * kb + krow) * W5 + c16; };
+            if constexpr (sizeof(T) == 4)
+                step_products_deep<T, NB>(a.G, g, lane, brow, acc[m]);
+            else
+                step_products<T, NB, CH>(a.G, g, lane, brow, acc[m]);
+        }
     }
     __syncthreads();                                     // every wavefront is done with B
 #pragma unroll
