@@ -389,11 +389,14 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     unsigned qm[NQ];
 #pragma unroll
     for (int n = 0; n < NQ; ++n) qm[n] = a.qmask ? unsigned(a.qmask[e0 + (16 * n + c16) % NE]) : 0xffu;
-    if constexpr (sizeof(T) == 4) {
-        // work items (row block, column half): the three directions together,
-        // so each operator fragment is loaded once for 15 matrix
-        // instructions and every wavefront takes at most one item at p = 4
-        constexpr int NH = NB % 5 == 0 ? NB / 5 : 1, NBI = NB / NH;
+    if constexpr (sizeof(T) == 4 && NB == 10) {
+        // tiles of 32 (tets, prisms): work items (row block, column half)
+        // with the three directions together, so each operator fragment is
+        // loaded once for 15 matrix instructions and every wavefront takes
+        // at most one item at p = 4.  (Hexahedra, tiles of 16, keep the
+        // items per direction below: with one item per row block, 10 items
+        // would leave 6 of the 16 wavefronts idle.)
+        constexpr int NH = 2, NBI = 5;
         for (int it = w; it < a.M.nmg * NH; it += NW) {
             const int g = it / NH, h = it - NH * g;
             int frow[4];
