@@ -99,6 +99,17 @@ __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, R
     }
 }
 
+// Steps of a list that carry operator entries: the list is padded to a
+// multiple of 4 by repeating its last step with zero fragments.  The deep
+// walkers below stop there; an accumulator that starts at +0 is never -0
+// (a sum of opposite zeros rounds to +0), so the products they leave out
+// (exact zeros) would not have changed any bit of it.
+__device__ __forceinline__ int real_steps(const int32_t *kl, int ns) {
+    int n = ns;
+    while (n > 1 && sload(kl, n - 1) == sload(kl, n - 2)) --n;
+    return n;
+}
+
 // acc[n] += A_g B[:, 16 n .. 16 n + 15] like step_products, with the
 // operator fragments (memory) 4 steps ahead of their use and the B values
 // (LDS) one step ahead.
@@ -115,9 +126,11 @@ __device__ __forceinline__ void step_products_deep(const Op<T> &A, int g, int la
 #pragma unroll
         for (int n = 0; n < NB; ++n) b0[n] = br[16 * n];
     }
-    for (int st = 0; st < ns; st += 4) {
+    const int nr = real_steps(kl, ns);
+    for (int st = 0; st < nr; st += 4) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
+            if (st + d >= nr) break;
             const T *br = brow(sload(kl, min(st + d + 1, ns - 1)));
 #pragma unroll
             for (int n = 0; n < NB; ++n) b1[n] = br[16 * n];
@@ -156,9 +169,11 @@ __device__ __forceinline__ void interp3_products(const Op<T> &A, int g, int lane
 #pragma unroll
     for (int d = 0; d < 4; ++d) a[d] = Af[size_t(d) * 64];
     qload(0, b0);
-    for (int st = 0; st < ns; st += 4) {
+    const int nr = real_steps(kl, ns);
+    for (int st = 0; st < nr; st += 4) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
+            if (st + d >= nr) break;
             qload(min(st + d + 1, ns - 1), b1);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
