@@ -461,8 +461,11 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc2[n] = v4{0, 0, 0, 0};
         // rows of B past K are clamped to a real row (times zero columns of A)
-        step_products<T, NB, CH>(a.M, g, lane, [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; },
-                                 acc2);
+        auto qrowp = [&](int kb) { return Qj + min(4 * kb + krow, nu - 1) * W5; };
+        if constexpr (sizeof(T) == 4)
+            step_products_deep<T, NB>(a.M, g, lane, qrowp, acc2);
+        else
+            step_products<T, NB, CH>(a.M, g, lane, qrowp, acc2);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = frow[r];
