@@ -100,7 +100,8 @@ __device__ __forceinline__ void step_products(const Op<T> &A, int g, int lane, R
 }
 
 // Steps of a list that carry operator entries: the list is padded to a
-// multiple of 4 by repeating its last step with zero fragments.  The deep
+// multiple of 4 by repeating its last step with zero fragments (a real
+// step names each K step once, so a repeat can only be padding).  The deep
 // walkers below stop there; an accumulator that starts at +0 is never -0
 // (a sum of opposite zeros rounds to +0), so the products they leave out
 // (exact zeros) would not have changed any bit of it.
