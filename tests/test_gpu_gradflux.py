@@ -86,6 +86,13 @@ def _run(M, O, U, dt):
     return r, inter, s, prof
 
 
+def same_bits(a, b):
+    """Bit-for-bit equality of two float tensors (torch.equal compares values,
+    so +0 and -0 would pass it)."""
+    it = torch.int32 if a.dtype == torch.float32 else torch.int64
+    return a.shape == b.shape and a.dtype == b.dtype and torch.equal(a.view(it), b.view(it))
+
+
 CASES = [("mixed", 1, "fp32"), ("mixed", 2, "fp32"), ("mixed", 3, "fp32"), ("mixed", 4, "fp32"),
          ("mixed", 2, "fp64"), ("mixed", 4, "fp64"), ("big", 4, "fp32"), ("hybrid", 3, "fp32"),
          ("hybrid", 3, "fp64"), ("hybrid", 4, "fp32"), ("curvedwall", 3, "fp32"), ("wallbox", 2, "fp64"),
@@ -120,20 +127,20 @@ def test_fused_gradient_stage_gives_the_bits_of_the_separate_kernels(kind, p, pr
         assert p0[n][1] == (1 if t in ts else 0) and p1[n][1] == 0, (n, p0[n], p1[n])
         assert p0[g][1] == 0 and p1[g][1] == (1 if t in ts else 0), (g, p0[g], p1[g])
     for t in ts:
-        assert torch.equal(r0[t], r1[t]), ("rhs", NAMES[t])
+        assert same_bits(r0[t], r1[t]), ("rhs", NAMES[t])
         ne = O.types[NAMES[t]].nelem
         for which in (0, 1):
-            assert torch.equal(i0[(t, which)][:, :, :ne], i1[(t, which)][:, :, :ne]), ("intermediate", which, NAMES[t])
+            assert same_bits(i0[(t, which)][:, :, :ne], i1[(t, which)][:, :, :ne]), ("intermediate", which, NAMES[t])
         # the gradient at flux points: the same bits where the common flux
         # reads it; the fused kernel (of a fresh mesh) leaves the other
         # points at their initial zero, the separate kernels write them
         mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
         q0, q1 = i0[(t, 2)][:, :, :ne], i1[(t, 2)][:, :, :ne]
-        assert torch.equal(torch.where(mask, q0, 0), torch.where(mask, q1, 0)), ("Qf read", NAMES[t])
+        assert same_bits(torch.where(mask, q0, 0), torch.where(mask, q1, 0)), ("Qf read", NAMES[t])
         assert not torch.where(mask, 0, q0).any(), ("Qf written off the read faces", NAMES[t])
         assert torch.where(mask, 0, q1).any()
         print(f"  {NAMES[t]}: gradient written at {float(mask.float().mean()):.3f} of the flux points", flush=True)
-        assert torch.equal(s0[t], s1[t]), ("rk45 steps", NAMES[t])
+        assert same_bits(s0[t], s1[t]), ("rk45 steps", NAMES[t])
     assert max(float(r0[t].abs().max()) for t in ts) > 1e-3
 
 
@@ -165,12 +172,12 @@ def test_every_gradient_stage_form_gives_the_same_bits(kind, p):
         outs.append((r, inter, s))
     for form in (1, 2):
         for t in ts:
-            assert torch.equal(outs[0][0][t], outs[form][0][t]), ("rhs", form, NAMES[t])
+            assert same_bits(outs[0][0][t], outs[form][0][t]), ("rhs", form, NAMES[t])
             ne = O.types[NAMES[t]].nelem
             mask = torch.from_numpy(np.ascontiguousarray(rp[NAMES[t]].T)).to("cuda")[:, None, :]
-            assert torch.equal(torch.where(mask, outs[0][1][(t, 2)][:, :, :ne], 0),
-                               torch.where(mask, outs[form][1][(t, 2)][:, :, :ne], 0)), ("Qf", form)
-            assert torch.equal(outs[0][2][t], outs[form][2][t]), ("rk45", form, NAMES[t])
+            assert same_bits(torch.where(mask, outs[0][1][(t, 2)][:, :, :ne], 0),
+                             torch.where(mask, outs[form][1][(t, 2)][:, :, :ne], 0)), ("Qf", form)
+            assert same_bits(outs[0][2][t], outs[form][2][t]), ("rk45", form, NAMES[t])
 
 
 @pytest.mark.parametrize("kind,system", [("mixed", "ns"), ("hybrid", "ns"), ("mixed", "euler"),
