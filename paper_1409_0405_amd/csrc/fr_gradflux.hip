@@ -706,7 +706,9 @@ hipError_t launch_gradflux(int etype, const GradFluxArgs<T> &a, hipStream_t s, b
     if (!lds || a.G.stage != 6 || a.M.stage != 6 || a.G.mbw != 1 || a.M.mbw != 1 || !a.G.klist ||
         !a.G.koff || !a.G.rowmap || !a.M.klist || !a.M.koff || !a.M.rowmap || a.G.M != 3 * a.nu ||
         a.M.M != a.nf || 4 * a.G.Kb < a.nu + a.nf || 4 * a.M.Kb < a.nu || a.ld % 64 || a.nelem > a.ld ||
-        (reinterpret_cast<uintptr_t>(a.U) | reinterpret_cast<uintptr_t>(a.Cf)) % 16)
+        (reinterpret_cast<uintptr_t>(a.U) | reinterpret_cast<uintptr_t>(a.Cf) |
+         reinterpret_cast<uintptr_t>(a.geom)) % 16 ||
+        reinterpret_cast<uintptr_t>(a.xi) % 4)   // 16- and 4-byte direct loads into LDS
         return hipErrorInvalidValue;
     if (!a.nelem) return hipSuccess;
     if constexpr (std::is_same<T, float>::value) {
