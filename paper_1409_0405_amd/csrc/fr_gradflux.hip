@@ -321,6 +321,19 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
                 step_products<T, NB, CH>(a.G, g, lane, brow, acc[m]);
         }
     }
+    // the states of this thread's first PI points of the point-wise phase,
+    // from B while it is still in LDS
+    constexpr int PI = 2;
+    T u0[PI][5];
+#pragma unroll
+    for (int q = 0; q < PI; ++q) {
+        const int it = q * 64 * NW + tid;
+        const int i = it / NE, e = it - i * NE;
+        if (it < nu * NE) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u0[q][v] = Bs[i * W5 + v * NE + e];
+        }
+    }
     __syncthreads();                                     // every wavefront is done with B
 #pragma unroll
     for (int m = 0; m < MG; ++m) {
@@ -336,19 +349,21 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
     __syncthreads();
 
     // 3. point-wise: one (solution point, element) per thread; Q replaces Qt
-    // in place, Ft goes to memory.  U comes again from memory (B's place in
-    // LDS holds Qt now; the tile was just read, so L2 serves it): a thread
-    // loads the states of its next PI points first, so that no load queues
-    // behind the Ft stores of the points before it (memory operations of a
-    // wavefront retire in order).
-    constexpr int PI = 2;
+    // in place, Ft goes to memory.  A thread's first PI states came from B
+    // above; further ones (B's place in LDS holds Qt now) come again from
+    // memory, where L2 serves them, and a thread loads those of its next PI
+    // points first, so that no load queues behind the Ft stores of the
+    // points before it (memory operations of a wavefront retire in order).
     for (int base = 0; base < nu * NE; base += PI * 64 * NW) {
         T uu[PI][5];
 #pragma unroll
         for (int q = 0; q < PI; ++q) {
             const int it = base + q * 64 * NW + tid;
             const int i = it / NE, e = it - i * NE;
-            if (it < nu * NE && e0 + e < a.nelem) {
+            if (base == 0) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) uu[q][v] = u0[q][v];
+            } else if (it < nu * NE && e0 + e < a.nelem) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) uu[q][v] = a.U[(int64_t(i) * 5 + v) * ld + e0 + e];
             }
