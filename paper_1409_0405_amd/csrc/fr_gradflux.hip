@@ -322,8 +322,9 @@ __global__ __launch_bounds__(64 * NW) void gradflux_kernel(GradFluxArgs<T> a) {
         }
     }
     // the states of this thread's first PI points of the point-wise phase,
-    // from B while it is still in LDS
-    constexpr int PI = 2;
+    // from B while it is still in LDS (at p = 4 three cover every point of
+    // an FP32 tet or prism tile)
+    constexpr int PI = sizeof(T) == 4 && ET < 2 ? 3 : 2;
     T u0[PI][5];
 #pragma unroll
     for (int q = 0; q < PI; ++q) {
