@@ -44,8 +44,8 @@ RIDGE = PEAK_FP32_MFMA / PEAK_HBM
 # variant not listed reports traffic null.
 TRAFFIC_SOURCE = "profiles/rhs_ns_p4_tgv_mixed_hbm_counters.md"
 MEASURED_TRAFFIC = {
-    ('gradflux_tet', 0, 0): 1281.9e6,
-    ('gradflux_pri', 0, 0): 1341.0e6,
+    ('gradflux_tet', 0, 0): 1164.4e6,
+    ('gradflux_pri', 0, 0): 1257.8e6,
     ('interp_tet', 2, 1): 373.8e6,
     ('interp_pri', 2, 1): 398.8e6,
     ('interp_pri', 1, 1): 398.5e6,
@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {
     ('interp_tet', 2, 0): 373.7e6,
     ('div_tet', 1, 3): 995.2e6,
     ('div_tet', 1, 1): 1037.2e6,
-    ('div_pri', 1, 6): 1256.9e6,
+    ('div_pri', 1, 6): 1208.7e6,
     ('common_flux', 0, 0): 1966.5e6,
     ('common_solution', 0, 0): 795.9e6,
     ('div_pri', 5, 0): 1067.5e6,
